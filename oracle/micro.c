@@ -1,0 +1,313 @@
+/*
+ * FP64 CPU oracle: time stepping and averaging of ONE micro problem.
+ *
+ * TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).  Plain loops, no blocking,
+ * no fusion, no reordering beyond what the paper's definitions state.
+ *
+ * Paper passages followed (Leitenmaier & Runborg, HMM for the LL equation):
+ *   - micro problem eq. (micro), Section 2.2: dm/dt = -m x H - alpha m x (m x H),
+ *     H = div(a grad m), on [-mu', mu']^d x [0, eta];
+ *   - second-order central difference for div(a grad m) (Section 2.3 and the
+ *     opening of Section 4); an optional fourth-order conservative variant;
+ *   - boundary conditions of Section 4.2: periodic m - m_init, or Dirichlet
+ *     m = m_init on the ghost points;
+ *   - HeunP and RK4P (Section 3.1): Runge-Kutta stages, then projection
+ *     m <- m / |m| every step.  Readings: HeunP's second stage uses the full
+ *     step m + dt k1 (the printed half step would make the method first
+ *     order, contradicting its stated second order); RK4's third stage is
+ *     k3 = f(m + dt/2 k2) (the printed "k_2" there is a typo);
+ *   - upscaling eq. (upscaling), Section 2.3: H_avg = sum_n w^n sum_j w_j Q_j(m^n)
+ *     with Q the discrete field H (field model), the face flux a grad m (flux
+ *     model) or m x H (torque model), accumulated in index order.
+ *
+ * Grid (extended with G ghost layers per side): interior index i in [0, N),
+ * extended side E = N + 2G, 2-D storage index (i1+G)*E + (i0+G) with axis 0
+ * fastest.  A[ax][idx] is the coefficient on the face between cell idx and
+ * idx + e_ax.  m_init is given on the whole extended grid.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define GW 3 /* ghost width: the fourth-order stencil reaches 3 cells */
+
+typedef struct {
+    int d, N, E, order, bc;
+    long cells_ext;
+    double dx;
+    const double *A;     /* [d][E^d] */
+    const double *minit; /* [3][E^d] */
+} grid_t;
+
+static long ext_index(const grid_t *g, int i0, int i1) {
+    if (g->d == 1) return (long)(i0 + GW);
+    return (long)(i1 + GW) * g->E + (i0 + GW);
+}
+
+static long axis_stride(const grid_t *g, int ax) { return ax == 0 ? 1 : g->E; }
+
+/* Fill the ghost layers of y (3 components, extended storage) from its interior. */
+static void fill_ghosts(const grid_t *g, double *y) {
+    const int N = g->N;
+    for (int ax = 0; ax < g->d; ++ax) {
+        int other_n = (g->d == 1) ? 1 : N;
+        for (int o = 0; o < other_n; ++o) {
+            for (int gi = -GW; gi < N + GW; ++gi) {
+                if (gi >= 0 && gi < N) continue;
+                int wrap = ((gi % N) + N) % N;
+                long gidx, widx;
+                if (ax == 0) {
+                    gidx = ext_index(g, gi, o);
+                    widx = ext_index(g, wrap, o);
+                } else {
+                    gidx = ext_index(g, o, gi);
+                    widx = ext_index(g, o, wrap);
+                }
+                for (int c = 0; c < 3; ++c) {
+                    const double *mi = g->minit + c * g->cells_ext;
+                    double *yc = y + c * g->cells_ext;
+                    if (g->bc == 0) /* periodic perturbation m - m_init */
+                        yc[gidx] = yc[widx] + (mi[gidx] - mi[widx]);
+                    else            /* Dirichlet: m = m_init on ghosts */
+                        yc[gidx] = mi[gidx];
+                }
+            }
+        }
+    }
+}
+
+/* Discrete gradient of component array yc on face idx (between idx and idx+s), times a. */
+static double face_flux(const grid_t *g, const double *yc, long idx, int ax) {
+    long s = axis_stride(g, ax);
+    double a = g->A[ax * g->cells_ext + idx];
+    if (g->order == 2) {
+        return a * (yc[idx + s] - yc[idx]) / g->dx;
+    }
+    double gp = 27.0 * (yc[idx + s] - yc[idx]) - (yc[idx + 2 * s] - yc[idx - s]);
+    return a * gp / (24.0 * g->dx);
+}
+
+/* H = div(a grad y) at interior cell idx (ghosts of y must be filled). */
+static double field_at(const grid_t *g, const double *yc, long idx) {
+    double h = 0.0;
+    for (int ax = 0; ax < g->d; ++ax) {
+        long s = axis_stride(g, ax);
+        if (g->order == 2) {
+            double fp = face_flux(g, yc, idx, ax);
+            double fm = face_flux(g, yc, idx - s, ax);
+            h += (fp - fm) / g->dx;
+        } else {
+            double f0 = face_flux(g, yc, idx, ax);
+            double fm1 = face_flux(g, yc, idx - s, ax);
+            double fp1 = face_flux(g, yc, idx + s, ax);
+            double fm2 = face_flux(g, yc, idx - 2 * s, ax);
+            h += (27.0 * (f0 - fm1) - (fp1 - fm2)) / (24.0 * g->dx);
+        }
+    }
+    return h;
+}
+
+static void cross(const double *a, const double *b, double *out) {
+    out[0] = a[1] * b[2] - a[2] * b[1];
+    out[1] = a[2] * b[0] - a[0] * b[2];
+    out[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+/* H for every interior cell: H[c][ext idx].  y gets its ghosts filled first. */
+static void field_all(const grid_t *g, double *y, double *H) {
+    fill_ghosts(g, y);
+    int n1 = (g->d == 1) ? 1 : g->N;
+    for (int c = 0; c < 3; ++c)
+        for (int i1 = 0; i1 < n1; ++i1)
+            for (int i0 = 0; i0 < g->N; ++i0) {
+                long idx = ext_index(g, i0, i1);
+                H[c * g->cells_ext + idx] = field_at(g, y + c * g->cells_ext, idx);
+            }
+}
+
+/* f(y) = -y x H - alpha y x (y x H) for every interior cell; also returns H. */
+static void rhs_all(const grid_t *g, double alpha, double *y, double *H, double *f) {
+    field_all(g, y, H);
+    int n1 = (g->d == 1) ? 1 : g->N;
+    long ce = g->cells_ext;
+    for (int i1 = 0; i1 < n1; ++i1)
+        for (int i0 = 0; i0 < g->N; ++i0) {
+            long idx = ext_index(g, i0, i1);
+            double m[3] = {y[idx], y[ce + idx], y[2 * ce + idx]};
+            double h[3] = {H[idx], H[ce + idx], H[2 * ce + idx]};
+            double mxh[3], mxmxh[3];
+            cross(m, h, mxh);
+            cross(m, mxh, mxmxh);
+            for (int c = 0; c < 3; ++c) f[c * ce + idx] = -mxh[c] - alpha * mxmxh[c];
+        }
+}
+
+/* Quantity sum at one time level: out3d[...] += wt * sum_j w_j Q_j. */
+static void accumulate(const grid_t *g, int quantity, double wt, double *y, double *H,
+                       const double *wx, const double *wy, const double *wfx,
+                       const double *wfy, double *out) {
+    field_all(g, y, H);
+    int n1 = (g->d == 1) ? 1 : g->N;
+    long ce = g->cells_ext;
+    if (quantity == 1) { /* flux model: a grad m on the east face of each cell */
+        for (int ax = 0; ax < g->d; ++ax)
+            for (int c = 0; c < 3; ++c) {
+                double s = 0.0;
+                for (int i1 = 0; i1 < n1; ++i1)
+                    for (int i0 = 0; i0 < g->N; ++i0) {
+                        long idx = ext_index(g, i0, i1);
+                        double w;
+                        if (g->d == 1) w = wfx[i0];
+                        else if (ax == 0) w = wfx[i0] * wy[i1];
+                        else w = wx[i0] * wfy[i1];
+                        s += w * face_flux(g, y + c * ce, idx, ax);
+                    }
+                out[ax * 3 + c] += wt * s;
+            }
+        return;
+    }
+    for (int c = 0; c < 3; ++c) {
+        double s = 0.0;
+        for (int i1 = 0; i1 < n1; ++i1)
+            for (int i0 = 0; i0 < g->N; ++i0) {
+                long idx = ext_index(g, i0, i1);
+                double w = (g->d == 1) ? wx[i0] : wx[i0] * wy[i1];
+                double q;
+                if (quantity == 0) {
+                    q = H[c * ce + idx];
+                } else { /* torque m x H */
+                    double m[3] = {y[idx], y[ce + idx], y[2 * ce + idx]};
+                    double h[3] = {H[idx], H[ce + idx], H[2 * ce + idx]};
+                    double t[3];
+                    cross(m, h, t);
+                    q = t[c];
+                }
+                s += w * q;
+            }
+        out[c] += wt * s;
+    }
+}
+
+static double energy(const grid_t *g, double *y) {
+    fill_ghosts(g, y);
+    int n1 = (g->d == 1) ? 1 : g->N;
+    long ce = g->cells_ext;
+    double e = 0.0;
+    for (int ax = 0; ax < g->d; ++ax)
+        for (int i1 = 0; i1 < n1; ++i1)
+            for (int i0 = 0; i0 < g->N; ++i0) {
+                long idx = ext_index(g, i0, i1);
+                double a = g->A[ax * ce + idx];
+                for (int c = 0; c < 3; ++c) {
+                    double fl = face_flux(g, y + c * ce, idx, ax);
+                    /* fl = a * grad; energy density a |grad|^2 / 2 = fl^2 / (2a) */
+                    e += 0.5 * fl * fl / a;
+                }
+            }
+    return e * pow(g->dx, g->d);
+}
+
+static double norm_dev(const grid_t *g, const double *y) {
+    int n1 = (g->d == 1) ? 1 : g->N;
+    long ce = g->cells_ext;
+    double dev = 0.0;
+    for (int i1 = 0; i1 < n1; ++i1)
+        for (int i0 = 0; i0 < g->N; ++i0) {
+            long idx = ext_index(g, i0, i1);
+            double n = sqrt(y[idx] * y[idx] + y[ce + idx] * y[ce + idx] + y[2 * ce + idx] * y[2 * ce + idx]);
+            double d = fabs(n - 1.0);
+            if (d > dev) dev = d;
+        }
+    return dev;
+}
+
+/* Evaluate H(y) once; y_ext [3][E^d] (interior used, ghosts refilled), H_out [3][N^d]. */
+int oracle_eval_field(int d, int N, int order, int bc, double dx, const double *A,
+                      const double *minit, const double *y_ext, double *H_out) {
+    grid_t g = {d, N, N + 2 * GW, order, bc, 0, dx, A, minit};
+    g.cells_ext = (d == 1) ? g.E : (long)g.E * g.E;
+    double *y = malloc(sizeof(double) * 3 * g.cells_ext);
+    double *H = calloc(3 * g.cells_ext, sizeof(double));
+    memcpy(y, y_ext, sizeof(double) * 3 * g.cells_ext);
+    field_all(&g, y, H);
+    int n1 = (d == 1) ? 1 : N;
+    long nc = (long)N * n1;
+    for (int c = 0; c < 3; ++c)
+        for (int i1 = 0; i1 < n1; ++i1)
+            for (int i0 = 0; i0 < N; ++i0)
+                H_out[c * nc + (long)i1 * N + i0] = H[c * g.cells_ext + ext_index(&g, i0, i1)];
+    free(y);
+    free(H);
+    return 0;
+}
+
+/*
+ * Solve one micro problem.
+ *   integ: 1 = HeunP, 2 = RK4P; bc: 0 periodic m - m_init, 1 Dirichlet;
+ *   quantity: 0 field, 1 flux, 2 torque; project: 1 normal, 0 off (tests only)
+ *   wx, wy: per-axis cell weights [N]; wfx, wfy: per-axis east-face weights [N]
+ *   wt: time weights [M+1]
+ *   out: [3] or [3d] (flux: [axis][component]); mfinal [3][N^d] (nullable);
+ *   energy_out, normdev_out: [M+1] (nullable)
+ */
+int oracle_solve_box(int d, int N, int order, int integ, int bc, int quantity, int project,
+                     double dx, double alpha, double dt, int M,
+                     const double *A, const double *minit,
+                     const double *wx, const double *wy, const double *wfx, const double *wfy,
+                     const double *wt, double *out, double *mfinal,
+                     double *energy_out, double *normdev_out) {
+    grid_t g = {d, N, N + 2 * GW, order, bc, 0, dx, A, minit};
+    g.cells_ext = (d == 1) ? g.E : (long)g.E * g.E;
+    long ce = g.cells_ext;
+    size_t bytes = sizeof(double) * 3 * ce;
+    double *m = malloc(bytes), *y = malloc(bytes), *H = calloc(3 * ce, sizeof(double));
+    double *k1 = calloc(3 * ce, sizeof(double)), *k2 = calloc(3 * ce, sizeof(double));
+    double *k3 = calloc(3 * ce, sizeof(double)), *k4 = calloc(3 * ce, sizeof(double));
+    memcpy(m, minit, bytes); /* interior = m_init; ghosts are refilled before use */
+    int nq = (quantity == 1) ? 3 * d : 3;
+    for (int q = 0; q < nq; ++q) out[q] = 0.0;
+    int n1 = (d == 1) ? 1 : N;
+
+    for (int n = 0; n <= M; ++n) {
+        accumulate(&g, quantity, wt[n], m, H, wx, wy, wfx, wfy, out);
+        if (energy_out) energy_out[n] = energy(&g, m);
+        if (normdev_out) normdev_out[n] = norm_dev(&g, m);
+        if (n == M) break;
+
+        rhs_all(&g, alpha, m, H, k1);
+        if (integ == 1) { /* HeunP */
+            for (long t = 0; t < 3 * ce; ++t) y[t] = m[t] + dt * k1[t];
+            rhs_all(&g, alpha, y, H, k2);
+            for (long t = 0; t < 3 * ce; ++t) m[t] = m[t] + 0.5 * dt * (k1[t] + k2[t]);
+        } else { /* RK4P */
+            for (long t = 0; t < 3 * ce; ++t) y[t] = m[t] + 0.5 * dt * k1[t];
+            rhs_all(&g, alpha, y, H, k2);
+            for (long t = 0; t < 3 * ce; ++t) y[t] = m[t] + 0.5 * dt * k2[t];
+            rhs_all(&g, alpha, y, H, k3);
+            for (long t = 0; t < 3 * ce; ++t) y[t] = m[t] + dt * k3[t];
+            rhs_all(&g, alpha, y, H, k4);
+            for (long t = 0; t < 3 * ce; ++t)
+                m[t] = m[t] + dt / 6.0 * (k1[t] + 2.0 * k2[t] + 2.0 * k3[t] + k4[t]);
+        }
+        if (project) {
+            for (int i1 = 0; i1 < n1; ++i1)
+                for (int i0 = 0; i0 < N; ++i0) {
+                    long idx = ext_index(&g, i0, i1);
+                    double nr = sqrt(m[idx] * m[idx] + m[ce + idx] * m[ce + idx] +
+                                     m[2 * ce + idx] * m[2 * ce + idx]);
+                    for (int c = 0; c < 3; ++c) m[c * ce + idx] /= nr;
+                }
+        }
+    }
+    if (mfinal) {
+        long nc = (long)N * n1;
+        for (int c = 0; c < 3; ++c)
+            for (int i1 = 0; i1 < n1; ++i1)
+                for (int i0 = 0; i0 < N; ++i0)
+                    mfinal[c * nc + (long)i1 * N + i0] = m[c * ce + ext_index(&g, i0, i1)];
+    }
+    free(m); free(y); free(H); free(k1); free(k2); free(k3); free(k4);
+    int bad = 0;
+    for (int q = 0; q < nq; ++q) if (!isfinite(out[q])) bad = 1;
+    return bad ? 1 : 0;
+}
