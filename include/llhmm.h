@@ -1,0 +1,221 @@
+/*
+ * llhmm.h - C ABI of the MI355X (gfx950) batched HMM micro-problem solver for
+ * the Landau-Lifshitz equation with an oscillatory exchange coefficient
+ * (Leitenmaier & Runborg, "Heterogeneous multiscale methods for the
+ * Landau-Lifshitz equation").
+ *
+ * What the library computes, for every micro box b of a batch (paper Section 2.2,
+ * eq. (micro), and Section 2.3, eq. (upscaling)):
+ *
+ *   1. micro initial data m_init around the macro point x_b: a caller-given
+ *      sampled field, or the normalized 4th-order interpolant Q_[4] of the
+ *      macro magnetization (Section 4.1, eq. (Q_k));
+ *   2. M explicit time steps (HeunP or RK4P with projection, Section 3.1) of
+ *      dm/dt = -m x H - alpha m x (m x H),  H = div(a^eps grad m),
+ *      discretized by a second-order central difference (Section 2.3) or a
+ *      fourth-order conservative stencil, on the box [-mu', mu']^d with
+ *      periodic m - m_init or Dirichlet m = m_init boundary values (Section 4.2);
+ *      M follows the stability rule dt / dx^2 <= C_stab (Section 3.2, eq. (Cstab));
+ *   3. the kernel-weighted average over [-mu, mu]^d x [0, eta] of the field H
+ *      (field model), of a grad m (flux model) or of m x H (torque model),
+ *      with kernels K in K^{p,q} and K0 in K_0^{p,q} (Definition 2.3).
+ *
+ * llhmm_macro_step advances the macro field model eq. (macro_disc) by MPEA
+ * (eqs. (h_mpea), (mpe_update)) or by HeunP / RK4P start-up stages.
+ *
+ * Conventions
+ *   - Every device pointer is caller-owned (e.g. a torch tensor's storage) and
+ *     must stay valid until the work enqueued on `stream` has completed.  The
+ *     library never frees caller memory.  Host pointers are read during the
+ *     call only.
+ *   - Calls are asynchronous on `stream` unless stated otherwise.
+ *   - Every function returns an llhmm_status.  On failure nothing has been
+ *     enqueued, and llhmm_last_error() returns a message (thread-local, valid
+ *     until the next call on the same thread).
+ *   - All results written by the library are FP64.
+ *   - A context is not thread-safe: one context per host thread, or locking.
+ *   - Grid convention (part of the contract for sampled inputs): on each axis,
+ *     dx = 2 mu' / n and the points are xi_j = -mu' + j dx, j = 0..n-1, with
+ *     LLHMM_GHOST ghost layers on each side (j = -3..-1 and n..n+2), so the
+ *     "extended" side is E = n + 6.  Absolute coordinates are center + xi.
+ *     2-D arrays are stored with axis 0 (x1) fastest: index (j1+3)*E + (j0+3).
+ */
+#ifndef LLHMM_H
+#define LLHMM_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LLHMM_ABI_VERSION 1
+#define LLHMM_GHOST 3
+#define LLHMM_MAX_TERMS 8
+
+typedef enum {
+    LLHMM_OK = 0,
+    LLHMM_E_INVALID = -1,   /* argument violates the paper's assumptions or the contract */
+    LLHMM_E_NOMEM = -2,     /* device or host allocation failed */
+    LLHMM_E_BUDGET = -3,    /* a box class does not fit the on-chip budget of any kernel */
+    LLHMM_E_UNSTABLE = -4,  /* a box produced non-finite values (see status words) */
+    LLHMM_E_HIP = -5,       /* a HIP runtime call failed */
+    LLHMM_E_NOTSUP = -6     /* valid request, no kernel built for it */
+} llhmm_status;
+
+typedef enum { LLHMM_FP64 = 0, LLHMM_FP32 = 1 } llhmm_precision;
+/* AUTO: HeunP when alpha > 0.2 (end of Section 3), else RK4P (Section 3.2). */
+typedef enum { LLHMM_INTEG_AUTO = 0, LLHMM_HEUNP = 1, LLHMM_RK4P = 2 } llhmm_integrator;
+/* PERIODIC_PERT: m - m_init periodic on the box; DIRICHLET: m = m_init on the ghosts. */
+typedef enum { LLHMM_BC_PERIODIC_PERT = 0, LLHMM_BC_DIRICHLET = 1 } llhmm_bc;
+/* Averaged quantity: FIELD -> 3 values; FLUX -> 3*dim values [axis][component]; TORQUE -> 3. */
+typedef enum { LLHMM_Q_FIELD = 0, LLHMM_Q_FLUX = 1, LLHMM_Q_TORQUE = 2 } llhmm_quantity;
+typedef enum { LLHMM_INIT_EXPLICIT = 0, LLHMM_INIT_MACRO_Q = 1 } llhmm_init_mode;
+typedef enum { LLHMM_MACRO_MPEA = 0, LLHMM_MACRO_HEUNP = 1, LLHMM_MACRO_RK4P = 2 } llhmm_macro_scheme;
+
+/* Averaging kernels K in K^{p_x,q_x} (space) and K0 in K_0^{p_t,q_t} (time),
+ * Definition 2.3.  The paper's experiments use 3, 7, 3, 7 (Section 4.3). */
+typedef struct { int32_t p_x, q_x, p_t, q_t; } llhmm_kernel;
+
+/* Material coefficient a^eps (eq. (prob), assumption (A1)), closed form
+ *   a(x) = c0 + sum_{t < n_terms} amp[t] * prod_{axis < dim} s_{t,axis}(x_axis),
+ *   s(x) = 1 if freq[t][axis] == 0, else sin(2 pi freq[t][axis] x + phase[t][axis]),
+ * or, with sampled != 0, face values supplied in a device array (see
+ * llhmm_micro_batch).  a_max is not read from here (see llhmm_box). */
+typedef struct {
+    int32_t dim, n_terms, sampled, pad_;
+    double c0;
+    double amp[LLHMM_MAX_TERMS];
+    double freq[LLHMM_MAX_TERMS][2];
+    double phase[LLHMM_MAX_TERMS][2];
+} llhmm_coef;
+
+/* One micro problem (eq. (micro)). */
+typedef struct {
+    int32_t dim;          /* d in {1, 2} */
+    int32_t n;            /* grid points per axis (square boxes in 2-D), >= 8 */
+    int32_t order;        /* spatial order of the stencil: 2 or 4 */
+    int32_t integrator;   /* llhmm_integrator */
+    int32_t bc;           /* llhmm_bc */
+    int32_t quantity;     /* llhmm_quantity */
+    int32_t init_mode;    /* llhmm_init_mode */
+    int32_t n_steps;      /* 0: stability rule picks M; > 0: forced M */
+    int32_t coef_index;   /* index into the batch's llhmm_coef table */
+    int32_t macro_index[2]; /* INIT_MACRO_Q: macro node k of the box centre */
+    int32_t pad_;
+    double eps;           /* epsilon (informational; frequencies carry it) */
+    double alpha;         /* micro damping alpha > 0 (artificial damping, Section 2.3) */
+    double mu;            /* averaging half-width, 0 < mu <= mu_box */
+    double mu_box;        /* box half-width mu' */
+    double eta;           /* averaging time, > 0 */
+    double a_max;         /* (A1) upper bound of a^eps, used by the stability rule */
+    double center[2];     /* x_b, absolute coordinates of the box centre */
+    int64_t init_offset;  /* INIT_EXPLICIT: element offset of this box's m_init */
+    int64_t coef_offset;  /* sampled coefficient: element offset of this box's faces */
+} llhmm_box;
+
+/* Periodic macro grid x_i = x0 + i dX, i in [0, n)^dim (eq. (macro_disc)). */
+typedef struct {
+    int32_t dim, n;
+    double dX;
+    double x0[2];
+} llhmm_macro;
+
+typedef struct llhmm_ctx llhmm_ctx;
+typedef struct llhmm_batch llhmm_batch;
+
+/* Library / context management ------------------------------------------ */
+int32_t llhmm_abi_version(void);
+const char *llhmm_last_error(void);
+/* Creates a context bound to HIP device `device`.  Requires a GPU. */
+llhmm_status llhmm_create(llhmm_ctx **ctx, int32_t device);
+llhmm_status llhmm_destroy(llhmm_ctx *ctx);
+
+/* Host-only planning (no GPU needed; ctx may be NULL) ---------------------
+ * Validates every box against assumptions (A1)-(A3) and the contract, resolves
+ * the integrator, and applies the stability rule of Section 3.2:
+ *   omega = sigma * dim * a_max / dx^2 with sigma = 4 (order 2) or (7/3)^2 (order 4),
+ *   r* = largest r with |R(s(-alpha + i))| <= 1 on [0, r] (R: Heun or RK4 polynomial),
+ *   M = ceil(eta / (0.9 r* / omega)), dt = eta / M.
+ * Outputs (host arrays of nboxes, each nullable): M, dt, resolved integrator. */
+llhmm_status llhmm_plan(const llhmm_box *boxes, int32_t nboxes, int32_t *n_steps_out,
+                        double *dt_out, int32_t *integrator_out);
+
+/* Exact-in-double coefficients of the averaging kernels (Definition 2.3 reading:
+ * K(x) = (1-x^2)^(q+1) sum_{i<=p} c_i x^i, K0(t) = t^(q+1)(1-t)^(q+1) sum_{i<=p} d_i t^i,
+ * moments fixed by int K x^r = delta_r0, r = 0..p).  c, d: host arrays of p+1. */
+llhmm_status llhmm_kernel_coeffs(const llhmm_kernel *K, double *c_space, double *d_time);
+
+/* Batches ---------------------------------------------------------------
+ * Plans the boxes (as llhmm_plan), chooses a kernel tile class per box,
+ * uploads the per-box descriptors and allocates the per-box FP64 partial sums.
+ * Host-synchronous.  Errors: LLHMM_E_INVALID (bad box), LLHMM_E_NOTSUP (no
+ * kernel for a box class), LLHMM_E_NOMEM. */
+llhmm_status llhmm_batch_create(llhmm_ctx *ctx, const llhmm_box *boxes, int32_t nboxes,
+                                const llhmm_kernel *K, const llhmm_coef *coefs,
+                                int32_t ncoefs, int32_t precision, llhmm_batch **batch);
+llhmm_status llhmm_batch_destroy(llhmm_ctx *ctx, llhmm_batch *batch);
+/* Number of micro cell-steps of the batch: sum over boxes of M * n^dim. */
+int64_t llhmm_batch_cell_steps(const llhmm_batch *batch);
+
+/* The micro solve (steps 1-3 above) for every box of the batch, on `stream`.
+ *   m_init_dev   INIT_EXPLICIT boxes: FP64 m_init on the extended grid,
+ *                box b at element offset init_offset, layout [3][E^dim]
+ *                (ghost layers are read: they define the boundary data).  Nullable
+ *                when no box uses INIT_EXPLICIT.
+ *   macro, M_macro_dev
+ *                INIT_MACRO_Q boxes: macro grid geometry (host struct) and FP64
+ *                macro field [3][n^dim] (axis 0 slowest: index (i0*n + i1)).
+ *                Nullable when unused.  The box centre must be the macro node.
+ *   coef_dev     boxes whose coefficient is `sampled`: FP64 face values,
+ *                layout [dim][E^dim] at coef_offset, entry (axis, j) = a^eps on
+ *                the face between point j and j + e_axis.  Nullable otherwise.
+ *   m_final_dev  nullable: FP64 final micro state, [nboxes][3][n^dim] packed
+ *                with the largest n of the batch as stride (tests only).
+ * The result stays in the batch until llhmm_upscale. */
+llhmm_status llhmm_micro_batch(llhmm_ctx *ctx, llhmm_batch *batch, const double *m_init_dev,
+                               const llhmm_macro *macro, const double *M_macro_dev,
+                               const double *coef_dev, double *m_final_dev,
+                               hipStream_t stream);
+
+/* Forms the upscaled quantity of every box from the FP64 per-wave partial
+ * sums of the last llhmm_micro_batch, summed in a fixed order:
+ *   H_avg_dev[b * ld + q], q < nq, nq = 3 (field, torque) or 3*dim (flux,
+ *   [axis][component]), FP64.  ld >= the largest nq of the batch.  Nullable.
+ *   status_dev (nullable, int32[nboxes]): 0 ok, 1 non-finite values.
+ * With `check` != 0 the call synchronizes the stream and returns
+ * LLHMM_E_UNSTABLE if any box is non-finite. */
+llhmm_status llhmm_upscale(llhmm_ctx *ctx, llhmm_batch *batch, double *H_avg_dev, int32_t ld,
+                           int32_t *status_dev, int32_t check, hipStream_t stream);
+
+/* One evaluation of the discrete field H(m_init) on every box (no time
+ * stepping): H_dev [nboxes][3][n^dim] packed like m_final_dev.  For tests of
+ * the stencil against the oracle. */
+llhmm_status llhmm_eval_field(llhmm_ctx *ctx, llhmm_batch *batch, const double *m_init_dev,
+                              const llhmm_macro *macro, const double *M_macro_dev,
+                              const double *coef_dev, double *H_dev, hipStream_t stream);
+
+/* Macro step (Section 3.1, 3.3) on npts macro points, FP64, component-major
+ * [3][npts] device arrays:
+ *   M_dev     M^j on entry; M^{j+1} after the last stage of step j.
+ *   H_avg_dev H_avg evaluated at the current stage input (row stride 3: [npts][3]).
+ *   Y_dev     out: the state at which the next micro batch must be solved.
+ *   work_dev  [7][3][npts] scratch kept between calls: history h^j, h^{j-1},
+ *             h^{j-2} (slots step % 3) and up to four stage slopes.
+ *   scheme    MPEA needs step_index >= 2 (history), HEUNP/RK4P are start-up
+ *             schemes with 2 / 4 stages per step.
+ * The stage input for stage 0 is M^j itself.  *next_stage_out (host) receives
+ * the stage to pass on the next call (0 when the step is complete).
+ * MPEA: h = H_avg + alpha M x H_avg, hbar = (23 h^j - 16 h^{j-1} + 5 h^{j-2})/12,
+ * M^{j+1} = (I - s[hbar]x)^{-1}(I + s[hbar]x) M^j, s = dt/2, in closed form
+ * [(1 - s^2|h|^2) M + 2s h x M + 2 s^2 (h.M) h] / (1 + s^2 |h|^2). */
+llhmm_status llhmm_macro_step(llhmm_ctx *ctx, int32_t npts, int32_t scheme, int32_t step_index,
+                              int32_t stage, double dt, double alpha, double *M_dev,
+                              const double *H_avg_dev, double *Y_dev, double *work_dev,
+                              int32_t *next_stage_out, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LLHMM_H */

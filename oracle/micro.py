@@ -29,37 +29,45 @@ from . import kernels, stability
 
 GW = 3
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB = None
+_LIBS = {}
+
+# Build variants of the same C source.  "plain": no FMA contraction (the
+# oracle).  "fma": identical algorithm with a*b+c contracted to fused
+# multiply-adds; the spread between the two measures the FP64 rounding floor
+# of a result, which bounds how closely any other correct FP64 implementation
+# can be expected to agree with the oracle.
+_VARIANTS = {"plain": ["-ffp-contract=off"], "fma": ["-ffp-contract=fast", "-mfma"]}
 
 
-def lib_path():
-    return os.path.join(_HERE, "_build", "liboracle.so")
+def lib_path(variant="plain"):
+    name = "liboracle.so" if variant == "plain" else "liboracle_%s.so" % variant
+    return os.path.join(_HERE, "_build", name)
 
 
-def build(force=False):
-    """Compile micro.c with gcc (plain -O2, no fast-math, no FMA contraction)."""
-    out = lib_path()
+def build(force=False, variant="plain"):
+    """Compile micro.c with gcc (-O2, no fast-math)."""
+    out = lib_path(variant)
     src = os.path.join(_HERE, "micro.c")
     if not force and os.path.exists(out) and os.path.getmtime(out) >= os.path.getmtime(src):
         return out
     os.makedirs(os.path.dirname(out), exist_ok=True)
     tmp = out + ".tmp%d" % os.getpid()
-    subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
-                           "-o", tmp, src, "-lm"])
+    subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared"] + _VARIANTS[variant] +
+                          ["-o", tmp, src, "-lm"])
     os.replace(tmp, out)
     return out
 
 
-def _lib():
-    global _LIB
-    if _LIB is None:
-        _LIB = ctypes.CDLL(build())
+def _lib(variant="plain"):
+    if variant not in _LIBS:
+        L = ctypes.CDLL(build(variant=variant))
         dp = ctypes.POINTER(ctypes.c_double)
-        _LIB.oracle_solve_box.argtypes = [ctypes.c_int] * 7 + [ctypes.c_double] * 3 + [ctypes.c_int] + [dp] * 11
-        _LIB.oracle_solve_box.restype = ctypes.c_int
-        _LIB.oracle_eval_field.argtypes = [ctypes.c_int] * 4 + [ctypes.c_double] + [dp] * 4
-        _LIB.oracle_eval_field.restype = ctypes.c_int
-    return _LIB
+        L.oracle_solve_box.argtypes = [ctypes.c_int] * 7 + [ctypes.c_double] * 3 + [ctypes.c_int] + [dp] * 11
+        L.oracle_solve_box.restype = ctypes.c_int
+        L.oracle_eval_field.argtypes = [ctypes.c_int] * 4 + [ctypes.c_double] + [dp] * 4
+        L.oracle_eval_field.restype = ctypes.c_int
+        _LIBS[variant] = L
+    return _LIBS[variant]
 
 
 def _ptr(a):
@@ -170,7 +178,7 @@ def weights(box, kernel, M):
 
 # ---------------------------------------------------------------- driver
 def solve_box(box, coef, init_fn=None, macro=None, kernel=(3, 7, 3, 7), project=True,
-              want_state=False, want_trace=False):
+              want_state=False, want_trace=False, variant="plain"):
     d, n = box["dim"], box["n"]
     A, dx = face_coefficients(box, coef)
     mi = initial_data(box, init_fn, macro)
@@ -181,7 +189,7 @@ def solve_box(box, coef, init_fn=None, macro=None, kernel=(3, 7, 3, 7), project=
     mfinal = np.zeros(3 * n ** d) if want_state else None
     en = np.zeros(M + 1) if want_trace else None
     nd = np.zeros(M + 1) if want_trace else None
-    rc = _lib().oracle_solve_box(d, n, box["order"], integ, box["bc"], box["quantity"],
+    rc = _lib(variant).oracle_solve_box(d, n, box["order"], integ, box["bc"], box["quantity"],
                                  1 if project else 0, dx, box["alpha"], dt, M,
                                  _ptr(A), _ptr(mi), _ptr(w), _ptr(w), _ptr(wf), _ptr(wf),
                                  _ptr(wt), _ptr(out), _ptr(mfinal), _ptr(en), _ptr(nd))

@@ -1,0 +1,123 @@
+// Small pointwise kernels around the micro solve.
+//
+//   k_upscale: forms the upscaled quantity of each box (eq. (upscaling)) from
+//              the FP64 per-wave partial sums in a fixed order, times the
+//              physical scale of the averaged quantity; writes a status word.
+//   k_macro:   one stage of the macro field model eq. (macro_disc) per macro
+//              point: MPEA (eqs. (h_mpea), (mpe_update)) or HeunP / RK4P
+//              start-up stages (Section 3.1).  FP64.
+#include "llhmm_internal.h"
+
+namespace llhmm {
+
+__global__ void __launch_bounds__(256) k_upscale(const double *partials, const int32_t *wave_status,
+                                                 const double *box_const, const BoxPlan *plans,
+                                                 int nboxes, double *H, int ld,
+                                                 int32_t *status) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nboxes) return;
+    const BoxPlan &P = plans[b];
+    int bad = 0;
+    for (int q = 0; q < P.nq; ++q) {
+        double s = 0.0;
+        for (int w = 0; w < P.nwaves; ++w) s += partials[((long)b * kMaxWaves + w) * kMaxQ + q];
+        // form 1: add the time-independent average of the reference part, times sum_n w^n
+        s = (s + P.wsum * box_const[(long)b * kMaxQ + q]) * P.out_scale;
+        if (!__builtin_isfinite(s)) bad = 1;
+        if (H) H[(long)b * ld + q] = s;
+    }
+    for (int w = 0; w < P.nwaves; ++w) bad |= wave_status[(long)b * kMaxWaves + w];
+    status[b] = bad;
+}
+
+hipError_t launch_upscale(const double *partials, const int32_t *wave_status, const double *box_const,
+                          const BoxPlan *plans, int nboxes, double *H, int ld, int32_t *status,
+                          int32_t *, hipStream_t s) {
+    if (nboxes <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_upscale, dim3((nboxes + 255) / 256), dim3(256), 0, s, partials,
+                       wave_status, box_const, plans, nboxes, H, ld, status);
+    return hipGetLastError();
+}
+
+__device__ __forceinline__ void cross3(const double a[3], const double b[3], double o[3]) {
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+// f(M, H) = -M x H - alpha M x (M x H)
+__device__ __forceinline__ void ll_rhs(const double m[3], const double h[3], double alpha, double f[3]) {
+    double c[3], e[3];
+    cross3(m, h, c);
+    cross3(m, c, e);
+    for (int i = 0; i < 3; ++i) f[i] = -c[i] - alpha * e[i];
+}
+
+__global__ void __launch_bounds__(256) k_macro(int npts, int scheme, int step, int stage, double dt,
+                                               double alpha, double *M, const double *H, double *Y,
+                                               double *work) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npts) return;
+    const long np = npts;
+    auto W = [&](int slot, int c) -> double & { return work[((long)slot * 3 + c) * np + i]; };
+    double m[3], h[3], y[3];
+    for (int c = 0; c < 3; ++c) {
+        m[c] = M[c * np + i];
+        h[c] = H[(long)i * 3 + c];
+        y[c] = Y[c * np + i];
+    }
+    if (stage == 0) {  // h^j = H_avg + alpha M^j x H_avg, eq. (h_term), kept for MPEA
+        double mh[3];
+        cross3(m, h, mh);
+        for (int c = 0; c < 3; ++c) W(step % 3, c) = h[c] + alpha * mh[c];
+    }
+    if (scheme == LLHMM_MACRO_MPEA) {
+        double hb[3];
+        for (int c = 0; c < 3; ++c)
+            hb[c] = (23.0 * W(step % 3, c) - 16.0 * W((step + 2) % 3, c) + 5.0 * W((step + 1) % 3, c)) / 12.0;
+        // (I - s[hb]x) M' = (I + s[hb]x) M, s = dt/2: rotation about hb (Cayley transform)
+        const double s = 0.5 * dt;
+        const double hh = hb[0] * hb[0] + hb[1] * hb[1] + hb[2] * hb[2];
+        const double hm = hb[0] * m[0] + hb[1] * m[1] + hb[2] * m[2];
+        double hxm[3];
+        cross3(hb, m, hxm);
+        const double den = 1.0 + s * s * hh;
+        for (int c = 0; c < 3; ++c) {
+            const double v = ((1.0 - s * s * hh) * m[c] + 2.0 * s * hxm[c] + 2.0 * s * s * hm * hb[c]) / den;
+            M[c * np + i] = v;
+            Y[c * np + i] = v;
+        }
+        return;
+    }
+    double k[3];
+    ll_rhs(stage == 0 ? m : y, h, alpha, k);
+    const int nst = (scheme == LLHMM_MACRO_HEUNP) ? 2 : 4;
+    if (stage < nst - 1) {
+        for (int c = 0; c < 3; ++c) W(3 + stage, c) = k[c];
+        double cfac = (scheme == LLHMM_MACRO_HEUNP) ? 1.0 : (stage == 2 ? 1.0 : 0.5);
+        for (int c = 0; c < 3; ++c) Y[c * np + i] = m[c] + cfac * dt * k[c];
+        return;
+    }
+    double mt[3];
+    if (scheme == LLHMM_MACRO_HEUNP) {
+        for (int c = 0; c < 3; ++c) mt[c] = m[c] + 0.5 * dt * (W(3, c) + k[c]);
+    } else {
+        for (int c = 0; c < 3; ++c)
+            mt[c] = m[c] + dt / 6.0 * (W(3, c) + 2.0 * W(4, c) + 2.0 * W(5, c) + k[c]);
+    }
+    const double nr = sqrt(mt[0] * mt[0] + mt[1] * mt[1] + mt[2] * mt[2]);
+    for (int c = 0; c < 3; ++c) {
+        M[c * np + i] = mt[c] / nr;
+        Y[c * np + i] = mt[c] / nr;
+    }
+}
+
+hipError_t launch_macro(int npts, int scheme, int step, int stage, double dt, double alpha,
+                        double *M, const double *H, double *Y, double *work, hipStream_t s) {
+    if (npts <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_macro, dim3((npts + 255) / 256), dim3(256), 0, s, npts, scheme, step, stage,
+                       dt, alpha, M, H, Y, work);
+    return hipGetLastError();
+}
+
+}  // namespace llhmm

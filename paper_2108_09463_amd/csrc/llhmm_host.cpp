@@ -1,0 +1,610 @@
+// Host side of libllhmm: validation, the stability rule, kernel coefficients,
+// batch planning (tile class per box, table offsets, time weights) and the
+// launches.  See include/llhmm.h for the contract.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "llhmm_internal.h"
+
+using namespace llhmm;
+
+namespace {
+
+thread_local std::string g_err;
+
+llhmm_status fail(llhmm_status code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail(LLHMM_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));    \
+    } while (0)
+
+// ------------------------------------------------------------- stability rule
+// |R(z)|^2 - 1 at z = s(-alpha + i); R = Heun (RK2) or RK4 stability polynomial.
+double growth(double s, double alpha, int integ) {
+    const double zr = -alpha * s, zi = s;
+    // powers of z
+    const double z2r = zr * zr - zi * zi, z2i = 2.0 * zr * zi;
+    double rr = 1.0 + zr + 0.5 * z2r, ri = zi + 0.5 * z2i;
+    if (integ == LLHMM_RK4P) {
+        const double z3r = z2r * zr - z2i * zi, z3i = z2r * zi + z2i * zr;
+        const double z4r = z3r * zr - z3i * zi, z4i = z3r * zi + z3i * zr;
+        rr += z3r / 6.0 + z4r / 24.0;
+        ri += z3i / 6.0 + z4i / 24.0;
+    }
+    return rr * rr + ri * ri - 1.0;
+}
+
+// Largest r with |R(s(-alpha+i))| <= 1 for all s in [0, r]: scan (step 1e-3), then bisection.
+double stability_radius(double alpha, int integ) {
+    const double h = 1e-3;
+    long k = 1;
+    for (;; ++k) {
+        if (growth(k * h, alpha, integ) > 0.0) break;
+        if (k * h > 20.0) return -1.0;
+    }
+    double lo = (k - 1) * h, hi = k * h;
+    for (int it = 0; it < 80; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (growth(mid, alpha, integ) > 0.0) hi = mid;
+        else lo = mid;
+    }
+    return lo;
+}
+
+int resolve_integrator(int integ, double alpha) {
+    if (integ == LLHMM_HEUNP || integ == LLHMM_RK4P) return integ;
+    return alpha > 0.2 ? LLHMM_HEUNP : LLHMM_RK4P;
+}
+
+llhmm_status validate_box(const llhmm_box &b, int i, int ncoefs) {
+    auto finite = [](double v) { return std::isfinite(v); };
+    if (b.dim != 1 && b.dim != 2) return fail(LLHMM_E_INVALID, "box %d: dim must be 1 or 2", i);
+    if (b.n < 8 || (b.n & 1)) return fail(LLHMM_E_INVALID, "box %d: n must be even and >= 8", i);
+    if (b.order != 2 && b.order != 4) return fail(LLHMM_E_INVALID, "box %d: order must be 2 or 4", i);
+    if (b.integrator < 0 || b.integrator > 2) return fail(LLHMM_E_INVALID, "box %d: bad integrator", i);
+    if (b.bc != 0 && b.bc != 1) return fail(LLHMM_E_INVALID, "box %d: bad bc", i);
+    if (b.quantity < 0 || b.quantity > 2) return fail(LLHMM_E_INVALID, "box %d: bad quantity", i);
+    if (b.init_mode != 0 && b.init_mode != 1) return fail(LLHMM_E_INVALID, "box %d: bad init_mode", i);
+    if (b.n_steps < 0) return fail(LLHMM_E_INVALID, "box %d: n_steps < 0", i);
+    if (b.coef_index < 0 || b.coef_index >= ncoefs)
+        return fail(LLHMM_E_INVALID, "box %d: coef_index out of range", i);
+    if (!(finite(b.eps) && b.eps > 0.0 && b.eps < 1.0))
+        return fail(LLHMM_E_INVALID, "box %d: need 0 < eps < 1 (assumption A2)", i);
+    if (!(finite(b.alpha) && b.alpha > 0.0))
+        return fail(LLHMM_E_INVALID, "box %d: need alpha > 0 (damping)", i);
+    if (!(finite(b.mu_box) && b.mu_box > 0.0)) return fail(LLHMM_E_INVALID, "box %d: need mu' > 0", i);
+    if (!(finite(b.mu) && b.mu > 0.0 && b.mu <= b.mu_box))
+        return fail(LLHMM_E_INVALID, "box %d: need 0 < mu <= mu'", i);
+    if (!(finite(b.eta) && b.eta > 0.0)) return fail(LLHMM_E_INVALID, "box %d: need eta > 0", i);
+    if (!(finite(b.a_max) && b.a_max > 0.0))
+        return fail(LLHMM_E_INVALID, "box %d: need a_max > 0 (assumption A1)", i);
+    if (!finite(b.center[0]) || !finite(b.center[1]))
+        return fail(LLHMM_E_INVALID, "box %d: non-finite centre", i);
+    if (b.init_mode == LLHMM_INIT_EXPLICIT && b.init_offset < 0)
+        return fail(LLHMM_E_INVALID, "box %d: negative init_offset", i);
+    return LLHMM_OK;
+}
+
+struct Planned {
+    int integ, M;
+    double dt;
+};
+
+llhmm_status plan_one(const llhmm_box &b, int i, Planned &out) {
+    out.integ = resolve_integrator(b.integrator, b.alpha);
+    if (b.n_steps > 0) {
+        out.M = b.n_steps;
+    } else {
+        const double dx = 2.0 * b.mu_box / b.n;
+        const double sigma = (b.order == 2) ? 4.0 : (7.0 / 3.0) * (7.0 / 3.0);
+        const double omega = sigma * b.dim * b.a_max / (dx * dx);
+        const double r = stability_radius(b.alpha, out.integ);
+        if (!(r > 0.0)) return fail(LLHMM_E_INVALID, "box %d: no stability limit found", i);
+        const double dt_max = 0.9 * r / omega;
+        const double Md = std::ceil(b.eta / dt_max);
+        if (!(Md >= 1.0 && Md < 2.0e9)) return fail(LLHMM_E_INVALID, "box %d: step count out of range", i);
+        out.M = (int)Md;
+    }
+    out.dt = b.eta / out.M;
+    return LLHMM_OK;
+}
+
+// ------------------------------------------------------------- kernel coefficients
+// Moment conditions solved in binary128 (113-bit significand, Gaussian elimination
+// with pivoting): the one-sided system is ill-conditioned (coefficients of size
+// 1e9 for p = 3, q = 7), so double or x87 long double would lose the last digits.
+typedef __float128 qreal;
+qreal qabs(qreal v) { return v < 0 ? -v : v; }
+
+llhmm_status kernel_coeffs(int p, int q, bool one_sided, double *out) {
+    if (p < 0 || p > 7 || q < 0 || q > 30) return fail(LLHMM_E_INVALID, "kernel p in [0,7], q in [0,30]");
+    const int n = p + 1;
+    qreal A[8][9];
+    // moment m of the weight: symmetric (1-x^2)^(q+1) on [-1,1]; one-sided t^(q+1)(1-t)^(q+1) on [0,1]
+    auto moment = [&](int m) -> qreal {
+        if (!one_sided) {
+            if (m & 1) return 0;
+            qreal s = 0, c = 1;  // sum_k C(q+1,k) (-1)^k 2/(2k+m+1)
+            for (int k = 0; k <= q + 1; ++k) {
+                s += c * 2 / (qreal)(2 * k + m + 1);
+                c = -c * (qreal)(q + 1 - k) / (qreal)(k + 1);
+            }
+            return s;
+        }
+        // Beta(q+2+m, q+2) = (q+1+m)! (q+1)! / (2q+3+m)!
+        qreal v = 1;
+        const int a = q + 1 + m, b = q + 1;
+        for (int k = 1; k <= b; ++k) v = v * (qreal)k / (qreal)(a + k);
+        return v / (qreal)(a + b + 1);
+    };
+    for (int r = 0; r < n; ++r) {
+        for (int c = 0; c < n; ++c) A[r][c] = moment(r + c);
+        A[r][n] = (r == 0) ? 1 : 0;
+    }
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < n; ++r)
+            if (qabs(A[r][c]) > qabs(A[piv][c])) piv = r;
+        for (int k = 0; k <= n; ++k) std::swap(A[c][k], A[piv][k]);
+        for (int r = 0; r < n; ++r) {
+            if (r == c || A[r][c] == 0) continue;
+            const qreal f = A[r][c] / A[c][c];
+            for (int k = c; k <= n; ++k) A[r][k] -= f * A[c][k];
+        }
+    }
+    for (int r = 0; r < n; ++r) {
+        qreal v = A[r][n] / A[r][r];
+        if (!one_sided && (r & 1)) v = 0;  // odd coefficients vanish by symmetry
+        out[r] = (double)v;
+    }
+    return LLHMM_OK;
+}
+
+double time_kernel(double t, const double *d, int p, int q) {
+    if (!(t > 0.0 && t < 1.0)) return 0.0;
+    double poly = 0.0, tp = 1.0;
+    for (int i = 0; i <= p; ++i) {
+        poly += d[i] * tp;
+        tp *= t;
+    }
+    double f = 1.0;
+    for (int i = 0; i < q + 1; ++i) f *= t * (1.0 - t);
+    return f * poly;
+}
+
+// ------------------------------------------------------------- tile registry
+struct TileKey {
+    int prec, dim, n, order, bc, qty;
+    bool operator<(const TileKey &o) const {
+        return std::tie(prec, dim, n, order, bc, qty) < std::tie(o.prec, o.dim, o.n, o.order, o.bc, o.qty);
+    }
+};
+
+const std::map<TileKey, const TileInfo *> &registry() {
+    static std::map<TileKey, const TileInfo *> reg = [] {
+        std::map<TileKey, const TileInfo *> r;
+        const TileInfo *(*fns[])(int *) = {tiles_f32_2d, tiles_f64_2d, tiles_f32_1d, tiles_f64_1d};
+        for (auto fn : fns) {
+            int cnt = 0;
+            const TileInfo *t = fn(&cnt);
+            for (int i = 0; i < cnt; ++i) {
+                TileKey k{t[i].prec, t[i].dim, t[i].n, t[i].order, t[i].bc, t[i].qty};
+                if (!r.count(k)) r[k] = &t[i];
+            }
+        }
+        return r;
+    }();
+    return reg;
+}
+
+template <typename T>
+hipError_t dev_upload(T **dst, const T *src, size_t count) {
+    *dst = nullptr;
+    if (count == 0) return hipSuccess;
+    hipError_t e = hipMalloc((void **)dst, sizeof(T) * count);
+    if (e != hipSuccess) return e;
+    return hipMemcpy(*dst, src, sizeof(T) * count, hipMemcpyHostToDevice);
+}
+
+}  // namespace
+
+struct llhmm_ctx {
+    int device;
+};
+
+struct ClassLaunch {
+    const TileInfo *tile;
+    int first, count, nblocks;  // range in the concatenated box-id list
+};
+
+struct llhmm_batch {
+    int nboxes, prec, dim_max, nmax;
+    int64_t cell_steps;
+    bool any_explicit, any_macro, any_sampled;
+    std::vector<BoxPlan> plans_h;
+    std::vector<ClassLaunch> classes;
+    BoxPlan *plans = nullptr;
+    int32_t *box_ids = nullptr;
+    CoefDev *coefs = nullptr;
+    void *tabs = nullptr;
+    double *wts = nullptr, *wt = nullptr, *partials = nullptr, *box_const = nullptr;
+    int32_t *wave_status = nullptr, *status = nullptr;
+    double kc[8];
+    int kp, kq;
+};
+
+extern "C" {
+
+int32_t llhmm_abi_version(void) { return LLHMM_ABI_VERSION; }
+
+const char *llhmm_last_error(void) { return g_err.c_str(); }
+
+llhmm_status llhmm_create(llhmm_ctx **ctx, int32_t device) {
+    if (!ctx) return fail(LLHMM_E_INVALID, "ctx is NULL");
+    int n = 0;
+    HIP_TRY(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) return fail(LLHMM_E_INVALID, "device %d out of range (%d)", device, n);
+    HIP_TRY(hipSetDevice(device));
+    *ctx = new llhmm_ctx{device};
+    return LLHMM_OK;
+}
+
+llhmm_status llhmm_destroy(llhmm_ctx *ctx) {
+    delete ctx;
+    return LLHMM_OK;
+}
+
+llhmm_status llhmm_plan(const llhmm_box *boxes, int32_t nboxes, int32_t *n_steps_out,
+                        double *dt_out, int32_t *integrator_out) {
+    if (nboxes < 0 || (nboxes > 0 && !boxes)) return fail(LLHMM_E_INVALID, "bad box array");
+    for (int i = 0; i < nboxes; ++i) {
+        llhmm_status s = validate_box(boxes[i], i, 1 << 30);
+        if (s != LLHMM_OK) return s;
+        Planned p;
+        s = plan_one(boxes[i], i, p);
+        if (s != LLHMM_OK) return s;
+        if (n_steps_out) n_steps_out[i] = p.M;
+        if (dt_out) dt_out[i] = p.dt;
+        if (integrator_out) integrator_out[i] = p.integ;
+    }
+    return LLHMM_OK;
+}
+
+llhmm_status llhmm_kernel_coeffs(const llhmm_kernel *K, double *c_space, double *d_time) {
+    if (!K) return fail(LLHMM_E_INVALID, "kernel is NULL");
+    llhmm_status s = LLHMM_OK;
+    if (c_space) s = kernel_coeffs(K->p_x, K->q_x, false, c_space);
+    if (s == LLHMM_OK && d_time) s = kernel_coeffs(K->p_t, K->q_t, true, d_time);
+    return s;
+}
+
+static void batch_free(llhmm_batch *b) {
+    if (!b) return;
+    void *ptrs[] = {b->plans, b->box_ids, b->coefs, b->tabs, b->wts, b->wt, b->partials,
+                    b->wave_status, b->status, b->box_const};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    delete b;
+}
+
+llhmm_status llhmm_batch_create(llhmm_ctx *ctx, const llhmm_box *boxes, int32_t nboxes,
+                                const llhmm_kernel *K, const llhmm_coef *coefs, int32_t ncoefs,
+                                int32_t precision, llhmm_batch **out) {
+    if (!ctx || !out) return fail(LLHMM_E_INVALID, "ctx/out is NULL");
+    *out = nullptr;
+    if (nboxes <= 0 || !boxes) return fail(LLHMM_E_INVALID, "empty batch");
+    if (!K || !coefs || ncoefs <= 0) return fail(LLHMM_E_INVALID, "kernel/coefficients missing");
+    if (precision != LLHMM_FP64 && precision != LLHMM_FP32) return fail(LLHMM_E_INVALID, "bad precision");
+    if (K->p_x > 7 || K->p_t > 7) return fail(LLHMM_E_INVALID, "kernel order p must be <= 7");
+    for (int c = 0; c < ncoefs; ++c) {
+        const llhmm_coef &cf = coefs[c];
+        if (cf.n_terms < 0 || cf.n_terms > LLHMM_MAX_TERMS || cf.dim < 1 || cf.dim > 2)
+            return fail(LLHMM_E_INVALID, "coef %d: bad dim / n_terms", c);
+    }
+    HIP_TRY(hipSetDevice(ctx->device));
+    double dcoef[8] = {0};
+    llhmm_batch *b = new llhmm_batch();
+    b->nboxes = nboxes;
+    b->prec = precision;
+    llhmm_status st = kernel_coeffs(K->p_x, K->q_x, false, b->kc);
+    if (st == LLHMM_OK) st = kernel_coeffs(K->p_t, K->q_t, true, dcoef);
+    if (st != LLHMM_OK) {
+        delete b;
+        return st;
+    }
+    b->kp = K->p_x;
+    b->kq = K->q_x;
+
+    const auto &reg = registry();
+    const size_t tsize = (precision == LLHMM_FP32) ? sizeof(float) : sizeof(double);
+    b->plans_h.resize(nboxes);
+    std::vector<const TileInfo *> tile_of(nboxes);
+    int dim_max = 1, nmax = 0;
+    for (int i = 0; i < nboxes; ++i) {
+        dim_max = std::max(dim_max, boxes[i].dim);
+        nmax = std::max(nmax, boxes[i].n);
+    }
+    b->dim_max = dim_max;
+    b->nmax = nmax;
+    int64_t tab_off = 0, w_off = 0;
+    std::map<int, int64_t> wt_off_of_M;
+    std::vector<double> wt_h;
+    int64_t cell_steps = 0;
+    for (int i = 0; i < nboxes; ++i) {
+        const llhmm_box &bx = boxes[i];
+        st = validate_box(bx, i, ncoefs);
+        if (st == LLHMM_OK && coefs[bx.coef_index].dim != bx.dim)
+            st = fail(LLHMM_E_INVALID, "box %d: coefficient dimension differs from box", i);
+        Planned pl{};
+        if (st == LLHMM_OK) st = plan_one(bx, i, pl);
+        if (st != LLHMM_OK) {
+            delete b;
+            return st;
+        }
+        auto it = reg.find(TileKey{precision, bx.dim, bx.n, bx.order, bx.bc, bx.quantity});
+        if (it == reg.end()) {
+            delete b;
+            return fail(LLHMM_E_NOTSUP,
+                        "box %d: no kernel for precision %s, dim %d, n %d, order %d, bc %d, quantity %d",
+                        i, precision == LLHMM_FP32 ? "fp32" : "fp64", bx.dim, bx.n, bx.order, bx.bc,
+                        bx.quantity);
+        }
+        tile_of[i] = it->second;
+        BoxPlan &P = b->plans_h[i];
+        memset(&P, 0, sizeof P);
+        P.dim = bx.dim;
+        P.n = bx.n;
+        P.order = bx.order;
+        P.stages = (pl.integ == LLHMM_RK4P) ? 4 : 2;
+        P.bc = bx.bc;
+        P.quantity = bx.quantity;
+        P.init_mode = bx.init_mode;
+        P.M = pl.M;
+        P.coef_index = bx.coef_index;
+        P.mi0 = bx.macro_index[0];
+        P.mi1 = bx.macro_index[1];
+        P.nq = (bx.quantity == LLHMM_Q_FLUX) ? 3 * bx.dim : 3;
+        P.coef_sampled = coefs[bx.coef_index].sampled ? 1 : 0;
+        P.nwaves = (bx.dim == 2) ? it->second->threads / 64 : 1;
+        P.prec = precision;
+        P.form = (precision == LLHMM_FP32) ? 1 : 0;
+        P.dt = pl.dt;
+        P.alpha = bx.alpha;
+        P.dx = 2.0 * bx.mu_box / bx.n;
+        P.mu = bx.mu;
+        P.mu_box = bx.mu_box;
+        P.a_scale = (bx.order == 2) ? 1.0 / (P.dx * P.dx) : 1.0 / (576.0 * P.dx * P.dx);
+        P.out_scale = (bx.quantity == LLHMM_Q_FLUX) ? ((bx.order == 2) ? P.dx : 24.0 * P.dx) : 1.0;
+        P.cx = bx.center[0];
+        P.cy = bx.center[1];
+        P.init_offset = bx.init_offset;
+        P.coef_offset = bx.coef_offset;
+        P.mfinal_offset = (int64_t)i * 3 * (bx.dim == 1 ? (int64_t)nmax : (int64_t)nmax * nmax);
+        P.tab_offset = tab_off;
+        tab_off += tab_layout(bx.dim, bx.n, P.form).size;
+        P.w_offset = w_off;
+        w_off += 2 * bx.n;
+        auto wit = wt_off_of_M.find(pl.M);
+        if (wit == wt_off_of_M.end()) {
+            const int64_t o = (int64_t)wt_h.size();
+            for (int n = 0; n <= pl.M; ++n)
+                wt_h.push_back(time_kernel((double)n / pl.M, dcoef, K->p_t, K->q_t) / pl.M);
+            wit = wt_off_of_M.emplace(pl.M, o).first;
+        }
+        P.wt_offset = wit->second;
+        double ws = 0.0;
+        for (int n = 0; n <= pl.M; ++n) ws += wt_h[P.wt_offset + n];
+        P.wsum = ws;
+        cell_steps += (int64_t)pl.M * (bx.dim == 1 ? bx.n : (int64_t)bx.n * bx.n);
+        b->any_explicit |= (bx.init_mode == LLHMM_INIT_EXPLICIT);
+        b->any_macro |= (bx.init_mode == LLHMM_INIT_MACRO_Q);
+        b->any_sampled |= (P.coef_sampled != 0);
+    }
+    b->cell_steps = cell_steps;
+
+    // group boxes by tile class; 1-D classes further by (M, stages) so that a
+    // block's boxes share the time loop; longest boxes first (LPT order)
+    std::map<std::tuple<const TileInfo *, int, int>, std::vector<int>> groups;
+    for (int i = 0; i < nboxes; ++i) {
+        const TileInfo *t = tile_of[i];
+        const int key_m = (t->dim == 1) ? b->plans_h[i].M : 0;
+        const int key_s = (t->dim == 1) ? b->plans_h[i].stages : 0;
+        groups[std::make_tuple(t, key_m, key_s)].push_back(i);
+    }
+    std::vector<int32_t> ids;
+    for (auto &kv : groups) {
+        const TileInfo *t = std::get<0>(kv.first);
+        auto &v = kv.second;
+        std::stable_sort(v.begin(), v.end(), [&](int a, int c) {
+            return (int64_t)b->plans_h[a].M * b->plans_h[a].stages > (int64_t)b->plans_h[c].M * b->plans_h[c].stages;
+        });
+        ClassLaunch cl;
+        cl.tile = t;
+        cl.first = (int)ids.size();
+        for (int i : v) ids.push_back(i);
+        if (t->dim == 1) {
+            while ((ids.size() - cl.first) % t->boxes_per_block) ids.push_back(-1);
+        }
+        cl.count = (int)ids.size() - cl.first;
+        cl.nblocks = cl.count / t->boxes_per_block;
+        b->classes.push_back(cl);
+    }
+
+    hipError_t e = hipSuccess;
+    std::vector<CoefDev> cdev(ncoefs);
+    memcpy(cdev.data(), coefs, sizeof(CoefDev) * ncoefs);
+    if (e == hipSuccess) e = dev_upload(&b->plans, b->plans_h.data(), b->plans_h.size());
+    if (e == hipSuccess) e = dev_upload(&b->box_ids, ids.data(), ids.size());
+    if (e == hipSuccess) e = dev_upload(&b->coefs, cdev.data(), cdev.size());
+    if (e == hipSuccess) e = dev_upload(&b->wt, wt_h.data(), wt_h.size());
+    if (e == hipSuccess) e = hipMalloc(&b->tabs, tsize * std::max<int64_t>(tab_off, 1));
+    if (e == hipSuccess) e = hipMalloc((void **)&b->wts, sizeof(double) * std::max<int64_t>(w_off, 1));
+    if (e == hipSuccess)
+        e = hipMalloc((void **)&b->partials, sizeof(double) * (size_t)nboxes * kMaxWaves * kMaxQ);
+    if (e == hipSuccess)
+        e = hipMalloc((void **)&b->wave_status, sizeof(int32_t) * (size_t)nboxes * kMaxWaves);
+    if (e == hipSuccess) e = hipMalloc((void **)&b->status, sizeof(int32_t) * (size_t)nboxes);
+    if (e == hipSuccess) e = hipMalloc((void **)&b->box_const, sizeof(double) * (size_t)nboxes * kMaxQ);
+    if (e != hipSuccess) {
+        batch_free(b);
+        return fail(e == hipErrorOutOfMemory ? LLHMM_E_NOMEM : LLHMM_E_HIP, "batch allocation: %s",
+                    hipGetErrorString(e));
+    }
+    *out = b;
+    return LLHMM_OK;
+}
+
+llhmm_status llhmm_batch_destroy(llhmm_ctx *, llhmm_batch *batch) {
+    batch_free(batch);
+    return LLHMM_OK;
+}
+
+int64_t llhmm_batch_cell_steps(const llhmm_batch *batch) { return batch ? batch->cell_steps : -1; }
+
+static llhmm_status run_batch(llhmm_ctx *ctx, llhmm_batch *b, const double *m_init_dev,
+                              const llhmm_macro *macro, const double *M_macro_dev,
+                              const double *coef_dev, double *field_dev, int mode,
+                              hipStream_t stream) {
+    if (!ctx || !b) return fail(LLHMM_E_INVALID, "ctx/batch is NULL");
+    if (b->any_explicit && !m_init_dev) return fail(LLHMM_E_INVALID, "explicit init needs m_init_dev");
+    if (b->any_macro && (!macro || !M_macro_dev))
+        return fail(LLHMM_E_INVALID, "macro-interpolated init needs macro and M_macro_dev");
+    if (b->any_sampled && !coef_dev) return fail(LLHMM_E_INVALID, "sampled coefficient needs coef_dev");
+    MacroDev md{};
+    if (b->any_macro) {
+        if (macro->n < 5 || !(macro->dX > 0.0)) return fail(LLHMM_E_INVALID, "macro grid: n >= 5, dX > 0");
+        md.dim = macro->dim;
+        md.n = macro->n;
+        md.dX = macro->dX;
+        md.x0[0] = macro->x0[0];
+        md.x0[1] = macro->x0[1];
+        for (int i = 0; i < b->nboxes; ++i) {
+            const BoxPlan &P = b->plans_h[i];
+            if (P.init_mode != LLHMM_INIT_MACRO_Q) continue;
+            if (macro->dim != P.dim) return fail(LLHMM_E_INVALID, "box %d: macro dim differs", i);
+            if (P.mi0 < 0 || P.mi0 >= macro->n || (P.dim == 2 && (P.mi1 < 0 || P.mi1 >= macro->n)))
+                return fail(LLHMM_E_INVALID, "box %d: macro_index out of range", i);
+            const double tol = 1e-9 * macro->dX;
+            if (std::fabs(P.cx - (macro->x0[0] + P.mi0 * macro->dX)) > tol ||
+                (P.dim == 2 && std::fabs(P.cy - (macro->x0[1] + P.mi1 * macro->dX)) > tol))
+                return fail(LLHMM_E_INVALID, "box %d: centre is not its macro node", i);
+        }
+    }
+    HIP_TRY(hipSetDevice(ctx->device));
+    PrologueArgs pa{};
+    pa.plans = b->plans;
+    pa.nboxes = b->nboxes;
+    pa.coefs = b->coefs;
+    pa.m_init = m_init_dev;
+    pa.M_macro = M_macro_dev;
+    pa.macro = md;
+    pa.coef_samples = coef_dev;
+    pa.tabs = b->tabs;
+    pa.wts = b->wts;
+    pa.box_const = b->box_const;
+    memcpy(pa.kc, b->kc, sizeof pa.kc);
+    pa.kp = b->kp;
+    pa.kq = b->kq;
+    HIP_TRY(launch_prologue(b->prec, pa, stream));
+    for (const ClassLaunch &cl : b->classes) {
+        MicroArgs a{};
+        a.plans = b->plans;
+        a.box_ids = b->box_ids + cl.first;
+        a.nbox_class = cl.count;
+        a.mode = mode;
+        a.tabs = b->tabs;
+        a.wts = b->wts;
+        a.wt = b->wt;
+        a.partials = b->partials;
+        a.wave_status = b->wave_status;
+        a.out_field = field_dev;
+        HIP_TRY(cl.tile->launch(a, cl.nblocks, stream));
+    }
+    return LLHMM_OK;
+}
+
+llhmm_status llhmm_micro_batch(llhmm_ctx *ctx, llhmm_batch *batch, const double *m_init_dev,
+                               const llhmm_macro *macro, const double *M_macro_dev,
+                               const double *coef_dev, double *m_final_dev, hipStream_t stream) {
+    return run_batch(ctx, batch, m_init_dev, macro, M_macro_dev, coef_dev, m_final_dev, 0, stream);
+}
+
+llhmm_status llhmm_eval_field(llhmm_ctx *ctx, llhmm_batch *batch, const double *m_init_dev,
+                              const llhmm_macro *macro, const double *M_macro_dev,
+                              const double *coef_dev, double *H_dev, hipStream_t stream) {
+    if (!H_dev) return fail(LLHMM_E_INVALID, "H_dev is NULL");
+    return run_batch(ctx, batch, m_init_dev, macro, M_macro_dev, coef_dev, H_dev, 1, stream);
+}
+
+llhmm_status llhmm_upscale(llhmm_ctx *ctx, llhmm_batch *b, double *H_avg_dev, int32_t ld,
+                           int32_t *status_dev, int32_t check, hipStream_t stream) {
+    if (!ctx || !b) return fail(LLHMM_E_INVALID, "ctx/batch is NULL");
+    if (H_avg_dev && ld < 3 * b->dim_max) {
+        bool flux2d = false;
+        for (const BoxPlan &P : b->plans_h) flux2d |= (P.nq > ld);
+        if (flux2d) return fail(LLHMM_E_INVALID, "ld %d smaller than the outputs per box", ld);
+    }
+    HIP_TRY(hipSetDevice(ctx->device));
+    HIP_TRY(launch_upscale(b->partials, b->wave_status, b->box_const, b->plans, b->nboxes, H_avg_dev, ld,
+                           b->status, nullptr, stream));
+    if (status_dev)
+        HIP_TRY(hipMemcpyAsync(status_dev, b->status, sizeof(int32_t) * b->nboxes,
+                               hipMemcpyDeviceToDevice, stream));
+    if (check) {
+        std::vector<int32_t> st(b->nboxes);
+        HIP_TRY(hipMemcpyAsync(st.data(), b->status, sizeof(int32_t) * b->nboxes,
+                               hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        for (int i = 0; i < b->nboxes; ++i)
+            if (st[i]) return fail(LLHMM_E_UNSTABLE, "box %d produced non-finite values", i);
+    }
+    return LLHMM_OK;
+}
+
+llhmm_status llhmm_macro_step(llhmm_ctx *ctx, int32_t npts, int32_t scheme, int32_t step_index,
+                              int32_t stage, double dt, double alpha, double *M_dev,
+                              const double *H_avg_dev, double *Y_dev, double *work_dev,
+                              int32_t *next_stage_out, hipStream_t stream) {
+    if (!ctx) return fail(LLHMM_E_INVALID, "ctx is NULL");
+    if (npts <= 0 || !M_dev || !H_avg_dev || !Y_dev || !work_dev)
+        return fail(LLHMM_E_INVALID, "macro step: empty grid or NULL buffer");
+    if (!(dt > 0.0) || !(alpha >= 0.0)) return fail(LLHMM_E_INVALID, "macro step: dt > 0, alpha >= 0");
+    int nst;
+    if (scheme == LLHMM_MACRO_MPEA) {
+        if (step_index < 2) return fail(LLHMM_E_INVALID, "MPEA needs two start-up steps (step_index >= 2)");
+        nst = 1;
+    } else if (scheme == LLHMM_MACRO_HEUNP) {
+        nst = 2;
+    } else if (scheme == LLHMM_MACRO_RK4P) {
+        nst = 4;
+    } else {
+        return fail(LLHMM_E_INVALID, "unknown macro scheme %d", scheme);
+    }
+    if (stage < 0 || stage >= nst) return fail(LLHMM_E_INVALID, "stage %d out of range", stage);
+    HIP_TRY(hipSetDevice(ctx->device));
+    HIP_TRY(launch_macro(npts, scheme, step_index, stage, dt, alpha, M_dev, H_avg_dev, Y_dev, work_dev, stream));
+    if (next_stage_out) *next_stage_out = (stage + 1 < nst) ? stage + 1 : 0;
+    return LLHMM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,137 @@
+// Internal types shared by the host side (llhmm_host.cpp) and the gfx950
+// kernels.  Not part of the public ABI.
+#pragma once
+#include <stdint.h>
+#include <hip/hip_runtime.h>
+#include "../../include/llhmm.h"
+
+namespace llhmm {
+
+constexpr int kGhost = LLHMM_GHOST;
+constexpr int kMaxWaves = 16;  // partial-sum slots per box
+constexpr int kMaxQ = 6;       // outputs per box (flux in 2-D)
+constexpr int kFaceHalo = 3;   // faces -2 .. n stored per line: n + 3 entries
+
+// Per-box plan as the kernels read it.
+struct BoxPlan {
+    int32_t dim, n, order, stages;       // stages: 2 (HeunP) or 4 (RK4P)
+    int32_t bc, quantity, init_mode, M;  // M: number of time steps
+    int32_t coef_index, mi0, mi1, nq;    // macro node; nq = outputs per box
+    int32_t coef_sampled, nwaves, prec, form;   // form: 0 direct, 1 reference + perturbation
+    double dt, alpha, dx, mu;
+    double mu_box, a_scale, out_scale, cx;
+    double cy, wsum;                     // wsum = sum_n w^n (time weights)
+    int64_t init_offset, coef_offset, wt_offset, mfinal_offset;
+    int64_t tab_offset;                  // element offset (in T) of the box's tables
+    int64_t w_offset;                    // element offset (double) of the space weights
+};
+
+// Per-box table layout (elements of T, starting at tab_offset), n = points per
+// axis, C = n^dim points, lines = n^(dim-1).
+//   form 0 (direct: the state is m itself; FP64 path)
+//     m0   [3][C]                  initial micro state
+//     ax   [lines][n + 3]          x1 faces f = -2..n (index f + 2), scaled a
+//     ay   [n][n + 3]   (2-D)      x2 faces per column, index f + 2
+//     tau1 [lines][2][3][8]        boundary flux offsets, x1 (west, east): per face
+//                                  hi[3], 0, lo[3], 0 with tau = hi + lo (double word)
+//     tau2 [n][2][3][8] (2-D)      boundary flux offsets, x2 (south, north)
+//   form 1 (reference + perturbation: m = r + u; FP32 path)
+//     u0   [3][C]                  m_init - r, the rounding residual of the reference
+//     r    [3][C]                  reference r = fl(m_init) at the points
+//     dm   [C]                     |r|^2 - 1 (computed in FP64)
+//     H0   [3][C]                  H(r) with the boundary data, computed in FP64
+//     ax, ay as in form 0 (no tau tables: u is periodic or zero on the ghosts)
+// Space weights (double, at w_offset): wc [n] (points), wf [n] (east faces).
+struct TabLayout {
+    int64_t m0, ref, dm, H0, ax, ay, tau1, tau2, size;
+};
+__host__ __device__ inline TabLayout tab_layout(int d, int n, int form) {
+    TabLayout t;
+    const int64_t C = (d == 1) ? (int64_t)n : (int64_t)n * n;
+    const int64_t lines = (d == 1) ? 1 : n;
+    t.m0 = 0;
+    if (form == 1) {
+        t.ref = 3 * C;
+        t.dm = 6 * C;
+        t.H0 = 7 * C;
+        t.ax = 10 * C;
+    } else {
+        t.ref = t.dm = t.H0 = 0;
+        t.ax = 3 * C;
+    }
+    t.ay = t.ax + lines * (n + kFaceHalo);
+    t.tau1 = t.ay + (d == 1 ? 0 : (int64_t)n * (n + kFaceHalo));
+    t.tau2 = t.tau1 + (form == 1 ? 0 : lines * 48);
+    t.size = t.tau2 + (form == 1 || d == 1 ? 0 : (int64_t)n * 48);
+    t.size = (t.size + 63) & ~(int64_t)63;
+    return t;
+}
+
+// Kernel-side view of a material coefficient (same layout as llhmm_coef).
+struct CoefDev {
+    int32_t dim, n_terms, sampled, pad_;
+    double c0;
+    double amp[LLHMM_MAX_TERMS];
+    double freq[LLHMM_MAX_TERMS][2];
+    double phase[LLHMM_MAX_TERMS][2];
+};
+static_assert(sizeof(CoefDev) == sizeof(llhmm_coef), "coef layout");
+
+struct MacroDev {
+    int32_t dim, n;
+    double dX, x0[2];
+};
+
+struct PrologueArgs {
+    const BoxPlan *plans;
+    int32_t nboxes, mode_pad;
+    const CoefDev *coefs;
+    const double *m_init;
+    const double *M_macro;
+    MacroDev macro;
+    const double *coef_samples;
+    void *tabs;            // T tables
+    double *wts;           // space weights
+    double *box_const;     // [nboxes][kMaxQ]: average of the reference part (form 1)
+    double kc[8];          // space kernel coefficients c_0..c_p
+    int32_t kp, kq;
+};
+
+// Everything a micro-kernel launch needs.  Passed by value.
+struct MicroArgs {
+    const BoxPlan *plans;      // [nboxes]
+    const int32_t *box_ids;    // boxes of this tile class, in launch order
+    int32_t nbox_class;        // entries in box_ids
+    int32_t mode;              // 0 solve, 1 evaluate H(m0) only
+    const void *tabs;          // per-box tables (T)
+    const double *wts;         // space weights
+    const double *wt;          // time-weight table
+    double *partials;          // [nboxes][kMaxWaves][kMaxQ]
+    int32_t *wave_status;      // [nboxes][kMaxWaves]
+    double *out_field;         // m_final or H (nullable)
+};
+
+using LaunchFn = hipError_t (*)(const MicroArgs &, int nblocks, hipStream_t);
+
+struct TileInfo {
+    int dim, n, order, bc, prec, qty; // class it serves
+    int L, K, R, NG, NBUF;            // layout
+    int threads, boxes_per_block;
+    LaunchFn launch;
+    const char *name;
+};
+
+const TileInfo *tiles_f32_2d(int *count);
+const TileInfo *tiles_f64_2d(int *count);
+const TileInfo *tiles_f32_1d(int *count);
+const TileInfo *tiles_f64_1d(int *count);
+
+hipError_t launch_prologue(int prec, const PrologueArgs &a, hipStream_t s);
+hipError_t launch_upscale(const double *partials, const int32_t *wave_status,
+                          const double *box_const, const BoxPlan *plans, int nboxes, double *H, int ld,
+                          int32_t *status, int32_t *any_bad, hipStream_t s);
+hipError_t launch_macro(int npts, int scheme, int step_index, int stage, double dt,
+                        double alpha, double *M, const double *H, double *Y,
+                        double *work, hipStream_t s);
+
+}  // namespace llhmm

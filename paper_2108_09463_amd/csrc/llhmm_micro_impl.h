@@ -1,0 +1,521 @@
+// Time-stepping kernel for gfx950 (CDNA4): one workgroup per 2-D micro box
+// (or several 1-D boxes per workgroup), the whole box resident on chip for all
+// of its time steps.
+//
+// Method (Leitenmaier & Runborg): eq. (micro) of Section 2.2 time-stepped with
+// HeunP / RK4P (Section 3.1), H = div(a grad m) by the second-order central
+// difference of Section 2.3 (or a fourth-order conservative stencil), boundary
+// data of Section 4.2, and the kernel average eq. (upscaling).
+//
+// Layout.  A "row group" of L lanes (L = 16: one DPP row; L = 64: a whole
+// wavefront) spans a full box row of N = K*L points; lane j owns the K
+// consecutive columns [jK, jK+K) of the R rows [gR, gR+R) of its group g.
+// State m, stage input y and the Runge-Kutta accumulator live in VGPRs.
+//   * x1 neighbours come from the adjacent lane through DPP row/wave rotations
+//     (periodic m - m_init) or shifts with zero fill (Dirichlet), which the
+//     compiler fuses into the consuming VALU instruction;
+//   * x2 neighbours across row groups go through a small LDS halo buffer
+//     (YH rows per group side; double buffered: one barrier per stage);
+//   * boundary data enter as a constant offset tau_f = a_f G_f(delta) on the
+//     fluxes of the faces whose stencil reaches a ghost point (delta = ghost
+//     value minus wrapped value, or the ghost value for Dirichlet): the stencil
+//     is linear, so wrapped or zero-filled neighbours plus tau_f reproduce the
+//     ghost-point stencil exactly;
+//   * the kernel-weighted average is accumulated per lane in FP64 (per step:
+//     sum_j w_j Q_j(m^n) times the time weight w^n), reduced across the
+//     wavefront by shuffles and written as one FP64 partial per wave.
+#pragma once
+#include "llhmm_internal.h"
+
+namespace llhmm {
+
+// ----------------------------------------------------------------- DPP
+template <int L> struct DppCtl;
+// FR: lane i <- lane i+1 ("from the right"); FL: lane i <- lane i-1.
+template <> struct DppCtl<16> {
+    static constexpr int ROT_FR = 0x12F;  // row_ror:15
+    static constexpr int ROT_FL = 0x121;  // row_ror:1
+    static constexpr int SH_FR = 0x101;   // row_shl:1 (lane 15 of the row reads 0)
+    static constexpr int SH_FL = 0x111;   // row_shr:1 (lane 0 of the row reads 0)
+};
+template <> struct DppCtl<64> {
+    static constexpr int ROT_FR = 0x134;  // wave_rol:1
+    static constexpr int ROT_FL = 0x13C;  // wave_ror:1
+    static constexpr int SH_FR = 0x130;   // wave_shl:1
+    static constexpr int SH_FL = 0x138;   // wave_shr:1
+};
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+    return __builtin_bit_cast(
+        float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, true));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+    uint64_t u = __builtin_bit_cast(uint64_t, v);
+    int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xF, 0xF, true);
+    int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, true);
+    return __builtin_bit_cast(double, (uint64_t)(uint32_t)lo | ((uint64_t)(uint32_t)hi << 32));
+}
+
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float rsqrt_t(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsqrt_t(double x) { return 1.0 / __builtin_sqrt(x); }
+
+enum { AVG_NONE = 0, AVG_FIELD = 1, AVG_TORQUE = 2, AVG_FLUX = 3, AVG_EVAL = 4 };
+
+template <typename T, int D, int ORD, int BC, int QTY, int L, int K, int R, int NG, int NBUF>
+struct MicroLane {
+    static constexpr int N = K * L;
+    static constexpr int YH = (ORD == 2) ? 1 : 3;  // neighbour reach in points
+    static constexpr int FW = (ORD == 2) ? 1 : 2;  // faces west/south of the first own point
+    static constexpr int FE = (ORD == 2) ? 0 : 1;  // faces east/north of the last own point
+    static constexpr int NF = K + FW + FE;         // x1 faces per lane row
+    static constexpr int NFR = R + FW + FE;        // x2 faces per lane column
+    static constexpr int GF = (ORD == 2) ? 1 : 3;  // faces per side touched by ghosts
+    static constexpr int KD = (D == 2) ? K : 1;
+    static constexpr int NFRD = (D == 2) ? NFR : 1;
+    static constexpr int NQ = (QTY == LLHMM_Q_FLUX) ? 3 * D : 3;
+    static constexpr int AVG = (QTY == LLHMM_Q_FIELD) ? 1 : ((QTY == LLHMM_Q_TORQUE) ? 2 : 3);
+    static constexpr int HALO = (D == 2) ? NG * 2 * YH * 3 * N : 1;
+    static constexpr int TAU_LDS = (D == 2) ? 2 * N * 48 + 24 : 1;
+    static constexpr int ZOFF = 2 * N * 48;
+    static constexpr int WLDS = (D == 2) ? 2 * N : NG * 2 * N;  // space weights in LDS
+    // form 1 (FP32): m = r + u with the FP32 reference r = fl(m_init) and H(r)
+    // precomputed in FP64; the state u starts at the rounding residual m_init - r
+    // and stays periodic (or zero) on the ghosts, so no boundary offsets are needed.
+    static constexpr int FORM = (sizeof(T) == 4) ? 1 : 0;
+    static constexpr int CELLS = (D == 1) ? N : N * N;
+    static constexpr int REF_LDS = FORM ? ((D == 2) ? 7 * CELLS : NG * 7 * N) : 1;
+    static_assert(K >= YH, "lane tile narrower than the stencil reach");
+    static_assert(D == 1 || R >= YH, "row band thinner than the stencil reach");
+    static_assert(D == 1 || R * NG == N, "row groups must tile the box");
+    static_assert(D == 2 || R == 1, "1-D boxes are one row");
+    static_assert(L == 16 || L == 64, "row group is a DPP row or a wavefront");
+
+    T m[R][K][3], y[R][K][3], acc[R][K][3];
+    T ax[R][NF];
+    T ay[KD][NFRD];
+    T tauF[(D == 1) ? GF : 1][6], tauL[(D == 1) ? GF : 1][6];  // hi[3], lo[3]
+    int tFb, tFs, tLb, tLs, tSb, tSs, tNb, tNs;  // LDS offsets: base + index * stride
+    double acc64[NQ];
+    int g, c0, r0, gs, gn;
+    bool zero_s, zero_n;
+    T alpha, dt;
+    T *s_halo, *s_zero, *s_tau;
+    const T *s_ref;    // form 1: this box's r [3][C], |r|^2-1 [C], H(r) [3][C] (LDS)
+    const double *wl;  // this box's point weights [N] then east-face weights [N] (LDS)
+
+    template <int CTRL_ROT, int CTRL_SH>
+    __device__ __forceinline__ static T nb(T v) {
+        return dpp_mov<(BC == LLHMM_BC_PERIODIC_PERT) ? CTRL_ROT : CTRL_SH>(v);
+    }
+    __device__ __forceinline__ double wv(int i) const { return wl[i]; }
+    __device__ __forceinline__ double wy(int r) const { return (D == 2) ? wv(r0 + r) : 1.0; }
+    __device__ __forceinline__ T tau_lds(int off) const {
+        return FORM ? (T)0 : s_tau[off];
+    }
+    __device__ __forceinline__ T ref(int q, int cell) const { return s_ref[q * CELLS + cell]; }
+
+    // One Runge-Kutta stage on stage input y: H(y), f(y), accumulator and
+    // next stage input (or the projected new state when LAST).  With AVG != 0
+    // this is stage 1 of a step: y == m^n and Q(m^n) is added to the average.
+    template <int AVG, bool FIRST, bool LAST>
+    __device__ __forceinline__ void stage(T bs, T cdt, double wn, int tstage, double *eval_out,
+                                          long eval_cells) {
+        asm volatile("" ::: "memory");  // keep per-cell LDS tables out of registers across stages
+        // ---- x2 halo exchange through LDS
+        const T *srcS = s_zero, *srcN = s_zero;
+        if (D == 2) {
+            T *hb = s_halo + (NBUF == 2 ? (tstage & 1) * HALO : 0);
+            if (NBUF == 1) __syncthreads();
+#pragma unroll
+            for (int q = 0; q < YH; ++q)
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+#pragma unroll
+                    for (int k = 0; k < K; ++k) {
+                        hb[(((g * 2 + 0) * YH + q) * 3 + c) * N + c0 + k] = y[q][k][c];
+                        hb[(((g * 2 + 1) * YH + q) * 3 + c) * N + c0 + k] = y[R - YH + q][k][c];
+                    }
+            __syncthreads();
+            srcS = zero_s ? s_zero : hb + ((gs * 2 + 1) * YH) * 3 * N;
+            srcN = zero_n ? s_zero : hb + ((gn * 2 + 0) * YH) * 3 * N;
+        }
+        auto yat = [&](int q, int k, int c) -> T {  // local row q in [-YH, R+YH); halo rows from LDS
+            if (q < 0) return *(const T *)(srcS + ((q + YH) * 3 + c) * N + c0 + k);
+            if (q >= R) return *(const T *)(srcN + ((q - R) * 3 + c) * N + c0 + k);
+            return y[(q < 0 || q >= R) ? 0 : q][k][c];
+        };
+        auto face2 = [&](int lr, int k, int c) -> T {  // flux on x2 face row lr
+            const int q = lr - FW;                      // face between rows q and q+1
+            T gr;
+            if (ORD == 2) gr = yat(q + 1, k, c) - yat(q, k, c);
+            else gr = (T)27 * (yat(q + 1, k, c) - yat(q, k, c)) - (yat(q + 2, k, c) - yat(q - 1, k, c));
+            if (FORM == 1 || (lr >= GF && lr < NFR - GF)) return ay[k][lr] * gr;
+            // boundary face: flux + tau as a double word (hi by FMA, then lo)
+            const int off = (lr < GF) ? tSb + k * tSs + lr * 8 : tNb + k * tNs + (lr - (NFR - GF)) * 8;
+            return fma_t(ay[k][lr], gr, tau_lds(off + c)) + tau_lds(off + 4 + c);
+        };
+        // sliding window of x2 face fluxes: faces lr = r .. r+FW+FE-1 before row r
+        T F2[(D == 2) ? FW + FE : 1][KD][3];
+        if (D == 2) {
+#pragma unroll
+            for (int w = 0; w < FW + FE; ++w)
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) F2[w][k][c] = face2(w, k, c);
+        }
+        double sq[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) sq[q] = 0.0;
+
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            // x1 halo values from the neighbouring lanes (taken before any update of this row)
+            T yw[YH][3], ye[YH][3];
+#pragma unroll
+            for (int i = 0; i < YH; ++i)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    yw[i][c] = nb<DppCtl<L>::ROT_FL, DppCtl<L>::SH_FL>(y[r][K - YH + i][c]);
+                    ye[i][c] = nb<DppCtl<L>::ROT_FR, DppCtl<L>::SH_FR>(y[r][i][c]);
+                }
+            // row values at local column p in [-YH, K+YH)
+            auto yrow = [&](int p, int c) -> T {
+                return (p < 0) ? yw[p + YH][c] : ((p >= K) ? ye[p - K][c] : y[r][p][c]);
+            };
+            auto face1 = [&](int lf, int c) -> T {  // flux on x1 face lf (between p and p+1)
+                const int p = lf - FW;
+                T gr;
+                if (ORD == 2) gr = yrow(p + 1, c) - yrow(p, c);
+                else gr = (T)27 * (yrow(p + 1, c) - yrow(p, c)) - (yrow(p + 2, c) - yrow(p - 1, c));
+                if (FORM == 1 || (lf >= GF && lf < NF - GF)) return ax[r][lf] * gr;
+                // boundary face: flux + tau as a double word (hi by FMA, then lo)
+                T hi, lo;
+                if (lf < GF) {
+                    hi = (D == 1) ? tauF[(D == 1) ? lf : 0][c] : tau_lds(tFb + r * tFs + lf * 8 + c);
+                    lo = (D == 1) ? tauF[(D == 1) ? lf : 0][3 + c] : tau_lds(tFb + r * tFs + lf * 8 + 4 + c);
+                } else {
+                    const int q = lf - (NF - GF);
+                    hi = (D == 1) ? tauL[(D == 1) ? q : 0][c] : tau_lds(tLb + r * tLs + q * 8 + c);
+                    lo = (D == 1) ? tauL[(D == 1) ? q : 0][3 + c] : tau_lds(tLb + r * tLs + q * 8 + 4 + c);
+                }
+                return fma_t(ax[r][lf], gr, hi) + lo;
+            };
+            // rolling window of x1 fluxes: faces lf = k .. k+FW+FE-1 before cell k
+            T Fw[FW + FE][3];
+#pragma unroll
+            for (int w = 0; w < FW + FE; ++w)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) Fw[w][c] = face1(w, c);
+
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                T H[3], Fx_east[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const T fnew = face1(k + FW + FE, c);
+                    if (ORD == 2) H[c] = fnew - Fw[0][c];
+                    else H[c] = (T)27 * (Fw[(ORD == 2) ? 0 : 2][c] - Fw[(ORD == 2) ? 0 : 1][c]) - (fnew - Fw[0][c]);
+                    Fx_east[c] = (FW == FW + FE) ? fnew : Fw[(FW < FW + FE) ? FW : 0][c];
+#pragma unroll
+                    for (int w = 0; w + 1 < FW + FE; ++w) Fw[w][c] = Fw[w + 1][c];
+                    Fw[FW + FE - 1][c] = fnew;
+                }
+                T Fy_north[3];
+                if (D == 2) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const T fnew = face2(r + FW + FE, k, c);
+                        T h2;
+                        if (ORD == 2) h2 = fnew - F2[0][k][c];
+                        else h2 = (T)27 * (F2[(ORD == 2) ? 0 : 2][k][c] - F2[(ORD == 2) ? 0 : 1][k][c]) - (fnew - F2[0][k][c]);
+                        H[c] = H[c] + h2;
+                        Fy_north[c] = (FW == FW + FE) ? fnew : F2[(FW < FW + FE) ? FW : 0][k][c];
+#pragma unroll
+                        for (int w = 0; w + 1 < FW + FE; ++w) F2[w][k][c] = F2[w + 1][k][c];
+                        F2[FW + FE - 1][k][c] = fnew;
+                    }
+                }
+                if (AVG == AVG_EVAL) {
+                    const int cell = (D == 1 ? 0 : (r0 + r) * N) + c0 + k;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c)
+                        eval_out[c * eval_cells + (long)(r0 + r) * N + c0 + k] =
+                            (double)H[c] + (FORM ? (double)ref(4 + c, cell) : 0.0);
+                    continue;
+                }
+                // ---- right-hand side f = -y x H - alpha y x (y x H), average, update
+                const int cell = (D == 1 ? 0 : (r0 + r) * N) + c0 + k;
+                // full state and field at this point: form 0 y, H; form 1 r + v, H(r) + D(v)
+                T m0 = y[r][k][0], m1 = y[r][k][1], m2 = y[r][k][2];
+                T h0 = H[0], h1 = H[1], h2 = H[2];
+                if (FORM == 1) {
+                    m0 += ref(0, cell);
+                    m1 += ref(1, cell);
+                    m2 += ref(2, cell);
+                    h0 += ref(4, cell);
+                    h1 += ref(5, cell);
+                    h2 += ref(6, cell);
+                }
+                const T cx = m1 * h2 - m2 * h1;
+                const T cy = m2 * h0 - m0 * h2;
+                const T cz = m0 * h1 - m1 * h0;
+                const T ex = m1 * cz - m2 * cy;
+                const T ey = m2 * cx - m0 * cz;
+                const T ez = m0 * cy - m1 * cx;
+                const T f[3] = {-fma_t(alpha, ex, cx), -fma_t(alpha, ey, cy), -fma_t(alpha, ez, cz)};
+                if (AVG == AVG_FIELD || AVG == AVG_TORQUE) {
+                    // form 1 field: only D(u); the constant sum_j w_j H(r)_j is added at upscale
+                    const double w = wv(c0 + k) * wy(r);
+                    sq[0] = fma(w, (double)(AVG == AVG_FIELD ? H[0] : cx), sq[0]);
+                    sq[1] = fma(w, (double)(AVG == AVG_FIELD ? H[1] : cy), sq[1]);
+                    sq[2] = fma(w, (double)(AVG == AVG_FIELD ? H[2] : cz), sq[2]);
+                } else if (AVG == AVG_FLUX) {
+                    const double w1 = wv(N + c0 + k) * wy(r);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) sq[c] = fma(w1, (double)Fx_east[c], sq[c]);
+                    if (D == 2) {
+                        const double w2 = wv(c0 + k) * wv(N + r0 + r);
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) sq[(D == 2 ? 3 : 0) + c] = fma(w2, (double)Fy_north[c], sq[(D == 2 ? 3 : 0) + c]);
+                    }
+                }
+                if (!LAST) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        acc[r][k][c] = FIRST ? bs * f[c] : fma_t(bs, f[c], acc[r][k][c]);
+                        y[r][k][c] = fma_t(cdt, f[c], m[r][k][c]);
+                    }
+                } else if (FORM == 0) {
+                    T mt[3];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) mt[c] = fma_t(dt, fma_t(bs, f[c], acc[r][k][c]), m[r][k][c]);
+                    const T inv = rsqrt_t(fma_t(mt[0], mt[0], fma_t(mt[1], mt[1], mt[2] * mt[2])));
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        m[r][k][c] = mt[c] * inv;
+                        y[r][k][c] = m[r][k][c];
+                    }
+                } else {
+                    // projection of r + ut onto the unit sphere, kept in perturbation form:
+                    // e = |r + ut|^2 - 1 = 2 r.ut + |ut|^2 + (|r|^2 - 1), n = sqrt(1 + e),
+                    // u = (r + ut)/n - r = (ut - r e / (1 + n)) / n
+                    T ut[3];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) ut[c] = fma_t(dt, fma_t(bs, f[c], acc[r][k][c]), m[r][k][c]);
+                    const T r0v = ref(0, cell), r1v = ref(1, cell), r2v = ref(2, cell);
+                    const T e = fma_t((T)2, fma_t(r0v, ut[0], fma_t(r1v, ut[1], r2v * ut[2])),
+                                      fma_t(ut[0], ut[0], fma_t(ut[1], ut[1], fma_t(ut[2], ut[2], ref(3, cell)))));
+                    const T inv = rsqrt_t((T)1 + e);
+                    const T nn = ((T)1 + e) * inv;
+                    const T q = e / ((T)1 + nn);
+                    m[r][k][0] = (ut[0] - r0v * q) * inv;
+                    m[r][k][1] = (ut[1] - r1v * q) * inv;
+                    m[r][k][2] = (ut[2] - r2v * q) * inv;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) y[r][k][c] = m[r][k][c];
+                }
+            }
+        }
+        if (AVG >= AVG_FIELD && AVG <= AVG_FLUX) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) acc64[q] = fma(wn, sq[q], acc64[q]);
+        }
+    }
+};
+
+template <typename T, int D, int ORD, int BC, int QTY, int L, int K, int R, int NG, int NBUF, int MINW>
+__global__ void __launch_bounds__(L * NG, MINW) k_micro(MicroArgs A) {
+    using Lane = MicroLane<T, D, ORD, BC, QTY, L, K, R, NG, NBUF>;
+    constexpr int N = Lane::N, NF = Lane::NF, NFR = Lane::NFR, FW = Lane::FW, GF = Lane::GF;
+    constexpr int YH = Lane::YH, NQ = Lane::NQ;
+    __shared__ T s_halo[NBUF * Lane::HALO];
+    __shared__ T s_zero[(D == 2) ? YH * 3 * N : 1];
+    __shared__ T s_tau[Lane::FORM ? 1 : Lane::TAU_LDS];
+    __shared__ T s_refl[Lane::REF_LDS];
+    __shared__ double s_w[Lane::WLDS];
+    constexpr int FORM = Lane::FORM;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int j = (L == 16) ? (lane & 15) : lane;
+    Lane S;
+    S.g = (L == 16) ? (wave * 4 + (lane >> 4)) : wave;
+    S.c0 = j * K;
+    S.r0 = (D == 2) ? S.g * R : 0;
+    const int g = S.g, c0 = S.c0, r0 = S.r0;
+
+    // 2-D: one box per block.  1-D: NG boxes per block (one per row group); the
+    // host groups 1-D boxes so that a block's boxes share M, the integrator and
+    // the time weights, and pads the last block with -1 (inactive groups).
+    const int slot = (D == 2) ? (int)blockIdx.x : (int)blockIdx.x * NG + g;
+    const int lead = A.box_ids[(D == 2) ? (int)blockIdx.x : (int)blockIdx.x * NG];
+    int box = (slot < A.nbox_class) ? A.box_ids[slot] : -1;
+    const bool active = box >= 0;
+    if (!active) box = lead;
+    const BoxPlan &P = A.plans[box];
+    const BoxPlan &PU = A.plans[lead];  // block-uniform controls
+    const T *tab = (const T *)A.tabs + P.tab_offset;
+    constexpr long CELLS = (D == 1) ? (long)N : (long)N * N;
+    const TabLayout TL = tab_layout(D, N, FORM);
+    constexpr int LF = N + kFaceHalo;  // faces stored per line
+
+    // ---------------- load the box tables
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int lf = 0; lf < NF; ++lf)
+            S.ax[r][lf] = tab[TL.ax + (long)(r0 + r) * LF + (c0 - FW + lf) + 2];
+    if (D == 2) {
+#pragma unroll
+        for (int k = 0; k < Lane::KD; ++k)
+#pragma unroll
+            for (int lr = 0; lr < Lane::NFRD; ++lr)
+                S.ay[k][lr] = tab[TL.ay + (long)(c0 + k) * LF + (r0 - FW + lr) + 2];
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                S.m[r][k][c] = tab[TL.m0 + c * CELLS + (long)(r0 + r) * N + c0 + k];
+                S.y[r][k][c] = S.m[r][k][c];
+                S.acc[r][k][c] = (T)0;
+            }
+    // space weights of this box into LDS
+    const double *wsrc = A.wts + P.w_offset;
+    if (D == 2) {
+        for (int i = tid; i < 2 * N; i += L * NG) s_w[i] = wsrc[i];
+        S.wl = s_w;
+    } else {
+        for (int i = j; i < 2 * N; i += L) s_w[g * 2 * N + i] = wsrc[i];
+        S.wl = s_w + g * 2 * N;
+    }
+    S.s_ref = nullptr;
+    if (FORM == 1) {
+        // reference, |r|^2 - 1 and H(r) of this box into LDS (7 values per point)
+        if (D == 2) {
+            for (int i = tid; i < 7 * N * N; i += L * NG) s_refl[i] = tab[TL.ref + i];
+            S.s_ref = s_refl;
+        } else {
+            for (int i = j; i < 7 * N; i += L) s_refl[g * 7 * N + i] = tab[TL.ref + i];
+            S.s_ref = s_refl + g * 7 * N;
+        }
+        for (int i = tid; i < ((D == 2) ? YH * 3 * N : 0); i += L * NG) s_zero[i] = (T)0;
+#pragma unroll
+        for (int q = 0; q < ((D == 1) ? GF : 1); ++q)
+#pragma unroll
+            for (int c = 0; c < 6; ++c) S.tauF[q][c] = S.tauL[q][c] = (T)0;
+        S.tFb = S.tFs = S.tLb = S.tLs = S.tSb = S.tSs = S.tNb = S.tNs = 0;
+    } else {
+        // boundary offsets: 1-D in registers (lanes 0 and L-1), 2-D in LDS
+        if (D == 1) {
+#pragma unroll
+            for (int q = 0; q < ((D == 1) ? GF : 1); ++q)
+#pragma unroll
+                for (int c = 0; c < 6; ++c) {
+                    const int e = (c < 3) ? c : c + 1;  // hi[0..2] at 0..2, lo[0..2] at 4..6
+                    T tf = tab[TL.tau1 + (0 * 3 + q) * 8 + e];
+                    T tl = tab[TL.tau1 + (1 * 3 + q) * 8 + e];
+                    S.tauF[q][c] = (j == 0) ? tf : (T)0;
+                    S.tauL[q][c] = (j == L - 1) ? tl : (T)0;
+                }
+        } else {
+            for (int i = tid; i < 2 * N * 48; i += L * NG) s_tau[i] = tab[TL.tau1 + i];
+            for (int i = tid; i < 24; i += L * NG) s_tau[Lane::ZOFF + i] = (T)0;
+            for (int i = tid; i < YH * 3 * N; i += L * NG) s_zero[i] = (T)0;
+            S.tFb = (j == 0) ? (r0 * 2 + 0) * 24 : Lane::ZOFF;
+            S.tFs = (j == 0) ? 48 : 0;
+            S.tLb = (j == L - 1) ? (r0 * 2 + 1) * 24 : Lane::ZOFF;
+            S.tLs = (j == L - 1) ? 48 : 0;
+            S.tSb = (g == 0) ? N * 48 + (c0 * 2 + 0) * 24 : Lane::ZOFF;
+            S.tSs = (g == 0) ? 48 : 0;
+            S.tNb = (g == NG - 1) ? N * 48 + (c0 * 2 + 1) * 24 : Lane::ZOFF;
+            S.tNs = (g == NG - 1) ? 48 : 0;
+        }
+    }
+    __syncthreads();
+    S.gs = (g + NG - 1) % NG;
+    S.gn = (g + 1) % NG;
+    S.zero_s = (BC == LLHMM_BC_DIRICHLET) && (g == 0);
+    S.zero_n = (BC == LLHMM_BC_DIRICHLET) && (g == NG - 1);
+    S.s_halo = s_halo;
+    S.s_zero = s_zero;
+    S.s_tau = s_tau;
+    S.alpha = (T)P.alpha;
+    S.dt = (T)P.dt;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) S.acc64[q] = 0.0;
+
+    if (A.mode == 1) {  // evaluate H(m0) only
+        if (active)
+            S.template stage<AVG_EVAL, true, false>((T)0, (T)0, 0.0, 0, A.out_field + P.mfinal_offset, CELLS);
+        return;
+    }
+
+    const int M = PU.M;
+    const bool rk4 = (PU.stages == 4);
+    // stage-1 data: b_1 and c_2 dt; RK4P b = (1,2,2,1)/6, c = (1/2, 1/2, 1); HeunP b = (1/2, 1/2), c = (1)
+    const T b1 = rk4 ? (T)(1.0 / 6.0) : (T)0.5;
+    const T c2dt = rk4 ? (T)(0.5 * P.dt) : (T)P.dt;  // per box (1-D lanes may differ)
+    const T third = (T)(1.0 / 3.0);
+    const T half_dt = (T)(0.5 * P.dt);
+    const double *wtab = A.wt + PU.wt_offset;
+    int ts = 0;
+    for (int n = 0; n < M; ++n) {
+        const double wn = wtab[n];
+        asm volatile("" ::: "memory");
+        S.template stage<Lane::AVG, true, false>(b1, c2dt, wn, ts, nullptr, 0);
+        ++ts;
+        // RK4P: two middle stages (b = 1/3; c = 1/2, 1), then the last (b = 1/6).
+        // HeunP: only the last stage (b = 1/2).
+        const int nmid = rk4 ? 2 : 0;
+        for (int sm = 0; sm < nmid; ++sm) {
+            S.template stage<AVG_NONE, false, false>(third, sm == 0 ? half_dt : S.dt, 0.0, ts++, nullptr, 0);
+        }
+        S.template stage<AVG_NONE, false, true>(rk4 ? (T)(1.0 / 6.0) : (T)0.5, (T)0, 0.0, ts++, nullptr, 0);
+    }
+
+    // ---------------- outputs
+    if (A.out_field && active) {
+        double *dst = A.out_field + P.mfinal_offset;
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    dst[c * CELLS + (long)(r0 + r) * N + c0 + k] =
+                        (double)S.m[r][k][c] +
+                        (FORM ? (double)S.s_ref[c * CELLS + (D == 1 ? 0 : (r0 + r) * N) + c0 + k] : 0.0);
+    }
+    // reduce over the row group (1-D: one box) or the wavefront (2-D)
+    constexpr int RED = (D == 1) ? L : 64;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        double v = S.acc64[q];
+#pragma unroll
+        for (int off = 1; off < RED; off <<= 1) v += __shfl_xor(v, off, 64);
+        S.acc64[q] = v;
+    }
+    const bool writer = (D == 1) ? (j == 0) : (lane == 0);
+    if (writer && active) {
+        const int wslot = (D == 1) ? 0 : wave;
+        double *dst = A.partials + ((long)box * kMaxWaves + wslot) * kMaxQ;
+        int bad = 0;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            dst[q] = S.acc64[q];
+            if (!__builtin_isfinite(S.acc64[q])) bad = 1;
+        }
+        A.wave_status[(long)box * kMaxWaves + wslot] = bad;
+    }
+}
+
+}  // namespace llhmm

@@ -1,0 +1,31 @@
+// FP32 2-D tile classes (state and stencil in FP32, averages in FP64).
+#include "llhmm_tiles.h"
+
+namespace llhmm {
+static const TileInfo kTiles[] = {
+    LLHMM_TILE(float, 1, 2, 2, 0, 0, 16, 2, 4, 8, 2, 2),
+    LLHMM_TILE(float, 1, 2, 2, 0, 0, 16, 3, 3, 16, 2, 2),
+    LLHMM_TILE(float, 1, 2, 4, 0, 0, 16, 3, 3, 16, 1, 1),
+    LLHMM_TILE(float, 1, 2, 2, 0, 1, 16, 2, 4, 8, 2, 2),
+    LLHMM_TILE(float, 1, 2, 2, 0, 1, 16, 3, 3, 16, 2, 2),
+    LLHMM_TILE(float, 1, 2, 4, 0, 1, 16, 3, 3, 16, 1, 1),
+    LLHMM_TILE(float, 1, 2, 2, 0, 2, 16, 2, 4, 8, 2, 2),
+    LLHMM_TILE(float, 1, 2, 2, 0, 2, 16, 3, 3, 16, 2, 2),
+    LLHMM_TILE(float, 1, 2, 4, 0, 2, 16, 3, 3, 16, 1, 1),
+    LLHMM_TILE(float, 1, 2, 2, 0, 0, 64, 1, 8, 8, 2, 2),
+    LLHMM_TILE(float, 1, 2, 2, 1, 0, 16, 2, 4, 8, 2, 2),
+    LLHMM_TILE(float, 1, 2, 2, 1, 0, 16, 3, 3, 16, 2, 2),
+    LLHMM_TILE(float, 1, 2, 4, 1, 0, 16, 3, 3, 16, 1, 1),
+    LLHMM_TILE(float, 1, 2, 2, 1, 1, 16, 2, 4, 8, 2, 2),
+    LLHMM_TILE(float, 1, 2, 2, 1, 1, 16, 3, 3, 16, 2, 2),
+    LLHMM_TILE(float, 1, 2, 4, 1, 1, 16, 3, 3, 16, 1, 1),
+    LLHMM_TILE(float, 1, 2, 2, 1, 2, 16, 2, 4, 8, 2, 2),
+    LLHMM_TILE(float, 1, 2, 2, 1, 2, 16, 3, 3, 16, 2, 2),
+    LLHMM_TILE(float, 1, 2, 4, 1, 2, 16, 3, 3, 16, 1, 1),
+    LLHMM_TILE(float, 1, 2, 2, 1, 0, 64, 1, 8, 8, 2, 2),
+};
+const TileInfo *tiles_f32_2d(int *count) {
+    *count = (int)(sizeof(kTiles) / sizeof(kTiles[0]));
+    return kTiles;
+}
+}  // namespace llhmm

@@ -1,0 +1,90 @@
+"""CPU checks of the C-ABI library: it loads, exports every declared entry
+point, and its host-side planning (validation, stability rule, kernel
+coefficients) agrees with the oracle.  No kernel is launched here."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2108_09463_amd import inputs
+from paper_2108_09463_amd import llhmm as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(L.LIB_PATH):
+        from paper_2108_09463_amd import build
+        build.build(verbose=False)
+    return L.lib()
+
+
+def test_exports_every_declared_symbol(lib):
+    hdr = open(os.path.join(ROOT, "include", "llhmm.h")).read()
+    names = set(re.findall(r"\b(llhmm_[a-z_]+)\s*\(", hdr))
+    assert len(names) >= 12
+    for n in sorted(names):
+        assert hasattr(lib, n), n
+    assert L.llhmm_abi_version() == 1
+
+
+def _all_boxes():
+    out = []
+    out += inputs.one_d_single().boxes
+    out += inputs.two_d_batch().boxes[:64]
+    out += inputs.uneven_batch(nboxes=200).boxes
+    b5, _ = inputs.served_boxes(n_macro=16)
+    out += b5
+    return out
+
+
+def test_plan_matches_oracle():
+    """Integer step counts are bit-exact with the oracle's stability rule."""
+    from oracle import micro
+    boxes = _all_boxes()
+    M, dt, integ = L.llhmm_plan(boxes)
+    for i, b in enumerate(boxes):
+        oi, oM, odt = micro.plan(b)
+        assert (M[i], integ[i]) == (oM, oi), (i, b)
+        assert dt[i] == pytest.approx(odt, rel=1e-15)
+
+
+def test_kernel_coefficients_match_oracle():
+    from oracle import kernels
+    for (p, q) in [(3, 7), (1, 3), (5, 9), (2, 4)]:
+        c, d = L.llhmm_kernel_coeffs(p, q, p, q)
+        ce = np.array([float(v) for v in kernels.space_coeffs(p, q)])
+        de = np.array([float(v) for v in kernels.time_coeffs(p, q)])
+        assert np.array_equal(c, ce) and np.array_equal(d, de)
+
+
+@pytest.mark.parametrize("field,value,msg", [
+    ("dim", 3, "dim"), ("n", 7, "even"), ("order", 3, "order"), ("alpha", 0.0, "alpha"),
+    ("mu", 0.0, "mu"), ("eta", -1.0, "eta"), ("a_max", 0.0, "a_max"), ("eps", 1.5, "eps"),
+    ("bc", 5, "bc"), ("quantity", 9, "quantity"), ("n_steps", -2, "n_steps"),
+])
+def test_invalid_boxes_rejected(field, value, msg):
+    """Fault injection: assumptions (A1)-(A2) and the contract are checked before any launch."""
+    b = inputs.make_box(dim=2, n=32, eps=0.01, mu=0.03, mu_box=0.03, eta=1e-4)
+    b[field] = value
+    with pytest.raises(L.LlhmmError) as ei:
+        L.llhmm_plan([b])
+    assert ei.value.code == L.E_INVALID and msg in str(ei.value)
+
+
+def test_mu_larger_than_box_rejected():
+    b = inputs.make_box(dim=1, n=32, mu=0.05, mu_box=0.03)
+    with pytest.raises(L.LlhmmError):
+        L.llhmm_plan([b])
+
+
+def test_unstable_rule_bounds():
+    """The rule's step count follows dt ~ dx^2 (Section 3.2): doubling n at fixed
+    box quadruples M (up to the ceiling)."""
+    b = [inputs.make_box(dim=2, n=n, eps=0.005, alpha=0.1, mu=0.015, mu_box=0.015, eta=2.5e-5)
+         for n in (32, 64, 128)]
+    M, _, _ = L.llhmm_plan(b)
+    assert abs(M[1] / M[0] - 4) < 0.05 and abs(M[2] / M[1] - 4) < 0.02
