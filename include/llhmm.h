@@ -158,6 +158,19 @@ llhmm_status llhmm_batch_create(llhmm_ctx *ctx, const llhmm_box *boxes, int32_t 
 llhmm_status llhmm_batch_destroy(llhmm_ctx *ctx, llhmm_batch *batch);
 /* Number of micro cell-steps of the batch: sum over boxes of M * n^dim. */
 int64_t llhmm_batch_cell_steps(const llhmm_batch *batch);
+/* Phase timing.  With timing enabled (enable != 0; enabling also forgets
+ * earlier timed calls), every llhmm_micro_batch / llhmm_eval_field call on
+ * the batch records three HIP events on its stream: before the set-up kernel
+ * (tables from m_init or Q_[4]), between set-up and time stepping, and after
+ * the last time-stepping launch.  The batch owns LLHMM_TIMING_SLOTS such event
+ * triples and reuses them in turn, so timing adds no host synchronization.
+ * llhmm_batch_timing waits for the events of the timed call `back` calls
+ * before the last one (back = 0: the last) and returns its two phases'
+ * elapsed milliseconds; LLHMM_E_INVALID if timing is off or that call is not
+ * among the last min(calls, LLHMM_TIMING_SLOTS). */
+#define LLHMM_TIMING_SLOTS 64
+llhmm_status llhmm_batch_set_timing(llhmm_batch *batch, int32_t enable);
+llhmm_status llhmm_batch_timing(llhmm_batch *batch, int32_t back, float *setup_ms, float *step_ms);
 
 /* The micro solve (steps 1-3 above) for every box of the batch, on `stream`.
  *   m_init_dev   INIT_EXPLICIT boxes: FP64 m_init on the extended grid,

@@ -247,8 +247,11 @@ struct llhmm_batch {
     int32_t *box_ids = nullptr;
     CoefDev *coefs = nullptr;
     void *tabs = nullptr;
-    double *wts = nullptr, *wt = nullptr, *partials = nullptr, *box_const = nullptr;
+    double *wts = nullptr, *wt = nullptr, *partials = nullptr, *box_const = nullptr, *scratch64 = nullptr;
     int32_t *wave_status = nullptr, *status = nullptr;
+    hipEvent_t ev[LLHMM_TIMING_SLOTS][3] = {};
+    bool timing = false;
+    int64_t timed = 0;  // timed calls since timing was enabled
     double kc[8];
     int kp, kq;
 };
@@ -301,9 +304,12 @@ llhmm_status llhmm_kernel_coeffs(const llhmm_kernel *K, double *c_space, double 
 static void batch_free(llhmm_batch *b) {
     if (!b) return;
     void *ptrs[] = {b->plans, b->box_ids, b->coefs, b->tabs, b->wts, b->wt, b->partials,
-                    b->wave_status, b->status, b->box_const};
+                    b->wave_status, b->status, b->box_const, b->scratch64};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
+    for (auto &slot : b->ev)
+        for (hipEvent_t e : slot)
+            if (e) (void)hipEventDestroy(e);
     delete b;
 }
 
@@ -346,7 +352,7 @@ llhmm_status llhmm_batch_create(llhmm_ctx *ctx, const llhmm_box *boxes, int32_t 
     }
     b->dim_max = dim_max;
     b->nmax = nmax;
-    int64_t tab_off = 0, w_off = 0;
+    int64_t tab_off = 0, w_off = 0, s64_off = 0;
     std::map<int, int64_t> wt_off_of_M;
     std::vector<double> wt_h;
     int64_t cell_steps = 0;
@@ -404,6 +410,8 @@ llhmm_status llhmm_batch_create(llhmm_ctx *ctx, const llhmm_box *boxes, int32_t 
         tab_off += tab_layout(bx.dim, bx.n, P.form).size;
         P.w_offset = w_off;
         w_off += 2 * bx.n;
+        P.s64_offset = s64_off;
+        if (P.form == 1) s64_off += scratch64_size(bx.dim, bx.n);
         auto wit = wt_off_of_M.find(pl.M);
         if (wit == wt_off_of_M.end()) {
             const int64_t o = (int64_t)wt_h.size();
@@ -465,6 +473,7 @@ llhmm_status llhmm_batch_create(llhmm_ctx *ctx, const llhmm_box *boxes, int32_t 
         e = hipMalloc((void **)&b->wave_status, sizeof(int32_t) * (size_t)nboxes * kMaxWaves);
     if (e == hipSuccess) e = hipMalloc((void **)&b->status, sizeof(int32_t) * (size_t)nboxes);
     if (e == hipSuccess) e = hipMalloc((void **)&b->box_const, sizeof(double) * (size_t)nboxes * kMaxQ);
+    if (e == hipSuccess) e = hipMalloc((void **)&b->scratch64, sizeof(double) * std::max<int64_t>(s64_off, 1));
     if (e != hipSuccess) {
         batch_free(b);
         return fail(e == hipErrorOutOfMemory ? LLHMM_E_NOMEM : LLHMM_E_HIP, "batch allocation: %s",
@@ -522,10 +531,14 @@ static llhmm_status run_batch(llhmm_ctx *ctx, llhmm_batch *b, const double *m_in
     pa.tabs = b->tabs;
     pa.wts = b->wts;
     pa.box_const = b->box_const;
+    pa.scratch64 = b->scratch64;
     memcpy(pa.kc, b->kc, sizeof pa.kc);
     pa.kp = b->kp;
     pa.kq = b->kq;
+    hipEvent_t *ev = b->ev[b->timed % LLHMM_TIMING_SLOTS];
+    if (b->timing) HIP_TRY(hipEventRecord(ev[0], stream));
     HIP_TRY(launch_prologue(b->prec, pa, stream));
+    if (b->timing) HIP_TRY(hipEventRecord(ev[1], stream));
     for (const ClassLaunch &cl : b->classes) {
         MicroArgs a{};
         a.plans = b->plans;
@@ -540,6 +553,37 @@ static llhmm_status run_batch(llhmm_ctx *ctx, llhmm_batch *b, const double *m_in
         a.out_field = field_dev;
         HIP_TRY(cl.tile->launch(a, cl.nblocks, stream));
     }
+    if (b->timing) {
+        HIP_TRY(hipEventRecord(ev[2], stream));
+        ++b->timed;
+    }
+    return LLHMM_OK;
+}
+
+llhmm_status llhmm_batch_set_timing(llhmm_batch *b, int32_t enable) {
+    if (!b) return fail(LLHMM_E_INVALID, "batch is NULL");
+    if (enable)
+        for (auto &slot : b->ev)
+            for (hipEvent_t &e : slot)
+                if (!e) HIP_TRY(hipEventCreate(&e));
+    b->timing = enable != 0;
+    b->timed = 0;
+    return LLHMM_OK;
+}
+
+llhmm_status llhmm_batch_timing(llhmm_batch *b, int32_t back, float *setup_ms, float *step_ms) {
+    if (!b) return fail(LLHMM_E_INVALID, "batch is NULL");
+    if (!b->timing) return fail(LLHMM_E_INVALID, "timing is off");
+    if (back < 0 || back >= LLHMM_TIMING_SLOTS || back >= b->timed)
+        return fail(LLHMM_E_INVALID, "timed call %d back is not kept (%lld timed calls)", back,
+                    (long long)b->timed);
+    hipEvent_t *ev = b->ev[(b->timed - 1 - back) % LLHMM_TIMING_SLOTS];
+    HIP_TRY(hipEventSynchronize(ev[2]));
+    float s = 0.f, t = 0.f;
+    HIP_TRY(hipEventElapsedTime(&s, ev[0], ev[1]));
+    HIP_TRY(hipEventElapsedTime(&t, ev[1], ev[2]));
+    if (setup_ms) *setup_ms = s;
+    if (step_ms) *step_ms = t;
     return LLHMM_OK;
 }
 

@@ -24,6 +24,7 @@ struct BoxPlan {
     int64_t init_offset, coef_offset, wt_offset, mfinal_offset;
     int64_t tab_offset;                  // element offset (in T) of the box's tables
     int64_t w_offset;                    // element offset (double) of the space weights
+    int64_t s64_offset;                  // element offset (double) of the set-up scratch (form 1)
 };
 
 // Per-box table layout (elements of T, starting at tab_offset), n = points per
@@ -42,6 +43,14 @@ struct BoxPlan {
 //     H0   [3][C]                  H(r) with the boundary data, computed in FP64
 //     ax, ay as in form 0 (no tau tables: u is periodic or zero on the ghosts)
 // Space weights (double, at w_offset): wc [n] (points), wf [n] (east faces).
+// Form-1 set-up scratch per box (doubles): FP64 scaled face coefficients
+// ax [lines][n+3], ay [n][n+3] (2-D), then ghost references gx [lines][2][3][3]
+// (x1: points -3..-1 and n..n+2 of each line), gy [n][2][3][3] (2-D).
+__host__ __device__ inline int64_t scratch64_size(int d, int n) {
+    const int64_t lines = (d == 1) ? 1 : n;
+    return (lines + (d == 2 ? n : 0)) * (n + 3) + (lines + (d == 2 ? n : 0)) * 18;
+}
+
 struct TabLayout {
     int64_t m0, ref, dm, H0, ax, ay, tau1, tau2, size;
 };
@@ -93,6 +102,7 @@ struct PrologueArgs {
     void *tabs;            // T tables
     double *wts;           // space weights
     double *box_const;     // [nboxes][kMaxQ]: average of the reference part (form 1)
+    double *scratch64;     // form 1 set-up scratch: FP64 faces and ghost references per box
     double kc[8];          // space kernel coefficients c_0..c_p
     int32_t kp, kq;
 };

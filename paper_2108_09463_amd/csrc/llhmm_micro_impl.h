@@ -79,8 +79,15 @@ struct MicroLane {
     static constexpr int NQ = (QTY == LLHMM_Q_FLUX) ? 3 * D : 3;
     static constexpr int AVG = (QTY == LLHMM_Q_FIELD) ? 1 : ((QTY == LLHMM_Q_TORQUE) ? 2 : 3);
     static constexpr int HALO = (D == 2) ? NG * 2 * YH * 3 * N : 1;
-    static constexpr int TAU_LDS = (D == 2) ? 2 * N * 48 + 24 : 1;
-    static constexpr int ZOFF = 2 * N * 48;
+    // 2-D boundary offsets in LDS: [2N lines/columns][2 sides][GF faces][hi 4, lo 4],
+    // then a zero block read by lanes without boundary faces
+    static constexpr int TAU_LDS = (D == 2) ? 4 * N * GF * 8 + 24 : 1;
+    static constexpr int ZOFF = 4 * N * GF * 8;
+    // FP64: face coefficients are read from LDS (x1 faces [lines][LF], 2-D x2
+    // faces [N][LF] after them) instead of being held in registers
+    static constexpr bool AXL = (sizeof(T) == 8);
+    static constexpr int LF = N + kFaceHalo;
+    static constexpr int AX_LDS = AXL ? ((D == 2) ? 2 * N * LF : NG * LF) : 1;
     static constexpr int WLDS = (D == 2) ? 2 * N : NG * 2 * N;  // space weights in LDS
     // form 1 (FP32): m = r + u with the FP32 reference r = fl(m_init) and H(r)
     // precomputed in FP64; the state u starts at the rounding residual m_init - r
@@ -95,8 +102,9 @@ struct MicroLane {
     static_assert(L == 16 || L == 64, "row group is a DPP row or a wavefront");
 
     T m[R][K][3], y[R][K][3], acc[R][K][3];
-    T ax[R][NF];
-    T ay[KD][NFRD];
+    T ax[AXL ? 1 : R][AXL ? 1 : NF];
+    T ay[AXL ? 1 : KD][AXL ? 1 : NFRD];
+    const T *s_axl;  // AXL: this group's face coefficients in LDS
     T tauF[(D == 1) ? GF : 1][6], tauL[(D == 1) ? GF : 1][6];  // hi[3], lo[3]
     int tFb, tFs, tLb, tLs, tSb, tSs, tNb, tNs;  // LDS offsets: base + index * stride
     double acc64[NQ];
@@ -117,6 +125,13 @@ struct MicroLane {
         return FORM ? (T)0 : s_tau[off];
     }
     __device__ __forceinline__ T ref(int q, int cell) const { return s_ref[q * CELLS + cell]; }
+    // face coefficient of x1 face lf of own row r / x2 face lr of own column k
+    __device__ __forceinline__ T axv(int r, int lf) const {
+        return AXL ? s_axl[(r0 + r) * LF + c0 - FW + lf + 2] : ax[AXL ? 0 : r][AXL ? 0 : lf];
+    }
+    __device__ __forceinline__ T ayv(int k, int lr) const {
+        return AXL ? s_axl[N * LF + (c0 + k) * LF + r0 - FW + lr + 2] : ay[AXL ? 0 : k][AXL ? 0 : lr];
+    }
 
     // One Runge-Kutta stage on stage input y: H(y), f(y), accumulator and
     // next stage input (or the projected new state when LAST).  With AVG != 0
@@ -153,10 +168,10 @@ struct MicroLane {
             T gr;
             if (ORD == 2) gr = yat(q + 1, k, c) - yat(q, k, c);
             else gr = (T)27 * (yat(q + 1, k, c) - yat(q, k, c)) - (yat(q + 2, k, c) - yat(q - 1, k, c));
-            if (FORM == 1 || (lr >= GF && lr < NFR - GF)) return ay[k][lr] * gr;
+            if (FORM == 1 || (lr >= GF && lr < NFR - GF)) return ayv(k, lr) * gr;
             // boundary face: flux + tau as a double word (hi by FMA, then lo)
             const int off = (lr < GF) ? tSb + k * tSs + lr * 8 : tNb + k * tNs + (lr - (NFR - GF)) * 8;
-            return fma_t(ay[k][lr], gr, tau_lds(off + c)) + tau_lds(off + 4 + c);
+            return fma_t(ayv(k, lr), gr, tau_lds(off + c)) + tau_lds(off + 4 + c);
         };
         // sliding window of x2 face fluxes: faces lr = r .. r+FW+FE-1 before row r
         T F2[(D == 2) ? FW + FE : 1][KD][3];
@@ -192,7 +207,7 @@ struct MicroLane {
                 T gr;
                 if (ORD == 2) gr = yrow(p + 1, c) - yrow(p, c);
                 else gr = (T)27 * (yrow(p + 1, c) - yrow(p, c)) - (yrow(p + 2, c) - yrow(p - 1, c));
-                if (FORM == 1 || (lf >= GF && lf < NF - GF)) return ax[r][lf] * gr;
+                if (FORM == 1 || (lf >= GF && lf < NF - GF)) return axv(r, lf) * gr;
                 // boundary face: flux + tau as a double word (hi by FMA, then lo)
                 T hi, lo;
                 if (lf < GF) {
@@ -203,7 +218,7 @@ struct MicroLane {
                     hi = (D == 1) ? tauL[(D == 1) ? q : 0][c] : tau_lds(tLb + r * tLs + q * 8 + c);
                     lo = (D == 1) ? tauL[(D == 1) ? q : 0][3 + c] : tau_lds(tLb + r * tLs + q * 8 + 4 + c);
                 }
-                return fma_t(ax[r][lf], gr, hi) + lo;
+                return fma_t(axv(r, lf), gr, hi) + lo;
             };
             // rolling window of x1 fluxes: faces lf = k .. k+FW+FE-1 before cell k
             T Fw[FW + FE][3];
@@ -338,6 +353,7 @@ __global__ void __launch_bounds__(L * NG, MINW) k_micro(MicroArgs A) {
     __shared__ T s_tau[Lane::FORM ? 1 : Lane::TAU_LDS];
     __shared__ T s_refl[Lane::REF_LDS];
     __shared__ double s_w[Lane::WLDS];
+    __shared__ T s_ax[Lane::AX_LDS];
     constexpr int FORM = Lane::FORM;
 
     const int tid = threadIdx.x;
@@ -366,17 +382,29 @@ __global__ void __launch_bounds__(L * NG, MINW) k_micro(MicroArgs A) {
     constexpr int LF = N + kFaceHalo;  // faces stored per line
 
     // ---------------- load the box tables
+    if (Lane::AXL) {
+        // x1 faces then (2-D) x2 faces; ay follows ax in the table
+        if (D == 2) {
+            for (int i = tid; i < 2 * N * LF; i += L * NG) s_ax[i] = tab[TL.ax + i];
+            S.s_axl = s_ax;
+        } else {
+            for (int i = j; i < LF; i += L) s_ax[g * LF + i] = tab[TL.ax + i];
+            S.s_axl = s_ax + g * LF;
+        }
+    } else {
+        S.s_axl = nullptr;
 #pragma unroll
-    for (int r = 0; r < R; ++r)
+        for (int r = 0; r < (Lane::AXL ? 0 : R); ++r)
 #pragma unroll
-        for (int lf = 0; lf < NF; ++lf)
-            S.ax[r][lf] = tab[TL.ax + (long)(r0 + r) * LF + (c0 - FW + lf) + 2];
-    if (D == 2) {
+            for (int lf = 0; lf < NF; ++lf)
+                S.ax[Lane::AXL ? 0 : r][Lane::AXL ? 0 : lf] = tab[TL.ax + (long)(r0 + r) * LF + (c0 - FW + lf) + 2];
+        if (D == 2) {
 #pragma unroll
-        for (int k = 0; k < Lane::KD; ++k)
+            for (int k = 0; k < (Lane::AXL ? 0 : Lane::KD); ++k)
 #pragma unroll
-            for (int lr = 0; lr < Lane::NFRD; ++lr)
-                S.ay[k][lr] = tab[TL.ay + (long)(c0 + k) * LF + (r0 - FW + lr) + 2];
+                for (int lr = 0; lr < Lane::NFRD; ++lr)
+                    S.ay[Lane::AXL ? 0 : k][Lane::AXL ? 0 : lr] = tab[TL.ay + (long)(c0 + k) * LF + (r0 - FW + lr) + 2];
+        }
     }
 #pragma unroll
     for (int r = 0; r < R; ++r)
@@ -427,17 +455,19 @@ __global__ void __launch_bounds__(L * NG, MINW) k_micro(MicroArgs A) {
                     S.tauL[q][c] = (j == L - 1) ? tl : (T)0;
                 }
         } else {
-            for (int i = tid; i < 2 * N * 48; i += L * NG) s_tau[i] = tab[TL.tau1 + i];
+            // tables hold [2N][2 sides][3][8]; LDS keeps the GF faces that are used
+            constexpr int TS = GF * 8;
+            for (int i = tid; i < 4 * N * TS; i += L * NG) s_tau[i] = tab[TL.tau1 + (i / TS) * 24 + i % TS];
             for (int i = tid; i < 24; i += L * NG) s_tau[Lane::ZOFF + i] = (T)0;
             for (int i = tid; i < YH * 3 * N; i += L * NG) s_zero[i] = (T)0;
-            S.tFb = (j == 0) ? (r0 * 2 + 0) * 24 : Lane::ZOFF;
-            S.tFs = (j == 0) ? 48 : 0;
-            S.tLb = (j == L - 1) ? (r0 * 2 + 1) * 24 : Lane::ZOFF;
-            S.tLs = (j == L - 1) ? 48 : 0;
-            S.tSb = (g == 0) ? N * 48 + (c0 * 2 + 0) * 24 : Lane::ZOFF;
-            S.tSs = (g == 0) ? 48 : 0;
-            S.tNb = (g == NG - 1) ? N * 48 + (c0 * 2 + 1) * 24 : Lane::ZOFF;
-            S.tNs = (g == NG - 1) ? 48 : 0;
+            S.tFb = (j == 0) ? (r0 * 2 + 0) * TS : Lane::ZOFF;
+            S.tFs = (j == 0) ? 2 * TS : 0;
+            S.tLb = (j == L - 1) ? (r0 * 2 + 1) * TS : Lane::ZOFF;
+            S.tLs = (j == L - 1) ? 2 * TS : 0;
+            S.tSb = (g == 0) ? 2 * N * TS + (c0 * 2 + 0) * TS : Lane::ZOFF;
+            S.tSs = (g == 0) ? 2 * TS : 0;
+            S.tNb = (g == NG - 1) ? 2 * N * TS + (c0 * 2 + 1) * TS : Lane::ZOFF;
+            S.tNs = (g == NG - 1) ? 2 * TS : 0;
         }
     }
     __syncthreads();

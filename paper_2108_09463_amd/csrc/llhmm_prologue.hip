@@ -168,37 +168,64 @@ __device__ double kernel_space(const PrologueArgs &A, double x) {
 
 }  // namespace
 
-// Reference value r at point (i0, i1) for form 1 (interior: the stored FP32
-// reference; ghost: chosen so that u = m - r is periodic (periodic m - m_init:
-// r_g = r_w + m_init(g) - m_init(w)) or zero (Dirichlet: r_g = m_init(g))).
-template <typename T>
-__device__ double ref_at(const PrologueArgs &A, const BoxPlan &P, const T *tab, const TabLayout &L,
-                         int i0, int i1, int c) {
+// Form-1 set-up scratch views (see scratch64_size).
+struct Scratch64 {
+    double *ax, *ay, *gx, *gy;
+    int n, lines;
+    __device__ Scratch64(double *base, int d, int n_) : n(n_) {
+        lines = (d == 1) ? 1 : n;
+        ax = base;
+        ay = ax + (long)lines * (n + 3);
+        gx = ay + (d == 2 ? (long)n * (n + 3) : 0);
+        gy = gx + (long)lines * 18;
+    }
+};
+
+// Reference value r at a ghost point (i0, i1), form 1.  Periodic m - m_init:
+// r_g = r_w + m_init(g) - m_init(w), so that u = m - r is periodic with r_w the
+// stored reference of the wrapped point w.  Dirichlet: r_g = m_init(g), so
+// that u vanishes on the ghosts.
+__device__ double ref_ghost(const PrologueArgs &A, const BoxPlan &P, int i0, int i1, int c) {
     const int N = P.n, D = P.dim;
-    const long C = (D == 1) ? (long)N : (long)N * N;
-    auto inside = [&](int i) { return i >= 0 && i < N; };
-    if (inside(i0) && (D == 1 || inside(i1)))
-        return (double)tab[L.ref + c * C + (long)(D == 1 ? 0 : i1) * N + i0];
     double g[3];
     minit_at(A, P, i0, i1, g);
     if (P.bc == LLHMM_BC_DIRICHLET) return g[c];
     const int w0 = ((i0 % N) + N) % N, w1 = (D == 1) ? 0 : ((i1 % N) + N) % N;
     double h[3];
     minit_at(A, P, w0, w1, h);
-    return (double)tab[L.ref + c * C + (long)w1 * N + w0] + (g[c] - h[c]);
+    // stored reference of w: m_init(w) rounded to the batch precision
+    const double rw = (P.prec == LLHMM_FP32) ? (double)(float)h[c] : h[c];
+    return rw + (g[c] - h[c]);
+}
+
+template <typename T>
+__device__ __forceinline__ double ref_at(const BoxPlan &P, const T *tab, const TabLayout &L,
+                                         const Scratch64 &S, int i0, int i1, int c) {
+    const int N = P.n, D = P.dim;
+    const long C = (D == 1) ? (long)N : (long)N * N;
+    if (i0 < 0 || i0 >= N) {  // x1 ghost
+        const int side = (i0 < 0) ? 0 : 1, layer = (i0 < 0) ? i0 + 3 : i0 - N;
+        return S.gx[(((long)(D == 1 ? 0 : i1) * 2 + side) * 3 + layer) * 3 + c];
+    }
+    if (D == 2 && (i1 < 0 || i1 >= N)) {  // x2 ghost
+        const int side = (i1 < 0) ? 0 : 1, layer = (i1 < 0) ? i1 + 3 : i1 - N;
+        return S.gy[(((long)i0 * 2 + side) * 3 + layer) * 3 + c];
+    }
+    return (double)tab[L.ref + c * C + (long)(D == 1 ? 0 : i1) * N + i0];
 }
 
 // Flux a' G(r) on the face between (i0, i1) and (i0, i1) + e_axis, FP64.
 template <typename T>
-__device__ double ref_flux(const PrologueArgs &A, const BoxPlan &P, const T *tab, const TabLayout &L,
+__device__ double ref_flux(const BoxPlan &P, const T *tab, const TabLayout &L, const Scratch64 &S,
                            int axis, int i0, int i1, int c) {
     const int s0 = (axis == 0), s1 = (axis == 1);
-    const double a = face_coef(A, P, axis, i0, i1) * P.a_scale;
-    const double r0 = ref_at(A, P, tab, L, i0, i1, c);
-    const double rp = ref_at(A, P, tab, L, i0 + s0, i1 + s1, c);
+    const double a = (axis == 0) ? S.ax[(long)(P.dim == 1 ? 0 : i1) * (P.n + 3) + i0 + 2]
+                                 : S.ay[(long)i0 * (P.n + 3) + i1 + 2];
+    const double r0 = ref_at(P, tab, L, S, i0, i1, c);
+    const double rp = ref_at(P, tab, L, S, i0 + s0, i1 + s1, c);
     if (P.order == 2) return a * (rp - r0);
-    const double rpp = ref_at(A, P, tab, L, i0 + 2 * s0, i1 + 2 * s1, c);
-    const double rm = ref_at(A, P, tab, L, i0 - s0, i1 - s1, c);
+    const double rpp = ref_at(P, tab, L, S, i0 + 2 * s0, i1 + 2 * s1, c);
+    const double rm = ref_at(P, tab, L, S, i0 - s0, i1 - s1, c);
     return a * (27.0 * (rp - r0) - (rpp - rm));
 }
 
@@ -236,14 +263,19 @@ __global__ void __launch_bounds__(256) k_prologue(PrologueArgs A) {
     }
     // face coefficients: x1 faces of every line, x2 faces of every column
     const int nf = N + kFaceHalo;
+    Scratch64 S64(A.scratch64 + (P.form == 1 ? P.s64_offset : 0), D, N);
     for (long t = tid; t < (long)lines * nf; t += nth) {
         int line = (int)(t / nf), f = (int)(t % nf) - 2;
-        tab[L.ax + t] = (T)(face_coef(A, P, 0, f, line) * P.a_scale);
+        const double a = face_coef(A, P, 0, f, line) * P.a_scale;
+        tab[L.ax + t] = (T)a;
+        if (P.form == 1) S64.ax[t] = a;
     }
     if (D == 2) {
         for (long t = tid; t < (long)N * nf; t += nth) {
             int col = (int)(t / nf), f = (int)(t % nf) - 2;
-            tab[L.ay + t] = (T)(face_coef(A, P, 1, col, f) * P.a_scale);
+            const double a = face_coef(A, P, 1, col, f) * P.a_scale;
+            tab[L.ay + t] = (T)a;
+            if (P.form == 1) S64.ay[t] = a;
         }
     }
     // space weights of the scaled kernel at points and east faces
@@ -276,7 +308,20 @@ __global__ void __launch_bounds__(256) k_prologue(PrologueArgs A) {
         if (tid < kMaxQ) A.box_const[(long)box * kMaxQ + tid] = 0.0;
         return;
     }
-    __syncthreads();  // reference values and weights written (form 1)
+    // ghost references: x1 ghosts of every line, x2 ghosts of every column
+    for (long t = tid; t < (long)lines * 18; t += nth) {
+        const int line = (int)(t / 18), side = (int)((t / 9) % 2), layer = (int)((t / 3) % 3), c = (int)(t % 3);
+        const int i0 = (side == 0) ? layer - 3 : N + layer;
+        S64.gx[t] = ref_ghost(A, P, i0, line, c);
+    }
+    if (D == 2) {
+        for (long t = tid; t < (long)N * 18; t += nth) {
+            const int col = (int)(t / 18), side = (int)((t / 9) % 2), layer = (int)((t / 3) % 3), c = (int)(t % 3);
+            const int i1 = (side == 0) ? layer - 3 : N + layer;
+            S64.gy[t] = ref_ghost(A, P, col, i1, c);
+        }
+    }
+    __syncthreads();  // reference values, scratch and weights written (form 1)
     // H0 = H(r) in FP64 and the time-independent part of the average:
     //   field: sum_j w_j H0_j; flux: sum_f w_f a'_f G_f(r); torque: 0 (accumulated whole)
     double acc[kMaxQ] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -288,18 +333,18 @@ __global__ void __launch_bounds__(256) k_prologue(PrologueArgs A) {
             for (int ax = 0; ax < D; ++ax) {
                 const int s0 = (ax == 0), s1 = (ax == 1);
                 if (P.order == 2) {
-                    h += ref_flux(A, P, tab, L, ax, i0, i1, c) -
-                         ref_flux(A, P, tab, L, ax, i0 - s0, i1 - s1, c);
+                    h += ref_flux(P, tab, L, S64, ax, i0, i1, c) -
+                         ref_flux(P, tab, L, S64, ax, i0 - s0, i1 - s1, c);
                 } else {
-                    const double f0 = ref_flux(A, P, tab, L, ax, i0, i1, c);
-                    const double fm1 = ref_flux(A, P, tab, L, ax, i0 - s0, i1 - s1, c);
-                    const double fp1 = ref_flux(A, P, tab, L, ax, i0 + s0, i1 + s1, c);
-                    const double fm2 = ref_flux(A, P, tab, L, ax, i0 - 2 * s0, i1 - 2 * s1, c);
+                    const double f0 = ref_flux(P, tab, L, S64, ax, i0, i1, c);
+                    const double fm1 = ref_flux(P, tab, L, S64, ax, i0 - s0, i1 - s1, c);
+                    const double fp1 = ref_flux(P, tab, L, S64, ax, i0 + s0, i1 + s1, c);
+                    const double fm2 = ref_flux(P, tab, L, S64, ax, i0 - 2 * s0, i1 - 2 * s1, c);
                     h += 27.0 * (f0 - fm1) - (fp1 - fm2);
                 }
                 if (P.quantity == LLHMM_Q_FLUX) {
                     const double wf = (ax == 0) ? w[N + i0] * wy : w[i0] * wfy;
-                    acc[3 * ax + c] += wf * ref_flux(A, P, tab, L, ax, i0, i1, c);
+                    acc[3 * ax + c] += wf * ref_flux(P, tab, L, S64, ax, i0, i1, c);
                 }
             }
             tab[L.H0 + c * cells + p] = (T)h;

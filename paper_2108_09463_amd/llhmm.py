@@ -14,6 +14,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libllhmm.so")
 GHOST = 3
+TIMING_SLOTS = 64          # LLHMM_TIMING_SLOTS
 MAX_TERMS = 8
 
 OK, E_INVALID, E_NOMEM, E_BUDGET, E_UNSTABLE, E_HIP, E_NOTSUP = 0, -1, -2, -3, -4, -5, -6
@@ -72,6 +73,10 @@ _SYMBOLS = {
                                           ctypes.POINTER(ctypes.c_void_p)]),
     "llhmm_batch_destroy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "llhmm_batch_cell_steps": (ctypes.c_int64, [ctypes.c_void_p]),
+    "llhmm_batch_set_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "llhmm_batch_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32,
+                                          ctypes.POINTER(ctypes.c_float),
+                                          ctypes.POINTER(ctypes.c_float)]),
     "llhmm_micro_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                          ctypes.POINTER(Macro), ctypes.c_void_p, ctypes.c_void_p,
                                          ctypes.c_void_p, ctypes.c_void_p]),
@@ -226,6 +231,16 @@ class Batch:
 
     def cell_steps(self):
         return int(lib().llhmm_batch_cell_steps(self.h))
+
+    def set_timing(self, enable=True):
+        _check(lib().llhmm_batch_set_timing(self.h, 1 if enable else 0))
+
+    def timing(self, back=0):
+        """(set-up ms, time-stepping ms) of the timed call `back` calls before the
+        last one (waits for it)."""
+        s, t = ctypes.c_float(), ctypes.c_float()
+        _check(lib().llhmm_batch_timing(self.h, back, ctypes.byref(s), ctypes.byref(t)))
+        return float(s.value), float(t.value)
 
     def close(self):
         if self.h:
