@@ -25,6 +25,7 @@ SOURCES = [
     "llhmm_tiles_f64_2d.hip",
     "llhmm_tiles_f32_1d.hip",
     "llhmm_tiles_f64_1d.hip",
+    "llhmm_tiles_band.hip",
 ]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,

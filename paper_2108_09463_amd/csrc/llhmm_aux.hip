@@ -20,13 +20,13 @@ __global__ void __launch_bounds__(256) k_upscale(const double *partials, const i
     int bad = 0;
     for (int q = 0; q < P.nq; ++q) {
         double s = 0.0;
-        for (int w = 0; w < P.nwaves; ++w) s += partials[((long)b * kMaxWaves + w) * kMaxQ + q];
+        for (int w = 0; w < P.nwaves; ++w) s += partials[(P.part_offset + w) * kMaxQ + q];
         // form 1: add the time-independent average of the reference part, times sum_n w^n
         s = (s + P.wsum * box_const[(long)b * kMaxQ + q]) * P.out_scale;
         if (!__builtin_isfinite(s)) bad = 1;
         if (H) H[(long)b * ld + q] = s;
     }
-    for (int w = 0; w < P.nwaves; ++w) bad |= wave_status[(long)b * kMaxWaves + w];
+    for (int w = 0; w < P.nwaves; ++w) bad |= wave_status[P.part_offset + w];
     status[b] = bad;
 }
 

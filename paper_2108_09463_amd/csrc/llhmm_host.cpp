@@ -217,6 +217,53 @@ const std::map<TileKey, const TileInfo *> &registry() {
     return reg;
 }
 
+struct BandKey {
+    int prec, n, bc, qty;
+    bool operator<(const BandKey &o) const {
+        return std::tie(prec, n, bc, qty) < std::tie(o.prec, o.n, o.bc, o.qty);
+    }
+};
+
+const std::map<BandKey, const BandTileInfo *> &band_registry() {
+    static std::map<BandKey, const BandTileInfo *> reg = [] {
+        std::map<BandKey, const BandTileInfo *> r;
+        int cnt = 0;
+        const BandTileInfo *t = tiles_band(&cnt);
+        for (int i = 0; i < cnt; ++i) {
+            BandKey k{t[i].prec, t[i].n, t[i].bc, t[i].qty};
+            if (!r.count(k)) r[k] = &t[i];
+        }
+        return r;
+    }();
+    return reg;
+}
+
+// Strip geometry of a band box: steps per launch s, halo rows h = s * stages
+// rounded up to a multiple of the rows per lane R (so that box row 0 starts a
+// row group), at most `cap` own rows per strip (a multiple of R), and own-row
+// counts that split the box's n / R row groups as evenly as possible.
+struct BandGeom {
+    int s, h, strips;
+    std::vector<std::pair<int, int>> own;  // (first row, rows) per strip
+};
+
+bool band_geometry(const BandTileInfo &t, int n, int stages, int steps_per_launch, BandGeom &g) {
+    const int R = t.R, WR = t.R * t.NG;
+    if (n % R != 0 || WR > n) return false;
+    g.s = std::max(1, steps_per_launch);
+    g.h = ((g.s * stages + R - 1) / R) * R;
+    const int cap = ((WR - 2 * g.h) / R) * R;
+    if (cap < R) return false;
+    const int groups = n / R, per = cap / R;
+    g.strips = (groups + per - 1) / per;
+    g.own.clear();
+    for (int t2 = 0; t2 < g.strips; ++t2) {
+        const int a = (int)((int64_t)t2 * groups / g.strips), b = (int)((int64_t)(t2 + 1) * groups / g.strips);
+        g.own.emplace_back(a * R, (b - a) * R);
+    }
+    return true;
+}
+
 template <typename T>
 hipError_t dev_upload(T **dst, const T *src, size_t count) {
     *dst = nullptr;
@@ -237,13 +284,23 @@ struct ClassLaunch {
     int first, count, nblocks;  // range in the concatenated box-id list
 };
 
+struct BandClass {
+    const BandTileInfo *tile;
+    int s, h;                     // steps per launch, halo rows
+    int first, count;             // range in the concatenated job list
+    std::vector<int> active;      // jobs still running in launch p (a prefix: longest boxes first)
+};
+
 struct llhmm_batch {
     int nboxes, prec, dim_max, nmax;
     int64_t cell_steps;
     bool any_explicit, any_macro, any_sampled;
     std::vector<BoxPlan> plans_h;
     std::vector<ClassLaunch> classes;
+    std::vector<BandClass> bands;
     BoxPlan *plans = nullptr;
+    BandJob *jobs = nullptr;
+    void *state[2] = {nullptr, nullptr};  // band boxes' state, ping-pong between launches
     int32_t *box_ids = nullptr;
     CoefDev *coefs = nullptr;
     void *tabs = nullptr;
@@ -304,7 +361,8 @@ llhmm_status llhmm_kernel_coeffs(const llhmm_kernel *K, double *c_space, double 
 static void batch_free(llhmm_batch *b) {
     if (!b) return;
     void *ptrs[] = {b->plans, b->box_ids, b->coefs, b->tabs, b->wts, b->wt, b->partials,
-                    b->wave_status, b->status, b->box_const, b->scratch64};
+                    b->wave_status, b->status, b->box_const, b->scratch64, b->jobs,
+                    b->state[0], b->state[1]};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (auto &slot : b->ev)
@@ -342,9 +400,12 @@ llhmm_status llhmm_batch_create(llhmm_ctx *ctx, const llhmm_box *boxes, int32_t 
     b->kq = K->q_x;
 
     const auto &reg = registry();
+    const auto &bregistry = band_registry();
     const size_t tsize = (precision == LLHMM_FP32) ? sizeof(float) : sizeof(double);
     b->plans_h.resize(nboxes);
     std::vector<const TileInfo *> tile_of(nboxes);
+    std::vector<const BandTileInfo *> band_of(nboxes, nullptr);
+    std::vector<BandGeom> geom_of(nboxes);
     int dim_max = 1, nmax = 0;
     for (int i = 0; i < nboxes; ++i) {
         dim_max = std::max(dim_max, boxes[i].dim);
@@ -352,7 +413,7 @@ llhmm_status llhmm_batch_create(llhmm_ctx *ctx, const llhmm_box *boxes, int32_t 
     }
     b->dim_max = dim_max;
     b->nmax = nmax;
-    int64_t tab_off = 0, w_off = 0, s64_off = 0;
+    int64_t tab_off = 0, w_off = 0, s64_off = 0, part_off = 0, state_off = 0;
     std::map<int, int64_t> wt_off_of_M;
     std::vector<double> wt_h;
     int64_t cell_steps = 0;
@@ -368,14 +429,24 @@ llhmm_status llhmm_batch_create(llhmm_ctx *ctx, const llhmm_box *boxes, int32_t 
             return st;
         }
         auto it = reg.find(TileKey{precision, bx.dim, bx.n, bx.order, bx.bc, bx.quantity});
-        if (it == reg.end()) {
+        const BandTileInfo *bt = nullptr;
+        BandGeom bg;
+        if (it == reg.end() && bx.dim == 2 && bx.order == 2) {
+            auto bit = bregistry.find(BandKey{precision, bx.n, bx.bc, bx.quantity});
+            const int stages = (pl.integ == LLHMM_RK4P) ? 4 : 2;
+            if (bit != bregistry.end() && band_geometry(*bit->second, bx.n, stages, 4 / stages, bg))
+                bt = bit->second;
+        }
+        if (it == reg.end() && !bt) {
             delete b;
             return fail(LLHMM_E_NOTSUP,
                         "box %d: no kernel for precision %s, dim %d, n %d, order %d, bc %d, quantity %d",
                         i, precision == LLHMM_FP32 ? "fp32" : "fp64", bx.dim, bx.n, bx.order, bx.bc,
                         bx.quantity);
         }
-        tile_of[i] = it->second;
+        tile_of[i] = bt ? nullptr : it->second;
+        band_of[i] = bt;
+        if (bt) geom_of[i] = bg;
         BoxPlan &P = b->plans_h[i];
         memset(&P, 0, sizeof P);
         P.dim = bx.dim;
@@ -391,9 +462,21 @@ llhmm_status llhmm_batch_create(llhmm_ctx *ctx, const llhmm_box *boxes, int32_t 
         P.mi1 = bx.macro_index[1];
         P.nq = (bx.quantity == LLHMM_Q_FLUX) ? 3 * bx.dim : 3;
         P.coef_sampled = coefs[bx.coef_index].sampled ? 1 : 0;
-        P.nwaves = (bx.dim == 2) ? it->second->threads / 64 : 1;
+        if (band_of[i]) {
+            P.band = 1;
+            P.strips = geom_of[i].strips;
+            P.nwaves = geom_of[i].strips * (band_of[i]->threads / 64);
+        } else {
+            P.nwaves = (bx.dim == 2) ? it->second->threads / 64 : 1;
+        }
+        P.part_offset = part_off;
+        part_off += P.nwaves;
+        if (band_of[i]) {
+            P.state_offset = state_off;
+            state_off += 3 * (int64_t)bx.n * bx.n;
+        }
         P.prec = precision;
-        P.form = (precision == LLHMM_FP32) ? 1 : 0;
+        P.form = (precision == LLHMM_FP32 || P.band) ? 1 : 0;
         P.dt = pl.dt;
         P.alpha = bx.alpha;
         P.dx = 2.0 * bx.mu_box / bx.n;
@@ -435,6 +518,7 @@ llhmm_status llhmm_batch_create(llhmm_ctx *ctx, const llhmm_box *boxes, int32_t 
     std::map<std::tuple<const TileInfo *, int, int>, std::vector<int>> groups;
     for (int i = 0; i < nboxes; ++i) {
         const TileInfo *t = tile_of[i];
+        if (!t) continue;  // band box
         const int key_m = (t->dim == 1) ? b->plans_h[i].M : 0;
         const int key_s = (t->dim == 1) ? b->plans_h[i].stages : 0;
         groups[std::make_tuple(t, key_m, key_s)].push_back(i);
@@ -458,6 +542,36 @@ llhmm_status llhmm_batch_create(llhmm_ctx *ctx, const llhmm_box *boxes, int32_t 
         b->classes.push_back(cl);
     }
 
+    // band boxes: classes by (tile, steps per launch, halo), jobs of the longest boxes first
+    std::map<std::tuple<const BandTileInfo *, int, int>, std::vector<int>> bgroups;
+    for (int i = 0; i < nboxes; ++i)
+        if (band_of[i]) bgroups[std::make_tuple(band_of[i], geom_of[i].s, geom_of[i].h)].push_back(i);
+    std::vector<BandJob> jobs_h;
+    for (auto &kv : bgroups) {
+        auto &v = kv.second;
+        std::stable_sort(v.begin(), v.end(), [&](int a, int c) { return b->plans_h[a].M > b->plans_h[c].M; });
+        BandClass bc;
+        bc.tile = std::get<0>(kv.first);
+        bc.s = std::get<1>(kv.first);
+        bc.h = std::get<2>(kv.first);
+        bc.first = (int)jobs_h.size();
+        std::vector<int> jobM;
+        for (int i : v) {
+            const BandGeom &g = geom_of[i];
+            for (int t = 0; t < g.strips; ++t) {
+                jobs_h.push_back(BandJob{i, t, g.own[t].first, g.own[t].second});
+                jobM.push_back(b->plans_h[i].M);
+            }
+        }
+        bc.count = (int)jobs_h.size() - bc.first;
+        const int launches = (jobM[0] + bc.s - 1) / bc.s;
+        for (int p = 0, cnt = bc.count; p < launches; ++p) {
+            while (cnt > 0 && jobM[cnt - 1] <= p * bc.s) --cnt;
+            bc.active.push_back(cnt);
+        }
+        b->bands.push_back(std::move(bc));
+    }
+
     hipError_t e = hipSuccess;
     std::vector<CoefDev> cdev(ncoefs);
     memcpy(cdev.data(), coefs, sizeof(CoefDev) * ncoefs);
@@ -467,10 +581,10 @@ llhmm_status llhmm_batch_create(llhmm_ctx *ctx, const llhmm_box *boxes, int32_t 
     if (e == hipSuccess) e = dev_upload(&b->wt, wt_h.data(), wt_h.size());
     if (e == hipSuccess) e = hipMalloc(&b->tabs, tsize * std::max<int64_t>(tab_off, 1));
     if (e == hipSuccess) e = hipMalloc((void **)&b->wts, sizeof(double) * std::max<int64_t>(w_off, 1));
-    if (e == hipSuccess)
-        e = hipMalloc((void **)&b->partials, sizeof(double) * (size_t)nboxes * kMaxWaves * kMaxQ);
-    if (e == hipSuccess)
-        e = hipMalloc((void **)&b->wave_status, sizeof(int32_t) * (size_t)nboxes * kMaxWaves);
+    if (e == hipSuccess) e = hipMalloc((void **)&b->partials, sizeof(double) * (size_t)part_off * kMaxQ);
+    if (e == hipSuccess) e = hipMalloc((void **)&b->wave_status, sizeof(int32_t) * (size_t)part_off);
+    if (e == hipSuccess && !jobs_h.empty()) e = dev_upload(&b->jobs, jobs_h.data(), jobs_h.size());
+    for (int k = 0; k < 2 && e == hipSuccess && state_off > 0; ++k) e = hipMalloc(&b->state[k], tsize * state_off);
     if (e == hipSuccess) e = hipMalloc((void **)&b->status, sizeof(int32_t) * (size_t)nboxes);
     if (e == hipSuccess) e = hipMalloc((void **)&b->box_const, sizeof(double) * (size_t)nboxes * kMaxQ);
     if (e == hipSuccess) e = hipMalloc((void **)&b->scratch64, sizeof(double) * std::max<int64_t>(s64_off, 1));
@@ -552,6 +666,34 @@ static llhmm_status run_batch(llhmm_ctx *ctx, llhmm_batch *b, const double *m_in
         a.wave_status = b->wave_status;
         a.out_field = field_dev;
         HIP_TRY(cl.tile->launch(a, cl.nblocks, stream));
+    }
+    for (const BandClass &bc : b->bands) {
+        BandArgs a{};
+        a.plans = b->plans;
+        a.jobs = b->jobs + bc.first;
+        a.mode = mode;
+        a.h = bc.h;
+        a.tabs = b->tabs;
+        a.wts = b->wts;
+        a.wt = b->wt;
+        a.partials = b->partials;
+        a.wave_status = b->wave_status;
+        a.out_field = field_dev;
+        if (mode == 1) {
+            a.njobs = bc.count;
+            a.step0 = 0;
+            a.steps = 0;
+            HIP_TRY(bc.tile->launch(a, bc.count, stream));
+            continue;
+        }
+        for (size_t p = 0; p < bc.active.size(); ++p) {
+            a.njobs = bc.active[p];
+            a.step0 = (int)p * bc.s;
+            a.steps = bc.s;
+            a.state_in = b->state[p & 1];
+            a.state_out = b->state[(p + 1) & 1];
+            HIP_TRY(bc.tile->launch(a, a.njobs, stream));
+        }
     }
     if (b->timing) {
         HIP_TRY(hipEventRecord(ev[2], stream));

@@ -8,7 +8,7 @@
 namespace llhmm {
 
 constexpr int kGhost = LLHMM_GHOST;
-constexpr int kMaxWaves = 16;  // partial-sum slots per box
+constexpr int kMaxWaves = 16;  // waves per block of the resident kernels
 constexpr int kMaxQ = 6;       // outputs per box (flux in 2-D)
 constexpr int kFaceHalo = 3;   // faces -2 .. n stored per line: n + 3 entries
 
@@ -18,6 +18,7 @@ struct BoxPlan {
     int32_t bc, quantity, init_mode, M;  // M: number of time steps
     int32_t coef_index, mi0, mi1, nq;    // macro node; nq = outputs per box
     int32_t coef_sampled, nwaves, prec, form;   // form: 0 direct, 1 reference + perturbation
+    int32_t band, strips, pad0_, pad1_;  // band: box advanced in row strips (large boxes)
     double dt, alpha, dx, mu;
     double mu_box, a_scale, out_scale, cx;
     double cy, wsum;                     // wsum = sum_n w^n (time weights)
@@ -25,6 +26,8 @@ struct BoxPlan {
     int64_t tab_offset;                  // element offset (in T) of the box's tables
     int64_t w_offset;                    // element offset (double) of the space weights
     int64_t s64_offset;                  // element offset (double) of the set-up scratch (form 1)
+    int64_t part_offset;                 // first partial-sum slot of the box (nwaves slots)
+    int64_t state_offset;                // band: element offset (T) of the box's state [3][n][n]
 };
 
 // Per-box table layout (elements of T, starting at tab_offset), n = points per
@@ -116,10 +119,48 @@ struct MicroArgs {
     const void *tabs;          // per-box tables (T)
     const double *wts;         // space weights
     const double *wt;          // time-weight table
-    double *partials;          // [nboxes][kMaxWaves][kMaxQ]
-    int32_t *wave_status;      // [nboxes][kMaxWaves]
+    double *partials;          // [slots][kMaxQ], box slots from part_offset
+    int32_t *wave_status;      // [slots]
     double *out_field;         // m_final or H (nullable)
 };
+
+// Large 2-D boxes are advanced in full-width row strips ("band" mode): a block
+// holds a window of rows = its strip's own rows plus h halo rows on each side,
+// runs `steps` time steps on it without exchanging data with other blocks
+// (the halo rows absorb the error that enters from the window edges, one row
+// per stage), and writes back only its own rows.  Successive launches
+// ping-pong the state between two buffers.
+struct BandJob {
+    int32_t box, strip, o0, rows;  // strip owns box rows [o0, o0 + rows)
+};
+
+struct BandArgs {
+    const BoxPlan *plans;
+    const BandJob *jobs;        // one per block
+    int32_t njobs, mode;        // mode 0 solve, 1 evaluate H(m0) only
+    int32_t step0, steps;       // this launch: steps [step0, min(step0 + steps, M))
+    int32_t h, pad_;            // halo rows on each side of a strip
+    const void *tabs;           // per-box tables (T)
+    const double *wts;          // space weights
+    const double *wt;           // time-weight table
+    double *partials;           // [slots][kMaxQ]
+    int32_t *wave_status;       // [slots]
+    const void *state_in;       // T, per box at state_offset (unused when step0 == 0)
+    void *state_out;            // T
+    double *out_field;          // m_final or H (nullable)
+};
+
+using BandLaunchFn = hipError_t (*)(const BandArgs &, int nblocks, hipStream_t);
+
+struct BandTileInfo {
+    int n, bc, prec, qty;       // class it serves (2-D, second order)
+    int L, K, R, NG, NBUF;      // layout: window of R * NG rows
+    int threads;
+    BandLaunchFn launch;
+    const char *name;
+};
+
+const BandTileInfo *tiles_band(int *count);
 
 using LaunchFn = hipError_t (*)(const MicroArgs &, int nblocks, hipStream_t);
 

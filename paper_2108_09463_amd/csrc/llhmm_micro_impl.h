@@ -65,7 +65,8 @@ __device__ __forceinline__ double rsqrt_t(double x) { return 1.0 / __builtin_sqr
 
 enum { AVG_NONE = 0, AVG_FIELD = 1, AVG_TORQUE = 2, AVG_FLUX = 3, AVG_EVAL = 4 };
 
-template <typename T, int D, int ORD, int BC, int QTY, int L, int K, int R, int NG, int NBUF>
+template <typename T, int D, int ORD, int BC, int QTY, int L, int K, int R, int NG, int NBUF,
+          bool BAND = false>
 struct MicroLane {
     static constexpr int N = K * L;
     static constexpr int YH = (ORD == 2) ? 1 : 3;  // neighbour reach in points
@@ -85,19 +86,26 @@ struct MicroLane {
     static constexpr int ZOFF = 4 * N * GF * 8;
     // FP64: face coefficients are read from LDS (x1 faces [lines][LF], 2-D x2
     // faces [N][LF] after them) instead of being held in registers
-    static constexpr bool AXL = (sizeof(T) == 8);
+    static constexpr bool AXL = !BAND && sizeof(T) == 8;
     static constexpr int LF = N + kFaceHalo;
     static constexpr int AX_LDS = AXL ? ((D == 2) ? 2 * N * LF : NG * LF) : 1;
     static constexpr int WLDS = (D == 2) ? 2 * N : NG * 2 * N;  // space weights in LDS
     // form 1 (FP32): m = r + u with the FP32 reference r = fl(m_init) and H(r)
     // precomputed in FP64; the state u starts at the rounding residual m_init - r
     // and stays periodic (or zero) on the ghosts, so no boundary offsets are needed.
-    static constexpr int FORM = (sizeof(T) == 4) ? 1 : 0;
+    // Band mode (a window of R * NG rows of a larger 2-D box) always uses form 1.
+    static constexpr int FORM = (BAND || sizeof(T) == 4) ? 1 : 0;
     static constexpr int CELLS = (D == 1) ? N : N * N;
-    static constexpr int REF_LDS = FORM ? ((D == 2) ? 7 * CELLS : NG * 7 * N) : 1;
+    static constexpr int WR = R * NG;                       // rows held by the block
+    static constexpr int CELLS_W = BAND ? WR * N : CELLS;    // points held by the block
+    // FP64 band: the reference tables are read from global memory (box indexing)
+    static constexpr bool REFG = BAND && sizeof(T) == 8;
+    static constexpr int RSTRIDE = REFG ? CELLS : CELLS_W;  // stride between reference planes
+    static constexpr int REF_LDS = (FORM && !REFG) ? ((D == 2) ? 7 * CELLS_W : NG * 7 * N) : 1;
     static_assert(K >= YH, "lane tile narrower than the stencil reach");
     static_assert(D == 1 || R >= YH, "row band thinner than the stencil reach");
-    static_assert(D == 1 || R * NG == N, "row groups must tile the box");
+    static_assert(D == 1 || BAND || R * NG == N, "row groups must tile the box");
+    static_assert(!BAND || (D == 2 && ORD == 2), "band mode: 2-D, second order");
     static_assert(D == 2 || R == 1, "1-D boxes are one row");
     static_assert(L == 16 || L == 64, "row group is a DPP row or a wavefront");
 
@@ -114,17 +122,31 @@ struct MicroLane {
     T *s_halo, *s_zero, *s_tau;
     const T *s_ref;    // form 1: this box's r [3][C], |r|^2-1 [C], H(r) [3][C] (LDS)
     const double *wl;  // this box's point weights [N] then east-face weights [N] (LDS)
+    // band mode: box row of each own row, whether the block owns it, and the
+    // x2 point / face weights of the window rows (zero on rows it does not own)
+    int brow[BAND ? R : 1];
+    bool own[BAND ? R : 1];
+    const double *s_wyl;
 
     template <int CTRL_ROT, int CTRL_SH>
     __device__ __forceinline__ static T nb(T v) {
         return dpp_mov<(BC == LLHMM_BC_PERIODIC_PERT) ? CTRL_ROT : CTRL_SH>(v);
     }
     __device__ __forceinline__ double wv(int i) const { return wl[i]; }
-    __device__ __forceinline__ double wy(int r) const { return (D == 2) ? wv(r0 + r) : 1.0; }
+    __device__ __forceinline__ double wy(int r) const {
+        return BAND ? s_wyl[r0 + r] : ((D == 2) ? wv(r0 + r) : 1.0);
+    }
+    __device__ __forceinline__ double wyf(int r) const { return BAND ? s_wyl[WR + r0 + r] : wv(N + r0 + r); }
+    __device__ __forceinline__ bool owned(int r) const { return BAND ? own[BAND ? r : 0] : true; }
+    __device__ __forceinline__ int out_row(int r) const { return BAND ? brow[BAND ? r : 0] : r0 + r; }
+    // index of own point (r, k) in the reference tables
+    __device__ __forceinline__ int cell_of(int r, int k) const {
+        return BAND ? ((REFG ? brow[BAND ? r : 0] : r0 + r) * N + c0 + k) : ((D == 1 ? 0 : (r0 + r) * N) + c0 + k);
+    }
     __device__ __forceinline__ T tau_lds(int off) const {
         return FORM ? (T)0 : s_tau[off];
     }
-    __device__ __forceinline__ T ref(int q, int cell) const { return s_ref[q * CELLS + cell]; }
+    __device__ __forceinline__ T ref(int q, int cell) const { return s_ref[q * RSTRIDE + cell]; }
     // face coefficient of x1 face lf of own row r / x2 face lr of own column k
     __device__ __forceinline__ T axv(int r, int lf) const {
         return AXL ? s_axl[(r0 + r) * LF + c0 - FW + lf + 2] : ax[AXL ? 0 : r][AXL ? 0 : lf];
@@ -256,15 +278,17 @@ struct MicroLane {
                     }
                 }
                 if (AVG == AVG_EVAL) {
-                    const int cell = (D == 1 ? 0 : (r0 + r) * N) + c0 + k;
+                    const int cell = cell_of(r, k);
+                    if (owned(r)) {
 #pragma unroll
-                    for (int c = 0; c < 3; ++c)
-                        eval_out[c * eval_cells + (long)(r0 + r) * N + c0 + k] =
-                            (double)H[c] + (FORM ? (double)ref(4 + c, cell) : 0.0);
+                        for (int c = 0; c < 3; ++c)
+                            eval_out[c * eval_cells + (long)out_row(r) * N + c0 + k] =
+                                (double)H[c] + (FORM ? (double)ref(4 + c, cell) : 0.0);
+                    }
                     continue;
                 }
                 // ---- right-hand side f = -y x H - alpha y x (y x H), average, update
-                const int cell = (D == 1 ? 0 : (r0 + r) * N) + c0 + k;
+                const int cell = cell_of(r, k);
                 // full state and field at this point: form 0 y, H; form 1 r + v, H(r) + D(v)
                 T m0 = y[r][k][0], m1 = y[r][k][1], m2 = y[r][k][2];
                 T h0 = H[0], h1 = H[1], h2 = H[2];
@@ -283,18 +307,18 @@ struct MicroLane {
                 const T ey = m2 * cx - m0 * cz;
                 const T ez = m0 * cy - m1 * cx;
                 const T f[3] = {-fma_t(alpha, ex, cx), -fma_t(alpha, ey, cy), -fma_t(alpha, ez, cz)};
-                if (AVG == AVG_FIELD || AVG == AVG_TORQUE) {
+                if ((AVG == AVG_FIELD || AVG == AVG_TORQUE) && owned(r)) {
                     // form 1 field: only D(u); the constant sum_j w_j H(r)_j is added at upscale
                     const double w = wv(c0 + k) * wy(r);
                     sq[0] = fma(w, (double)(AVG == AVG_FIELD ? H[0] : cx), sq[0]);
                     sq[1] = fma(w, (double)(AVG == AVG_FIELD ? H[1] : cy), sq[1]);
                     sq[2] = fma(w, (double)(AVG == AVG_FIELD ? H[2] : cz), sq[2]);
-                } else if (AVG == AVG_FLUX) {
+                } else if (AVG == AVG_FLUX && owned(r)) {
                     const double w1 = wv(N + c0 + k) * wy(r);
 #pragma unroll
                     for (int c = 0; c < 3; ++c) sq[c] = fma(w1, (double)Fx_east[c], sq[c]);
                     if (D == 2) {
-                        const double w2 = wv(c0 + k) * wv(N + r0 + r);
+                        const double w2 = wv(c0 + k) * wyf(r);
 #pragma unroll
                         for (int c = 0; c < 3; ++c) sq[(D == 2 ? 3 : 0) + c] = fma(w2, (double)Fy_north[c], sq[(D == 2 ? 3 : 0) + c]);
                     }
@@ -537,14 +561,200 @@ __global__ void __launch_bounds__(L * NG, MINW) k_micro(MicroArgs A) {
     const bool writer = (D == 1) ? (j == 0) : (lane == 0);
     if (writer && active) {
         const int wslot = (D == 1) ? 0 : wave;
-        double *dst = A.partials + ((long)box * kMaxWaves + wslot) * kMaxQ;
+        double *dst = A.partials + (P.part_offset + wslot) * kMaxQ;
         int bad = 0;
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
             dst[q] = S.acc64[q];
             if (!__builtin_isfinite(S.acc64[q])) bad = 1;
         }
-        A.wave_status[(long)box * kMaxWaves + wslot] = bad;
+        A.wave_status[P.part_offset + wslot] = bad;
+    }
+}
+
+
+// Band mode: one block advances a window of R * NG full-width rows of a large
+// 2-D box (its strip's own rows plus A.h halo rows on each side) through up to
+// A.steps time steps, then writes back the rows it owns.  The window does not
+// exchange data with other blocks during the launch: its outermost rows see
+// zeros beyond the window, and the error this causes moves inwards by one row
+// per stage, so it stays inside the halo when A.h >= steps * stages.  Rows are
+// periodic images of box rows (periodic m - m_init) or ghost rows held at
+// u = 0 (Dirichlet).  The host aligns windows so that box row 0 starts a row
+// group; a group's rows are then consecutive box rows and each group loads the
+// x2 face coefficients of its own rows, which keeps the faces on either side
+// of the box's periodic seam distinct.
+template <typename T, int QTY, int BC, int L, int K, int R, int NG, int NBUF, int MINW>
+__global__ void __launch_bounds__(L * NG, MINW) k_band(BandArgs A) {
+    constexpr int D = 2, ORD = 2;
+    using Lane = MicroLane<T, D, ORD, BC, QTY, L, K, R, NG, NBUF, true>;
+    constexpr int N = Lane::N, NF = Lane::NF, NFR = Lane::NFR, FW = Lane::FW, NQ = Lane::NQ;
+    constexpr int YH = Lane::YH, WR = Lane::WR;
+    constexpr long C = (long)N * N;
+    constexpr int LF = N + kFaceHalo;
+    __shared__ T s_halo[NBUF * Lane::HALO];
+    __shared__ T s_zero[YH * 3 * N];
+    __shared__ T s_refl[Lane::REF_LDS];
+    __shared__ double s_w[2 * N];
+    __shared__ double s_wyl[2 * WR];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int j = (L == 16) ? (lane & 15) : lane;
+    const BandJob job = A.jobs[blockIdx.x];
+    const BoxPlan &P = A.plans[job.box];
+    const T *tab = (const T *)A.tabs + P.tab_offset;
+    const TabLayout TL = tab_layout(D, N, 1);
+    const int h = A.h;
+    const int w0 = job.o0 - h;  // box row of window row 0, before wrapping
+    auto wrap = [](int br) { return ((br % N) + N) % N; };
+    // Dirichlet: window rows outside the box are ghost rows (u = 0), whole groups at a time
+    auto dead = [&](int gg) {
+        const int br = w0 + gg * R;
+        return BC == LLHMM_BC_DIRICHLET && (br < 0 || br >= N);
+    };
+
+    Lane S;
+    S.g = (L == 16) ? (wave * 4 + (lane >> 4)) : wave;
+    S.c0 = j * K;
+    S.r0 = S.g * R;
+    const int g = S.g, c0 = S.c0, r0 = S.r0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int wr = r0 + r;
+        S.brow[r] = wrap(w0 + wr);
+        S.own[r] = (wr >= h) && (wr < h + job.rows);
+    }
+    const bool gdead = dead(g);
+
+    // space weights; window-row weights (zero on rows this block does not own)
+    const double *wsrc = A.wts + P.w_offset;
+    for (int i = tid; i < 2 * N; i += L * NG) s_w[i] = wsrc[i];
+    for (int i = tid; i < WR; i += L * NG) {
+        const bool own = (i >= h) && (i < h + job.rows);
+        const int br = wrap(w0 + i);
+        s_wyl[i] = own ? wsrc[br] : 0.0;
+        s_wyl[WR + i] = own ? wsrc[N + br] : 0.0;
+    }
+    S.wl = s_w;
+    S.s_wyl = s_wyl;
+    // reference r, |r|^2 - 1 and H(r): window copy in LDS (FP32) or the box tables (FP64)
+    if (Lane::REFG) {
+        S.s_ref = tab + TL.ref;
+    } else {
+        for (int i = tid; i < 7 * WR * N; i += L * NG) {
+            const int q = i / (WR * N), rem = i % (WR * N);
+            s_refl[i] = tab[TL.ref + q * C + (long)wrap(w0 + rem / N) * N + rem % N];
+        }
+        S.s_ref = s_refl;
+    }
+    for (int i = tid; i < YH * 3 * N; i += L * NG) s_zero[i] = (T)0;
+    // face coefficients of the own rows (x1) and of the own column segment (x2)
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int lf = 0; lf < NF; ++lf) S.ax[r][lf] = tab[TL.ax + (long)S.brow[r] * LF + (c0 - FW + lf) + 2];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int lr = 0; lr < NFR; ++lr) S.ay[k][lr] = tab[TL.ay + (long)(c0 + k) * LF + (S.brow[0] - FW + lr) + 2];
+    // state: u0 from the tables on the first launch, else the previous launch's output
+    const bool first = (A.step0 == 0);
+    const T *src = first ? tab + TL.m0 : (const T *)A.state_in + P.state_offset;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                S.m[r][k][c] = gdead ? (T)0 : src[c * C + (long)S.brow[r] * N + c0 + k];
+                S.y[r][k][c] = S.m[r][k][c];
+                S.acc[r][k][c] = (T)0;
+            }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) S.tauF[0][c] = S.tauL[0][c] = (T)0;
+    S.tFb = S.tFs = S.tLb = S.tLs = S.tSb = S.tSs = S.tNb = S.tNs = 0;
+    __syncthreads();
+    S.gs = (g > 0) ? g - 1 : 0;
+    S.gn = (g < NG - 1) ? g + 1 : 0;
+    S.zero_s = (g == 0) || dead(g - 1);
+    S.zero_n = (g == NG - 1) || dead(g + 1);
+    S.s_halo = s_halo;
+    S.s_zero = s_zero;
+    S.s_tau = nullptr;
+    S.alpha = (T)P.alpha;
+    S.dt = (T)P.dt;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) S.acc64[q] = 0.0;
+
+    if (A.mode == 1) {  // evaluate H(m0) on the own rows only
+        S.template stage<AVG_EVAL, true, false>((T)0, (T)0, 0.0, 0, A.out_field + P.mfinal_offset, C);
+        return;
+    }
+    const int s_end = min(A.step0 + A.steps, P.M);
+    const bool last = (s_end >= P.M);
+    const bool rk4 = (P.stages == 4);
+    const T b1 = rk4 ? (T)(1.0 / 6.0) : (T)0.5;
+    const T c2dt = rk4 ? (T)(0.5 * P.dt) : (T)P.dt;
+    const T third = (T)(1.0 / 3.0);
+    const T half_dt = (T)(0.5 * P.dt);
+    const double *wtab = A.wt + P.wt_offset;
+    int ts = 0;
+    for (int n = A.step0; n < s_end; ++n) {
+        const double wn = wtab[n];
+        asm volatile("" ::: "memory");
+        S.template stage<Lane::AVG, true, false>(b1, c2dt, wn, ts, nullptr, 0);
+        ++ts;
+        const int nmid = rk4 ? 2 : 0;
+        for (int sm = 0; sm < nmid; ++sm) {
+            S.template stage<AVG_NONE, false, false>(third, sm == 0 ? half_dt : S.dt, 0.0, ts++, nullptr, 0);
+        }
+        S.template stage<AVG_NONE, false, true>(rk4 ? (T)(1.0 / 6.0) : (T)0.5, (T)0, 0.0, ts++, nullptr, 0);
+    }
+
+    // ---------------- own rows out: the state for the next launch, or m = r + u at the end
+    if (!last) {
+        T *dst = (T *)A.state_out + P.state_offset;
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (S.own[r] && !gdead)
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) dst[c * C + (long)S.brow[r] * N + c0 + k] = S.m[r][k][c];
+    } else if (A.out_field) {
+        double *dst = A.out_field + P.mfinal_offset;
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (S.own[r] && !gdead)
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const long cell = (long)S.brow[r] * N + c0 + k;
+                        dst[c * C + cell] = (double)S.m[r][k][c] + (double)tab[TL.ref + c * C + cell];
+                    }
+    }
+    // per-wave partial sums, accumulated over launches in a fixed order
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        double v = S.acc64[q];
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
+        S.acc64[q] = v;
+    }
+    if (lane == 0) {
+        const long slot = P.part_offset + (long)job.strip * (L * NG / 64) + wave;
+        double *dst = A.partials + slot * kMaxQ;
+        int bad = 0;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const double v = first ? S.acc64[q] : dst[q] + S.acc64[q];
+            dst[q] = v;
+            if (!__builtin_isfinite(v)) bad = 1;
+        }
+        A.wave_status[slot] = first ? bad : (A.wave_status[slot] | bad);
     }
 }
 

@@ -23,6 +23,10 @@ static const TileInfo kTiles[] = {
     LLHMM_TILE(float, 1, 2, 2, 1, 2, 16, 3, 3, 16, 2, 2),
     LLHMM_TILE(float, 1, 2, 4, 1, 2, 16, 3, 3, 16, 1, 1),
     LLHMM_TILE(float, 1, 2, 2, 1, 0, 64, 1, 8, 8, 2, 2),
+    LLHMM_TILE(float, 1, 2, 2, 0, 1, 64, 1, 8, 8, 2, 2),
+    LLHMM_TILE(float, 1, 2, 2, 0, 2, 64, 1, 8, 8, 2, 2),
+    LLHMM_TILE(float, 1, 2, 2, 1, 1, 64, 1, 8, 8, 2, 2),
+    LLHMM_TILE(float, 1, 2, 2, 1, 2, 64, 1, 8, 8, 2, 2),
 };
 const TileInfo *tiles_f32_2d(int *count) {
     *count = (int)(sizeof(kTiles) / sizeof(kTiles[0]));
