@@ -1,16 +1,18 @@
 """Benchmark of the batched HMM micro-problem solve on one MI355X.
 
-Workload (default): 1024 micro boxes of 64x64 points, one per node of a 32x32
-macro grid, eps = 1/200, mu = mu' = 3 eps, eta = eps^2, alpha = 0.1 (RK4P,
-517 steps), a = 1 + 0.5 sin(2 pi x1/eps) sin(2 pi x2/eps), Q_[4] initial data
-from a seeded Gaussian random macro field, averaged field.  One "step" is one
-llhmm_micro_batch + llhmm_upscale over the whole batch (all boxes, all time
-steps); inputs are resident in HBM before timing.
+Headline workload (default): 1024 micro boxes of 64x64 points, one per node of
+a 32x32 macro grid, eps = 1/200, mu = mu' = 3 eps, eta = eps^2, alpha = 0.1
+(RK4P, 517 steps), a = 1 + 0.5 sin(2 pi x1/eps) sin(2 pi x2/eps), Q_[4]
+initial data from a seeded Gaussian random macro field, averaged field.  One
+"step" is one llhmm_micro_batch + llhmm_upscale over the whole batch (all
+boxes, all time steps); inputs are resident in HBM before timing.
 
 Printed: one JSON line.  `value` is FP32 micro cell-steps/s (cell-step = one
 grid point advanced one full time step); the FP64 path is timed on the same
 batch and reported beside it, with p50/p99 batch latency, the roofline of the
-dominant kernel and the oracle timed on the host cores.
+time-stepping kernel (from the library's HIP events on the launch stream), the
+oracle timed on the host cores, and the 4096-box uneven FP32 batch (sizes 32
+to 128, large boxes in band mode) as a nested record.
 """
 from __future__ import annotations
 
@@ -167,14 +169,68 @@ def cpu_baseline(wl, sample, gpu_H=None):
     return out, errs
 
 
+def algorithmic_flops(boxes):
+    """Sum over boxes of F x M x n^d (algorithmic flops of one step of the whole batch)."""
+    from paper_2108_09463_amd import llhmm as L
+    M, _, integ = L.llhmm_plan(boxes)
+    tot = 0
+    for b, m, ig in zip(boxes, M, integ):
+        tot += flops_per_cell_step(b["dim"], b["order"], int(ig)) * int(m) * b["n"] ** b["dim"]
+    return float(tot)
+
+
+def measure(wl, precision, steps, warmup):
+    """Times one workload at one precision; returns rates, latencies and the
+    roofline of the time-stepping phase."""
+    import torch
+    from paper_2108_09463_amd import inputs
+    from paper_2108_09463_amd.runner import Prepared
+    prep = Prepared(wl, precision=precision)
+    cs = prep.cell_steps()
+    flops = algorithmic_flops(prep.boxes)
+    t = time_batch(prep, steps, warmup)
+    torch.cuda.synchronize()
+    H = prep.H.cpu().numpy()
+    st = prep.status.cpu().numpy()
+    del prep
+    rate = cs / (t["ms_per_step"] * 1e-3)
+    # roofline of the time-stepping phase: algorithmic flops of the batch over the
+    # event-timed duration of its time-stepping launches
+    achieved = flops / (t["kernel_ms"] * 1e-3)
+    peak = PEAK_FP32 if precision == inputs.FP32 else PEAK_FP64
+    name = "fp32" if precision == inputs.FP32 else "fp64"
+    return dict(cell_steps=cs, ms_per_step=t["ms_per_step"], rate=rate,
+                p50_ms=pct(t["lat_ms"], 50), p99_ms=pct(t["lat_ms"], 99),
+                setup_ms=t["setup_ms"], kernel_ms=t["kernel_ms"], H=H, status_ok=bool((st == 0).all()),
+                roofline=dict(bound="alu", achieved=achieved / 1e12, peak=peak / 1e12,
+                              unit="TFLOP/s", frac=achieved / peak,
+                              traffic=measured_traffic(name) if wl.name == "two_d_batch" else None,
+                              kernel="time-stepping kernels", kernel_ms=t["kernel_ms"],
+                              flops_per_cell_step=flops / cs, flops_per_launch=flops))
+
+
+WORKLOADS = {
+    "two_d_batch": ("two_d_batch: 1024 boxes of 64x64 (32x32 macro grid), eps=1/200, mu=mu'=3eps, "
+                    "eta=eps^2, alpha=0.1 RK4P (517 steps), order-2 stencil, Q4 macro init, field average"),
+    "uneven_batch": ("uneven_batch: 4096 2-D boxes, n uniform over {32,48,64,96,128}, quasi-periodic a, "
+                     "alpha ~ U[0.01,0.2] (RK4P), mu=mu'=3eps, eps=1/200, eta=eps^2, EX2 initial data, "
+                     "field average"),
+    "one_d_batch": ("one_d_batch: 16384 1-D boxes of 256 points, mu=mu'=4eps, eps=0.01, alpha=0.01 RK4P, "
+                    "eta=eps^2, seeded phases, flux average"),
+}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
-    ap.add_argument("--cpu-sample", type=int, default=512)
+    ap.add_argument("--cpu-sample", type=int, default=1024)
     ap.add_argument("--precision", choices=["both", "fp32", "fp64"], default="both")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="two_d_batch")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the uneven-batch measurement added to the default line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (PMC counter calibration)")
     args = ap.parse_args()
@@ -186,44 +242,18 @@ def main():
         copy_calibration()
         return
 
-    import torch
     from paper_2108_09463_amd import inputs
-    from paper_2108_09463_amd.runner import Prepared
 
-    wl = inputs.two_d_batch()
-    b0 = wl.boxes[0]
-    res = {}
-    gpu_H = {}
+    wl = getattr(inputs, args.workload)()
     precs = {"fp32": inputs.FP32, "fp64": inputs.FP64}
     if args.precision != "both":
         precs = {args.precision: precs[args.precision]}
-    for name, prec in precs.items():
-        prep = Prepared(wl, precision=prec)
-        cs = prep.cell_steps()
-        t = time_batch(prep, args.steps, args.warmup)
-        torch.cuda.synchronize()
-        gpu_H[name] = prep.H.cpu().numpy()
-        integ = 2 if b0["alpha"] <= 0.2 else 1
-        F = flops_per_cell_step(2, b0["order"], integ)
-        rate = cs / (t["ms_per_step"] * 1e-3)
-        # roofline of the time-stepping kernel: algorithmic flops per launch
-        # (F x cell-steps of the batch) over its own event-timed duration
-        achieved = F * cs / (t["kernel_ms"] * 1e-3)
-        peak = PEAK_FP32 if prec == inputs.FP32 else PEAK_FP64
-        res[name] = dict(cell_steps=cs, ms_per_step=t["ms_per_step"], rate=rate,
-                         p50_ms=pct(t["lat_ms"], 50), p99_ms=pct(t["lat_ms"], 99),
-                         setup_ms=t["setup_ms"], kernel_ms=t["kernel_ms"],
-                         roofline=dict(bound="alu", achieved=achieved / 1e12, peak=peak / 1e12,
-                                       unit="TFLOP/s", frac=achieved / peak,
-                                       traffic=measured_traffic(name),
-                                       kernel="k_micro (time stepping)",
-                                       kernel_ms=t["kernel_ms"], flops_per_cell_step=F,
-                                       flops_per_launch=F * cs))
-        del prep
+    res = {name: measure(wl, prec, args.steps, args.warmup) for name, prec in precs.items()}
+    gpu_H = {k: v["H"] for k, v in res.items()}
     cpu = None
     errs = {}
     if not args.no_cpu:
-        cpu, errs = cpu_baseline(wl, args.cpu_sample, gpu_H)
+        cpu, errs = cpu_baseline(wl, min(args.cpu_sample, len(wl.boxes)), gpu_H)
     head = "fp32" if "fp32" in res else "fp64"
     r = res[head]
     line = {
@@ -239,15 +269,14 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if head == "fp32" else "f64",
         "data": "synthetic",
-        "config": {"workload": "two_d_batch: 1024 boxes of 64x64 (32x32 macro grid), eps=1/200, "
-                               "mu=mu'=3eps, eta=eps^2, alpha=0.1 RK4P (517 steps), order-2 stencil, "
-                               "Q4 macro init, field average",
+        "config": {"workload": WORKLOADS[args.workload],
                    "boxes": len(wl.boxes), "cell_steps_per_step": r["cell_steps"]},
         "roofline": r["roofline"],
         "latency_ms": {"p50": r["p50_ms"], "p99": r["p99_ms"]},
         "phase_ms": {"setup": r["setup_ms"], "time_stepping": r["kernel_ms"]},
         "cpu_baseline": cpu,
         "max_rel_err_vs_oracle": errs,
+        "status_ok": r["status_ok"],
     }
     if "fp64" in res and head == "fp32":
         f = res["fp64"]
@@ -256,6 +285,15 @@ def main():
                         "phase_ms": {"setup": f["setup_ms"], "time_stepping": f["kernel_ms"]},
                         "roofline": f["roofline"]}
         line["speedup_fp32_vs_fp64"] = r["rate"] / f["rate"]
+    if args.workload == "two_d_batch" and not args.no_extra:
+        wu = inputs.uneven_batch()
+        u = measure(wu, inputs.FP32, 3, 1)
+        line["uneven_batch"] = {"workload": WORKLOADS["uneven_batch"], "dtype": "f32",
+                                "value": u["rate"], "unit": "cell-steps/s",
+                                "ms_per_step": u["ms_per_step"], "cell_steps_per_step": u["cell_steps"],
+                                "latency_ms": {"p50": u["p50_ms"], "p99": u["p99_ms"]},
+                                "phase_ms": {"setup": u["setup_ms"], "time_stepping": u["kernel_ms"]},
+                                "roofline": u["roofline"], "status_ok": u["status_ok"]}
     print(json.dumps(line), flush=True)
 
 

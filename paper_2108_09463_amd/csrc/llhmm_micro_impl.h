@@ -63,6 +63,38 @@ __device__ __forceinline__ double fma_t(double a, double b, double c) { return _
 __device__ __forceinline__ float rsqrt_t(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double rsqrt_t(double x) { return 1.0 / __builtin_sqrt(x); }
 
+
+// ----------------------------------------------------------------- table copies
+// Copies ROWS rows of N elements from global memory into LDS (row r to
+// dst + r * N) with 16-byte accesses.  All of a thread's loads are issued
+// before its first LDS store, so they are in flight together instead of each
+// paying the full memory latency.  src_row(r) is the global start of row r
+// (16-byte aligned).
+template <typename T, int N, int ROWS, int NT, typename SrcRow>
+__device__ __forceinline__ void copy_rows_to_lds(T *dst, SrcRow src_row, int tid) {
+    constexpr int V = 16 / (int)sizeof(T);
+    static_assert(N % V == 0, "rows must split into 16-byte vectors");
+    typedef T VT __attribute__((ext_vector_type(V)));
+    constexpr int RV = N / V, TOT = ROWS * RV, ITER = (TOT + NT - 1) / NT;
+    VT buf[ITER];
+#pragma unroll
+    for (int it = 0; it < ITER; ++it) {
+        const int i = it * NT + tid;
+        if (TOT % NT == 0 || i < TOT) {
+            const int r = i / RV, cv = i - r * RV;
+            buf[it] = *(const VT *)(src_row(r) + cv * V);
+        }
+    }
+#pragma unroll
+    for (int it = 0; it < ITER; ++it) {
+        const int i = it * NT + tid;
+        if (TOT % NT == 0 || i < TOT) {
+            const int r = i / RV, cv = i - r * RV;
+            *(VT *)(dst + r * N + cv * V) = buf[it];
+        }
+    }
+}
+
 enum { AVG_NONE = 0, AVG_FIELD = 1, AVG_TORQUE = 2, AVG_FLUX = 3, AVG_EVAL = 4 };
 
 template <typename T, int D, int ORD, int BC, int QTY, int L, int K, int R, int NG, int NBUF,
@@ -453,7 +485,9 @@ __global__ void __launch_bounds__(L * NG, MINW) k_micro(MicroArgs A) {
     if (FORM == 1) {
         // reference, |r|^2 - 1 and H(r) of this box into LDS (7 values per point)
         if (D == 2) {
-            for (int i = tid; i < 7 * N * N; i += L * NG) s_refl[i] = tab[TL.ref + i];
+            const T *src = tab + TL.ref;
+            copy_rows_to_lds<T, N, (D == 2) ? 7 * N : 1, L * NG>(
+                s_refl, [&](int r) { return src + (long)r * N; }, tid);
             S.s_ref = s_refl;
         } else {
             for (int i = j; i < 7 * N; i += L) s_refl[g * 7 * N + i] = tab[TL.ref + i];
@@ -643,10 +677,14 @@ __global__ void __launch_bounds__(L * NG, MINW) k_band(BandArgs A) {
     if (Lane::REFG) {
         S.s_ref = tab + TL.ref;
     } else {
-        for (int i = tid; i < 7 * WR * N; i += L * NG) {
-            const int q = i / (WR * N), rem = i % (WR * N);
-            s_refl[i] = tab[TL.ref + q * C + (long)wrap(w0 + rem / N) * N + rem % N];
-        }
+        const T *src = tab + TL.ref;
+        copy_rows_to_lds<T, N, Lane::REFG ? 1 : 7 * WR, L * NG>(
+            s_refl,
+            [&](int r) {
+                const int q = r / WR, wr = r - q * WR;
+                return src + q * C + (long)wrap(w0 + wr) * N;
+            },
+            tid);
         S.s_ref = s_refl;
     }
     for (int i = tid; i < YH * 3 * N; i += L * NG) s_zero[i] = (T)0;
