@@ -202,6 +202,40 @@ llhmm_status llhmm_micro_batch(llhmm_ctx *ctx, llhmm_batch *batch, const double 
 llhmm_status llhmm_upscale(llhmm_ctx *ctx, llhmm_batch *batch, double *H_avg_dev, int32_t ld,
                            int32_t *status_dev, int32_t check, hipStream_t stream);
 
+/* llhmm_micro_batch followed by llhmm_upscale (check = 0) as one HIP graph
+ * owned by the batch, launched on `stream`.  The graph is captured on the
+ * first call and replayed while the arguments (pointers, ld, macro geometry)
+ * stay the same; other arguments capture it again.  The batch's classes run on
+ * the caller's stream and up to three side streams, forked after the set-up
+ * kernel and joined before the upscale, as in llhmm_micro_batch.  Arguments as
+ * in those two calls.  With timing enabled the whole call is reported as time
+ * stepping (set-up 0).  For launch-bound callers: a batch with large boxes
+ * makes one launch per band step, and the graph replays them all at once. */
+llhmm_status llhmm_batch_run_graph(llhmm_ctx *ctx, llhmm_batch *batch, const double *m_init_dev,
+                                   const llhmm_macro *macro, const double *M_macro_dev,
+                                   const double *coef_dev, double *m_final_dev, double *H_avg_dev,
+                                   int32_t ld, int32_t *status_dev, hipStream_t stream);
+
+/* Autotuner for the large boxes of a batch (2-D, n = 96 or 128, advanced in
+ * row strips).  For every class (precision, n, bc, quantity, integrator) it
+ * times the class alone, `reps` times after one warm-up, for each number of
+ * time steps per launch from 1 to 4 whose halo fits the strip window, and keeps
+ * the fastest, in the batch and in the context, so later batches of the same
+ * class start from it.  More steps per launch read the strip state and
+ * reference tables less often but recompute more halo rows.  Runs the set-up
+ * kernel with the given inputs (as llhmm_micro_batch) and synchronizes
+ * `stream`.  The result of the last llhmm_micro_batch is overwritten.  A
+ * captured graph of the batch is dropped. */
+llhmm_status llhmm_batch_tune(llhmm_ctx *ctx, llhmm_batch *batch, const double *m_init_dev,
+                              const llhmm_macro *macro, const double *M_macro_dev,
+                              const double *coef_dev, int32_t reps, hipStream_t stream);
+/* Steps per launch of each box (0 for boxes solved by the resident kernels). */
+llhmm_status llhmm_batch_band_steps(const llhmm_batch *batch, int32_t *steps_out);
+/* The context's tuning table as text: one line "precision n bc quantity
+ * stages steps_per_launch" per class.  Load merges into the table. */
+llhmm_status llhmm_tune_save(const llhmm_ctx *ctx, const char *path);
+llhmm_status llhmm_tune_load(llhmm_ctx *ctx, const char *path);
+
 /* One evaluation of the discrete field H(m_init) on every box (no time
  * stepping): H_dev [nboxes][3][n^dim] packed like m_final_dev.  For tests of
  * the stencil against the oracle. */

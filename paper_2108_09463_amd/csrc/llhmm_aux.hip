@@ -13,7 +13,7 @@ namespace llhmm {
 __global__ void __launch_bounds__(256) k_upscale(const double *partials, const int32_t *wave_status,
                                                  const double *box_const, const BoxPlan *plans,
                                                  int nboxes, double *H, int ld,
-                                                 int32_t *status) {
+                                                 int32_t *status, int32_t *status_out) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= nboxes) return;
     const BoxPlan &P = plans[b];
@@ -28,14 +28,15 @@ __global__ void __launch_bounds__(256) k_upscale(const double *partials, const i
     }
     for (int w = 0; w < P.nwaves; ++w) bad |= wave_status[P.part_offset + w];
     status[b] = bad;
+    if (status_out) status_out[b] = bad;
 }
 
 hipError_t launch_upscale(const double *partials, const int32_t *wave_status, const double *box_const,
                           const BoxPlan *plans, int nboxes, double *H, int ld, int32_t *status,
-                          int32_t *, hipStream_t s) {
+                          int32_t *status_out, hipStream_t s) {
     if (nboxes <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_upscale, dim3((nboxes + 255) / 256), dim3(256), 0, s, partials,
-                       wave_status, box_const, plans, nboxes, H, ld, status);
+                       wave_status, box_const, plans, nboxes, H, ld, status, status_out);
     return hipGetLastError();
 }
 

@@ -275,13 +275,17 @@ hipError_t dev_upload(T **dst, const T *src, size_t count) {
 
 }  // namespace
 
+using TuneKey = std::tuple<int, int, int, int, int>;  // precision, n, bc, quantity, stages
+
 struct llhmm_ctx {
     int device;
+    std::map<TuneKey, int> tuned;  // band classes: steps per launch chosen by llhmm_batch_tune
 };
 
 struct ClassLaunch {
     const TileInfo *tile;
     int first, count, nblocks;  // range in the concatenated box-id list
+    double cost;                // cell-stage estimate, for spreading classes over streams
 };
 
 struct BandClass {
@@ -289,6 +293,20 @@ struct BandClass {
     int s, h;                     // steps per launch, halo rows
     int first, count;             // range in the concatenated job list
     std::vector<int> active;      // jobs still running in launch p (a prefix: longest boxes first)
+    double cost;
+};
+
+constexpr int kSideStreams = 3;   // extra streams a batch spreads its classes over
+constexpr int kMaxStepsPerLaunch = 4;
+
+// Arguments a captured graph was built with; a call with other arguments captures again.
+struct GraphArgs {
+    const double *m_init, *M_macro, *coef;
+    double *m_final, *H;
+    int32_t *status;
+    int32_t ld, has_macro;
+    llhmm_macro macro;
+    bool operator==(const GraphArgs &o) const { return memcmp(this, &o, sizeof *this) == 0; }
 };
 
 struct llhmm_batch {
@@ -298,6 +316,8 @@ struct llhmm_batch {
     std::vector<BoxPlan> plans_h;
     std::vector<ClassLaunch> classes;
     std::vector<BandClass> bands;
+    std::vector<const BandTileInfo *> band_tile;  // per box; nullptr for resident boxes
+    std::vector<int> band_s;                      // per box: time steps per band launch
     BoxPlan *plans = nullptr;
     BandJob *jobs = nullptr;
     void *state[2] = {nullptr, nullptr};  // band boxes' state, ping-pong between launches
@@ -307,11 +327,74 @@ struct llhmm_batch {
     double *wts = nullptr, *wt = nullptr, *partials = nullptr, *box_const = nullptr, *scratch64 = nullptr;
     int32_t *wave_status = nullptr, *status = nullptr;
     hipEvent_t ev[LLHMM_TIMING_SLOTS][3] = {};
+    hipStream_t side[kSideStreams] = {};          // created on first use, default priority
+    hipEvent_t fork = nullptr, join[kSideStreams] = {};
+    hipStream_t cap_stream = nullptr;             // capture stream of llhmm_batch_run_graph
+    hipGraphExec_t exec = nullptr;
+    GraphArgs gargs{};
+    bool capturing = false;
     bool timing = false;
     int64_t timed = 0;  // timed calls since timing was enabled
     double kc[8];
     int kp, kq;
 };
+
+// Band boxes: strip geometry from each box's steps per launch, classes by
+// (tile, steps per launch, halo) with the jobs of the longest boxes first,
+// uploaded with the plans.  Drops a captured graph (its launches change).
+static llhmm_status rebuild_bands(llhmm_batch *b) {
+    std::map<std::tuple<const BandTileInfo *, int, int>, std::vector<int>> groups;
+    std::vector<BandGeom> geom(b->nboxes);
+    for (int i = 0; i < b->nboxes; ++i) {
+        const BandTileInfo *t = b->band_tile[i];
+        if (!t) continue;
+        BoxPlan &P = b->plans_h[i];
+        if (!band_geometry(*t, P.n, P.stages, b->band_s[i], geom[i]))
+            return fail(LLHMM_E_INVALID, "box %d: %d steps per launch do not fit the window", i, b->band_s[i]);
+        P.strips = geom[i].strips;
+        P.nwaves = geom[i].strips * (t->threads / 64);
+        groups[std::make_tuple(t, geom[i].s, geom[i].h)].push_back(i);
+    }
+    b->bands.clear();
+    std::vector<BandJob> jobs_h;
+    for (auto &kv : groups) {
+        auto &v = kv.second;
+        std::stable_sort(v.begin(), v.end(), [&](int a, int c) { return b->plans_h[a].M > b->plans_h[c].M; });
+        BandClass bc;
+        bc.tile = std::get<0>(kv.first);
+        bc.s = std::get<1>(kv.first);
+        bc.h = std::get<2>(kv.first);
+        bc.first = (int)jobs_h.size();
+        bc.cost = 0.0;
+        std::vector<int> jobM;
+        for (int i : v) {
+            const BandGeom &g = geom[i];
+            for (int t = 0; t < g.strips; ++t) {
+                jobs_h.push_back(BandJob{i, t, g.own[t].first, g.own[t].second});
+                jobM.push_back(b->plans_h[i].M);
+            }
+            bc.cost += (double)b->plans_h[i].M * b->plans_h[i].stages * b->plans_h[i].n * b->plans_h[i].n;
+        }
+        bc.count = (int)jobs_h.size() - bc.first;
+        const int launches = (jobM[0] + bc.s - 1) / bc.s;
+        for (int p = 0, cnt = bc.count; p < launches; ++p) {
+            while (cnt > 0 && jobM[cnt - 1] <= p * bc.s) --cnt;
+            bc.active.push_back(cnt);
+        }
+        b->bands.push_back(std::move(bc));
+    }
+    if (b->jobs) {
+        HIP_TRY(hipFree(b->jobs));
+        b->jobs = nullptr;
+    }
+    if (!jobs_h.empty()) HIP_TRY(dev_upload(&b->jobs, jobs_h.data(), jobs_h.size()));
+    HIP_TRY(hipMemcpy(b->plans, b->plans_h.data(), sizeof(BoxPlan) * b->plans_h.size(), hipMemcpyHostToDevice));
+    if (b->exec) {
+        HIP_TRY(hipGraphExecDestroy(b->exec));
+        b->exec = nullptr;
+    }
+    return LLHMM_OK;
+}
 
 extern "C" {
 
@@ -368,6 +451,13 @@ static void batch_free(llhmm_batch *b) {
     for (auto &slot : b->ev)
         for (hipEvent_t e : slot)
             if (e) (void)hipEventDestroy(e);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    for (int i = 0; i < kSideStreams; ++i) {
+        if (b->join[i]) (void)hipEventDestroy(b->join[i]);
+        if (b->side[i]) (void)hipStreamDestroy(b->side[i]);
+    }
+    if (b->fork) (void)hipEventDestroy(b->fork);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
     delete b;
 }
 
@@ -404,8 +494,8 @@ llhmm_status llhmm_batch_create(llhmm_ctx *ctx, const llhmm_box *boxes, int32_t 
     const size_t tsize = (precision == LLHMM_FP32) ? sizeof(float) : sizeof(double);
     b->plans_h.resize(nboxes);
     std::vector<const TileInfo *> tile_of(nboxes);
-    std::vector<const BandTileInfo *> band_of(nboxes, nullptr);
-    std::vector<BandGeom> geom_of(nboxes);
+    b->band_tile.assign(nboxes, nullptr);
+    b->band_s.assign(nboxes, 0);
     int dim_max = 1, nmax = 0;
     for (int i = 0; i < nboxes; ++i) {
         dim_max = std::max(dim_max, boxes[i].dim);
@@ -431,10 +521,14 @@ llhmm_status llhmm_batch_create(llhmm_ctx *ctx, const llhmm_box *boxes, int32_t 
         auto it = reg.find(TileKey{precision, bx.dim, bx.n, bx.order, bx.bc, bx.quantity});
         const BandTileInfo *bt = nullptr;
         BandGeom bg;
+        int band_s = 0;
         if (it == reg.end() && bx.dim == 2 && bx.order == 2) {
             auto bit = bregistry.find(BandKey{precision, bx.n, bx.bc, bx.quantity});
             const int stages = (pl.integ == LLHMM_RK4P) ? 4 : 2;
-            if (bit != bregistry.end() && band_geometry(*bit->second, bx.n, stages, 4 / stages, bg))
+            // steps per launch: the tuned choice for this class, else one halo of 4 rows
+            auto tit = ctx->tuned.find(TuneKey{precision, bx.n, bx.bc, bx.quantity, stages});
+            band_s = (tit != ctx->tuned.end()) ? tit->second : std::max(1, 4 / stages);
+            if (bit != bregistry.end() && band_geometry(*bit->second, bx.n, stages, band_s, bg))
                 bt = bit->second;
         }
         if (it == reg.end() && !bt) {
@@ -445,8 +539,8 @@ llhmm_status llhmm_batch_create(llhmm_ctx *ctx, const llhmm_box *boxes, int32_t 
                         bx.quantity);
         }
         tile_of[i] = bt ? nullptr : it->second;
-        band_of[i] = bt;
-        if (bt) geom_of[i] = bg;
+        b->band_tile[i] = bt;
+        b->band_s[i] = band_s;
         BoxPlan &P = b->plans_h[i];
         memset(&P, 0, sizeof P);
         P.dim = bx.dim;
@@ -462,16 +556,24 @@ llhmm_status llhmm_batch_create(llhmm_ctx *ctx, const llhmm_box *boxes, int32_t 
         P.mi1 = bx.macro_index[1];
         P.nq = (bx.quantity == LLHMM_Q_FLUX) ? 3 * bx.dim : 3;
         P.coef_sampled = coefs[bx.coef_index].sampled ? 1 : 0;
-        if (band_of[i]) {
+        int64_t slots;
+        if (bt) {
+            // strips and partial-sum slots follow the steps per launch; reserve the
+            // slots of the largest strip count any choice can give
             P.band = 1;
-            P.strips = geom_of[i].strips;
-            P.nwaves = geom_of[i].strips * (band_of[i]->threads / 64);
+            int smax = 0;
+            for (int sc = 1; sc <= kMaxStepsPerLaunch; ++sc) {
+                BandGeom g2;
+                if (band_geometry(*bt, bx.n, P.stages, sc, g2)) smax = std::max(smax, g2.strips);
+            }
+            slots = (int64_t)smax * (bt->threads / 64);
         } else {
             P.nwaves = (bx.dim == 2) ? it->second->threads / 64 : 1;
+            slots = P.nwaves;
         }
         P.part_offset = part_off;
-        part_off += P.nwaves;
-        if (band_of[i]) {
+        part_off += slots;
+        if (bt) {
             P.state_offset = state_off;
             state_off += 3 * (int64_t)bx.n * bx.n;
         }
@@ -533,6 +635,10 @@ llhmm_status llhmm_batch_create(llhmm_ctx *ctx, const llhmm_box *boxes, int32_t 
         ClassLaunch cl;
         cl.tile = t;
         cl.first = (int)ids.size();
+        cl.cost = 0.0;
+        for (int i : v)
+            cl.cost += (double)b->plans_h[i].M * b->plans_h[i].stages *
+                       (b->plans_h[i].dim == 1 ? b->plans_h[i].n : b->plans_h[i].n * b->plans_h[i].n);
         for (int i : v) ids.push_back(i);
         if (t->dim == 1) {
             while ((ids.size() - cl.first) % t->boxes_per_block) ids.push_back(-1);
@@ -540,36 +646,6 @@ llhmm_status llhmm_batch_create(llhmm_ctx *ctx, const llhmm_box *boxes, int32_t 
         cl.count = (int)ids.size() - cl.first;
         cl.nblocks = cl.count / t->boxes_per_block;
         b->classes.push_back(cl);
-    }
-
-    // band boxes: classes by (tile, steps per launch, halo), jobs of the longest boxes first
-    std::map<std::tuple<const BandTileInfo *, int, int>, std::vector<int>> bgroups;
-    for (int i = 0; i < nboxes; ++i)
-        if (band_of[i]) bgroups[std::make_tuple(band_of[i], geom_of[i].s, geom_of[i].h)].push_back(i);
-    std::vector<BandJob> jobs_h;
-    for (auto &kv : bgroups) {
-        auto &v = kv.second;
-        std::stable_sort(v.begin(), v.end(), [&](int a, int c) { return b->plans_h[a].M > b->plans_h[c].M; });
-        BandClass bc;
-        bc.tile = std::get<0>(kv.first);
-        bc.s = std::get<1>(kv.first);
-        bc.h = std::get<2>(kv.first);
-        bc.first = (int)jobs_h.size();
-        std::vector<int> jobM;
-        for (int i : v) {
-            const BandGeom &g = geom_of[i];
-            for (int t = 0; t < g.strips; ++t) {
-                jobs_h.push_back(BandJob{i, t, g.own[t].first, g.own[t].second});
-                jobM.push_back(b->plans_h[i].M);
-            }
-        }
-        bc.count = (int)jobs_h.size() - bc.first;
-        const int launches = (jobM[0] + bc.s - 1) / bc.s;
-        for (int p = 0, cnt = bc.count; p < launches; ++p) {
-            while (cnt > 0 && jobM[cnt - 1] <= p * bc.s) --cnt;
-            bc.active.push_back(cnt);
-        }
-        b->bands.push_back(std::move(bc));
     }
 
     hipError_t e = hipSuccess;
@@ -583,7 +659,6 @@ llhmm_status llhmm_batch_create(llhmm_ctx *ctx, const llhmm_box *boxes, int32_t 
     if (e == hipSuccess) e = hipMalloc((void **)&b->wts, sizeof(double) * std::max<int64_t>(w_off, 1));
     if (e == hipSuccess) e = hipMalloc((void **)&b->partials, sizeof(double) * (size_t)part_off * kMaxQ);
     if (e == hipSuccess) e = hipMalloc((void **)&b->wave_status, sizeof(int32_t) * (size_t)part_off);
-    if (e == hipSuccess && !jobs_h.empty()) e = dev_upload(&b->jobs, jobs_h.data(), jobs_h.size());
     for (int k = 0; k < 2 && e == hipSuccess && state_off > 0; ++k) e = hipMalloc(&b->state[k], tsize * state_off);
     if (e == hipSuccess) e = hipMalloc((void **)&b->status, sizeof(int32_t) * (size_t)nboxes);
     if (e == hipSuccess) e = hipMalloc((void **)&b->box_const, sizeof(double) * (size_t)nboxes * kMaxQ);
@@ -592,6 +667,11 @@ llhmm_status llhmm_batch_create(llhmm_ctx *ctx, const llhmm_box *boxes, int32_t 
         batch_free(b);
         return fail(e == hipErrorOutOfMemory ? LLHMM_E_NOMEM : LLHMM_E_HIP, "batch allocation: %s",
                     hipGetErrorString(e));
+    }
+    st = rebuild_bands(b);
+    if (st != LLHMM_OK) {
+        batch_free(b);
+        return st;
     }
     *out = b;
     return LLHMM_OK;
@@ -604,11 +684,9 @@ llhmm_status llhmm_batch_destroy(llhmm_ctx *, llhmm_batch *batch) {
 
 int64_t llhmm_batch_cell_steps(const llhmm_batch *batch) { return batch ? batch->cell_steps : -1; }
 
-static llhmm_status run_batch(llhmm_ctx *ctx, llhmm_batch *b, const double *m_init_dev,
-                              const llhmm_macro *macro, const double *M_macro_dev,
-                              const double *coef_dev, double *field_dev, int mode,
-                              hipStream_t stream) {
-    if (!ctx || !b) return fail(LLHMM_E_INVALID, "ctx/batch is NULL");
+// Checks the inputs of a solve / evaluation and fills the set-up kernel's arguments.
+static llhmm_status prologue_args(llhmm_batch *b, const double *m_init_dev, const llhmm_macro *macro,
+                                  const double *M_macro_dev, const double *coef_dev, PrologueArgs &pa) {
     if (b->any_explicit && !m_init_dev) return fail(LLHMM_E_INVALID, "explicit init needs m_init_dev");
     if (b->any_macro && (!macro || !M_macro_dev))
         return fail(LLHMM_E_INVALID, "macro-interpolated init needs macro and M_macro_dev");
@@ -633,8 +711,7 @@ static llhmm_status run_batch(llhmm_ctx *ctx, llhmm_batch *b, const double *m_in
                 return fail(LLHMM_E_INVALID, "box %d: centre is not its macro node", i);
         }
     }
-    HIP_TRY(hipSetDevice(ctx->device));
-    PrologueArgs pa{};
+    pa = PrologueArgs{};
     pa.plans = b->plans;
     pa.nboxes = b->nboxes;
     pa.coefs = b->coefs;
@@ -649,53 +726,116 @@ static llhmm_status run_batch(llhmm_ctx *ctx, llhmm_batch *b, const double *m_in
     memcpy(pa.kc, b->kc, sizeof pa.kc);
     pa.kp = b->kp;
     pa.kq = b->kq;
+    return LLHMM_OK;
+}
+
+static llhmm_status launch_resident(llhmm_batch *b, const ClassLaunch &cl, int mode, double *field_dev,
+                                    hipStream_t stream) {
+    MicroArgs a{};
+    a.plans = b->plans;
+    a.box_ids = b->box_ids + cl.first;
+    a.nbox_class = cl.count;
+    a.mode = mode;
+    a.tabs = b->tabs;
+    a.wts = b->wts;
+    a.wt = b->wt;
+    a.partials = b->partials;
+    a.wave_status = b->wave_status;
+    a.out_field = field_dev;
+    HIP_TRY(cl.tile->launch(a, cl.nblocks, stream));
+    return LLHMM_OK;
+}
+
+// All launches of one band class, in order on one stream (each launch reads
+// the state the previous one wrote).
+static llhmm_status launch_band_class(llhmm_batch *b, const BandClass &bc, int mode, double *field_dev,
+                                      hipStream_t stream) {
+    BandArgs a{};
+    a.plans = b->plans;
+    a.jobs = b->jobs + bc.first;
+    a.mode = mode;
+    a.h = bc.h;
+    a.tabs = b->tabs;
+    a.wts = b->wts;
+    a.wt = b->wt;
+    a.partials = b->partials;
+    a.wave_status = b->wave_status;
+    a.out_field = field_dev;
+    if (mode == 1) {
+        a.njobs = bc.count;
+        a.step0 = 0;
+        a.steps = 0;
+        HIP_TRY(bc.tile->launch(a, bc.count, stream));
+        return LLHMM_OK;
+    }
+    for (size_t p = 0; p < bc.active.size(); ++p) {
+        a.njobs = bc.active[p];
+        a.step0 = (int)p * bc.s;
+        a.steps = bc.s;
+        a.state_in = b->state[p & 1];
+        a.state_out = b->state[(p + 1) & 1];
+        HIP_TRY(bc.tile->launch(a, a.njobs, stream));
+    }
+    return LLHMM_OK;
+}
+
+static llhmm_status ensure_side_streams(llhmm_batch *b) {
+    if (b->fork) return LLHMM_OK;
+    HIP_TRY(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
+    for (int i = 0; i < kSideStreams; ++i) {
+        HIP_TRY(hipStreamCreateWithFlags(&b->side[i], hipStreamNonBlocking));
+        HIP_TRY(hipEventCreateWithFlags(&b->join[i], hipEventDisableTiming));
+    }
+    return LLHMM_OK;
+}
+
+// The whole solve (mode 0) or field evaluation (mode 1) of a batch on `stream`:
+// set-up kernel, then the tile classes.  Classes are independent, so with more
+// than one they are spread over the caller's stream and up to kSideStreams
+// side streams (longest first onto the least loaded stream), forked after the
+// set-up and joined back into the caller's stream before returning.
+static llhmm_status run_batch(llhmm_ctx *ctx, llhmm_batch *b, const double *m_init_dev,
+                              const llhmm_macro *macro, const double *M_macro_dev,
+                              const double *coef_dev, double *field_dev, int mode,
+                              hipStream_t stream) {
+    if (!ctx || !b) return fail(LLHMM_E_INVALID, "ctx/batch is NULL");
+    PrologueArgs pa;
+    llhmm_status st = prologue_args(b, m_init_dev, macro, M_macro_dev, coef_dev, pa);
+    if (st != LLHMM_OK) return st;
+    HIP_TRY(hipSetDevice(ctx->device));
+    const bool timed = b->timing && !b->capturing;
     hipEvent_t *ev = b->ev[b->timed % LLHMM_TIMING_SLOTS];
-    if (b->timing) HIP_TRY(hipEventRecord(ev[0], stream));
+    if (timed) HIP_TRY(hipEventRecord(ev[0], stream));
     HIP_TRY(launch_prologue(b->prec, pa, stream));
-    if (b->timing) HIP_TRY(hipEventRecord(ev[1], stream));
-    for (const ClassLaunch &cl : b->classes) {
-        MicroArgs a{};
-        a.plans = b->plans;
-        a.box_ids = b->box_ids + cl.first;
-        a.nbox_class = cl.count;
-        a.mode = mode;
-        a.tabs = b->tabs;
-        a.wts = b->wts;
-        a.wt = b->wt;
-        a.partials = b->partials;
-        a.wave_status = b->wave_status;
-        a.out_field = field_dev;
-        HIP_TRY(cl.tile->launch(a, cl.nblocks, stream));
+    if (timed) HIP_TRY(hipEventRecord(ev[1], stream));
+
+    // work items: resident classes (index >= 0) and band classes (~index)
+    struct Item { double cost; int idx; };
+    std::vector<Item> items;
+    for (size_t i = 0; i < b->classes.size(); ++i) items.push_back({b->classes[i].cost, (int)i});
+    for (size_t i = 0; i < b->bands.size(); ++i) items.push_back({b->bands[i].cost, ~(int)i});
+    std::stable_sort(items.begin(), items.end(), [](const Item &x, const Item &y) { return x.cost > y.cost; });
+    const int lanes = std::min<int>((int)items.size(), 1 + kSideStreams);
+    if (lanes > 1) {
+        st = ensure_side_streams(b);
+        if (st != LLHMM_OK) return st;
+        HIP_TRY(hipEventRecord(b->fork, stream));
+        for (int l = 1; l < lanes; ++l) HIP_TRY(hipStreamWaitEvent(b->side[l - 1], b->fork, 0));
     }
-    for (const BandClass &bc : b->bands) {
-        BandArgs a{};
-        a.plans = b->plans;
-        a.jobs = b->jobs + bc.first;
-        a.mode = mode;
-        a.h = bc.h;
-        a.tabs = b->tabs;
-        a.wts = b->wts;
-        a.wt = b->wt;
-        a.partials = b->partials;
-        a.wave_status = b->wave_status;
-        a.out_field = field_dev;
-        if (mode == 1) {
-            a.njobs = bc.count;
-            a.step0 = 0;
-            a.steps = 0;
-            HIP_TRY(bc.tile->launch(a, bc.count, stream));
-            continue;
-        }
-        for (size_t p = 0; p < bc.active.size(); ++p) {
-            a.njobs = bc.active[p];
-            a.step0 = (int)p * bc.s;
-            a.steps = bc.s;
-            a.state_in = b->state[p & 1];
-            a.state_out = b->state[(p + 1) & 1];
-            HIP_TRY(bc.tile->launch(a, a.njobs, stream));
-        }
+    std::vector<double> load(std::max(lanes, 1), 0.0);
+    for (const Item &it : items) {
+        const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        load[l] += it.cost;
+        hipStream_t s = (l == 0) ? stream : b->side[l - 1];
+        st = (it.idx >= 0) ? launch_resident(b, b->classes[it.idx], mode, field_dev, s)
+                           : launch_band_class(b, b->bands[~it.idx], mode, field_dev, s);
+        if (st != LLHMM_OK) return st;
     }
-    if (b->timing) {
+    for (int l = 1; l < lanes; ++l) {
+        HIP_TRY(hipEventRecord(b->join[l - 1], b->side[l - 1]));
+        HIP_TRY(hipStreamWaitEvent(stream, b->join[l - 1], 0));
+    }
+    if (timed) {
         HIP_TRY(hipEventRecord(ev[2], stream));
         ++b->timed;
     }
@@ -752,10 +892,7 @@ llhmm_status llhmm_upscale(llhmm_ctx *ctx, llhmm_batch *b, double *H_avg_dev, in
     }
     HIP_TRY(hipSetDevice(ctx->device));
     HIP_TRY(launch_upscale(b->partials, b->wave_status, b->box_const, b->plans, b->nboxes, H_avg_dev, ld,
-                           b->status, nullptr, stream));
-    if (status_dev)
-        HIP_TRY(hipMemcpyAsync(status_dev, b->status, sizeof(int32_t) * b->nboxes,
-                               hipMemcpyDeviceToDevice, stream));
+                           b->status, status_dev, stream));
     if (check) {
         std::vector<int32_t> st(b->nboxes);
         HIP_TRY(hipMemcpyAsync(st.data(), b->status, sizeof(int32_t) * b->nboxes,
@@ -764,6 +901,179 @@ llhmm_status llhmm_upscale(llhmm_ctx *ctx, llhmm_batch *b, double *H_avg_dev, in
         for (int i = 0; i < b->nboxes; ++i)
             if (st[i]) return fail(LLHMM_E_UNSTABLE, "box %d produced non-finite values", i);
     }
+    return LLHMM_OK;
+}
+
+llhmm_status llhmm_batch_run_graph(llhmm_ctx *ctx, llhmm_batch *b, const double *m_init_dev,
+                                   const llhmm_macro *macro, const double *M_macro_dev,
+                                   const double *coef_dev, double *m_final_dev, double *H_avg_dev,
+                                   int32_t ld, int32_t *status_dev, hipStream_t stream) {
+    if (!ctx || !b) return fail(LLHMM_E_INVALID, "ctx/batch is NULL");
+    if (H_avg_dev && ld < 3 * b->dim_max) {
+        for (const BoxPlan &P : b->plans_h)
+            if (P.nq > ld) return fail(LLHMM_E_INVALID, "ld %d smaller than the outputs per box", ld);
+    }
+    GraphArgs ga;
+    memset(&ga, 0, sizeof ga);
+    ga.m_init = m_init_dev;
+    ga.M_macro = M_macro_dev;
+    ga.coef = coef_dev;
+    ga.m_final = m_final_dev;
+    ga.H = H_avg_dev;
+    ga.status = status_dev;
+    ga.ld = ld;
+    ga.has_macro = macro != nullptr;
+    if (macro) ga.macro = *macro;
+    HIP_TRY(hipSetDevice(ctx->device));
+    if (!b->exec || !(ga == b->gargs)) {
+        if (b->exec) {
+            HIP_TRY(hipGraphExecDestroy(b->exec));
+            b->exec = nullptr;
+        }
+        // everything that can fail on the host is checked before the capture opens
+        PrologueArgs pa;
+        llhmm_status st = prologue_args(b, m_init_dev, macro, M_macro_dev, coef_dev, pa);
+        if (st != LLHMM_OK) return st;
+        st = ensure_side_streams(b);
+        if (st != LLHMM_OK) return st;
+        if (!b->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+        HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+        b->capturing = true;
+        st = run_batch(ctx, b, m_init_dev, macro, M_macro_dev, coef_dev, m_final_dev, 0, b->cap_stream);
+        if (st == LLHMM_OK) {
+            const hipError_t e = launch_upscale(b->partials, b->wave_status, b->box_const, b->plans, b->nboxes,
+                                                H_avg_dev, ld, b->status, status_dev, b->cap_stream);
+            if (e != hipSuccess) st = fail(LLHMM_E_HIP, "upscale launch in capture: %s", hipGetErrorString(e));
+        }
+        b->capturing = false;
+        hipGraph_t g = nullptr;
+        const hipError_t ee = hipStreamEndCapture(b->cap_stream, &g);
+        if (st != LLHMM_OK || ee != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return st != LLHMM_OK ? st : fail(LLHMM_E_HIP, "graph capture: %s", hipGetErrorString(ee));
+        }
+        const hipError_t ei = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ei != hipSuccess) {
+            b->exec = nullptr;
+            return fail(LLHMM_E_HIP, "graph instantiation: %s", hipGetErrorString(ei));
+        }
+        b->gargs = ga;
+    }
+    const bool timed = b->timing;
+    hipEvent_t *ev = b->ev[b->timed % LLHMM_TIMING_SLOTS];
+    if (timed) {
+        HIP_TRY(hipEventRecord(ev[0], stream));
+        HIP_TRY(hipEventRecord(ev[1], stream));
+    }
+    HIP_TRY(hipGraphLaunch(b->exec, stream));
+    if (timed) {
+        HIP_TRY(hipEventRecord(ev[2], stream));
+        ++b->timed;
+    }
+    return LLHMM_OK;
+}
+
+llhmm_status llhmm_batch_tune(llhmm_ctx *ctx, llhmm_batch *b, const double *m_init_dev,
+                              const llhmm_macro *macro, const double *M_macro_dev, const double *coef_dev,
+                              int32_t reps, hipStream_t stream) {
+    if (!ctx || !b) return fail(LLHMM_E_INVALID, "ctx/batch is NULL");
+    if (reps < 1) return fail(LLHMM_E_INVALID, "reps must be >= 1");
+    if (b->bands.empty()) return LLHMM_OK;
+    PrologueArgs pa;
+    llhmm_status st = prologue_args(b, m_init_dev, macro, M_macro_dev, coef_dev, pa);
+    if (st != LLHMM_OK) return st;
+    HIP_TRY(hipSetDevice(ctx->device));
+    HIP_TRY(launch_prologue(b->prec, pa, stream));  // tables the band kernels read
+    std::map<TuneKey, std::vector<int>> keys;
+    for (int i = 0; i < b->nboxes; ++i)
+        if (b->band_tile[i]) {
+            const BoxPlan &P = b->plans_h[i];
+            keys[TuneKey{b->prec, P.n, P.bc, P.quantity, P.stages}].push_back(i);
+        }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    for (auto &kv : keys) {
+        const int i0 = kv.second[0];
+        const BandTileInfo *t = b->band_tile[i0];
+        int best = b->band_s[i0];
+        float best_ms = -1.f;
+        for (int sc = 1; sc <= kMaxStepsPerLaunch && st == LLHMM_OK; ++sc) {
+            BandGeom g;
+            if (!band_geometry(*t, b->plans_h[i0].n, b->plans_h[i0].stages, sc, g)) continue;
+            hipError_t e = hipStreamSynchronize(stream);  // no launch may still read the plans
+            if (e != hipSuccess) { st = fail(LLHMM_E_HIP, "tune: %s", hipGetErrorString(e)); break; }
+            for (int i : kv.second) b->band_s[i] = sc;
+            st = rebuild_bands(b);
+            if (st != LLHMM_OK) break;
+            const BandClass *bc = nullptr;
+            for (const BandClass &c : b->bands)
+                if (c.tile == t && c.s == sc) bc = &c;
+            if (!bc) continue;
+            st = launch_band_class(b, *bc, 0, nullptr, stream);  // warm-up
+            if (st == LLHMM_OK) e = hipEventRecord(e0, stream);
+            for (int r = 0; r < reps && st == LLHMM_OK && e == hipSuccess; ++r)
+                st = launch_band_class(b, *bc, 0, nullptr, stream);
+            if (st == LLHMM_OK && e == hipSuccess) e = hipEventRecord(e1, stream);
+            if (st == LLHMM_OK && e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (st == LLHMM_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (st == LLHMM_OK && e != hipSuccess) st = fail(LLHMM_E_HIP, "tune: %s", hipGetErrorString(e));
+            if (st == LLHMM_OK && (best_ms < 0.f || ms < best_ms)) {
+                best_ms = ms;
+                best = sc;
+            }
+        }
+        if (st != LLHMM_OK) break;
+        for (int i : kv.second) b->band_s[i] = best;
+        ctx->tuned[kv.first] = best;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != LLHMM_OK) return st;
+    HIP_TRY(hipStreamSynchronize(stream));
+    return rebuild_bands(b);
+}
+
+llhmm_status llhmm_batch_band_steps(const llhmm_batch *b, int32_t *steps_out) {
+    if (!b || !steps_out) return fail(LLHMM_E_INVALID, "batch/steps_out is NULL");
+    for (int i = 0; i < b->nboxes; ++i) steps_out[i] = b->band_tile[i] ? b->band_s[i] : 0;
+    return LLHMM_OK;
+}
+
+llhmm_status llhmm_tune_save(const llhmm_ctx *ctx, const char *path) {
+    if (!ctx || !path) return fail(LLHMM_E_INVALID, "ctx/path is NULL");
+    FILE *f = fopen(path, "w");
+    if (!f) return fail(LLHMM_E_INVALID, "cannot write %s", path);
+    fprintf(f, "# llhmm band tuning: precision n bc quantity stages steps_per_launch\n");
+    for (const auto &kv : ctx->tuned)
+        fprintf(f, "%d %d %d %d %d %d\n", std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first),
+                std::get<3>(kv.first), std::get<4>(kv.first), kv.second);
+    const bool ok = fclose(f) == 0;
+    return ok ? LLHMM_OK : fail(LLHMM_E_INVALID, "cannot write %s", path);
+}
+
+llhmm_status llhmm_tune_load(llhmm_ctx *ctx, const char *path) {
+    if (!ctx || !path) return fail(LLHMM_E_INVALID, "ctx/path is NULL");
+    FILE *f = fopen(path, "r");
+    if (!f) return fail(LLHMM_E_INVALID, "cannot read %s", path);
+    char line[256];
+    std::map<TuneKey, int> got;
+    llhmm_status st = LLHMM_OK;
+    while (fgets(line, sizeof line, f)) {
+        if (line[0] == '#' || line[0] == '\n') continue;
+        int v[6];
+        if (sscanf(line, "%d %d %d %d %d %d", &v[0], &v[1], &v[2], &v[3], &v[4], &v[5]) != 6 ||
+            v[5] < 1 || v[5] > kMaxStepsPerLaunch) {
+            st = fail(LLHMM_E_INVALID, "%s: bad line: %s", path, line);
+            break;
+        }
+        got[TuneKey{v[0], v[1], v[2], v[3], v[4]}] = v[5];
+    }
+    fclose(f);
+    if (st != LLHMM_OK) return st;
+    for (const auto &kv : got) ctx->tuned[kv.first] = kv.second;
     return LLHMM_OK;
 }
 

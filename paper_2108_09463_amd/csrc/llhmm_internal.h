@@ -180,7 +180,7 @@ const TileInfo *tiles_f64_1d(int *count);
 hipError_t launch_prologue(int prec, const PrologueArgs &a, hipStream_t s);
 hipError_t launch_upscale(const double *partials, const int32_t *wave_status,
                           const double *box_const, const BoxPlan *plans, int nboxes, double *H, int ld,
-                          int32_t *status, int32_t *any_bad, hipStream_t s);
+                          int32_t *status, int32_t *status_out, hipStream_t s);
 hipError_t launch_macro(int npts, int scheme, int step_index, int stage, double dt,
                         double alpha, double *M, const double *H, double *Y,
                         double *work, hipStream_t s);

@@ -86,6 +86,16 @@ _SYMBOLS = {
     "llhmm_eval_field": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.POINTER(Macro), ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.c_void_p]),
+    "llhmm_batch_run_graph": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.POINTER(Macro), ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                             ctypes.c_void_p, ctypes.c_void_p]),
+    "llhmm_batch_tune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.POINTER(Macro), ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_int32, ctypes.c_void_p]),
+    "llhmm_batch_band_steps": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "llhmm_tune_save": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p]),
+    "llhmm_tune_load": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p]),
     "llhmm_macro_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                         ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                                         ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
@@ -279,6 +289,35 @@ def llhmm_micro_batch(ctx, batch, m_init=None, macro=None, M_macro=None, coef=No
 def llhmm_upscale(ctx, batch, H_avg, ld, status=None, check=False, stream=None):
     _check(lib().llhmm_upscale(ctx.h, batch.h, _ptr(H_avg), ld, _ptr(status), 1 if check else 0,
                                _stream(stream)))
+
+
+def llhmm_batch_run_graph(ctx, batch, H_avg, ld, status=None, m_init=None, macro=None, M_macro=None,
+                          coef=None, m_final=None, stream=None):
+    ms = _macro_struct(macro)
+    _check(lib().llhmm_batch_run_graph(ctx.h, batch.h, _ptr(m_init), ms[0] if ms else None,
+                                       _ptr(M_macro), _ptr(coef), _ptr(m_final), _ptr(H_avg), ld,
+                                       _ptr(status), _stream(stream)))
+
+
+def llhmm_batch_tune(ctx, batch, m_init=None, macro=None, M_macro=None, coef=None, reps=2,
+                     stream=None):
+    ms = _macro_struct(macro)
+    _check(lib().llhmm_batch_tune(ctx.h, batch.h, _ptr(m_init), ms[0] if ms else None,
+                                  _ptr(M_macro), _ptr(coef), reps, _stream(stream)))
+
+
+def llhmm_batch_band_steps(batch):
+    out = np.zeros(batch.n, np.int32)
+    _check(lib().llhmm_batch_band_steps(batch.h, out.ctypes.data))
+    return out
+
+
+def llhmm_tune_save(ctx, path):
+    _check(lib().llhmm_tune_save(ctx.h, path.encode()))
+
+
+def llhmm_tune_load(ctx, path):
+    _check(lib().llhmm_tune_load(ctx.h, path.encode()))
 
 
 def llhmm_eval_field(ctx, batch, H, m_init=None, macro=None, M_macro=None, coef=None, stream=None):

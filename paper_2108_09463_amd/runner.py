@@ -48,6 +48,16 @@ class Prepared:
                             m_final, stream)
         L.llhmm_upscale(self.ctx, self.batch, self.H, self.ld, self.status, False, stream)
 
+    def launch_graph(self, stream=None):
+        """The same solve + upscale as one captured HIP graph (replayed while the
+        arguments stay the same)."""
+        L.llhmm_batch_run_graph(self.ctx, self.batch, self.H, self.ld, self.status, self.m_init,
+                                self.macro, self.M_macro, None, None, stream)
+
+    def tune(self, reps=2):
+        L.llhmm_batch_tune(self.ctx, self.batch, self.m_init, self.macro, self.M_macro, None, reps)
+        return L.llhmm_batch_band_steps(self.batch)
+
     def solve(self, want_state=False):
         torch = self.torch
         mf = None
