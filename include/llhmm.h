@@ -124,6 +124,7 @@ typedef struct {
 
 typedef struct llhmm_ctx llhmm_ctx;
 typedef struct llhmm_batch llhmm_batch;
+typedef struct llhmm_server llhmm_server;
 
 /* Library / context management ------------------------------------------ */
 int32_t llhmm_abi_version(void);
@@ -261,6 +262,58 @@ llhmm_status llhmm_macro_step(llhmm_ctx *ctx, int32_t npts, int32_t scheme, int3
                               int32_t stage, double dt, double alpha, double *M_dev,
                               const double *H_avg_dev, double *Y_dev, double *work_dev,
                               int32_t *next_stage_out, hipStream_t stream);
+
+/* Serving -----------------------------------------------------------------
+ * A request loop for micro problems that arrive over time: in the HMM loop
+ * each macro stage issues one micro problem per macro point (Section 2.2,
+ * eq. (macro_disc)), here in bursts.  Requests wait in a FIFO queue.  Submit
+ * and poll admit them, in arrival order, into micro-batches whenever one of
+ * max_inflight stream slots is free and the server's device memory can hold
+ * their tables and state; micro-batches run concurrently on their own
+ * streams (continuous batching: requests that arrive while others are on the
+ * GPU start as soon as a slot and memory free up).  The server reserves
+ * device_bytes once at creation and allocates every micro-batch inside it,
+ * so admitting work never calls hipMalloc; the budget is the admission
+ * limit.  A request's result does not depend on which other requests shared
+ * its micro-batch. */
+typedef struct {
+    int32_t precision;        /* llhmm_precision of every request */
+    int32_t max_inflight;     /* micro-batches on the device at once, 1..16 */
+    int32_t max_batch_boxes;  /* requests per micro-batch, >= 1 */
+    int32_t pad_;
+    int64_t device_bytes;     /* device memory the server reserves (>= 1 MiB) */
+    llhmm_kernel K;           /* averaging kernels of every request */
+} llhmm_server_cfg;
+
+/* Coefficients are copied (closed forms only; sampled coefficients return
+ * LLHMM_E_NOTSUP at submit).  Errors: LLHMM_E_INVALID, LLHMM_E_NOMEM. */
+llhmm_status llhmm_server_create(llhmm_ctx *ctx, const llhmm_server_cfg *cfg, const llhmm_coef *coefs,
+                                 int32_t ncoefs, llhmm_server **server);
+/* Waits for work in flight, then frees everything. */
+llhmm_status llhmm_server_destroy(llhmm_server *server);
+/* Queues n requests (boxes as in llhmm_batch_create, ids chosen by the
+ * caller) and admits what fits.  m_init_dev / macro + M_macro_dev as in
+ * llhmm_micro_batch; they must stay valid and unchanged until the requests
+ * complete.  Requests of one micro-batch share these inputs, so a change of
+ * source starts a new micro-batch.  Checks each box (LLHMM_E_INVALID,
+ * LLHMM_E_NOTSUP) before queuing any; host-side only apart from launches. */
+llhmm_status llhmm_server_submit(llhmm_server *server, const llhmm_box *boxes, int32_t n,
+                                 const int64_t *ids, const double *m_init_dev,
+                                 const llhmm_macro *macro, const double *M_macro_dev);
+/* Completes finished micro-batches, admits queued requests and returns up
+ * to `max` results (host arrays, all nullable except ndone): ids_out[k],
+ * H_out[k * 6 + q] (upscaled quantity, q < 3 or 3*dim), status_out[k] (0 ok,
+ * 1 non-finite, LLHMM_E_BUDGET when the request alone exceeds the budget, or
+ * another llhmm_status when its batch could not be set up) and
+ * latency_us_out[k] (host time from submit to completion seen by poll).  With
+ * wait != 0 it blocks until at least one result is ready or nothing is left
+ * in flight. */
+llhmm_status llhmm_server_poll(llhmm_server *server, int32_t wait, int32_t max, int64_t *ids_out,
+                               double *H_out, int32_t *status_out, double *latency_us_out,
+                               int32_t *ndone);
+/* Requests queued, requests in flight, device bytes in use and reserved. */
+llhmm_status llhmm_server_stats(const llhmm_server *server, int64_t *queued, int64_t *inflight,
+                                int64_t *bytes_in_use, int64_t *bytes_total);
 
 #ifdef __cplusplus
 }

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
+#include <deque>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -277,6 +279,59 @@ hipError_t dev_upload(T **dst, const T *src, size_t count) {
 
 using TuneKey = std::tuple<int, int, int, int, int>;  // precision, n, bc, quantity, stages
 
+// Device memory reserved once and handed out in 256-byte aligned pieces
+// (first fit, neighbouring free pieces merged on release).  The serving loop
+// allocates its micro-batches here, so admitting work never calls hipMalloc.
+struct Arena {
+    static constexpr size_t kAlign = 256;
+    char *base = nullptr;
+    size_t size = 0, used = 0;
+    std::map<size_t, size_t> free_, taken_;  // offset -> bytes
+    hipError_t init(size_t bytes) {
+        bytes = (bytes + kAlign - 1) / kAlign * kAlign;
+        hipError_t e = hipMalloc((void **)&base, bytes);
+        if (e != hipSuccess) return e;
+        size = bytes;
+        free_[0] = bytes;
+        return hipSuccess;
+    }
+    void *alloc(size_t bytes) {
+        bytes = std::max<size_t>(kAlign, (bytes + kAlign - 1) / kAlign * kAlign);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < bytes) continue;
+            const size_t off = it->first, left = it->second - bytes;
+            free_.erase(it);
+            if (left) free_[off + bytes] = left;
+            taken_[off] = bytes;
+            used += bytes;
+            return base + off;
+        }
+        return nullptr;
+    }
+    void release(void *p) {
+        auto t = taken_.find((size_t)((char *)p - base));
+        if (t == taken_.end()) return;
+        size_t off = t->first, bytes = t->second;
+        taken_.erase(t);
+        used -= bytes;
+        auto nx = free_.lower_bound(off);
+        if (nx != free_.end() && nx->first == off + bytes) {
+            bytes += nx->second;
+            free_.erase(nx);
+        }
+        auto pv = free_.lower_bound(off);
+        if (pv != free_.begin()) {
+            --pv;
+            if (pv->first + pv->second == off) {
+                off = pv->first;
+                bytes += pv->second;
+                free_.erase(pv);
+            }
+        }
+        free_[off] = bytes;
+    }
+};
+
 struct llhmm_ctx {
     int device;
     std::map<TuneKey, int> tuned;  // band classes: steps per launch chosen by llhmm_batch_tune
@@ -329,6 +384,8 @@ struct llhmm_batch {
     hipEvent_t ev[LLHMM_TIMING_SLOTS][3] = {};
     hipStream_t side[kSideStreams] = {};          // created on first use, default priority
     hipEvent_t fork = nullptr, join[kSideStreams] = {};
+    Arena *arena = nullptr;                       // device memory source (nullptr: hipMalloc)
+    int max_lanes = 1 + kSideStreams;             // streams the classes may spread over
     hipStream_t cap_stream = nullptr;             // capture stream of llhmm_batch_run_graph
     hipGraphExec_t exec = nullptr;
     GraphArgs gargs{};
@@ -338,6 +395,29 @@ struct llhmm_batch {
     double kc[8];
     int kp, kq;
 };
+
+static hipError_t balloc(llhmm_batch *b, void **p, size_t bytes) {
+    if (b->arena) {
+        *p = b->arena->alloc(bytes);
+        return *p ? hipSuccess : hipErrorOutOfMemory;
+    }
+    return hipMalloc(p, bytes);
+}
+
+static void bfree(llhmm_batch *b, void *p) {
+    if (!p) return;
+    if (b->arena) b->arena->release(p);
+    else (void)hipFree(p);
+}
+
+template <typename T>
+static hipError_t bupload(llhmm_batch *b, T **dst, const T *src, size_t count) {
+    *dst = nullptr;
+    if (count == 0) return hipSuccess;
+    hipError_t e = balloc(b, (void **)dst, sizeof(T) * count);
+    if (e != hipSuccess) return e;
+    return hipMemcpy(*dst, src, sizeof(T) * count, hipMemcpyHostToDevice);
+}
 
 // Band boxes: strip geometry from each box's steps per launch, classes by
 // (tile, steps per launch, halo) with the jobs of the longest boxes first,
@@ -384,10 +464,14 @@ static llhmm_status rebuild_bands(llhmm_batch *b) {
         b->bands.push_back(std::move(bc));
     }
     if (b->jobs) {
-        HIP_TRY(hipFree(b->jobs));
+        bfree(b, b->jobs);
         b->jobs = nullptr;
     }
-    if (!jobs_h.empty()) HIP_TRY(dev_upload(&b->jobs, jobs_h.data(), jobs_h.size()));
+    if (!jobs_h.empty()) {
+        const hipError_t e = bupload(b, &b->jobs, jobs_h.data(), jobs_h.size());
+        if (e == hipErrorOutOfMemory) return fail(LLHMM_E_NOMEM, "band jobs: out of memory");
+        HIP_TRY(e);
+    }
     HIP_TRY(hipMemcpy(b->plans, b->plans_h.data(), sizeof(BoxPlan) * b->plans_h.size(), hipMemcpyHostToDevice));
     if (b->exec) {
         HIP_TRY(hipGraphExecDestroy(b->exec));
@@ -446,8 +530,7 @@ static void batch_free(llhmm_batch *b) {
     void *ptrs[] = {b->plans, b->box_ids, b->coefs, b->tabs, b->wts, b->wt, b->partials,
                     b->wave_status, b->status, b->box_const, b->scratch64, b->jobs,
                     b->state[0], b->state[1]};
-    for (void *p : ptrs)
-        if (p) (void)hipFree(p);
+    for (void *p : ptrs) bfree(b, p);
     for (auto &slot : b->ev)
         for (hipEvent_t e : slot)
             if (e) (void)hipEventDestroy(e);
@@ -461,9 +544,21 @@ static void batch_free(llhmm_batch *b) {
     delete b;
 }
 
+static llhmm_status batch_create_impl(llhmm_ctx *ctx, const llhmm_box *boxes, int32_t nboxes,
+                                      const llhmm_kernel *K, const llhmm_coef *coefs, int32_t ncoefs,
+                                      int32_t precision, Arena *arena, int max_lanes, llhmm_batch **out);
+
 llhmm_status llhmm_batch_create(llhmm_ctx *ctx, const llhmm_box *boxes, int32_t nboxes,
                                 const llhmm_kernel *K, const llhmm_coef *coefs, int32_t ncoefs,
                                 int32_t precision, llhmm_batch **out) {
+    return batch_create_impl(ctx, boxes, nboxes, K, coefs, ncoefs, precision, nullptr, 1 + kSideStreams, out);
+}
+
+}  // extern "C"
+
+static llhmm_status batch_create_impl(llhmm_ctx *ctx, const llhmm_box *boxes, int32_t nboxes,
+                                      const llhmm_kernel *K, const llhmm_coef *coefs, int32_t ncoefs,
+                                      int32_t precision, Arena *arena, int max_lanes, llhmm_batch **out) {
     if (!ctx || !out) return fail(LLHMM_E_INVALID, "ctx/out is NULL");
     *out = nullptr;
     if (nboxes <= 0 || !boxes) return fail(LLHMM_E_INVALID, "empty batch");
@@ -478,6 +573,8 @@ llhmm_status llhmm_batch_create(llhmm_ctx *ctx, const llhmm_box *boxes, int32_t 
     HIP_TRY(hipSetDevice(ctx->device));
     double dcoef[8] = {0};
     llhmm_batch *b = new llhmm_batch();
+    b->arena = arena;
+    b->max_lanes = std::max(1, std::min(max_lanes, 1 + kSideStreams));
     b->nboxes = nboxes;
     b->prec = precision;
     llhmm_status st = kernel_coeffs(K->p_x, K->q_x, false, b->kc);
@@ -651,18 +748,18 @@ llhmm_status llhmm_batch_create(llhmm_ctx *ctx, const llhmm_box *boxes, int32_t 
     hipError_t e = hipSuccess;
     std::vector<CoefDev> cdev(ncoefs);
     memcpy(cdev.data(), coefs, sizeof(CoefDev) * ncoefs);
-    if (e == hipSuccess) e = dev_upload(&b->plans, b->plans_h.data(), b->plans_h.size());
-    if (e == hipSuccess) e = dev_upload(&b->box_ids, ids.data(), ids.size());
-    if (e == hipSuccess) e = dev_upload(&b->coefs, cdev.data(), cdev.size());
-    if (e == hipSuccess) e = dev_upload(&b->wt, wt_h.data(), wt_h.size());
-    if (e == hipSuccess) e = hipMalloc(&b->tabs, tsize * std::max<int64_t>(tab_off, 1));
-    if (e == hipSuccess) e = hipMalloc((void **)&b->wts, sizeof(double) * std::max<int64_t>(w_off, 1));
-    if (e == hipSuccess) e = hipMalloc((void **)&b->partials, sizeof(double) * (size_t)part_off * kMaxQ);
-    if (e == hipSuccess) e = hipMalloc((void **)&b->wave_status, sizeof(int32_t) * (size_t)part_off);
-    for (int k = 0; k < 2 && e == hipSuccess && state_off > 0; ++k) e = hipMalloc(&b->state[k], tsize * state_off);
-    if (e == hipSuccess) e = hipMalloc((void **)&b->status, sizeof(int32_t) * (size_t)nboxes);
-    if (e == hipSuccess) e = hipMalloc((void **)&b->box_const, sizeof(double) * (size_t)nboxes * kMaxQ);
-    if (e == hipSuccess) e = hipMalloc((void **)&b->scratch64, sizeof(double) * std::max<int64_t>(s64_off, 1));
+    if (e == hipSuccess) e = bupload(b, &b->plans, b->plans_h.data(), b->plans_h.size());
+    if (e == hipSuccess) e = bupload(b, &b->box_ids, ids.data(), ids.size());
+    if (e == hipSuccess) e = bupload(b, &b->coefs, cdev.data(), cdev.size());
+    if (e == hipSuccess) e = bupload(b, &b->wt, wt_h.data(), wt_h.size());
+    if (e == hipSuccess) e = balloc(b, &b->tabs, tsize * std::max<int64_t>(tab_off, 1));
+    if (e == hipSuccess) e = balloc(b, (void **)&b->wts, sizeof(double) * std::max<int64_t>(w_off, 1));
+    if (e == hipSuccess) e = balloc(b, (void **)&b->partials, sizeof(double) * (size_t)part_off * kMaxQ);
+    if (e == hipSuccess) e = balloc(b, (void **)&b->wave_status, sizeof(int32_t) * (size_t)part_off);
+    for (int k = 0; k < 2 && e == hipSuccess && state_off > 0; ++k) e = balloc(b, &b->state[k], tsize * state_off);
+    if (e == hipSuccess) e = balloc(b, (void **)&b->status, sizeof(int32_t) * (size_t)nboxes);
+    if (e == hipSuccess) e = balloc(b, (void **)&b->box_const, sizeof(double) * (size_t)nboxes * kMaxQ);
+    if (e == hipSuccess) e = balloc(b, (void **)&b->scratch64, sizeof(double) * std::max<int64_t>(s64_off, 1));
     if (e != hipSuccess) {
         batch_free(b);
         return fail(e == hipErrorOutOfMemory ? LLHMM_E_NOMEM : LLHMM_E_HIP, "batch allocation: %s",
@@ -676,6 +773,8 @@ llhmm_status llhmm_batch_create(llhmm_ctx *ctx, const llhmm_box *boxes, int32_t 
     *out = b;
     return LLHMM_OK;
 }
+
+extern "C" {
 
 llhmm_status llhmm_batch_destroy(llhmm_ctx *, llhmm_batch *batch) {
     batch_free(batch);
@@ -815,7 +914,7 @@ static llhmm_status run_batch(llhmm_ctx *ctx, llhmm_batch *b, const double *m_in
     for (size_t i = 0; i < b->classes.size(); ++i) items.push_back({b->classes[i].cost, (int)i});
     for (size_t i = 0; i < b->bands.size(); ++i) items.push_back({b->bands[i].cost, ~(int)i});
     std::stable_sort(items.begin(), items.end(), [](const Item &x, const Item &y) { return x.cost > y.cost; });
-    const int lanes = std::min<int>((int)items.size(), 1 + kSideStreams);
+    const int lanes = std::min<int>((int)items.size(), b->max_lanes);
     if (lanes > 1) {
         st = ensure_side_streams(b);
         if (st != LLHMM_OK) return st;
@@ -1100,6 +1199,362 @@ llhmm_status llhmm_macro_step(llhmm_ctx *ctx, int32_t npts, int32_t scheme, int3
     HIP_TRY(hipSetDevice(ctx->device));
     HIP_TRY(launch_macro(npts, scheme, step_index, stage, dt, alpha, M_dev, H_avg_dev, Y_dev, work_dev, stream));
     if (next_stage_out) *next_stage_out = (stage + 1 < nst) ? stage + 1 : 0;
+    return LLHMM_OK;
+}
+
+}  // extern "C"
+
+// ===================================================================== serving
+namespace {
+
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+struct ServeReq {
+    llhmm_box box;
+    int64_t id;
+    double t_submit;                 // host steady clock, seconds
+    const double *m_init, *M_macro;  // caller's device inputs for this request
+    llhmm_macro macro;
+    int32_t has_macro;
+    int64_t bytes;                   // device memory its share of a micro-batch needs (upper bound)
+};
+
+struct ServeDone {
+    int64_t id;
+    double H[kMaxQ];
+    int32_t status;
+    double latency_us;
+};
+
+struct ServeFlight {
+    llhmm_batch *batch = nullptr;
+    std::vector<ServeReq> reqs;
+    double *H_dev = nullptr;
+    int32_t *st_dev = nullptr;
+    hipEvent_t done = nullptr;
+    int64_t bytes = 0, seq = 0;
+    bool busy = false;
+};
+
+constexpr int64_t kBatchSlack = 32 * 256;  // alignment slack of one micro-batch's allocations
+
+bool same_source(const ServeReq &a, const ServeReq &b) {
+    return a.m_init == b.m_init && a.M_macro == b.M_macro && a.has_macro == b.has_macro &&
+           (!a.has_macro || memcmp(&a.macro, &b.macro, sizeof a.macro) == 0);
+}
+
+}  // namespace
+
+struct llhmm_server {
+    llhmm_ctx *ctx = nullptr;
+    llhmm_server_cfg cfg{};
+    std::vector<llhmm_coef> coefs;
+    Arena arena;
+    std::deque<ServeReq> queue;
+    std::vector<ServeFlight> slots;
+    std::vector<hipStream_t> streams;
+    double *H_host = nullptr;    // pinned [slots][max_batch_boxes][kMaxQ]
+    int32_t *st_host = nullptr;  // pinned [slots][max_batch_boxes]
+    std::deque<ServeDone> done;
+    int64_t reserved = 0, seq = 0;
+};
+
+// Device memory one request adds to a micro-batch (tables, weights, set-up
+// scratch, partial-sum slots, band state, time weights, descriptors), an upper
+// bound of what llhmm_batch_create allocates for it.
+static llhmm_status request_bytes(const llhmm_server *sv, const llhmm_box &bx, int i, int64_t &bytes) {
+    llhmm_status st = validate_box(bx, i, (int)sv->coefs.size());
+    if (st != LLHMM_OK) return st;
+    if (sv->coefs[bx.coef_index].dim != bx.dim)
+        return fail(LLHMM_E_INVALID, "request %d: coefficient dimension differs from box", i);
+    if (sv->coefs[bx.coef_index].sampled)
+        return fail(LLHMM_E_NOTSUP, "request %d: sampled coefficients are not served", i);
+    Planned pl{};
+    st = plan_one(bx, i, pl);
+    if (st != LLHMM_OK) return st;
+    const int prec = sv->cfg.precision;
+    const int64_t tsize = (prec == LLHMM_FP32) ? 4 : 8;
+    const int stages = (pl.integ == LLHMM_RK4P) ? 4 : 2;
+    auto it = registry().find(TileKey{prec, bx.dim, bx.n, bx.order, bx.bc, bx.quantity});
+    const BandTileInfo *bt = nullptr;
+    if (it == registry().end() && bx.dim == 2 && bx.order == 2) {
+        auto bit = band_registry().find(BandKey{prec, bx.n, bx.bc, bx.quantity});
+        BandGeom g;
+        if (bit != band_registry().end() && band_geometry(*bit->second, bx.n, stages, 1, g)) bt = bit->second;
+    }
+    if (it == registry().end() && !bt)
+        return fail(LLHMM_E_NOTSUP, "request %d: no kernel for dim %d, n %d, order %d, bc %d, quantity %d", i,
+                    bx.dim, bx.n, bx.order, bx.bc, bx.quantity);
+    const int form = (prec == LLHMM_FP32 || bt) ? 1 : 0;
+    const int64_t C = (bx.dim == 1) ? bx.n : (int64_t)bx.n * bx.n;
+    int64_t slots = (bx.dim == 2) ? 16 : 1;
+    int64_t band_state = 0, jobs = 0;
+    if (bt) {
+        int smax = 0;
+        for (int sc = 1; sc <= kMaxStepsPerLaunch; ++sc) {
+            BandGeom g;
+            if (band_geometry(*bt, bx.n, stages, sc, g)) smax = std::max(smax, g.strips);
+        }
+        slots = (int64_t)smax * (bt->threads / 64);
+        band_state = 2 * 3 * C * tsize;
+        jobs = smax * (int64_t)sizeof(BandJob);
+    }
+    bytes = tab_layout(bx.dim, bx.n, form).size * tsize + 2 * bx.n * 8 +
+            (form == 1 ? scratch64_size(bx.dim, bx.n) * 8 : 0) + slots * (kMaxQ * 8 + 4) + band_state + jobs +
+            (int64_t)(pl.M + 1) * 8 + (int64_t)sizeof(BoxPlan) + 4 + kMaxQ * 8 + 4 + kMaxQ * 8 + 4 +
+            (int64_t)sizeof(CoefDev) + 2 * 256;
+    return LLHMM_OK;
+}
+
+static void serve_release(llhmm_server *sv, ServeFlight &f) {
+    if (f.batch) batch_free(f.batch);
+    if (f.H_dev) sv->arena.release(f.H_dev);
+    if (f.st_dev) sv->arena.release(f.st_dev);
+    f.batch = nullptr;
+    f.H_dev = nullptr;
+    f.st_dev = nullptr;
+    sv->reserved -= f.bytes;
+    f.bytes = 0;
+    f.reqs.clear();
+    f.busy = false;
+}
+
+// Completes finished micro-batches (non-blocking).
+static llhmm_status serve_complete(llhmm_server *sv) {
+    const int mb = sv->cfg.max_batch_boxes;
+    for (size_t k = 0; k < sv->slots.size(); ++k) {
+        ServeFlight &f = sv->slots[k];
+        if (!f.busy) continue;
+        const hipError_t e = hipEventQuery(f.done);
+        if (e == hipErrorNotReady) continue;
+        if (e != hipSuccess) return fail(LLHMM_E_HIP, "serving: %s", hipGetErrorString(e));
+        const double t = now_s();
+        for (size_t r = 0; r < f.reqs.size(); ++r) {
+            ServeDone d;
+            d.id = f.reqs[r].id;
+            memcpy(d.H, sv->H_host + ((size_t)k * mb + r) * kMaxQ, sizeof d.H);
+            d.status = sv->st_host[(size_t)k * mb + r];
+            d.latency_us = (t - f.reqs[r].t_submit) * 1e6;
+            sv->done.push_back(d);
+        }
+        serve_release(sv, f);
+    }
+    return LLHMM_OK;
+}
+
+static void serve_fail_front(llhmm_server *sv, size_t count, llhmm_status code) {
+    const double t = now_s();
+    for (size_t r = 0; r < count && !sv->queue.empty(); ++r) {
+        ServeDone d{};
+        d.id = sv->queue.front().id;
+        d.status = code;
+        d.latency_us = (t - sv->queue.front().t_submit) * 1e6;
+        sv->done.push_back(d);
+        sv->queue.pop_front();
+    }
+}
+
+// Admits queued requests in arrival order while a stream slot is free and the
+// server's memory can hold them; each admitted group is one micro-batch on
+// its own stream: set-up, time stepping, upscale, copy of the results to
+// pinned host memory, completion event.
+static llhmm_status serve_admit(llhmm_server *sv) {
+    const int mb = sv->cfg.max_batch_boxes;
+    while (!sv->queue.empty()) {
+        int slot = -1;
+        bool any_busy = false;
+        for (size_t k = 0; k < sv->slots.size(); ++k) {
+            if (!sv->slots[k].busy && slot < 0) slot = (int)k;
+            any_busy |= sv->slots[k].busy;
+        }
+        if (slot < 0) break;
+        const ServeReq &head = sv->queue.front();
+        const int64_t avail = (int64_t)sv->arena.size - sv->reserved - kBatchSlack;
+        int64_t bytes = 0;
+        size_t n = 0;
+        for (const ServeReq &r : sv->queue) {
+            if ((int)n == mb || !same_source(r, head) || bytes + r.bytes > avail) break;
+            bytes += r.bytes;
+            ++n;
+        }
+        if (n == 0) {
+            if (any_busy) break;  // wait for memory to come back
+            serve_fail_front(sv, 1, LLHMM_E_BUDGET);  // larger than the whole budget
+            continue;
+        }
+        std::vector<llhmm_box> boxes(n);
+        for (size_t r = 0; r < n; ++r) boxes[r] = sv->queue[r].box;
+        ServeFlight &f = sv->slots[slot];
+        llhmm_status st = batch_create_impl(sv->ctx, boxes.data(), (int32_t)n, &sv->cfg.K, sv->coefs.data(),
+                                            (int32_t)sv->coefs.size(), sv->cfg.precision, &sv->arena, 1, &f.batch);
+        if (st == LLHMM_E_NOMEM) {
+            f.batch = nullptr;
+            if (any_busy) break;
+            serve_fail_front(sv, n, LLHMM_E_BUDGET);
+            continue;
+        }
+        if (st != LLHMM_OK) {
+            f.batch = nullptr;
+            serve_fail_front(sv, n, st);
+            continue;
+        }
+        f.H_dev = (double *)sv->arena.alloc(n * kMaxQ * sizeof(double));
+        f.st_dev = (int32_t *)sv->arena.alloc(n * sizeof(int32_t));
+        f.bytes = bytes + kBatchSlack;
+        sv->reserved += f.bytes;
+        f.busy = true;
+        if (!f.H_dev || !f.st_dev) {
+            serve_release(sv, f);
+            if (any_busy) break;
+            serve_fail_front(sv, n, LLHMM_E_BUDGET);
+            continue;
+        }
+        hipStream_t s = sv->streams[slot];
+        st = run_batch(sv->ctx, f.batch, head.m_init, head.has_macro ? &head.macro : nullptr, head.M_macro,
+                       nullptr, nullptr, 0, s);
+        if (st != LLHMM_OK) {
+            serve_release(sv, f);
+            serve_fail_front(sv, n, st);
+            continue;
+        }
+        HIP_TRY(launch_upscale(f.batch->partials, f.batch->wave_status, f.batch->box_const, f.batch->plans,
+                               (int)n, f.H_dev, kMaxQ, f.batch->status, f.st_dev, s));
+        HIP_TRY(hipMemcpyAsync(sv->H_host + (size_t)slot * mb * kMaxQ, f.H_dev, n * kMaxQ * sizeof(double),
+                               hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(sv->st_host + (size_t)slot * mb, f.st_dev, n * sizeof(int32_t),
+                               hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipEventRecord(f.done, s));
+        f.seq = sv->seq++;
+        f.reqs.assign(sv->queue.begin(), sv->queue.begin() + n);
+        sv->queue.erase(sv->queue.begin(), sv->queue.begin() + n);
+    }
+    return LLHMM_OK;
+}
+
+static void server_free(llhmm_server *sv) {
+    if (!sv) return;
+    for (ServeFlight &f : sv->slots) {
+        if (f.busy && f.done) (void)hipEventSynchronize(f.done);
+        if (f.busy) serve_release(sv, f);
+        if (f.done) (void)hipEventDestroy(f.done);
+    }
+    for (hipStream_t s : sv->streams)
+        if (s) (void)hipStreamDestroy(s);
+    if (sv->H_host) (void)hipHostFree(sv->H_host);
+    if (sv->st_host) (void)hipHostFree(sv->st_host);
+    if (sv->arena.base) (void)hipFree(sv->arena.base);
+    delete sv;
+}
+
+extern "C" {
+
+llhmm_status llhmm_server_create(llhmm_ctx *ctx, const llhmm_server_cfg *cfg, const llhmm_coef *coefs,
+                                 int32_t ncoefs, llhmm_server **out) {
+    if (!ctx || !cfg || !out) return fail(LLHMM_E_INVALID, "ctx/cfg/out is NULL");
+    *out = nullptr;
+    if (cfg->precision != LLHMM_FP32 && cfg->precision != LLHMM_FP64) return fail(LLHMM_E_INVALID, "bad precision");
+    if (cfg->max_inflight < 1 || cfg->max_inflight > 16) return fail(LLHMM_E_INVALID, "max_inflight in [1, 16]");
+    if (cfg->max_batch_boxes < 1) return fail(LLHMM_E_INVALID, "max_batch_boxes >= 1");
+    if (cfg->device_bytes < (1 << 20)) return fail(LLHMM_E_INVALID, "device_bytes >= 1 MiB");
+    if (!coefs || ncoefs <= 0) return fail(LLHMM_E_INVALID, "coefficients missing");
+    if (cfg->K.p_x > 7 || cfg->K.p_t > 7) return fail(LLHMM_E_INVALID, "kernel order p must be <= 7");
+    HIP_TRY(hipSetDevice(ctx->device));
+    llhmm_server *sv = new llhmm_server();
+    sv->ctx = ctx;
+    sv->cfg = *cfg;
+    sv->coefs.assign(coefs, coefs + ncoefs);
+    hipError_t e = sv->arena.init((size_t)cfg->device_bytes);
+    const size_t mb = (size_t)cfg->max_batch_boxes;
+    if (e == hipSuccess) e = hipHostMalloc((void **)&sv->H_host, sizeof(double) * cfg->max_inflight * mb * kMaxQ);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&sv->st_host, sizeof(int32_t) * cfg->max_inflight * mb);
+    sv->slots.resize(cfg->max_inflight);
+    sv->streams.assign(cfg->max_inflight, nullptr);
+    for (int k = 0; k < cfg->max_inflight && e == hipSuccess; ++k) {
+        e = hipStreamCreateWithFlags(&sv->streams[k], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&sv->slots[k].done, hipEventDisableTiming);
+    }
+    if (e != hipSuccess) {
+        server_free(sv);
+        return fail(e == hipErrorOutOfMemory ? LLHMM_E_NOMEM : LLHMM_E_HIP, "server: %s", hipGetErrorString(e));
+    }
+    *out = sv;
+    return LLHMM_OK;
+}
+
+llhmm_status llhmm_server_destroy(llhmm_server *sv) {
+    server_free(sv);
+    return LLHMM_OK;
+}
+
+llhmm_status llhmm_server_submit(llhmm_server *sv, const llhmm_box *boxes, int32_t n, const int64_t *ids,
+                                 const double *m_init_dev, const llhmm_macro *macro, const double *M_macro_dev) {
+    if (!sv || (n > 0 && (!boxes || !ids))) return fail(LLHMM_E_INVALID, "server/boxes/ids is NULL");
+    std::vector<ServeReq> reqs(n);
+    const double t = now_s();
+    for (int i = 0; i < n; ++i) {
+        ServeReq &r = reqs[i];
+        r.box = boxes[i];
+        r.id = ids[i];
+        r.t_submit = t;
+        r.m_init = m_init_dev;
+        r.M_macro = M_macro_dev;
+        memset(&r.macro, 0, sizeof r.macro);
+        r.has_macro = macro != nullptr;
+        if (macro) r.macro = *macro;
+        if (boxes[i].init_mode == LLHMM_INIT_EXPLICIT && !m_init_dev)
+            return fail(LLHMM_E_INVALID, "request %d: explicit init needs m_init_dev", i);
+        if (boxes[i].init_mode == LLHMM_INIT_MACRO_Q && (!macro || !M_macro_dev))
+            return fail(LLHMM_E_INVALID, "request %d: macro init needs macro and M_macro_dev", i);
+        llhmm_status st = request_bytes(sv, r.box, i, r.bytes);
+        if (st != LLHMM_OK) return st;
+    }
+    for (ServeReq &r : reqs) sv->queue.push_back(r);
+    return serve_admit(sv);
+}
+
+llhmm_status llhmm_server_poll(llhmm_server *sv, int32_t wait, int32_t max, int64_t *ids_out, double *H_out,
+                               int32_t *status_out, double *latency_us_out, int32_t *ndone) {
+    if (!sv || !ndone) return fail(LLHMM_E_INVALID, "server/ndone is NULL");
+    *ndone = 0;
+    HIP_TRY(hipSetDevice(sv->ctx->device));
+    llhmm_status st = serve_complete(sv);
+    if (st == LLHMM_OK) st = serve_admit(sv);
+    while (st == LLHMM_OK && wait && sv->done.empty()) {
+        ServeFlight *oldest = nullptr;
+        for (ServeFlight &f : sv->slots)
+            if (f.busy && (!oldest || f.seq < oldest->seq)) oldest = &f;
+        if (!oldest) break;  // nothing in flight and nothing admissible
+        HIP_TRY(hipEventSynchronize(oldest->done));
+        st = serve_complete(sv);
+        if (st == LLHMM_OK) st = serve_admit(sv);
+    }
+    if (st != LLHMM_OK) return st;
+    int k = 0;
+    while (k < max && !sv->done.empty()) {
+        const ServeDone &d = sv->done.front();
+        if (ids_out) ids_out[k] = d.id;
+        if (H_out) memcpy(H_out + (size_t)k * kMaxQ, d.H, sizeof d.H);
+        if (status_out) status_out[k] = d.status;
+        if (latency_us_out) latency_us_out[k] = d.latency_us;
+        sv->done.pop_front();
+        ++k;
+    }
+    *ndone = k;
+    return LLHMM_OK;
+}
+
+llhmm_status llhmm_server_stats(const llhmm_server *sv, int64_t *queued, int64_t *inflight,
+                                int64_t *bytes_in_use, int64_t *bytes_total) {
+    if (!sv) return fail(LLHMM_E_INVALID, "server is NULL");
+    int64_t fl = 0;
+    for (const ServeFlight &f : sv->slots)
+        if (f.busy) fl += (int64_t)f.reqs.size();
+    if (queued) *queued = (int64_t)sv->queue.size();
+    if (inflight) *inflight = fl;
+    if (bytes_in_use) *bytes_in_use = (int64_t)sv->arena.used;
+    if (bytes_total) *bytes_total = (int64_t)sv->arena.size;
     return LLHMM_OK;
 }
 

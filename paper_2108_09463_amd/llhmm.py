@@ -58,6 +58,12 @@ class Macro(ctypes.Structure):
                 ("x0", ctypes.c_double * 2)]
 
 
+class ServerCfg(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("max_inflight", ctypes.c_int32),
+                ("max_batch_boxes", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("device_bytes", ctypes.c_int64), ("K", Kernel)]
+
+
 _lib = None
 _SYMBOLS = {
     "llhmm_abi_version": (ctypes.c_int32, []),
@@ -96,6 +102,17 @@ _SYMBOLS = {
     "llhmm_batch_band_steps": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "llhmm_tune_save": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p]),
     "llhmm_tune_load": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p]),
+    "llhmm_server_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ServerCfg), ctypes.POINTER(Coef),
+                                           ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]),
+    "llhmm_server_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "llhmm_server_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Box), ctypes.c_int32,
+                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(Macro),
+                                           ctypes.c_void_p]),
+    "llhmm_server_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.POINTER(ctypes.c_int32)]),
+    "llhmm_server_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_void_p]),
     "llhmm_macro_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                         ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                                         ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
@@ -364,3 +381,58 @@ def pack_explicit_init(boxes, init_of):
 
 def macro_dict(macro, dim=2):
     return dict(dim=dim, n=macro["n"], dX=macro["dX"], x0=macro.get("x0", (0.0, 0.0)))
+
+
+# ---------------------------------------------------------------- serving
+class Server:
+    """Continuous-batching request loop of the library (llhmm_server_*)."""
+
+    def __init__(self, ctx, coefs, precision, max_inflight=4, max_batch_boxes=1024,
+                 device_bytes=8 << 30, K=None):
+        self.ctx = ctx
+        cfg = ServerCfg()
+        cfg.precision = precision
+        cfg.max_inflight = max_inflight
+        cfg.max_batch_boxes = max_batch_boxes
+        cfg.device_bytes = int(device_bytes)
+        cfg.K = K or kernel()
+        self.coefs = (Coef * len(coefs))(*coefs)
+        h = ctypes.c_void_p()
+        _check(lib().llhmm_server_create(ctx.h, ctypes.byref(cfg), self.coefs, len(coefs), ctypes.byref(h)))
+        self.h = h
+        self.max_batch = max_batch_boxes
+        self._keep = []   # host structs of pending submits
+
+    def submit(self, boxes, ids, m_init=None, macro=None, M_macro=None):
+        arr = box_array(boxes)
+        idv = np.ascontiguousarray(ids, dtype=np.int64)
+        ms = _macro_struct(macro)
+        _check(lib().llhmm_server_submit(self.h, arr, len(boxes), idv.ctypes.data, _ptr(m_init),
+                                         ms[0] if ms else None, _ptr(M_macro)))
+
+    def poll(self, wait=False, max_results=4096):
+        ids = np.zeros(max_results, np.int64)
+        H = np.zeros((max_results, 6), np.float64)
+        st = np.zeros(max_results, np.int32)
+        lat = np.zeros(max_results, np.float64)
+        n = ctypes.c_int32()
+        _check(lib().llhmm_server_poll(self.h, 1 if wait else 0, max_results, ids.ctypes.data, H.ctypes.data,
+                                       st.ctypes.data, lat.ctypes.data, ctypes.byref(n)))
+        k = n.value
+        return ids[:k], H[:k], st[:k], lat[:k]
+
+    def stats(self):
+        v = [ctypes.c_int64() for _ in range(4)]
+        _check(lib().llhmm_server_stats(self.h, *[ctypes.byref(x) for x in v]))
+        return dict(queued=v[0].value, inflight=v[1].value, bytes_in_use=v[2].value, bytes_total=v[3].value)
+
+    def close(self):
+        if self.h:
+            lib().llhmm_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,159 @@
+"""The continuous-batching request loop (llhmm_server_*) on the GPU.
+
+* Each result is the same alone and in a mix: requests solved one at a time
+  and the same requests released in overlapping bursts give identical
+  upscaled fields (the kernels and reduction order per box do not depend on
+  the batch), and they match the FP32 bar against the oracle.
+* A small device budget makes requests queue until memory comes back; every
+  request still completes with the batch solution.
+* A request larger than the whole budget completes with LLHMM_E_BUDGET.
+* A served macro stage equals the same stage solved as one batch.
+"""
+import numpy as np
+import pytest
+
+from paper_2108_09463_amd import inputs
+from paper_2108_09463_amd import llhmm as L
+
+from test_gpu_parity import rel_err, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return L.llhmm_create(0)
+
+
+def request_set(n=40, seed=41, eta_scale=0.05):
+    """Mixed-size 2-D requests (explicit EX2 data) with random damping."""
+    eps = 1.0 / 200.0
+    rng = np.random.default_rng(seed)
+    ns = rng.choice(np.array(inputs.UNEVEN_SIZES), size=n)
+    boxes = [inputs.make_box(dim=2, n=int(ns[i]), eps=eps, alpha=float(rng.uniform(0.01, 0.2)),
+                             mu=3 * eps, mu_box=3 * eps, eta=eta_scale * eps ** 2, a_max=1.65,
+                             center=(float(rng.random()), float(rng.random()))) for i in range(n)]
+    wl = inputs.Workload("requests", 2, boxes, [inputs.coef_quasi(eps)], init=inputs.InitEX2(),
+                         precision=inputs.FP32)
+    return wl
+
+
+def upload_init(wl):
+    import torch
+    host, offs = L.pack_explicit_init(wl.boxes, wl.init_of)
+    for b, o in zip(wl.boxes, offs):
+        b["init_offset"] = o
+    return torch.from_numpy(host).to(torch.device("cuda", 0))
+
+
+def drain(sv, n, H, st=None):
+    got = 0
+    while got < n:
+        ids, Hk, s, _ = sv.poll(wait=True)
+        H[ids] = Hk[:, :3]
+        if st is not None:
+            st[ids] = s
+        got += len(ids)
+
+
+def test_alone_equals_mix(ctx):
+    wl = request_set()
+    m_init = upload_init(wl)
+    n = len(wl.boxes)
+    sv = L.Server(ctx, [L.to_coef(c) for c in wl.coefs], inputs.FP32, max_inflight=4,
+                  max_batch_boxes=16, device_bytes=1 << 30)
+    H_alone = np.full((n, 3), np.nan)
+    for i in range(n):
+        sv.submit([wl.boxes[i]], [i], m_init=m_init)
+        drain(sv, 1, H_alone)
+    H_mix = np.full((n, 3), np.nan)
+    st = np.full(n, -9, np.int32)
+    order = np.random.default_rng(5).permutation(n)
+    got = 0
+    for part in np.array_split(order, 3):      # bursts released while earlier ones run
+        sv.submit([wl.boxes[i] for i in part], part, m_init=m_init)
+        ids, Hk, s, _ = sv.poll(wait=False)
+        H_mix[ids] = Hk[:, :3]
+        st[ids] = s
+        got += len(ids)
+    drain(sv, n - got, H_mix, st)
+    assert (st == 0).all()
+    assert np.array_equal(H_alone, H_mix)
+    idx = [int(np.nonzero(np.array([b["n"] for b in wl.boxes]) == s)[0][0]) for s in (32, 96, 128)]
+    Ho = np.stack([r["out"] for r in run_oracle(wl, idx)])
+    assert rel_err(H_mix[idx], Ho).max() <= 1e-5
+    sv.close()
+
+
+def test_small_budget_queues_and_completes(ctx):
+    from paper_2108_09463_amd.runner import Prepared
+    wl = request_set(n=30, seed=42)
+    m_init = upload_init(wl)
+    n = len(wl.boxes)
+    budget = 24 << 20        # a few large boxes at a time
+    sv = L.Server(ctx, [L.to_coef(c) for c in wl.coefs], inputs.FP32, max_inflight=3,
+                  max_batch_boxes=8, device_bytes=budget)
+    sv.submit(wl.boxes, np.arange(n), m_init=m_init)
+    seen_queue = sv.stats()["queued"]
+    H = np.full((n, 3), np.nan)
+    st = np.full(n, -9, np.int32)
+    got = 0
+    while got < n:
+        s = sv.stats()
+        assert s["bytes_in_use"] <= s["bytes_total"]
+        ids, Hk, stk, _ = sv.poll(wait=True)
+        H[ids] = Hk[:, :3]
+        st[ids] = stk
+        got += len(ids)
+    assert seen_queue > 0, "the budget should have held requests back"
+    assert (st == 0).all()
+    p = Prepared(wl, precision=inputs.FP32, ctx=ctx)
+    out = p.solve()
+    assert np.array_equal(out["H"][:, :3], H)
+    sv.close()
+
+
+def test_request_over_budget(ctx):
+    wl = request_set(n=3, seed=43)
+    for i, n in enumerate((32, 128, 32)):
+        wl.boxes[i]["n"] = n
+    m_init = upload_init(wl)
+    sv = L.Server(ctx, [L.to_coef(c) for c in wl.coefs], inputs.FP32, max_inflight=2,
+                  max_batch_boxes=4, device_bytes=1 << 20)
+    sv.submit(wl.boxes, np.arange(3), m_init=m_init)
+    st = {}
+    while len(st) < 3:
+        ids, _, s, _ = sv.poll(wait=True)
+        st.update(zip(ids.tolist(), s.tolist()))
+    assert st[1] == L.E_BUDGET
+    sv.close()
+
+
+def test_served_stage_equals_batch(ctx):
+    import torch
+    from paper_2108_09463_amd.runner import Prepared
+    from paper_2108_09463_amd.serve import ServedRun
+    n_macro = 12
+    boxes, coefs = inputs.served_boxes(n_macro, seed=5)
+    for b in boxes:                       # short micro runs keep the test fast
+        b["eta"] = 0.05 * b["eps"] ** 2
+    run = ServedRun(n_macro=n_macro, ctx=ctx, boxes=boxes, coefs=coefs, max_inflight=3,
+                    max_batch_boxes=40, device_bytes=1 << 30)
+    rec = run.stage(run.Y, 0)
+    assert (rec["status"] == 0).all()
+    wl = inputs.Workload("served", 2, boxes, coefs, macro=dict(n=n_macro, dX=1.0 / n_macro,
+                         x0=(0.0, 0.0), M=inputs.served_macro(n_macro)), precision=inputs.FP32)
+    p = Prepared(wl, precision=inputs.FP32, ctx=ctx)
+    out = p.solve()
+    assert np.array_equal(out["H"][:, :3], rec["H"])
+    # two more macro stages run through the loop (HeunP start-up)
+    nxt = run.macro_stage(0, 0, rec["H"])
+    assert nxt == 1
+    rec2 = run.stage(run.Y, 1)
+    assert (rec2["status"] == 0).all() and np.isfinite(rec2["H"]).all()
+    assert run.macro_stage(0, 1, rec2["H"]) == 0
+    M = run.M.cpu().numpy()
+    assert np.abs(np.linalg.norm(M, axis=0) - 1).max() < 1e-13
+    run.close()
