@@ -93,15 +93,16 @@ def flops_per_cell_step(dim, order, integ):
     return 2 * h + 77 if integ == 1 else 4 * h + 149
 
 
-def time_batch(prep, steps, warmup):
+def time_batch(prep, steps, warmup, graph=False):
     """Times `steps` whole steps (set-up + time stepping + upscale) with torch
     events on the launch stream; separately, the library's own HIP events on the
     same stream give the set-up and time-stepping kernels' durations per step."""
     import torch
     from paper_2108_09463_amd import llhmm as L
     stream = torch.cuda.current_stream()
+    launch = prep.launch_graph if graph else prep.launch
     for _ in range(warmup):
-        prep.launch()
+        launch()
     torch.cuda.synchronize()
     prep.batch.set_timing(True)
     lat = []
@@ -113,7 +114,7 @@ def time_batch(prep, steps, warmup):
         a = torch.cuda.Event(enable_timing=True)
         b = torch.cuda.Event(enable_timing=True)
         a.record(stream)
-        prep.launch()
+        launch()
         b.record(stream)
         lat.append((a, b))
     end_all.record(stream)
@@ -179,16 +180,22 @@ def algorithmic_flops(boxes):
     return float(tot)
 
 
-def measure(wl, precision, steps, warmup):
+def measure(wl, precision, steps, warmup, tune=False, graph=False):
     """Times one workload at one precision; returns rates, latencies and the
-    roofline of the time-stepping phase."""
+    roofline of the time-stepping phase.  tune: run the band-mode autotuner
+    first; graph: launch the whole solve as one captured HIP graph (the
+    library's events then time the whole call as time stepping)."""
     import torch
     from paper_2108_09463_amd import inputs
     from paper_2108_09463_amd.runner import Prepared
     prep = Prepared(wl, precision=precision)
     cs = prep.cell_steps()
     flops = algorithmic_flops(prep.boxes)
-    t = time_batch(prep, steps, warmup)
+    steps_per_launch = None
+    if tune:
+        sp = prep.tune(reps=1)
+        steps_per_launch = {int(n): int(k) for n, k in {b["n"]: k for b, k in zip(prep.boxes, sp) if k}.items()}
+    t = time_batch(prep, steps, warmup, graph=graph)
     torch.cuda.synchronize()
     H = prep.H.cpu().numpy()
     st = prep.status.cpu().numpy()
@@ -199,7 +206,7 @@ def measure(wl, precision, steps, warmup):
     achieved = flops / (t["kernel_ms"] * 1e-3)
     peak = PEAK_FP32 if precision == inputs.FP32 else PEAK_FP64
     name = "fp32" if precision == inputs.FP32 else "fp64"
-    return dict(cell_steps=cs, ms_per_step=t["ms_per_step"], rate=rate,
+    return dict(cell_steps=cs, ms_per_step=t["ms_per_step"], rate=rate, steps_per_launch=steps_per_launch,
                 p50_ms=pct(t["lat_ms"], 50), p99_ms=pct(t["lat_ms"], 99),
                 setup_ms=t["setup_ms"], kernel_ms=t["kernel_ms"], H=H, status_ok=bool((st == 0).all()),
                 roofline=dict(bound="alu", achieved=achieved / 1e12, peak=peak / 1e12,
@@ -207,6 +214,45 @@ def measure(wl, precision, steps, warmup):
                               traffic=measured_traffic(name) if wl.name == "two_d_batch" else None,
                               kernel="time-stepping kernels", kernel_ms=t["kernel_ms"],
                               flops_per_cell_step=flops / cs, flops_per_launch=flops))
+
+
+def served(stages):
+    """The served HMM run on a 128x128 macro grid: each macro stage issues
+    16384 micro requests (n in {32..128}, eps in {1/100, 1/200, 1/400},
+    alpha_micro = 1.2, HeunP, Q_[4] data), released in shuffled bursts of
+    256-4096 back to back (closed loop) into the request loop."""
+    import torch
+    from paper_2108_09463_amd.serve import ServedRun
+    run = ServedRun(n_macro=128, max_inflight=4, max_batch_boxes=2048, device_bytes=24 << 30)
+    recs = []
+    k = 0
+    for step in range(1 << 30):
+        stage = 0
+        while len(recs) < stages:
+            rec = run.stage(run.Y, k)
+            k += 1
+            stage = run.macro_stage(step, stage, rec["H"])
+            recs.append(rec)
+            if stage == 0:
+                break
+        if len(recs) >= stages:
+            break
+    torch.cuda.synchronize()
+    lat = np.concatenate([r["latency_us"] for r in recs]) * 1e-3
+    bl = np.concatenate([np.array(r["burst_s"]) for r in recs]) * 1e3
+    st = np.array([r["stage_s"] for r in recs])
+    ok = all(bool((r["status"] == 0).all()) for r in recs)
+    run.close()
+    return {"workload": "served: 128x128 macro grid (EX2 macro data), 16384 requests per macro stage, "
+                        "n in {32,48,64,96,128}, eps in {1/100,1/200,1/400}, mu=mu'=3eps, eta=eps^2, "
+                        "alpha_micro=1.2 HeunP, Q4 init, FP32; bursts of 256-4096 released back to back; "
+                        "4 micro-batch slots of up to 2048 requests",
+            "stages": len(recs), "value": run.cell_steps * len(recs) / st.sum(), "unit": "cell-steps/s",
+            "cell_steps_per_stage": run.cell_steps,
+            "request_latency_ms": {"p50": pct(list(lat), 50), "p99": pct(list(lat), 99)},
+            "burst_latency_ms": {"p50": pct(list(bl), 50), "p99": pct(list(bl), 99)},
+            "stage_latency_ms": {"p50": pct(list(st * 1e3), 50), "p99": pct(list(st * 1e3), 99)},
+            "status_ok": ok}
 
 
 WORKLOADS = {
@@ -230,7 +276,9 @@ def main():
     ap.add_argument("--precision", choices=["both", "fp32", "fp64"], default="both")
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="two_d_batch")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the uneven-batch measurement added to the default line")
+                    help="skip the uneven-batch and served measurements added to the default line")
+    ap.add_argument("--served-stages", type=int, default=1,
+                    help="macro stages of the served 128x128 run in the default line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (PMC counter calibration)")
     args = ap.parse_args()
@@ -287,13 +335,16 @@ def main():
         line["speedup_fp32_vs_fp64"] = r["rate"] / f["rate"]
     if args.workload == "two_d_batch" and not args.no_extra:
         wu = inputs.uneven_batch()
-        u = measure(wu, inputs.FP32, 3, 1)
-        line["uneven_batch"] = {"workload": WORKLOADS["uneven_batch"], "dtype": "f32",
+        u = measure(wu, inputs.FP32, 3, 1, tune=True, graph=True)
+        line["uneven_batch"] = {"workload": WORKLOADS["uneven_batch"] + "; band steps per launch tuned, "
+                                "whole solve launched as one HIP graph", "dtype": "f32",
                                 "value": u["rate"], "unit": "cell-steps/s",
                                 "ms_per_step": u["ms_per_step"], "cell_steps_per_step": u["cell_steps"],
                                 "latency_ms": {"p50": u["p50_ms"], "p99": u["p99_ms"]},
-                                "phase_ms": {"setup": u["setup_ms"], "time_stepping": u["kernel_ms"]},
+                                "band_steps_per_launch": u["steps_per_launch"],
                                 "roofline": u["roofline"], "status_ok": u["status_ok"]}
+        if args.served_stages > 0:
+            line["served"] = served(args.served_stages)
     print(json.dumps(line), flush=True)
 
 
