@@ -243,15 +243,34 @@ struct MicroLane {
 
 #pragma unroll
         for (int r = 0; r < R; ++r) {
+            // Periodic second order, form 1: every x1 face flux is formed once.  The
+            // east gradients of the own columns (the last one reaches the right
+            // neighbour), and the west flux of column 0 as the left neighbour's last
+            // east gradient times this lane's own west-face coefficient, so the two
+            // sides of the box's periodic seam keep their own coefficients.
+            constexpr bool X1FAST = (ORD == 2) && (FORM == 1) && (BC == LLHMM_BC_PERIODIC_PERT);
+            T ge[X1FAST ? K : 1][3], Fwest[3];
+            if constexpr (X1FAST) {
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c)
+                        ge[k][c] = (k + 1 < K) ? y[r][(k + 1 < K) ? k + 1 : 0][c] - y[r][k][c]
+                                               : dpp_mov<DppCtl<L>::ROT_FR>(y[r][0][c]) - y[r][K - 1][c];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) Fwest[c] = axv(r, 0) * dpp_mov<DppCtl<L>::ROT_FL>(ge[K - 1][c]);
+            }
             // x1 halo values from the neighbouring lanes (taken before any update of this row)
             T yw[YH][3], ye[YH][3];
+            if constexpr (!X1FAST) {
 #pragma unroll
-            for (int i = 0; i < YH; ++i)
+                for (int i = 0; i < YH; ++i)
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    yw[i][c] = nb<DppCtl<L>::ROT_FL, DppCtl<L>::SH_FL>(y[r][K - YH + i][c]);
-                    ye[i][c] = nb<DppCtl<L>::ROT_FR, DppCtl<L>::SH_FR>(y[r][i][c]);
-                }
+                    for (int c = 0; c < 3; ++c) {
+                        yw[i][c] = nb<DppCtl<L>::ROT_FL, DppCtl<L>::SH_FL>(y[r][K - YH + i][c]);
+                        ye[i][c] = nb<DppCtl<L>::ROT_FR, DppCtl<L>::SH_FR>(y[r][i][c]);
+                    }
+            }
             // row values at local column p in [-YH, K+YH)
             auto yrow = [&](int p, int c) -> T {
                 return (p < 0) ? yw[p + YH][c] : ((p >= K) ? ye[p - K][c] : y[r][p][c]);
@@ -276,16 +295,32 @@ struct MicroLane {
             };
             // rolling window of x1 fluxes: faces lf = k .. k+FW+FE-1 before cell k
             T Fw[FW + FE][3];
+            if constexpr (!X1FAST) {
 #pragma unroll
-            for (int w = 0; w < FW + FE; ++w)
+                for (int w = 0; w < FW + FE; ++w)
 #pragma unroll
-                for (int c = 0; c < 3; ++c) Fw[w][c] = face1(w, c);
+                    for (int c = 0; c < 3; ++c) Fw[w][c] = face1(w, c);
+            }
 
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 T H[3], Fx_east[3];
+                if constexpr (X1FAST) {
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
+                    for (int c = 0; c < 3; ++c) {
+                        if (k + 1 < K || AVG == AVG_FLUX) {
+                            const T fe = axv(r, k + 1) * ge[k][c];
+                            H[c] = fe - Fwest[c];
+                            Fx_east[c] = fe;
+                            Fwest[c] = fe;
+                        } else {
+                            H[c] = fma_t(axv(r, K), ge[K - 1][c], -Fwest[c]);
+                            Fx_east[c] = (T)0;
+                        }
+                    }
+                }
+#pragma unroll
+                for (int c = 0; c < (X1FAST ? 0 : 3); ++c) {
                     const T fnew = face1(k + FW + FE, c);
                     if (ORD == 2) H[c] = fnew - Fw[0][c];
                     else H[c] = (T)27 * (Fw[(ORD == 2) ? 0 : 2][c] - Fw[(ORD == 2) ? 0 : 1][c]) - (fnew - Fw[0][c]);

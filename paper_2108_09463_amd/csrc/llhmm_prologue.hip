@@ -64,8 +64,20 @@ __device__ void lagrange5(double s, double Lb[5]) {
     }
 }
 
+// Per-block tables for Q_[4]: the 5^dim x 3 macro values around the box's
+// macro node ([c][l0][l1] in 2-D, [c][l0] in 1-D) and the Lagrange basis at
+// every grid index i = -3 .. n+2 ([(i + 3) * 5 + l]; the same grid along x1
+// and x2).  Built once per box in LDS by init_tables.
+struct InitTables {
+    const double *Mloc;
+    const double *Lb;
+};
+
+constexpr int kLagMax = 256 + 2 * kGhost;  // grid indices of the largest (1-D) box
+
 // m_init at grid point (i0, i1); ghost points allowed.
-__device__ void minit_at(const PrologueArgs &A, const BoxPlan &P, int i0, int i1, double out[3]) {
+__device__ void minit_at(const PrologueArgs &A, const BoxPlan &P, const InitTables &T, int i0, int i1,
+                         double out[3]) {
     const int D = P.dim;
     if (P.init_mode == LLHMM_INIT_EXPLICIT) {
         const int E = P.n + 2 * kGhost;
@@ -77,26 +89,17 @@ __device__ void minit_at(const PrologueArgs &A, const BoxPlan &P, int i0, int i1
         out[2] = src[2 * cells + idx];
         return;
     }
-    const int nm = A.macro.n;
-    const long npts = (D == 1) ? (long)nm : (long)nm * nm;
-    double L0[5], L1[5];
-    lagrange5(grid_xi(P, i0) / A.macro.dX, L0);
+    const double *L0 = T.Lb + (i0 + kGhost) * 5;
     double p[3] = {0.0, 0.0, 0.0};
     if (D == 1) {
-        for (int l0 = 0; l0 < 5; ++l0) {
-            int k0 = ((P.mi0 + l0 - 2) % nm + nm) % nm;
-            for (int c = 0; c < 3; ++c) p[c] = p[c] + A.M_macro[c * npts + k0] * L0[l0];
-        }
+        for (int l0 = 0; l0 < 5; ++l0)
+            for (int c = 0; c < 3; ++c) p[c] = p[c] + T.Mloc[c * 5 + l0] * L0[l0];
     } else {
-        lagrange5(grid_xi(P, i1) / A.macro.dX, L1);
+        const double *L1 = T.Lb + (i1 + kGhost) * 5;
         for (int l1 = 0; l1 < 5; ++l1) {
-            int k1 = ((P.mi1 + l1 - 2) % nm + nm) % nm;
             double q[3] = {0.0, 0.0, 0.0};
-            for (int l0 = 0; l0 < 5; ++l0) {  // along x1 first
-                int k0 = ((P.mi0 + l0 - 2) % nm + nm) % nm;
-                for (int c = 0; c < 3; ++c)
-                    q[c] = q[c] + A.M_macro[c * npts + (long)k0 * nm + k1] * L0[l0];
-            }
+            for (int l0 = 0; l0 < 5; ++l0)  // along x1 first
+                for (int c = 0; c < 3; ++c) q[c] = q[c] + T.Mloc[(c * 5 + l0) * 5 + l1] * L0[l0];
             for (int c = 0; c < 3; ++c) p[c] = p[c] + q[c] * L1[l1];
         }
     }
@@ -107,24 +110,24 @@ __device__ void minit_at(const PrologueArgs &A, const BoxPlan &P, int i0, int i1
 }
 
 // Ghost offset delta at point p along `axis` (other coordinate o); zero inside.
-__device__ void ghost_delta(const PrologueArgs &A, const BoxPlan &P, int axis, int p, int o,
-                            double out[3]) {
+__device__ void ghost_delta(const PrologueArgs &A, const BoxPlan &P, const InitTables &T, int axis, int p,
+                            int o, double out[3]) {
     const int N = P.n;
     if (p >= 0 && p < N) {
         out[0] = out[1] = out[2] = 0.0;
         return;
     }
     double g[3];
-    if (axis == 0) minit_at(A, P, p, o, g);
-    else minit_at(A, P, o, p, g);
+    if (axis == 0) minit_at(A, P, T, p, o, g);
+    else minit_at(A, P, T, o, p, g);
     if (P.bc == LLHMM_BC_DIRICHLET) {
         out[0] = g[0]; out[1] = g[1]; out[2] = g[2];
         return;
     }
     int w = ((p % N) + N) % N;
     double h[3];
-    if (axis == 0) minit_at(A, P, w, o, h);
-    else minit_at(A, P, o, w, h);
+    if (axis == 0) minit_at(A, P, T, w, o, h);
+    else minit_at(A, P, T, o, w, h);
     out[0] = g[0] - h[0];
     out[1] = g[1] - h[1];
     out[2] = g[2] - h[2];
@@ -134,18 +137,18 @@ __device__ void ghost_delta(const PrologueArgs &A, const BoxPlan &P, int axis, i
 // hi + lo = a' * G(delta) (lo is the rounding error of the product, exact by
 // FMA): with Dirichlet data delta is O(1) and a' = O(dx^-2), so hi alone would
 // carry an absolute error far above the flux's own rounding.
-__device__ void face_tau(const PrologueArgs &A, const BoxPlan &P, int axis, int f, int o,
-                         double hi[3], double lo[3]) {
+__device__ void face_tau(const PrologueArgs &A, const BoxPlan &P, const InitTables &T, int axis, int f,
+                         int o, double hi[3], double lo[3]) {
     double a = face_coef(A, P, axis, axis == 0 ? f : o, axis == 0 ? o : f) * P.a_scale;
     double dp1[3], d0[3], g[3];
-    ghost_delta(A, P, axis, f + 1, o, dp1);
-    ghost_delta(A, P, axis, f, o, d0);
+    ghost_delta(A, P, T, axis, f + 1, o, dp1);
+    ghost_delta(A, P, T, axis, f, o, d0);
     if (P.order == 2) {
         for (int c = 0; c < 3; ++c) g[c] = dp1[c] - d0[c];
     } else {
         double dp2[3], dm1[3];
-        ghost_delta(A, P, axis, f + 2, o, dp2);
-        ghost_delta(A, P, axis, f - 1, o, dm1);
+        ghost_delta(A, P, T, axis, f + 2, o, dp2);
+        ghost_delta(A, P, T, axis, f - 1, o, dm1);
         for (int c = 0; c < 3; ++c) g[c] = 27.0 * (dp1[c] - d0[c]) - (dp2[c] - dm1[c]);
     }
     for (int c = 0; c < 3; ++c) {
@@ -185,17 +188,23 @@ struct Scratch64 {
 // r_g = r_w + m_init(g) - m_init(w), so that u = m - r is periodic with r_w the
 // stored reference of the wrapped point w.  Dirichlet: r_g = m_init(g), so
 // that u vanishes on the ghosts.
-__device__ double ref_ghost(const PrologueArgs &A, const BoxPlan &P, int i0, int i1, int c) {
+__device__ void ref_ghost(const PrologueArgs &A, const BoxPlan &P, const InitTables &T, int i0, int i1,
+                          double out[3]) {
     const int N = P.n, D = P.dim;
     double g[3];
-    minit_at(A, P, i0, i1, g);
-    if (P.bc == LLHMM_BC_DIRICHLET) return g[c];
+    minit_at(A, P, T, i0, i1, g);
+    if (P.bc == LLHMM_BC_DIRICHLET) {
+        for (int c = 0; c < 3; ++c) out[c] = g[c];
+        return;
+    }
     const int w0 = ((i0 % N) + N) % N, w1 = (D == 1) ? 0 : ((i1 % N) + N) % N;
     double h[3];
-    minit_at(A, P, w0, w1, h);
-    // stored reference of w: m_init(w) rounded to the batch precision
-    const double rw = (P.prec == LLHMM_FP32) ? (double)(float)h[c] : h[c];
-    return rw + (g[c] - h[c]);
+    minit_at(A, P, T, w0, w1, h);
+    for (int c = 0; c < 3; ++c) {
+        // stored reference of w: m_init(w) rounded to the batch precision
+        const double rw = (P.prec == LLHMM_FP32) ? (double)(float)h[c] : h[c];
+        out[c] = rw + (g[c] - h[c]);
+    }
 }
 
 template <typename T>
@@ -243,11 +252,33 @@ __global__ void __launch_bounds__(256) k_prologue(PrologueArgs A) {
     T *tab = (T *)A.tabs + P.tab_offset;
     const int nth = blockDim.x, tid = threadIdx.x;
     __shared__ double s_red[256][kMaxQ];
+    __shared__ double s_Mloc[75];
+    __shared__ double s_Lb[kLagMax * 5];
+    InitTables IT{s_Mloc, s_Lb};
+    if (P.init_mode == LLHMM_INIT_MACRO_Q) {
+        // the macro values around the node and the basis at every grid index, once per box
+        const int nm = A.macro.n;
+        const long npts = (D == 1) ? (long)nm : (long)nm * nm;
+        const int nv = (D == 1) ? 15 : 75;
+        for (int t = tid; t < nv; t += nth) {
+            if (D == 1) {
+                const int c = t / 5, l0 = t % 5;
+                const int k0 = ((P.mi0 + l0 - 2) % nm + nm) % nm;
+                s_Mloc[t] = A.M_macro[c * npts + k0];
+            } else {
+                const int c = t / 25, l0 = (t / 5) % 5, l1 = t % 5;
+                const int k0 = ((P.mi0 + l0 - 2) % nm + nm) % nm, k1 = ((P.mi1 + l1 - 2) % nm + nm) % nm;
+                s_Mloc[t] = A.M_macro[c * npts + (long)k0 * nm + k1];
+            }
+        }
+        for (int i = tid; i < N + 2 * kGhost; i += nth) lagrange5(grid_xi(P, i - kGhost) / A.macro.dX, s_Lb + i * 5);
+        __syncthreads();
+    }
 
     // initial state (form 0) or reference + residual (form 1)
     for (long p = tid; p < cells; p += nth) {
         double v[3];
-        minit_at(A, P, (int)(p % N), (int)(p / N), v);
+        minit_at(A, P, IT, (int)(p % N), (int)(p / N), v);
         if (P.form == 0) {
             for (int c = 0; c < 3; ++c) tab[L.m0 + c * cells + p] = (T)v[c];
         } else {
@@ -294,7 +325,7 @@ __global__ void __launch_bounds__(256) k_prologue(PrologueArgs A) {
                 double hi[3] = {0.0, 0.0, 0.0}, lo[3] = {0.0, 0.0, 0.0};
                 if (q < GF) {
                     int f = (side == 0) ? (-FW + q) : (N - GF + FE + q);
-                    face_tau(A, P, axis, f, line, hi, lo);
+                    face_tau(A, P, IT, axis, f, line, hi, lo);
                 }
                 T *dst = tab + (axis == 0 ? L.tau1 : L.tau2) + t * 8;
                 for (int c = 0; c < 3; ++c) {
@@ -308,17 +339,17 @@ __global__ void __launch_bounds__(256) k_prologue(PrologueArgs A) {
         if (tid < kMaxQ) A.box_const[(long)box * kMaxQ + tid] = 0.0;
         return;
     }
-    // ghost references: x1 ghosts of every line, x2 ghosts of every column
-    for (long t = tid; t < (long)lines * 18; t += nth) {
-        const int line = (int)(t / 18), side = (int)((t / 9) % 2), layer = (int)((t / 3) % 3), c = (int)(t % 3);
+    // ghost references: x1 ghosts of every line, x2 ghosts of every column (3 components each)
+    for (long t = tid; t < (long)lines * 6; t += nth) {
+        const int line = (int)(t / 6), side = (int)((t / 3) % 2), layer = (int)(t % 3);
         const int i0 = (side == 0) ? layer - 3 : N + layer;
-        S64.gx[t] = ref_ghost(A, P, i0, line, c);
+        ref_ghost(A, P, IT, i0, line, S64.gx + t * 3);
     }
     if (D == 2) {
-        for (long t = tid; t < (long)N * 18; t += nth) {
-            const int col = (int)(t / 18), side = (int)((t / 9) % 2), layer = (int)((t / 3) % 3), c = (int)(t % 3);
+        for (long t = tid; t < (long)N * 6; t += nth) {
+            const int col = (int)(t / 6), side = (int)((t / 3) % 2), layer = (int)(t % 3);
             const int i1 = (side == 0) ? layer - 3 : N + layer;
-            S64.gy[t] = ref_ghost(A, P, col, i1, c);
+            ref_ghost(A, P, IT, col, i1, S64.gy + t * 3);
         }
     }
     __syncthreads();  // reference values, scratch and weights written (form 1)
