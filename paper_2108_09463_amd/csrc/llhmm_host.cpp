@@ -226,15 +226,13 @@ struct BandKey {
     }
 };
 
-const std::map<BandKey, const BandTileInfo *> &band_registry() {
-    static std::map<BandKey, const BandTileInfo *> reg = [] {
-        std::map<BandKey, const BandTileInfo *> r;
+// Band tile variants per class, in registration order (the first is the default).
+const std::map<BandKey, std::vector<const BandTileInfo *>> &band_registry() {
+    static std::map<BandKey, std::vector<const BandTileInfo *>> reg = [] {
+        std::map<BandKey, std::vector<const BandTileInfo *>> r;
         int cnt = 0;
         const BandTileInfo *t = tiles_band(&cnt);
-        for (int i = 0; i < cnt; ++i) {
-            BandKey k{t[i].prec, t[i].n, t[i].bc, t[i].qty};
-            if (!r.count(k)) r[k] = &t[i];
-        }
+        for (int i = 0; i < cnt; ++i) r[BandKey{t[i].prec, t[i].n, t[i].bc, t[i].qty}].push_back(&t[i]);
         return r;
     }();
     return reg;
@@ -266,6 +264,19 @@ bool band_geometry(const BandTileInfo &t, int n, int stages, int steps_per_launc
     return true;
 }
 
+constexpr int kMaxStepsPerLaunch = 4;
+
+// Partial-sum slots a band box needs for any variant and any steps per launch.
+int64_t band_max_slots(const std::vector<const BandTileInfo *> &variants, int n, int stages) {
+    int64_t m = 0;
+    for (const BandTileInfo *t : variants)
+        for (int sc = 1; sc <= kMaxStepsPerLaunch; ++sc) {
+            BandGeom g;
+            if (band_geometry(*t, n, stages, sc, g)) m = std::max<int64_t>(m, (int64_t)g.strips * (t->threads / 64));
+        }
+    return m;
+}
+
 template <typename T>
 hipError_t dev_upload(T **dst, const T *src, size_t count) {
     *dst = nullptr;
@@ -278,6 +289,7 @@ hipError_t dev_upload(T **dst, const T *src, size_t count) {
 }  // namespace
 
 using TuneKey = std::tuple<int, int, int, int, int>;  // precision, n, bc, quantity, stages
+using TuneVal = std::pair<int, int>;                   // band tile variant, steps per launch
 
 // Device memory reserved once and handed out in 256-byte aligned pieces
 // (first fit, neighbouring free pieces merged on release).  The serving loop
@@ -334,7 +346,7 @@ struct Arena {
 
 struct llhmm_ctx {
     int device;
-    std::map<TuneKey, int> tuned;  // band classes: steps per launch chosen by llhmm_batch_tune
+    std::map<TuneKey, TuneVal> tuned;  // band classes: variant and steps per launch from llhmm_batch_tune
 };
 
 struct ClassLaunch {
@@ -352,7 +364,6 @@ struct BandClass {
 };
 
 constexpr int kSideStreams = 3;   // extra streams a batch spreads its classes over
-constexpr int kMaxStepsPerLaunch = 4;
 
 // Arguments a captured graph was built with; a call with other arguments captures again.
 struct GraphArgs {
@@ -619,14 +630,23 @@ static llhmm_status batch_create_impl(llhmm_ctx *ctx, const llhmm_box *boxes, in
         const BandTileInfo *bt = nullptr;
         BandGeom bg;
         int band_s = 0;
+        int64_t band_slots = 0;
         if (it == reg.end() && bx.dim == 2 && bx.order == 2) {
             auto bit = bregistry.find(BandKey{precision, bx.n, bx.bc, bx.quantity});
             const int stages = (pl.integ == LLHMM_RK4P) ? 4 : 2;
-            // steps per launch: the tuned choice for this class, else one halo of 4 rows
-            auto tit = ctx->tuned.find(TuneKey{precision, bx.n, bx.bc, bx.quantity, stages});
-            band_s = (tit != ctx->tuned.end()) ? tit->second : std::max(1, 4 / stages);
-            if (bit != bregistry.end() && band_geometry(*bit->second, bx.n, stages, band_s, bg))
-                bt = bit->second;
+            if (bit != bregistry.end()) {
+                // the tuned variant and steps per launch for this class, else the
+                // first variant with one halo of 4 rows
+                int v = 0;
+                band_s = std::max(1, 4 / stages);
+                auto tit = ctx->tuned.find(TuneKey{precision, bx.n, bx.bc, bx.quantity, stages});
+                if (tit != ctx->tuned.end() && tit->second.first < (int)bit->second.size()) {
+                    v = tit->second.first;
+                    band_s = tit->second.second;
+                }
+                if (band_geometry(*bit->second[v], bx.n, stages, band_s, bg)) bt = bit->second[v];
+                band_slots = band_max_slots(bit->second, bx.n, stages);
+            }
         }
         if (it == reg.end() && !bt) {
             delete b;
@@ -658,12 +678,7 @@ static llhmm_status batch_create_impl(llhmm_ctx *ctx, const llhmm_box *boxes, in
             // strips and partial-sum slots follow the steps per launch; reserve the
             // slots of the largest strip count any choice can give
             P.band = 1;
-            int smax = 0;
-            for (int sc = 1; sc <= kMaxStepsPerLaunch; ++sc) {
-                BandGeom g2;
-                if (band_geometry(*bt, bx.n, P.stages, sc, g2)) smax = std::max(smax, g2.strips);
-            }
-            slots = (int64_t)smax * (bt->threads / 64);
+            slots = band_slots;
         } else {
             P.nwaves = (bx.dim == 2) ? it->second->threads / 64 : 1;
             slots = P.nwaves;
@@ -1095,15 +1110,23 @@ llhmm_status llhmm_batch_tune(llhmm_ctx *ctx, llhmm_batch *b, const double *m_in
     HIP_TRY(hipEventCreate(&e1));
     for (auto &kv : keys) {
         const int i0 = kv.second[0];
-        const BandTileInfo *t = b->band_tile[i0];
-        int best = b->band_s[i0];
+        const BoxPlan &P0 = b->plans_h[i0];
+        const auto &variants = band_registry().at(BandKey{b->prec, P0.n, P0.bc, P0.quantity});
+        int best_v = 0, best = b->band_s[i0];
+        for (size_t v = 0; v < variants.size(); ++v)
+            if (variants[v] == b->band_tile[i0]) best_v = (int)v;
         float best_ms = -1.f;
-        for (int sc = 1; sc <= kMaxStepsPerLaunch && st == LLHMM_OK; ++sc) {
+        for (int cand = 0; cand < (int)variants.size() * kMaxStepsPerLaunch && st == LLHMM_OK; ++cand) {
+            const int v = cand / kMaxStepsPerLaunch, sc = 1 + cand % kMaxStepsPerLaunch;
+            const BandTileInfo *t = variants[v];
             BandGeom g;
-            if (!band_geometry(*t, b->plans_h[i0].n, b->plans_h[i0].stages, sc, g)) continue;
+            if (!band_geometry(*t, P0.n, P0.stages, sc, g)) continue;
             hipError_t e = hipStreamSynchronize(stream);  // no launch may still read the plans
             if (e != hipSuccess) { st = fail(LLHMM_E_HIP, "tune: %s", hipGetErrorString(e)); break; }
-            for (int i : kv.second) b->band_s[i] = sc;
+            for (int i : kv.second) {
+                b->band_tile[i] = t;
+                b->band_s[i] = sc;
+            }
             st = rebuild_bands(b);
             if (st != LLHMM_OK) break;
             const BandClass *bc = nullptr;
@@ -1122,11 +1145,15 @@ llhmm_status llhmm_batch_tune(llhmm_ctx *ctx, llhmm_batch *b, const double *m_in
             if (st == LLHMM_OK && (best_ms < 0.f || ms < best_ms)) {
                 best_ms = ms;
                 best = sc;
+                best_v = v;
             }
         }
         if (st != LLHMM_OK) break;
-        for (int i : kv.second) b->band_s[i] = best;
-        ctx->tuned[kv.first] = best;
+        for (int i : kv.second) {
+            b->band_tile[i] = variants[best_v];
+            b->band_s[i] = best;
+        }
+        ctx->tuned[kv.first] = TuneVal{best_v, best};
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -1145,10 +1172,10 @@ llhmm_status llhmm_tune_save(const llhmm_ctx *ctx, const char *path) {
     if (!ctx || !path) return fail(LLHMM_E_INVALID, "ctx/path is NULL");
     FILE *f = fopen(path, "w");
     if (!f) return fail(LLHMM_E_INVALID, "cannot write %s", path);
-    fprintf(f, "# llhmm band tuning: precision n bc quantity stages steps_per_launch\n");
+    fprintf(f, "# llhmm band tuning: precision n bc quantity stages variant steps_per_launch\n");
     for (const auto &kv : ctx->tuned)
-        fprintf(f, "%d %d %d %d %d %d\n", std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first),
-                std::get<3>(kv.first), std::get<4>(kv.first), kv.second);
+        fprintf(f, "%d %d %d %d %d %d %d\n", std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first),
+                std::get<3>(kv.first), std::get<4>(kv.first), kv.second.first, kv.second.second);
     const bool ok = fclose(f) == 0;
     return ok ? LLHMM_OK : fail(LLHMM_E_INVALID, "cannot write %s", path);
 }
@@ -1158,17 +1185,17 @@ llhmm_status llhmm_tune_load(llhmm_ctx *ctx, const char *path) {
     FILE *f = fopen(path, "r");
     if (!f) return fail(LLHMM_E_INVALID, "cannot read %s", path);
     char line[256];
-    std::map<TuneKey, int> got;
+    std::map<TuneKey, TuneVal> got;
     llhmm_status st = LLHMM_OK;
     while (fgets(line, sizeof line, f)) {
         if (line[0] == '#' || line[0] == '\n') continue;
-        int v[6];
-        if (sscanf(line, "%d %d %d %d %d %d", &v[0], &v[1], &v[2], &v[3], &v[4], &v[5]) != 6 ||
-            v[5] < 1 || v[5] > kMaxStepsPerLaunch) {
+        int v[7];
+        if (sscanf(line, "%d %d %d %d %d %d %d", &v[0], &v[1], &v[2], &v[3], &v[4], &v[5], &v[6]) != 7 ||
+            v[5] < 0 || v[5] > 15 || v[6] < 1 || v[6] > kMaxStepsPerLaunch) {
             st = fail(LLHMM_E_INVALID, "%s: bad line: %s", path, line);
             break;
         }
-        got[TuneKey{v[0], v[1], v[2], v[3], v[4]}] = v[5];
+        got[TuneKey{v[0], v[1], v[2], v[3], v[4]}] = TuneVal{v[5], v[6]};
     }
     fclose(f);
     if (st != LLHMM_OK) return st;
@@ -1279,10 +1306,13 @@ static llhmm_status request_bytes(const llhmm_server *sv, const llhmm_box &bx, i
     const int stages = (pl.integ == LLHMM_RK4P) ? 4 : 2;
     auto it = registry().find(TileKey{prec, bx.dim, bx.n, bx.order, bx.bc, bx.quantity});
     const BandTileInfo *bt = nullptr;
+    int64_t band_slots = 0;
     if (it == registry().end() && bx.dim == 2 && bx.order == 2) {
         auto bit = band_registry().find(BandKey{prec, bx.n, bx.bc, bx.quantity});
-        BandGeom g;
-        if (bit != band_registry().end() && band_geometry(*bit->second, bx.n, stages, 1, g)) bt = bit->second;
+        if (bit != band_registry().end()) {
+            bt = bit->second[0];
+            band_slots = band_max_slots(bit->second, bx.n, stages);
+        }
     }
     if (it == registry().end() && !bt)
         return fail(LLHMM_E_NOTSUP, "request %d: no kernel for dim %d, n %d, order %d, bc %d, quantity %d", i,
@@ -1292,14 +1322,9 @@ static llhmm_status request_bytes(const llhmm_server *sv, const llhmm_box &bx, i
     int64_t slots = (bx.dim == 2) ? 16 : 1;
     int64_t band_state = 0, jobs = 0;
     if (bt) {
-        int smax = 0;
-        for (int sc = 1; sc <= kMaxStepsPerLaunch; ++sc) {
-            BandGeom g;
-            if (band_geometry(*bt, bx.n, stages, sc, g)) smax = std::max(smax, g.strips);
-        }
-        slots = (int64_t)smax * (bt->threads / 64);
+        slots = band_slots;
         band_state = 2 * 3 * C * tsize;
-        jobs = smax * (int64_t)sizeof(BandJob);
+        jobs = band_slots * (int64_t)sizeof(BandJob);
     }
     bytes = tab_layout(bx.dim, bx.n, form).size * tsize + 2 * bx.n * 8 +
             (form == 1 ? scratch64_size(bx.dim, bx.n) * 8 : 0) + slots * (kMaxQ * 8 + 4) + band_state + jobs +

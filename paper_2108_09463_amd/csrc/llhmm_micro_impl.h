@@ -62,6 +62,11 @@ __device__ __forceinline__ float fma_t(float a, float b, float c) { return __bui
 __device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float rsqrt_t(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double rsqrt_t(double x) { return 1.0 / __builtin_sqrt(x); }
+// 1/x: the hardware reciprocal in FP32 (the projection divides a perturbation-size
+// quantity by 1 + sqrt(1 + e) ~ 2, where its 1-ulp error is far below the state's
+// rounding); exact division in FP64.
+__device__ __forceinline__ float rcp_t(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp_t(double x) { return 1.0 / x; }
 
 
 // ----------------------------------------------------------------- table copies
@@ -418,7 +423,7 @@ struct MicroLane {
                                       fma_t(ut[0], ut[0], fma_t(ut[1], ut[1], fma_t(ut[2], ut[2], ref(3, cell)))));
                     const T inv = rsqrt_t((T)1 + e);
                     const T nn = ((T)1 + e) * inv;
-                    const T q = e / ((T)1 + nn);
+                    const T q = e * rcp_t((T)1 + nn);
                     m[r][k][0] = (ut[0] - r0v * q) * inv;
                     m[r][k][1] = (ut[1] - r1v * q) * inv;
                     m[r][k][2] = (ut[2] - r2v * q) * inv;

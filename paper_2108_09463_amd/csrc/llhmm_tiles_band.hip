@@ -25,6 +25,9 @@ static const BandTileInfo kBand[] = {
     LLHMM_BAND_QTY(float, 1, 1, 64, 2, 4, 8, 1, 1),
     LLHMM_BAND_QTY(float, 1, 0, 16, 6, 2, 16, 1, 1),
     LLHMM_BAND_QTY(float, 1, 1, 16, 6, 2, 16, 1, 1),
+    // FP32 n = 96, second variant: 24-row windows, one row per lane, 6 waves per block
+    LLHMM_BAND_QTY(float, 1, 0, 16, 6, 1, 24, 1, 1),
+    LLHMM_BAND_QTY(float, 1, 1, 16, 6, 1, 24, 1, 1),
     // FP64: windows of 16 rows (reference tables read from global memory)
     LLHMM_BAND_QTY(double, 0, 0, 64, 2, 2, 8, 2, 1),
     LLHMM_BAND_QTY(double, 0, 1, 64, 2, 2, 8, 2, 1),

@@ -98,8 +98,10 @@ def test_tuner_keeps_results_and_round_trips(ctx, tmp_path):
     assert ((steps[ns >= 96] >= 1) & (steps[ns >= 96] <= 4)).all()
     out1 = p.solve()
     assert (out1["status"] == 0).all()
-    # same arithmetic per point; only the grouping of the FP64 partial sums changes
-    assert rel_err(out1["H"], out0["H"]).max() < 1e-12
+    # other steps per launch: same arithmetic per point, only the grouping of the
+    # FP64 partial sums changes; another tile variant may also contract the FP32
+    # stencil differently, which stays within the FP32 bar
+    assert rel_err(out1["H"], out0["H"]).max() < 1e-5
     path = str(tmp_path / "tune.txt")
     L.llhmm_tune_save(ctx, path)
     ctx2 = L.llhmm_create(0)
@@ -107,7 +109,7 @@ def test_tuner_keeps_results_and_round_trips(ctx, tmp_path):
     p2 = Prepared(wl, precision=inputs.FP32, ctx=ctx2)
     assert np.array_equal(L.llhmm_batch_band_steps(p2.batch), steps)
     out2 = p2.solve()
-    assert rel_err(out2["H"], out0["H"]).max() < 1e-12
+    assert np.array_equal(out2["H"], out1["H"])   # same variants and steps: same result
     torch.cuda.synchronize()
 
 
