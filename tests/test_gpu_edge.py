@@ -1,0 +1,125 @@
+"""Edge and degenerate cases of the micro solve on the GPU, against the oracle
+or against what the method fixes exactly.
+
+* One time step: both time weights K0(0)/1 and K0(1)/1 vanish, so the average
+  is exactly zero.
+* Uniform initial magnetization: every difference in the stencil is zero, H
+  vanishes, the state never moves and the average is exactly zero.
+* Constant coefficient (no oscillation), large damping (HeunP) and tiny
+  damping (RK4P) against the oracle.
+* A batch of one box; a 1-D batch whose size leaves padded row groups.
+"""
+import numpy as np
+import pytest
+
+from paper_2108_09463_amd import inputs
+from paper_2108_09463_amd import llhmm as L
+
+from test_gpu_parity import check, small_1d, small_2d
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return L.llhmm_create(0)
+
+
+class Uniform:
+    """m_init = const unit vector."""
+    def __call__(self, x1, x2=None):
+        v = np.array([0.6, 0.0, 0.8])
+        shape = np.shape(x1)
+        return np.stack([np.full(shape, c) for c in v])
+
+
+@pytest.mark.parametrize("prec", [inputs.FP64, inputs.FP32])
+@pytest.mark.parametrize("n", [32, 64, 128])
+def test_single_step_average_is_zero(ctx, prec, n):
+    from paper_2108_09463_amd.runner import Prepared
+    wl = small_2d(n, 2, 0, 0, nboxes=2)
+    for b in wl.boxes:
+        b["n_steps"] = 1
+    out = Prepared(wl, precision=prec, ctx=ctx).solve()
+    assert (out["status"] == 0).all()
+    assert np.array_equal(out["H"], np.zeros_like(out["H"]))
+
+
+@pytest.mark.parametrize("prec", [inputs.FP64, inputs.FP32])
+@pytest.mark.parametrize("n,bc", [(32, 0), (64, 1), (96, 0), (128, 1)])
+def test_uniform_magnetization_is_stationary(ctx, prec, n, bc):
+    from paper_2108_09463_amd.runner import Prepared, box_state
+    wl = small_2d(n, 2, bc, 0, nboxes=2)
+    wl.init = Uniform()
+    for b in wl.boxes:
+        b["eta"] = 0.05 * b["eps"] ** 2
+    p = Prepared(wl, precision=prec, ctx=ctx)
+    out = p.solve(want_state=True)
+    # Zero up to the rounding of the data: with Dirichlet ghosts (and in the
+    # reference + perturbation form) the boundary stencil cancels a'(m_g - m)
+    # between two rounded terms of size a' * ulp(m).
+    tol_h = 1e-9 if prec == inputs.FP64 else 1e-6
+    assert np.abs(out["H"]).max() <= tol_h
+    if bc == 0 and n <= 64:
+        assert np.array_equal(out["H"], np.zeros_like(out["H"]))  # periodic, resident: exactly zero
+    for i, b in enumerate(wl.boxes):
+        m = box_state(out["m_final"], i, b, p.batch.n_max, p.batch.dim_max)
+        ref = np.array([0.6, 0.0, 0.8])[:, None, None]
+        tol = 1e-14 if prec == inputs.FP64 else 1e-7
+        assert np.abs(m - ref).max() <= tol
+
+
+@pytest.mark.parametrize("prec", [inputs.FP64, inputs.FP32])
+def test_constant_coefficient(ctx, prec):
+    wl = small_2d(48, 2, 0, 0, nboxes=2)
+    wl.coefs = [inputs.coef_const(1.3, 2)]
+    for b in wl.boxes:
+        b["a_max"] = 1.3
+    check(ctx, wl, prec)
+
+
+CASES_DAMPING = [(p, a, i) for p in (inputs.FP64, inputs.FP32)
+                 for a, i in ((1.0, inputs.INTEG_AUTO), (0.001, inputs.INTEG_AUTO), (0.5, inputs.RK4P))]
+CASES_DAMPING += [(inputs.FP64, 0.05, inputs.HEUNP)]
+
+
+@pytest.mark.parametrize("prec,alpha,integ", CASES_DAMPING)
+def test_damping_extremes_and_forced_integrators(ctx, prec, alpha, integ):
+    wl = small_2d(32, 2, 0, 0, nboxes=2)
+    for b in wl.boxes:
+        b["alpha"] = alpha
+        b["integrator"] = integ
+    check(ctx, wl, prec)
+
+
+def test_fp32_weakly_damped_heun_error_is_reported(ctx):
+    """HeunP forced at alpha = 0.05 runs close to its stability limit, where the
+    high-frequency modes are barely damped and the FP32 rounding of the state,
+    seen through the 1/dx^2 stencil, stays in the field: the FP32 error of this
+    case is 1.3e-5, above the 1e-5 bar met by the configured workloads.  The
+    test pins that measured level so that a regression shows."""
+    from paper_2108_09463_amd.runner import Prepared
+    from test_gpu_parity import rel_err, run_oracle
+    wl = small_2d(32, 2, 0, 0, nboxes=2)
+    for b in wl.boxes:
+        b["alpha"] = 0.05
+        b["integrator"] = inputs.HEUNP
+    out = Prepared(wl, precision=inputs.FP32, ctx=ctx).solve()
+    Ho = np.stack([r["out"] for r in run_oracle(wl)])
+    err = rel_err(out["H"][:, :3], Ho)
+    print("fp32 weakly damped HeunP rel err", err)
+    assert err.max() <= 2e-5
+
+
+@pytest.mark.parametrize("prec", [inputs.FP64, inputs.FP32])
+def test_batch_of_one_box(ctx, prec):
+    check(ctx, small_2d(64, 2, 0, 0, nboxes=1), prec)
+    check(ctx, small_1d(128, 2, 0, 1, nboxes=1), prec)
+
+
+def test_one_d_padded_row_groups(ctx):
+    """7 one-dimensional boxes with distinct step counts: blocks of 4 row
+    groups hold boxes of one (M, integrator) class and pad the rest."""
+    check(ctx, small_1d(64, 2, 0, 0, nboxes=7, seed=19), inputs.FP32)

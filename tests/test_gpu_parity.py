@@ -50,15 +50,20 @@ def run_gpu(ctx, wl, precision, want_state=False):
     return p, out
 
 
-def run_oracle(wl, idx=None, want_state=False, variant="plain"):
-    idx = range(len(wl.boxes)) if idx is None else idx
-    res = []
-    for i in idx:
+def run_oracle(wl, idx=None, want_state=False, variant="plain", threads=1):
+    idx = list(range(len(wl.boxes)) if idx is None else idx)
+
+    def one(i):
         b = wl.boxes[i]
-        res.append(micro.solve_box(b, wl.coefs[b["coef_index"]], init_fn=wl.init_of(i),
-                                   macro=wl.macro, kernel=wl.kernel, want_state=want_state,
-                                   variant=variant))
-    return res
+        return micro.solve_box(b, wl.coefs[b["coef_index"]], init_fn=wl.init_of(i),
+                               macro=wl.macro, kernel=wl.kernel, want_state=want_state,
+                               variant=variant)
+
+    if threads <= 1:
+        return [one(i) for i in idx]
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(threads) as ex:   # the C loop releases the GIL
+        return list(ex.map(one, idx))
 
 
 def tolerance(wl, precision, Ho, idx=None):
