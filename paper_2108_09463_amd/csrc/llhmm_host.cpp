@@ -387,6 +387,7 @@ struct llhmm_batch {
     BoxPlan *plans = nullptr;
     BandJob *jobs = nullptr;
     void *state[2] = {nullptr, nullptr};  // band boxes' state, ping-pong between launches
+    void *refbuf[2] = {nullptr, nullptr}; // FP32 band boxes' reference tables, ping-pong
     int32_t *box_ids = nullptr;
     CoefDev *coefs = nullptr;
     void *tabs = nullptr;
@@ -540,7 +541,7 @@ static void batch_free(llhmm_batch *b) {
     if (!b) return;
     void *ptrs[] = {b->plans, b->box_ids, b->coefs, b->tabs, b->wts, b->wt, b->partials,
                     b->wave_status, b->status, b->box_const, b->scratch64, b->jobs,
-                    b->state[0], b->state[1]};
+                    b->state[0], b->state[1], b->refbuf[0], b->refbuf[1]};
     for (void *p : ptrs) bfree(b, p);
     for (auto &slot : b->ev)
         for (hipEvent_t e : slot)
@@ -611,7 +612,7 @@ static llhmm_status batch_create_impl(llhmm_ctx *ctx, const llhmm_box *boxes, in
     }
     b->dim_max = dim_max;
     b->nmax = nmax;
-    int64_t tab_off = 0, w_off = 0, s64_off = 0, part_off = 0, state_off = 0;
+    int64_t tab_off = 0, w_off = 0, s64_off = 0, part_off = 0, state_off = 0, ref_off = 0;
     std::map<int, int64_t> wt_off_of_M;
     std::vector<double> wt_h;
     int64_t cell_steps = 0;
@@ -688,6 +689,8 @@ static llhmm_status batch_create_impl(llhmm_ctx *ctx, const llhmm_box *boxes, in
         if (bt) {
             P.state_offset = state_off;
             state_off += 3 * (int64_t)bx.n * bx.n;
+            P.ref_offset = ref_off;
+            if (precision == LLHMM_FP32) ref_off += 7 * (int64_t)bx.n * bx.n;
         }
         P.prec = precision;
         P.form = (precision == LLHMM_FP32 || P.band) ? 1 : 0;
@@ -712,8 +715,16 @@ static llhmm_status batch_create_impl(llhmm_ctx *ctx, const llhmm_box *boxes, in
         auto wit = wt_off_of_M.find(pl.M);
         if (wit == wt_off_of_M.end()) {
             const int64_t o = (int64_t)wt_h.size();
+            // w^n = K0(n/M)/M, n = 0..M, then the tails sum_{n' >= n} w^n'
             for (int n = 0; n <= pl.M; ++n)
                 wt_h.push_back(time_kernel((double)n / pl.M, dcoef, K->p_t, K->q_t) / pl.M);
+            std::vector<double> tail(pl.M + 1);
+            double acc = 0.0;
+            for (int n = pl.M; n >= 0; --n) {
+                acc += wt_h[o + n];
+                tail[n] = acc;
+            }
+            wt_h.insert(wt_h.end(), tail.begin(), tail.end());
             wit = wt_off_of_M.emplace(pl.M, o).first;
         }
         P.wt_offset = wit->second;
@@ -772,6 +783,7 @@ static llhmm_status batch_create_impl(llhmm_ctx *ctx, const llhmm_box *boxes, in
     if (e == hipSuccess) e = balloc(b, (void **)&b->partials, sizeof(double) * (size_t)part_off * kMaxQ);
     if (e == hipSuccess) e = balloc(b, (void **)&b->wave_status, sizeof(int32_t) * (size_t)part_off);
     for (int k = 0; k < 2 && e == hipSuccess && state_off > 0; ++k) e = balloc(b, &b->state[k], tsize * state_off);
+    for (int k = 0; k < 2 && e == hipSuccess && ref_off > 0; ++k) e = balloc(b, &b->refbuf[k], tsize * ref_off);
     if (e == hipSuccess) e = balloc(b, (void **)&b->status, sizeof(int32_t) * (size_t)nboxes);
     if (e == hipSuccess) e = balloc(b, (void **)&b->box_const, sizeof(double) * (size_t)nboxes * kMaxQ);
     if (e == hipSuccess) e = balloc(b, (void **)&b->scratch64, sizeof(double) * std::max<int64_t>(s64_off, 1));
@@ -882,13 +894,20 @@ static llhmm_status launch_band_class(llhmm_batch *b, const BandClass &bc, int m
         HIP_TRY(bc.tile->launch(a, bc.count, stream));
         return LLHMM_OK;
     }
+    // FP32 reference tables: the set-up tables until the first re-reference,
+    // then whichever buffer the last re-referencing launch wrote
+    int cur = -1;
     for (size_t p = 0; p < bc.active.size(); ++p) {
         a.njobs = bc.active[p];
         a.step0 = (int)p * bc.s;
         a.steps = bc.s;
         a.state_in = b->state[p & 1];
         a.state_out = b->state[(p + 1) & 1];
+        a.reref = (b->prec == LLHMM_FP32) && a.step0 > 0 && (a.step0 % kRerefSteps) < bc.s;
+        a.ref_in = (cur < 0) ? nullptr : b->refbuf[cur];
+        a.ref_out = b->refbuf[(cur < 0) ? 0 : 1 - cur];
         HIP_TRY(bc.tile->launch(a, a.njobs, stream));
+        if (a.reref) cur = (cur < 0) ? 0 : 1 - cur;
     }
     return LLHMM_OK;
 }
@@ -1323,12 +1342,12 @@ static llhmm_status request_bytes(const llhmm_server *sv, const llhmm_box &bx, i
     int64_t band_state = 0, jobs = 0;
     if (bt) {
         slots = band_slots;
-        band_state = 2 * 3 * C * tsize;
+        band_state = 2 * 3 * C * tsize + (prec == LLHMM_FP32 ? 2 * 7 * C * tsize : 0);
         jobs = band_slots * (int64_t)sizeof(BandJob);
     }
     bytes = tab_layout(bx.dim, bx.n, form).size * tsize + 2 * bx.n * 8 +
             (form == 1 ? scratch64_size(bx.dim, bx.n) * 8 : 0) + slots * (kMaxQ * 8 + 4) + band_state + jobs +
-            (int64_t)(pl.M + 1) * 8 + (int64_t)sizeof(BoxPlan) + 4 + kMaxQ * 8 + 4 + kMaxQ * 8 + 4 +
+            2 * (int64_t)(pl.M + 1) * 8 + (int64_t)sizeof(BoxPlan) + 4 + kMaxQ * 8 + 4 + kMaxQ * 8 + 4 +
             (int64_t)sizeof(CoefDev) + 2 * 256;
     return LLHMM_OK;
 }

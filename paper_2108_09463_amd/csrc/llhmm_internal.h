@@ -11,6 +11,9 @@ constexpr int kGhost = LLHMM_GHOST;
 constexpr int kMaxWaves = 16;  // waves per block of the resident kernels
 constexpr int kMaxQ = 6;       // outputs per box (flux in 2-D)
 constexpr int kFaceHalo = 3;   // faces -2 .. n stored per line: n + 3 entries
+// FP32 reference + perturbation form: every kRerefSteps time steps the state
+// is re-expressed around a new reference r' = fl(r + u) (MicroLane::rereference).
+constexpr int kRerefSteps = 8;
 
 // Per-box plan as the kernels read it.
 struct BoxPlan {
@@ -28,6 +31,7 @@ struct BoxPlan {
     int64_t s64_offset;                  // element offset (double) of the set-up scratch (form 1)
     int64_t part_offset;                 // first partial-sum slot of the box (nwaves slots)
     int64_t state_offset;                // band: element offset (T) of the box's state [3][n][n]
+    int64_t ref_offset;                  // band, FP32: element offset (T) of its reference tables [7][n][n]
 };
 
 // Per-box table layout (elements of T, starting at tab_offset), n = points per
@@ -139,7 +143,8 @@ struct BandArgs {
     const BandJob *jobs;        // one per block
     int32_t njobs, mode;        // mode 0 solve, 1 evaluate H(m0) only
     int32_t step0, steps;       // this launch: steps [step0, min(step0 + steps, M))
-    int32_t h, pad_;            // halo rows on each side of a strip
+    int32_t h;                  // halo rows on each side of a strip
+    int32_t reref;              // FP32: re-reference at the launch start (then write the tables)
     const void *tabs;           // per-box tables (T)
     const double *wts;          // space weights
     const double *wt;           // time-weight table
@@ -147,6 +152,8 @@ struct BandArgs {
     int32_t *wave_status;       // [slots]
     const void *state_in;       // T, per box at state_offset (unused when step0 == 0)
     void *state_out;            // T
+    const void *ref_in;         // FP32: reference tables r, |r|^2-1, H(r) per box at ref_offset,
+    void *ref_out;              //   or nullptr: the set-up tables (until the first re-reference)
     double *out_field;          // m_final or H (nullable)
 };
 

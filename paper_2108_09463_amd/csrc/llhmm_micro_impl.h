@@ -100,7 +100,9 @@ __device__ __forceinline__ void copy_rows_to_lds(T *dst, SrcRow src_row, int tid
     }
 }
 
-enum { AVG_NONE = 0, AVG_FIELD = 1, AVG_TORQUE = 2, AVG_FLUX = 3, AVG_EVAL = 4 };
+enum { AVG_NONE = 0, AVG_FIELD = 1, AVG_TORQUE = 2, AVG_FLUX = 3, AVG_EVAL = 4, AVG_DREF = 5 };
+
+
 
 template <typename T, int D, int ORD, int BC, int QTY, int L, int K, int R, int NG, int NBUF,
           bool BAND = false>
@@ -157,13 +159,14 @@ struct MicroLane {
     bool zero_s, zero_n;
     T alpha, dt;
     T *s_halo, *s_zero, *s_tau;
-    const T *s_ref;    // form 1: this box's r [3][C], |r|^2-1 [C], H(r) [3][C] (LDS)
+    T *s_ref;          // form 1: this box's r [3][C], |r|^2-1 [C], H(r) [3][C] (LDS or global)
     const double *wl;  // this box's point weights [N] then east-face weights [N] (LDS)
     // band mode: box row of each own row, whether the block owns it, and the
     // x2 point / face weights of the window rows (zero on rows it does not own)
     int brow[BAND ? R : 1];
     bool own[BAND ? R : 1];
     const double *s_wyl;
+    const T *s_edge;   // band: z of the box rows just outside the window (re-referencing)
 
     template <int CTRL_ROT, int CTRL_SH>
     __device__ __forceinline__ static T nb(T v) {
@@ -216,6 +219,10 @@ struct MicroLane {
             __syncthreads();
             srcS = zero_s ? s_zero : hb + ((gs * 2 + 1) * YH) * 3 * N;
             srcN = zero_n ? s_zero : hb + ((gn * 2 + 0) * YH) * 3 * N;
+            if (BAND && AVG == AVG_DREF) {  // the reference change is known beyond the window
+                if (g == 0) srcS = s_edge;
+                if (g == NG - 1) srcN = s_edge + 3 * N;
+            }
         }
         auto yat = [&](int q, int k, int c) -> T {  // local row q in [-YH, R+YH); halo rows from LDS
             if (q < 0) return *(const T *)(srcS + ((q + YH) * 3 + c) * N + c0 + k);
@@ -313,7 +320,7 @@ struct MicroLane {
                 if constexpr (X1FAST) {
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
-                        if (k + 1 < K || AVG == AVG_FLUX) {
+                        if (k + 1 < K || AVG == AVG_FLUX || (AVG == AVG_DREF && QTY == LLHMM_Q_FLUX)) {
                             const T fe = axv(r, k + 1) * ge[k][c];
                             H[c] = fe - Fwest[c];
                             Fx_east[c] = fe;
@@ -348,6 +355,30 @@ struct MicroLane {
                         for (int w = 0; w + 1 < FW + FE; ++w) F2[w][k][c] = F2[w + 1][k][c];
                         F2[FW + FE - 1][k][c] = fnew;
                     }
+                }
+                if (AVG == AVG_DREF) {
+                    // field of the reference change: kept in acc, and its average times
+                    // the remaining time weight joins the constant part of the average
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) acc[r][k][c] = H[c];
+                    if (owned(r)) {
+                        if (QTY == LLHMM_Q_FIELD) {
+                            const double w = wv(c0 + k) * wy(r);
+#pragma unroll
+                            for (int c = 0; c < 3; ++c) sq[c] = fma(w, (double)H[c], sq[c]);
+                        } else if (QTY == LLHMM_Q_FLUX) {
+                            const double w1 = wv(N + c0 + k) * wy(r);
+#pragma unroll
+                            for (int c = 0; c < 3; ++c) sq[c] = fma(w1, (double)Fx_east[c], sq[c]);
+                            if (D == 2) {
+                                const double w2 = wv(c0 + k) * wyf(r);
+#pragma unroll
+                                for (int c = 0; c < 3; ++c)
+                                    sq[(D == 2 ? 3 : 0) + c] = fma(w2, (double)Fy_north[c], sq[(D == 2 ? 3 : 0) + c]);
+                            }
+                        }
+                    }
+                    continue;
                 }
                 if (AVG == AVG_EVAL) {
                     const int cell = cell_of(r, k);
@@ -432,10 +463,54 @@ struct MicroLane {
                 }
             }
         }
-        if (AVG >= AVG_FIELD && AVG <= AVG_FLUX) {
+        if ((AVG >= AVG_FIELD && AVG <= AVG_FLUX) || (AVG == AVG_DREF && QTY != LLHMM_Q_TORQUE)) {
 #pragma unroll
             for (int q = 0; q < NQ; ++q) acc64[q] = fma(wn, sq[q], acc64[q]);
         }
+    }
+
+    // FP32 form 1 only.  Over many small steps the FP32 perturbation u keeps
+    // only the top bits of each step's increment once |u| has grown, and the
+    // stencil's 1/dx^2 turns the lost bits into field error.  Re-referencing
+    // moves the representable part of u into the reference: r' = fl(r + u),
+    // z = r' - r and u' = u - z are exact (Fast2Sum, |r| >= |u|), so r' + u' =
+    // r + u and |u'| <= ulp(r)/2.  The tables follow: |r'|^2 - 1 from exact
+    // FP64 squares, H(r') = H(r) + D(z) (D linear; D(z) through the stage's
+    // stencil with z in the stage-input registers and the result in the
+    // accumulator, both free at a step boundary), and the average's constant
+    // part gains w_tail * sum_j w_j D(z)_j, w_tail = sum_{n' >= n} w^n'.
+    // Every lane writes only its own points' table entries.
+    __device__ __forceinline__ void rereference(double w_tail, int tstage) {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const int cell = cell_of(r, k);
+                double n2 = 0.0;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const T rv = s_ref[c * RSTRIDE + cell];
+                    const T sv = rv + m[r][k][c];
+                    const T z = sv - rv;
+                    m[r][k][c] = m[r][k][c] - z;
+                    y[r][k][c] = z;
+                    s_ref[c * RSTRIDE + cell] = sv;
+                    n2 = fma((double)sv, (double)sv, n2);
+                }
+                s_ref[3 * RSTRIDE + cell] = (T)(n2 - 1.0);
+            }
+        stage<AVG_DREF, true, false>((T)0, (T)0, w_tail, tstage, nullptr, 0);
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const int cell = cell_of(r, k);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    s_ref[(4 + c) * RSTRIDE + cell] = s_ref[(4 + c) * RSTRIDE + cell] + acc[r][k][c];
+                    y[r][k][c] = m[r][k][c];
+                }
+            }
     }
 };
 
@@ -589,15 +664,17 @@ __global__ void __launch_bounds__(L * NG, MINW) k_micro(MicroArgs A) {
 
     const int M = PU.M;
     const bool rk4 = (PU.stages == 4);
+    constexpr bool REREF = (FORM == 1) && (sizeof(T) == 4);
     // stage-1 data: b_1 and c_2 dt; RK4P b = (1,2,2,1)/6, c = (1/2, 1/2, 1); HeunP b = (1/2, 1/2), c = (1)
     const T b1 = rk4 ? (T)(1.0 / 6.0) : (T)0.5;
     const T c2dt = rk4 ? (T)(0.5 * P.dt) : (T)P.dt;  // per box (1-D lanes may differ)
     const T third = (T)(1.0 / 3.0);
     const T half_dt = (T)(0.5 * P.dt);
-    const double *wtab = A.wt + PU.wt_offset;
+    const double *wtab = A.wt + PU.wt_offset;  // w^0..w^M, then the tails sum_{n' >= n} w^n'
     int ts = 0;
     for (int n = 0; n < M; ++n) {
         const double wn = wtab[n];
+        if (REREF && n > 0 && n % kRerefSteps == 0) S.rereference(wtab[M + 1 + n], ts++);
         asm volatile("" ::: "memory");
         S.template stage<Lane::AVG, true, false>(b1, c2dt, wn, ts, nullptr, 0);
         ++ts;
@@ -671,6 +748,7 @@ __global__ void __launch_bounds__(L * NG, MINW) k_band(BandArgs A) {
     __shared__ T s_refl[Lane::REF_LDS];
     __shared__ double s_w[2 * N];
     __shared__ double s_wyl[2 * WR];
+    __shared__ T s_edge[(sizeof(T) == 4) ? 2 * 3 * N : 1];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -714,10 +792,11 @@ __global__ void __launch_bounds__(L * NG, MINW) k_band(BandArgs A) {
     S.wl = s_w;
     S.s_wyl = s_wyl;
     // reference r, |r|^2 - 1 and H(r): window copy in LDS (FP32) or the box tables (FP64)
+    const bool first = (A.step0 == 0);
     if (Lane::REFG) {
-        S.s_ref = tab + TL.ref;
+        S.s_ref = const_cast<T *>(tab) + TL.ref;
     } else {
-        const T *src = tab + TL.ref;
+        const T *src = A.ref_in ? (const T *)A.ref_in + P.ref_offset : tab + TL.ref;
         copy_rows_to_lds<T, N, Lane::REFG ? 1 : 7 * WR, L * NG>(
             s_refl,
             [&](int r) {
@@ -738,7 +817,6 @@ __global__ void __launch_bounds__(L * NG, MINW) k_band(BandArgs A) {
 #pragma unroll
         for (int lr = 0; lr < NFR; ++lr) S.ay[k][lr] = tab[TL.ay + (long)(c0 + k) * LF + (S.brow[0] - FW + lr) + 2];
     // state: u0 from the tables on the first launch, else the previous launch's output
-    const bool first = (A.step0 == 0);
     const T *src = first ? tab + TL.m0 : (const T *)A.state_in + P.state_offset;
 #pragma unroll
     for (int r = 0; r < R; ++r)
@@ -777,10 +855,35 @@ __global__ void __launch_bounds__(L * NG, MINW) k_band(BandArgs A) {
     const T c2dt = rk4 ? (T)(0.5 * P.dt) : (T)P.dt;
     const T third = (T)(1.0 / 3.0);
     const T half_dt = (T)(0.5 * P.dt);
-    const double *wtab = A.wt + P.wt_offset;
+    const double *wtab = A.wt + P.wt_offset;  // w^0..w^M, then the tails
+    constexpr bool REREF = !Lane::REFG && (sizeof(T) == 4);
+    // Re-reference only at the start of a launch (the host sets A.reref once
+    // the previous launches have reached a multiple of kRerefSteps): all window
+    // rows are exact then, and the reference change of the two box rows beyond
+    // the window is formed here from the launch's inputs, so D(z) is exact on
+    // every window row.
+    const bool reref = REREF && A.reref;
+    if (reref) {
+        const T *rin = A.ref_in ? (const T *)A.ref_in + P.ref_offset : tab + TL.ref;
+        const T *uin = (const T *)A.state_in + P.state_offset;
+        for (int i = tid; i < 2 * 3 * N; i += L * NG) {
+            const int side = i / (3 * N), c = (i / N) % 3, col = i % N;
+            const int raw = (side == 0) ? w0 - 1 : w0 + WR;
+            T z = (T)0;
+            if (BC != LLHMM_BC_DIRICHLET || (raw >= 0 && raw < N)) {
+                const long cell = (long)wrap(raw) * N + col;
+                const T rv = rin[c * C + cell];
+                z = (rv + uin[c * C + cell]) - rv;
+            }
+            s_edge[i] = z;
+        }
+        S.s_edge = s_edge;
+        __syncthreads();
+    }
     int ts = 0;
     for (int n = A.step0; n < s_end; ++n) {
         const double wn = wtab[n];
+        if (reref && n == A.step0) S.rereference(wtab[P.M + 1 + n], ts++);
         asm volatile("" ::: "memory");
         S.template stage<Lane::AVG, true, false>(b1, c2dt, wn, ts, nullptr, 0);
         ++ts;
@@ -801,6 +904,17 @@ __global__ void __launch_bounds__(L * NG, MINW) k_band(BandArgs A) {
                 for (int k = 0; k < K; ++k)
 #pragma unroll
                     for (int c = 0; c < 3; ++c) dst[c * C + (long)S.brow[r] * N + c0 + k] = S.m[r][k][c];
+        if (reref) {  // the moved reference tables, for the next launches
+            T *rdst = (T *)A.ref_out + P.ref_offset;
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                if (S.own[r] && !gdead)
+#pragma unroll
+                    for (int k = 0; k < K; ++k)
+#pragma unroll
+                        for (int q = 0; q < 7; ++q)
+                            rdst[q * C + (long)S.brow[r] * N + c0 + k] = S.ref(q, S.cell_of(r, k));
+        }
     } else if (A.out_field) {
         double *dst = A.out_field + P.mfinal_offset;
 #pragma unroll
@@ -811,7 +925,7 @@ __global__ void __launch_bounds__(L * NG, MINW) k_band(BandArgs A) {
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
                         const long cell = (long)S.brow[r] * N + c0 + k;
-                        dst[c * C + cell] = (double)S.m[r][k][c] + (double)tab[TL.ref + c * C + cell];
+                        dst[c * C + cell] = (double)S.m[r][k][c] + (double)S.ref(c, S.cell_of(r, k));
                     }
     }
     // per-wave partial sums, accumulated over launches in a fixed order

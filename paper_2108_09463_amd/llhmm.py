@@ -128,6 +128,10 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("libllhmm.so is missing: run `python -m paper_2108_09463_amd.build` "
                                "(the HIP library is required; there is no CPU path)")
+        # PyTorch carries its own HIP runtime (same soname as the system one);
+        # loading it first makes libllhmm bind to that single runtime, so the
+        # device pointers and streams PyTorch hands over belong to it.
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in _SYMBOLS.items():
             fn = getattr(L, name)
