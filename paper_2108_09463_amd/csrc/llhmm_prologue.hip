@@ -38,8 +38,20 @@ __device__ double coef_closed(const CoefDev &c, double x0, double x1) {
     return a;
 }
 
+// Sine factors of a closed-form coefficient, tabulated once per box: for term
+// t, S[(t * 4 + k) * kTabLen + idx] with k = 0: x1 factor at x1 faces f
+// (idx f + 2), 1: x1 factor at points, 2: x2 factor at x2 faces, 3: x2 factor
+// at points.  Each entry is the same expression coef_closed evaluates, so a
+// coefficient built from the table is bit-identical to the direct one.
+constexpr int kCoefTabTerms = 4;
+constexpr int kTabLen = 256 + 3;
+struct CoefTables {
+    const double *S;  // nullptr: evaluate directly
+};
+
 // a^eps on the face between point (i0, i1) and (i0, i1) + e_axis (unscaled).
-__device__ double face_coef(const PrologueArgs &A, const BoxPlan &P, int axis, int i0, int i1) {
+__device__ double face_coef(const PrologueArgs &A, const BoxPlan &P, const CoefTables &CT, int axis, int i0,
+                            int i1) {
     const int D = P.dim;
     if (P.coef_sampled) {
         const int E = P.n + 2 * kGhost;
@@ -48,6 +60,18 @@ __device__ double face_coef(const PrologueArgs &A, const BoxPlan &P, int axis, i
         return A.coef_samples[P.coef_offset + idx];
     }
     const CoefDev &c = A.coefs[P.coef_index];
+    if (CT.S) {
+        double a = c.c0;
+        for (int t = 0; t < c.n_terms; ++t) {
+            double p = c.amp[t];
+            const double *St = CT.S + t * 4 * kTabLen;
+            if (c.freq[t][0] != 0.0) p = p * (axis == 0 ? St[i0 + 2] : St[kTabLen + i0]);
+            if (c.dim == 2 && c.freq[t][1] != 0.0)
+                p = p * (axis == 1 ? St[2 * kTabLen + i1 + 2] : St[3 * kTabLen + i1]);
+            a = a + p;
+        }
+        return a;
+    }
     double x0 = P.cx + grid_xi(P, i0);
     double x1 = (D == 2) ? P.cy + grid_xi(P, i1) : 0.0;
     if (axis == 0) x0 = x0 + 0.5 * P.dx;
@@ -137,9 +161,9 @@ __device__ void ghost_delta(const PrologueArgs &A, const BoxPlan &P, const InitT
 // hi + lo = a' * G(delta) (lo is the rounding error of the product, exact by
 // FMA): with Dirichlet data delta is O(1) and a' = O(dx^-2), so hi alone would
 // carry an absolute error far above the flux's own rounding.
-__device__ void face_tau(const PrologueArgs &A, const BoxPlan &P, const InitTables &T, int axis, int f,
-                         int o, double hi[3], double lo[3]) {
-    double a = face_coef(A, P, axis, axis == 0 ? f : o, axis == 0 ? o : f) * P.a_scale;
+__device__ void face_tau(const PrologueArgs &A, const BoxPlan &P, const InitTables &T, const CoefTables &CT,
+                         int axis, int f, int o, double hi[3], double lo[3]) {
+    double a = face_coef(A, P, CT, axis, axis == 0 ? f : o, axis == 0 ? o : f) * P.a_scale;
     double dp1[3], d0[3], g[3];
     ghost_delta(A, P, T, axis, f + 1, o, dp1);
     ghost_delta(A, P, T, axis, f, o, d0);
@@ -251,10 +275,32 @@ __global__ void __launch_bounds__(256) k_prologue(PrologueArgs A) {
     const TabLayout L = tab_layout(D, N, P.form);
     T *tab = (T *)A.tabs + P.tab_offset;
     const int nth = blockDim.x, tid = threadIdx.x;
-    __shared__ double s_red[256][kMaxQ];
+    __shared__ double s_red[4][kMaxQ];
     __shared__ double s_Mloc[75];
     __shared__ double s_Lb[kLagMax * 5];
+    __shared__ double s_sin[kCoefTabTerms * 4 * kTabLen];
     InitTables IT{s_Mloc, s_Lb};
+    CoefTables CT{nullptr};
+    {
+        const CoefDev &c = A.coefs[P.coef_index];
+        if (!P.coef_sampled && c.n_terms <= kCoefTabTerms) {
+            // sine factors at every face and point position, once per box
+            const double two_pi = 6.283185307179586;
+            const int len = N + 3;
+            for (int t2 = tid; t2 < c.n_terms * 4 * len; t2 += nth) {
+                const int t = t2 / (4 * len), k = (t2 / len) % 4, idx = t2 % len;
+                const int ax = k / 2;
+                const bool face = (k % 2) == 0;
+                if (face ? idx > N + 2 : idx >= N) continue;
+                const int gi = face ? idx - 2 : idx;
+                if (ax == 1 && (c.dim != 2 || D != 2)) continue;
+                double x = (ax == 0 ? P.cx : P.cy) + grid_xi(P, gi);
+                if (face) x = x + 0.5 * P.dx;
+                s_sin[(t * 4 + k) * kTabLen + idx] = sin(two_pi * c.freq[t][ax] * x + c.phase[t][ax]);
+            }
+            CT.S = s_sin;
+        }
+    }
     if (P.init_mode == LLHMM_INIT_MACRO_Q) {
         // the macro values around the node and the basis at every grid index, once per box
         const int nm = A.macro.n;
@@ -272,8 +318,8 @@ __global__ void __launch_bounds__(256) k_prologue(PrologueArgs A) {
             }
         }
         for (int i = tid; i < N + 2 * kGhost; i += nth) lagrange5(grid_xi(P, i - kGhost) / A.macro.dX, s_Lb + i * 5);
-        __syncthreads();
     }
+    __syncthreads();  // per-box tables written
 
     // initial state (form 0) or reference + residual (form 1)
     for (long p = tid; p < cells; p += nth) {
@@ -297,14 +343,14 @@ __global__ void __launch_bounds__(256) k_prologue(PrologueArgs A) {
     Scratch64 S64(A.scratch64 + (P.form == 1 ? P.s64_offset : 0), D, N);
     for (long t = tid; t < (long)lines * nf; t += nth) {
         int line = (int)(t / nf), f = (int)(t % nf) - 2;
-        const double a = face_coef(A, P, 0, f, line) * P.a_scale;
+        const double a = face_coef(A, P, CT, 0, f, line) * P.a_scale;
         tab[L.ax + t] = (T)a;
         if (P.form == 1) S64.ax[t] = a;
     }
     if (D == 2) {
         for (long t = tid; t < (long)N * nf; t += nth) {
             int col = (int)(t / nf), f = (int)(t % nf) - 2;
-            const double a = face_coef(A, P, 1, col, f) * P.a_scale;
+            const double a = face_coef(A, P, CT, 1, col, f) * P.a_scale;
             tab[L.ay + t] = (T)a;
             if (P.form == 1) S64.ay[t] = a;
         }
@@ -325,7 +371,7 @@ __global__ void __launch_bounds__(256) k_prologue(PrologueArgs A) {
                 double hi[3] = {0.0, 0.0, 0.0}, lo[3] = {0.0, 0.0, 0.0};
                 if (q < GF) {
                     int f = (side == 0) ? (-FW + q) : (N - GF + FE + q);
-                    face_tau(A, P, IT, axis, f, line, hi, lo);
+                    face_tau(A, P, IT, CT, axis, f, line, hi, lo);
                 }
                 T *dst = tab + (axis == 0 ? L.tau1 : L.tau2) + t * 8;
                 for (int c = 0; c < 3; ++c) {
@@ -382,14 +428,14 @@ __global__ void __launch_bounds__(256) k_prologue(PrologueArgs A) {
             if (P.quantity == LLHMM_Q_FIELD) acc[c] += w[i0] * wy * h;
         }
     }
-    for (int q = 0; q < kMaxQ; ++q) s_red[tid][q] = acc[q];
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if (tid < off)
-            for (int q = 0; q < kMaxQ; ++q) s_red[tid][q] += s_red[tid + off][q];
-        __syncthreads();
+    // fixed-order reduction: wavefront shuffles, then the four wave sums
+    for (int q = 0; q < kMaxQ; ++q) {
+        double v = acc[q];
+        for (int off = 1; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
+        if ((tid & 63) == 0) s_red[tid >> 6][q] = v;
     }
-    if (tid < kMaxQ) A.box_const[(long)box * kMaxQ + tid] = s_red[0][tid];
+    __syncthreads();
+    if (tid < kMaxQ) A.box_const[(long)box * kMaxQ + tid] = (s_red[0][tid] + s_red[1][tid]) + (s_red[2][tid] + s_red[3][tid]);
 }
 #pragma clang fp contract(on)
 
