@@ -30,14 +30,13 @@ def skew(h):
 
 
 def implicit_midpoint_solve(M, hbar, dt):
-    """Solve (I - s[hbar]x) M' = (I + s[hbar]x) M pointwise, s = dt/2."""
+    """Solve (I - s[hbar]x) M' = (I + s[hbar]x) M pointwise, s = dt/2 (one 3 x 3
+    Gaussian elimination per point, all points in one stacked numpy.linalg.solve)."""
     s = 0.5 * dt
-    out = np.empty_like(M)
-    I = np.eye(3)
-    for i in range(M.shape[1]):
-        S = skew(hbar[:, i])
-        out[:, i] = np.linalg.solve(I - s * S, (I + s * S) @ M[:, i])
-    return out
+    S = np.stack([skew(hbar[:, i]) for i in range(M.shape[1])])      # [npts, 3, 3]
+    I = np.eye(3)[None]
+    rhs = np.einsum("pij,jp->pi", I + s * S, M)
+    return np.ascontiguousarray(np.linalg.solve(I - s * S, rhs[:, :, None])[:, :, 0].T)
 
 
 def mpea_hbar(h_j, h_jm1, h_jm2):
