@@ -1,0 +1,119 @@
+"""The HMM macro loop of eq. (macro_disc) on the GPU (Section 2.2, Section 3.1).
+
+One micro problem per macro node and stage: every stage of a macro step solves
+the whole batch at the stage input Y (micro initial data Q_[4] from Y, Section
+4.1), averages it to H_avg (eq. (upscaling)) and hands H_avg to
+llhmm_macro_step, which advances the macro state (HeunP start-up steps, then
+MPEA, eqs. (h_mpea), (mpe_update)).  The macro grid is periodic with nodes
+x_i = i dX (the unit interval or square); the macro state stays on the device
+and every stage is queued on one stream, the micro batch as a replayed HIP
+graph.
+"""
+from __future__ import annotations
+
+import copy
+
+import numpy as np
+
+from . import inputs
+from . import llhmm as L
+
+
+class HmmLoop:
+    """Runs eq. (macro_disc) with H_avg from the library's micro batches.
+
+    n_macro    macro nodes per axis (dX = 1 / n_macro)
+    M_init     macro initial data, [3, n_macro] or [3, n_macro, n_macro]
+    coef       the material coefficient a^eps (an inputs.SinSum)
+    micro      box fields shared by every micro problem (n, eps, mu, mu_box, eta,
+               alpha, bc, order, a_max, integrator, n_steps, quantity = field)
+    alpha, dt  macro damping and time step
+    """
+
+    def __init__(self, n_macro, M_init, coef, micro, alpha, dt, precision=inputs.FP32,
+                 K=None, ctx=None, graph=True, startup=None):
+        import torch
+        self.torch = torch
+        self.dev = torch.device("cuda", 0)
+        self.ctx = ctx or L.llhmm_create(0)
+        M_init = np.asarray(M_init, dtype=np.float64)
+        self.dim = M_init.ndim - 1
+        if self.dim not in (1, 2) or any(s != n_macro for s in M_init.shape[1:]):
+            raise ValueError("M_init must be [3, n] or [3, n, n] with n = n_macro")
+        self.n = n_macro
+        self.npts = n_macro ** self.dim
+        self.alpha, self.dt = float(alpha), float(dt)
+        self.startup = L.MACRO_HEUNP if startup is None else startup
+        dX = 1.0 / n_macro
+        boxes = []
+        for p in range(self.npts):
+            idx = (p // n_macro, p % n_macro) if self.dim == 2 else (p, 0)
+            b = inputs.make_box(**copy.deepcopy(micro))
+            b.update(dim=self.dim, quantity=inputs.Q_FIELD, init_mode=inputs.INIT_MACRO_Q,
+                     coef_index=0, center=(idx[0] * dX, idx[1] * dX if self.dim == 2 else 0.0),
+                     macro_index=idx)
+            boxes.append(b)
+        self.boxes = boxes
+        self.macro = dict(dim=self.dim, n=n_macro, dX=dX, x0=(0.0, 0.0))
+        self.batch = L.llhmm_batch_create(self.ctx, boxes, [L.to_coef(coef)], precision,
+                                          K or L.kernel())
+        self.graph = graph
+        f64 = dict(dtype=torch.float64, device=self.dev)
+        self.M = torch.from_numpy(np.ascontiguousarray(M_init.reshape(3, -1))).to(self.dev)
+        self.Y = self.M.clone()
+        self.H = torch.zeros((self.npts, 3), **f64)
+        self.work = torch.zeros(7 * 3 * self.npts, **f64)
+        self.status = torch.zeros(self.npts, dtype=torch.int32, device=self.dev)
+        self.bad = torch.zeros(self.npts, dtype=torch.int32, device=self.dev)
+        self.step_index = 0
+        self.stages = 0
+
+    def cell_steps_per_stage(self):
+        return self.batch.cell_steps()
+
+    def _micro(self):
+        if self.graph:
+            L.llhmm_batch_run_graph(self.ctx, self.batch, self.H, 3, self.status, None,
+                                    self.macro, self.Y)
+        else:
+            L.llhmm_micro_batch(self.ctx, self.batch, None, self.macro, self.Y)
+            L.llhmm_upscale(self.ctx, self.batch, self.H, 3, self.status, False)
+        self.bad |= self.status
+
+    def step(self):
+        """One macro step: as many micro batches and macro stages as the scheme has."""
+        scheme = self.startup if self.step_index < 2 else L.MACRO_MPEA
+        stage = 0
+        while True:
+            self._micro()
+            stage = L.llhmm_macro_step(self.ctx, self.npts, scheme, self.step_index, stage,
+                                       self.dt, self.alpha, self.M, self.H, self.Y, self.work)
+            self.stages += 1
+            if stage == 0:
+                break
+        self.step_index += 1
+
+    def run(self, steps, progress=None, every=100):
+        """`steps` macro steps; progress(step_index) is called every `every` steps
+        after the device has caught up (and checked for non-finite boxes)."""
+        for k in range(steps):
+            self.step()
+            if progress is not None and (self.step_index % every == 0 or k == steps - 1):
+                self.check()
+                progress(self.step_index)
+        self.check()
+
+    def check(self):
+        self.torch.cuda.synchronize(self.dev)
+        nbad = int((self.bad != 0).sum().item())
+        if nbad:
+            raise L.LlhmmError(L.E_UNSTABLE, f"{nbad} micro problems reported non-finite values")
+
+    def state(self):
+        """M as a host array shaped like M_init."""
+        self.torch.cuda.synchronize(self.dev)
+        shape = (3,) + (self.n,) * self.dim
+        return self.M.cpu().numpy().reshape(shape).copy()
+
+    def close(self):
+        self.batch.close()

@@ -25,6 +25,14 @@ external data set):
   alpha ~ U[0.01, 0.2], centres ~ U[0,1)^2, explicit init = EX2 initial data.
 * ``served``         128x128 macro grid, EX2 macro initial data, per point
   N in {32..128}, eps in {1/100,1/200,1/400}, alpha_micro = 1.2.
+* HMM loop setups (Section 4.5, fig:hmm_err_ex3): EX2 on the periodic unit
+  square, alpha = 0.01, T = 0.1, alpha_micro = 1.2, mu = 3.9 eps, Dirichlet
+  micro boxes, averaging kernels p = 3, q = 7.  eps = 1/384 (the paper: 1/400)
+  so that every macro node x = i dX, dX in {1/12, 1/24, 1/48, 1/96}, is a
+  multiple of eps, and dx = eps / P with an integer P, so all micro grids sit at
+  the same phase of a^eps.  s1-s4 take the paper's eta / eps^2 and the box
+  size mu' nearest the paper's that a supported N gives; s5 is an extra setup
+  with a smaller averaging error.
 """
 from __future__ import annotations
 
@@ -302,6 +310,31 @@ def uneven_batch(nboxes=4096, seed=4, precision=FP32, sizes=UNEVEN_SIZES, order=
 
 
 SERVED_EPS = (1.0 / 100.0, 1.0 / 200.0, 1.0 / 400.0)
+
+HMM_EPS = 1.0 / 384.0
+# name: (points per eps P, micro N, eta / eps^2); mu' = N / (2 P) eps.
+HMM_SETUPS = {
+    "s1": (6, 48, 0.15),     # mu' = 4 eps     (paper: 4)
+    "s2": (6, 64, 0.45),     # mu' = 5.33 eps  (paper: 5.5)
+    "s3": (6, 96, 0.7),      # mu' = 8 eps     (paper: 7.5)
+    "s4": (6, 128, 1.0),     # mu' = 10.67 eps (paper: 10)
+    "s5": (5, 128, 2.0),     # mu' = 12.8 eps
+}
+
+
+def hmm_micro(setup, eps=HMM_EPS, alpha=1.2, mu_over_eps=3.9):
+    """Box fields shared by every micro problem of an HMM loop setup."""
+    ppe, n, eta = HMM_SETUPS[setup]
+    return dict(n=n, order=2, integrator=INTEG_AUTO, bc=BC_DIRICHLET, eps=eps, alpha=alpha,
+                mu=mu_over_eps * eps, mu_box=0.5 * n / ppe * eps, eta=eta * eps * eps,
+                a_max=1.6)
+
+
+def ex2_macro(n_macro):
+    """EX2 initial data at the macro nodes x = (i, j) / n_macro, [3, n, n]."""
+    x = np.arange(n_macro) / n_macro
+    X1, X2 = np.meshgrid(x, x, indexing="ij")
+    return InitEX2()(X1, X2)
 
 
 def served_points(n_macro=128, seed=5, sizes=UNEVEN_SIZES):

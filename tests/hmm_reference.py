@@ -1,0 +1,88 @@
+"""Reference solutions for the HMM loop tests and study (oracle side only).
+
+* ``homogenized(ppe)``: the discrete homogenized matrix A^H of the micro
+  stencil (cell problem on P = ppe points per period, oracle.cell) and the
+  spectral reference M0(T) of eq. (hom) for EX2 on a 48 x 48 grid.  The micro
+  problems discretize a^eps with dx = eps / P at a fixed phase, so the HMM loop
+  converges to eq. (hom) with this discrete A^H; the continuous A^H differs
+  from it by the micro discretization error, which the paper assumes small.
+* ``oracle_loop``: the macro loop with H_avg from the FP64 C oracle's micro
+  solves (one per macro node and stage), oracle.macro time stepping.
+* ``ideal_loop``: the macro loop with the E_avg = 0 field (E_disc alone).
+"""
+from __future__ import annotations
+
+import functools
+import os
+
+import numpy as np
+
+from oracle import cell, homogenized as hg, micro
+from paper_2108_09463_amd import inputs
+
+NF = 48            # spectral grid of M0 (contains the macro grids 12, 24, 48)
+ALPHA = 0.01       # macro damping of the Section 4.5 experiment
+DT_FACTOR = 0.08   # macro dt = DT_FACTOR dX^2 (MPEA is stable below ~0.1 here)
+
+
+def steps_for(n_macro, T):
+    s = int(np.ceil(T / (DT_FACTOR / n_macro ** 2)))
+    return s, T / s
+
+
+@functools.lru_cache(maxsize=None)
+def discrete_AH(ppe):
+    return cell.homogenized_2d(inputs.coef_ex2(1.0), ppe)
+
+
+@functools.lru_cache(maxsize=None)
+def M0(ppe, T, A_key=None):
+    A = discrete_AH(ppe) if A_key is None else np.array(A_key).reshape(2, 2)
+    Mi = inputs.ex2_macro(NF)
+    return hg.solve_hom(Mi, A, ALPHA, T, hg.stable_steps(A, NF, ALPHA, T, 2))
+
+
+def a_avg():
+    """Cell average of the EX2 coefficient (the naive effective coefficient)."""
+    n = 256
+    y = np.arange(n) / n
+    Y1, Y2 = np.meshgrid(y, y, indexing="ij")
+    return float(np.mean(inputs.coef_ex2(1.0)(Y1, Y2)))
+
+
+def l2_err(M, ref):
+    """Discrete L2 norm on the unit square of M - ref at the macro nodes."""
+    n = M.shape[1]
+    r = ref[:, ::NF // n, ::NF // n]
+    return float(np.sqrt(np.mean(np.sum((M - r) ** 2, axis=0))))
+
+
+def ideal_loop(n_macro, ppe, T):
+    A = discrete_AH(ppe)
+    steps, dt = steps_for(n_macro, T)
+    M = hg.run_loop(inputs.ex2_macro(n_macro),
+                    lambda Y: hg.q4_node_field(Y.reshape(3, n_macro, n_macro), A,
+                                               1.0 / n_macro).reshape(3, -1),
+                    ALPHA, dt, steps)
+    return M.reshape(3, n_macro, n_macro)
+
+
+def oracle_loop(n_macro, setup, steps, dt, threads=None):
+    """`steps` macro steps with every stage's H_avg from the C oracle."""
+    from concurrent.futures import ThreadPoolExecutor
+    threads = threads or min(16, os.cpu_count() or 1)
+    tmpl = inputs.hmm_micro(setup)
+    coef = inputs.coef_ex2(tmpl["eps"])
+    dX = 1.0 / n_macro
+    boxes = [inputs.make_box(dim=2, quantity=inputs.Q_FIELD, init_mode=inputs.INIT_MACRO_Q,
+                             center=(i * dX, j * dX), macro_index=(i, j), **tmpl)
+             for i in range(n_macro) for j in range(n_macro)]
+
+    def field(Y):
+        mac = dict(n=n_macro, dX=dX, M=Y.reshape(3, n_macro, n_macro))
+        with ThreadPoolExecutor(threads) as ex:
+            out = list(ex.map(lambda b: micro.solve_box(b, coef, macro=mac)["out"], boxes))
+        return np.ascontiguousarray(np.stack(out).T)
+
+    return hg.run_loop(inputs.ex2_macro(n_macro), field, ALPHA, dt, steps).reshape(
+        3, n_macro, n_macro)
