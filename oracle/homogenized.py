@@ -22,6 +22,12 @@ check and the CPU baseline may use it.
   derivatives at the node follow from the Lagrange basis derivatives at 0 and
   the quotient rule for P / |P|.  A macro loop driven by this field is the HMM
   loop with E_avg = 0: its error against M0 is the discretization error alone.
+* Flux model eq. (macro_flux): the E_avg = 0 flux column j of grad Q A at the
+  staggered points x_i + dX/2 e_j (Q the interpolant around node i, evaluated
+  half a cell off the node) and its fourth-order staggered divergence.  The
+  paper asks for staggered flux locations but gives no divergence stencil;
+  fourth order matches the order of Q_[4].  Torque model eq. (macro_torque):
+  Q x div(grad Q A) at the nodes.
 * run_loop: the macro loop of eq. (macro_disc), time stepped by
   oracle.macro.MacroStepper (HeunP start-up, then MPEA), with the field of each
   stage supplied by a callable (the exact-interpolant field above, or H_avg
@@ -157,8 +163,8 @@ def plane_wave(xs, kvec, A, alpha, theta0, phi0, t):
 
 
 # ----------------------------------------------------------------- E_disc field
-def _lagrange_basis_derivs():
-    """D[p][l] = p-th derivative at s = 0 of the Lagrange basis polynomial L_l on
+def _lagrange_basis_derivs(s=0.0):
+    """D[p][l] = p-th derivative at s of the Lagrange basis polynomial L_l on
     the nodes -2..2 (l = 0..4 for the nodes -2..2), p = 0, 1, 2."""
     nodes = np.arange(-2, 3, dtype=np.float64)
     D = np.zeros((3, 5))
@@ -166,7 +172,7 @@ def _lagrange_basis_derivs():
         others = np.delete(nodes, l)
         poly = np.polynomial.Polynomial.fromroots(others) / np.prod(nodes[l] - others)
         for p in range(3):
-            D[p, l] = poly.deriv(p)(0.0) if p else poly(0.0)
+            D[p, l] = poly.deriv(p)(s) if p else poly(s)
     return D
 
 
@@ -224,12 +230,82 @@ def q4_node_field(M, A, dX):
     return F
 
 
+# ----------------------------------------------------------------- flux and torque models
+def q4_stagger_flux(M, A, dX, axis):
+    """E_avg = 0 flux of the flux model eq. (macro_flux): column `axis` of
+    grad Q A at the staggered points x_i + dX/2 e_axis, Q = P / |P| the
+    interpolant around node i (Section 4.1) evaluated half a cell off the node.
+    Returns F [3, n(, n)], F[..., i] belonging to x_i + dX/2 e_axis."""
+    M = np.asarray(M, dtype=np.float64)
+    d = M.ndim - 1
+    A = np.asarray(A, dtype=np.float64).reshape(d, d)
+    Dh = _lagrange_basis_derivs(0.5)      # along `axis`
+    D0 = _lagrange_basis_derivs(0.0)      # along the other axis
+    if d == 1:
+        def comb(p):
+            out = np.zeros_like(M)
+            for l in range(5):
+                out += Dh[p, l] * np.roll(M, -(l - 2), axis=1)
+            return out / dX ** p
+        P, dP = comb(0), [comb(1)]
+    else:
+        def comb(p0, p1):
+            B0 = Dh if axis == 0 else D0
+            B1 = Dh if axis == 1 else D0
+            out = np.zeros_like(M)
+            for a in range(5):
+                for b in range(5):
+                    w = B0[p0, a] * B1[p1, b]
+                    if w != 0.0:
+                        out += w * np.roll(np.roll(M, -(a - 2), axis=1), -(b - 2), axis=2)
+            return out / dX ** (p0 + p1)
+        P, dP = comb(0, 0), [comb(1, 0), comb(0, 1)]
+    r = np.sqrt(np.sum(P * P, axis=0))
+    F = np.zeros_like(P)
+    for k in range(d):
+        dQ = dP[k] / r - P * np.sum(P * dP[k], axis=0) / r ** 3
+        F += A[k, axis] * dQ
+    return F
+
+
+def staggered_divergence(F, dX, order=4):
+    """sum_j D_j F_j at the nodes from F_j at x_i + dX/2 e_j (F: list over axes of
+    [3, n(, n)]).  order 4: (27 (F_{i+1/2} - F_{i-1/2}) - (F_{i+3/2} - F_{i-3/2}))
+    / (24 dX); order 2: (F_{i+1/2} - F_{i-1/2}) / dX."""
+    out = np.zeros_like(F[0])
+    for j, Fj in enumerate(F):
+        ax = j + 1
+
+        def sh(k):           # F at staggered index i + k
+            return np.roll(Fj, -k, axis=ax)
+        if order == 4:
+            out += (27.0 * (sh(0) - sh(-1)) - (sh(1) - sh(-2))) / (24.0 * dX)
+        else:
+            out += (sh(0) - sh(-1)) / dX
+    return out
+
+
+def q4_flux_field(M, A, dX, order=4):
+    """The flux model's E_avg = 0 replacement for H_avg at the nodes."""
+    d = np.asarray(M).ndim - 1
+    return staggered_divergence([q4_stagger_flux(M, A, dX, j) for j in range(d)], dX, order)
+
+
+def q4_node_torque(M, A, dX):
+    """E_avg = 0 torque of eq. (macro_torque): Q x div(grad Q A) at the nodes."""
+    M = np.asarray(M, dtype=np.float64)
+    Q = M / np.sqrt(np.sum(M * M, axis=0, keepdims=True))
+    return np.cross(Q, q4_node_field(M, A, dX), axis=0)
+
+
 # ----------------------------------------------------------------- macro loop
-def run_loop(M_init, field_fn, alpha, dt, steps, startup="heunp"):
-    """`steps` macro steps of eq. (macro_disc); field_fn(Y) returns the field
-    [3, npts] at the stage input Y [3, npts].  Returns M [3, npts]."""
+def run_loop(M_init, field_fn, alpha, dt, steps, startup="heunp", model="field"):
+    """`steps` macro steps of eq. (macro_disc) (model "field"; the flux model
+    passes its divergence as the field) or eq. (macro_torque) (model "torque");
+    field_fn(Y) returns the averaged quantity [3, npts] at the stage input
+    Y [3, npts].  Returns M [3, npts]."""
     M0 = np.asarray(M_init, dtype=np.float64)
-    st = macro_mod.MacroStepper(M0.reshape(3, -1), alpha, dt, startup)
+    st = macro_mod.MacroStepper(M0.reshape(3, -1), alpha, dt, startup, model)
     while st.step < steps:
         st.advance(field_fn(st.Y))
     return st.M

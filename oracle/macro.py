@@ -13,6 +13,13 @@ Macro model eq. (macro_disc): dM_i/dt = -M_i x H_avg - alpha M_i x (M_i x H_avg)
   (Section 3.1: "values for m^1 (and m^2) ... using HeunP or RK4P"), each
   stage needing its own H_avg.
 
+* Torque model eq. (macro_torque): dM/dt = -T_avg - alpha M x T_avg.  It has no
+  cross product in its first term, so MPEA (built on the rotation structure)
+  does not apply; every step uses the start-up scheme (HeunP or RK4P) followed
+  by normalization (the projection of Section 3.1).
+* Flux model eq. (macro_flux): the field model with H_avg replaced by the
+  divergence of the averaged flux (see oracle.homogenized.staggered_divergence).
+
 State layout: component-major arrays [3, npts].
 """
 from __future__ import annotations
@@ -48,6 +55,10 @@ def rhs(M, Havg, alpha):
     return -c - alpha * np.cross(M, c, axis=0)
 
 
+def rhs_torque(M, T, alpha):
+    return -T - alpha * np.cross(M, T, axis=0)
+
+
 def normalize(M):
     return M / np.sqrt(np.sum(M * M, axis=0, keepdims=True))
 
@@ -56,7 +67,10 @@ class MacroStepper:
     """Drives one macro time step as a sequence of stages.  The caller supplies
     H_avg evaluated at ``self.Y`` for each stage."""
 
-    def __init__(self, M0, alpha, dt, startup="heunp"):
+    def __init__(self, M0, alpha, dt, startup="heunp", model="field"):
+        if model not in ("field", "torque"):
+            raise ValueError(model)
+        self.model = model
         self.M = np.array(M0, dtype=np.float64)
         self.Y = self.M.copy()
         self.alpha, self.dt = alpha, dt
@@ -67,6 +81,8 @@ class MacroStepper:
         self.k = []
 
     def scheme(self):
+        if self.model == "torque":
+            return self.startup
         if self.step >= 2:
             return "mpea"
         return self.startup
@@ -74,14 +90,14 @@ class MacroStepper:
     def advance(self, Havg):
         a, dt = self.alpha, self.dt
         sch = self.scheme()
-        if self.stage == 0:
+        if self.stage == 0 and self.model == "field":
             self.hist = [h_of(self.M, Havg, a)] + self.hist[:2]
         if sch == "mpea":
             hb = mpea_hbar(*self.hist)
             self.M = implicit_midpoint_solve(self.M, hb, dt)
             self._end_step()
             return
-        k = rhs(self.Y, Havg, a)
+        k = rhs(self.Y, Havg, a) if self.model == "field" else rhs_torque(self.Y, Havg, a)
         self.k.append(k)
         if sch == "heunp":
             if self.stage == 0:

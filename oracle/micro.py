@@ -11,7 +11,9 @@ Steps (paper passages in brackets):
   O3 init    explicit closed form, or the normalized interpolant
              Q_[4] = P_[4] / |P_[4]| of the macro values around x_k: 1-D
              Lagrange interpolation on the 5 macro nodes x_k + l dX,
-             l = -2..2, applied along x1 then x2 [Section 4.1, eq. (Q_k)].
+             l = -2..2, applied along x1 then x2 [Section 4.1, eq. (Q_k)],
+             at the absolute positions x_c + xi (the centre x_c may lie
+             between nodes, e.g. the staggered points of the flux model).
              Macro indices wrap periodically (the macro domain is periodic).
   O8 plan    oracle.stability.plan_steps, or a forced number of steps.
   O9/O10     oracle.kernels weights.
@@ -136,6 +138,21 @@ def q4_interpolant(macro, k, xi_axes):
     return P / np.sqrt(np.sum(P * P, axis=0, keepdims=True))
 
 
+def node_offsets(box, macro):
+    """Position of the box centre relative to its macro node x_k = x0 + k dX, per
+    axis.  The interpolant of Section 4.1 is evaluated at absolute positions, so a
+    centre between nodes (the staggered flux points of the flux model) shifts
+    the Lagrange arguments.  Offsets within 1e-9 dX of zero count as zero, so a
+    centre given as i / n and the node 0 + i dX are the same point."""
+    dX = macro["dX"]
+    x0 = macro.get("x0", (0.0, 0.0))
+    out = []
+    for a in range(box["dim"]):
+        o = box["center"][a] - (x0[a] + box["macro_index"][a] * dX)
+        out.append(0.0 if abs(o) <= 1e-9 * dX else o)
+    return out
+
+
 def initial_data(box, init_fn=None, macro=None):
     """m_init on the extended grid, [3][E^d] (2-D storage: [3][i1][i0])."""
     d, n = box["dim"], box["n"]
@@ -143,7 +160,8 @@ def initial_data(box, init_fn=None, macro=None):
     c = box["center"]
     if box["init_mode"] == 1:
         k = box["macro_index"]
-        axes = (xi,) if d == 1 else (xi, xi)
+        off = node_offsets(box, macro)
+        axes = (xi + off[0],) if d == 1 else (xi + off[0], xi + off[1])
         mi = q4_interpolant(macro, k, axes)
     elif d == 1:
         mi = init_fn(c[0] + xi)

@@ -134,3 +134,116 @@ def test_batched_midpoint_solve_matches_pointwise():
         S = macro.skew(h[:, i])
         ref = np.linalg.solve(np.eye(3) - 0.005 * S, (np.eye(3) + 0.005 * S) @ M[:, i])
         assert np.abs(out[:, i] - ref).max() < 1e-14
+
+
+def test_stagger_flux_matches_bruteforce_derivatives():
+    """Flux model: column j of grad Q A half a cell off the node against central
+    finite differences of micro.q4_interpolant evaluated there."""
+    n = 12
+    dX = 1.0 / n
+    M = inputs.InitEX2()(*grid(n))
+    mac = dict(n=n, dX=dX, M=M)
+    h = 2e-3 / n
+    for axis in (0, 1):
+        F = hg.q4_stagger_flux(M, A2, dX, axis)
+        for k in ((0, 0), (5, 7), (11, 3)):
+            o = [0.5 * dX if a == axis else 0.0 for a in (0, 1)]
+            x0 = o[0] + np.array([-h, 0.0, h])
+            x1 = o[1] + np.array([-h, 0.0, h])
+            Q = micro.q4_interpolant(mac, k, (x0, x1))          # [3, x2, x1]
+            g0 = (Q[:, 1, 2] - Q[:, 1, 0]) / (2 * h)
+            g1 = (Q[:, 2, 1] - Q[:, 0, 1]) / (2 * h)
+            want = A2[0, axis] * g0 + A2[1, axis] * g1
+            assert np.abs(F[:, k[0], k[1]] - want).max() < 1e-6 * np.abs(want).max(), (axis, k)
+
+
+def test_staggered_divergence_is_fourth_order():
+    """The staggered difference of exact plane-wave fluxes converges to the exact
+    field like dX^4 (and like dX^2 for the second-order stencil)."""
+    k = 2 * np.pi * np.array([1.0, 2.0])
+    errs = {2: [], 4: []}
+    for n in (16, 32, 64):
+        xs = grid(n)
+        F = []
+        for j in range(2):
+            sh = [x + (0.5 / n if a == j else 0.0) for a, x in enumerate(xs)]
+            m = hg.plane_wave(tuple(sh), k, A2, 0.0, 0.7, 0.3, 0.0)
+            grads = [kk * np.stack([-m[1], m[0], 0 * m[2]]) for kk in k]   # d_a m
+            F.append(sum(A2[a, j] * grads[a] for a in range(2)))
+        m = hg.plane_wave(xs, k, A2, 0.0, 0.7, 0.3, 0.0)
+        exact = -(k @ A2 @ k) * (m - m[2:3] * np.array([0, 0, 1.0])[:, None, None])
+        for order in (2, 4):
+            errs[order].append(np.abs(hg.staggered_divergence(F, 1.0 / n, order) - exact).max())
+    for order in (2, 4):
+        e = errs[order]
+        for a, b in zip(e, e[1:]):
+            assert abs(np.log2(a / b) - order) < 0.2, (order, e)
+
+
+def test_torque_stepper_follows_the_plane_wave():
+    """The torque-model stepping (RK4P on dM/dt = -T - alpha M x T) driven by the
+    exact torque M x F(M) reproduces the closed-form plane wave."""
+    N, T, alpha = 16, 0.004, 0.3
+    xs = grid(N)
+    k = 2 * np.pi * np.array([1.0, 1.0])
+    M0 = hg.plane_wave(xs, k, A2, alpha, 0.7, 0.2, 0.0)
+    steps = 2 * hg.stable_steps(A2, N, alpha, T, 2)
+    M = hg.run_loop(M0, lambda Y: np.cross(Y, hg.hom_field(Y.reshape(3, N, N), A2).reshape(3, -1),
+                                           axis=0),
+                    alpha, T / steps, steps, startup="rk4p", model="torque").reshape(3, N, N)
+    want = hg.plane_wave(xs, k, A2, alpha, 0.7, 0.2, T)
+    assert np.abs(M - want).max() < 1e-8
+    assert np.abs(want - M0).max() > 0.05
+
+
+@pytest.mark.parametrize("model", ["flux", "torque"])
+def test_ideal_flux_and_torque_loops_are_fourth_order(model):
+    """Flux model (staggered fluxes, fourth-order divergence, MPEA) and torque
+    model (RK4P) with E_avg = 0 converge to M0 like dX^4."""
+    A = cell.homogenized_2d(inputs.coef_ex2(1.0), 6)
+    T, alpha, Nf = 0.02, 0.01, 48
+    M0 = hg.solve_hom(inputs.InitEX2()(*grid(Nf)), A, alpha, T,
+                      hg.stable_steps(A, Nf, alpha, T, 2))
+    errs = []
+    for n in (12, 24):
+        steps = int(np.ceil(T / (0.08 / n ** 2)))
+        if model == "flux":
+            f = lambda Y: hg.q4_flux_field(Y.reshape(3, n, n), A, 1.0 / n).reshape(3, -1)
+            kw = dict(startup="heunp", model="field")
+        else:
+            f = lambda Y: hg.q4_node_torque(Y.reshape(3, n, n), A, 1.0 / n).reshape(3, -1)
+            kw = dict(startup="rk4p", model="torque")
+        M = hg.run_loop(inputs.InitEX2()(*grid(n)), f, alpha, T / steps, steps, **kw)
+        ref = M0[:, ::Nf // n, ::Nf // n]
+        errs.append(np.sqrt(np.mean(np.sum((M.reshape(3, n, n) - ref) ** 2, axis=0))))
+    assert errs[0] / errs[1] > 12.0, errs
+
+
+def test_offset_centre_interpolates_at_absolute_positions():
+    """Micro initial data of a box centred between macro nodes: with macro values
+    sampled from a polynomial of degree 4 per component, P_[4] reproduces the
+    polynomial, so Q_[4] must equal the normalized polynomial at the box's
+    absolute grid positions (centre on the node, half a cell off along x1,
+    along x2, or a third of a cell off along both)."""
+    n = 12
+    dX = 1.0 / n
+
+    def poly(x1, x2):
+        return np.stack([0.3 + x1 - 2 * x1 ** 2 + 3 * x1 ** 3 * x2 - x2 ** 4,
+                         0.5 - x2 + x1 * x2 + 0.7 * x2 ** 2 - x1 ** 4,
+                         1.0 + 0.2 * x1 + 0.1 * x2 ** 3 + x1 ** 2 * x2 ** 2])
+
+    x = np.arange(n) * dX
+    X1, X2 = np.meshgrid(x, x, indexing="ij")
+    mac = dict(n=n, dX=dX, M=poly(X1, X2))
+    k = (5, 6)
+    for off in ((0.0, 0.0), (0.5, 0.0), (0.0, 0.5), (1 / 3, 1 / 3)):
+        c = (k[0] * dX + off[0] * dX, k[1] * dX + off[1] * dX)
+        b = inputs.make_box(dim=2, n=16, init_mode=1, macro_index=k, center=c, mu=0.01,
+                            mu_box=0.01)
+        mi = micro.initial_data(b, macro=mac).reshape(3, 22, 22)      # [3][i1][i0]
+        xi, _ = micro.grid_positions(16, 0.01)
+        G0, G1 = np.meshgrid(c[0] + xi, c[1] + xi, indexing="xy")
+        want = poly(G0, G1)
+        want = want / np.sqrt(np.sum(want * want, axis=0, keepdims=True))
+        assert np.abs(mi - want).max() < 1e-12, off
