@@ -21,9 +21,10 @@
  *     model) or m x H (torque model), accumulated in index order.
  *
  * Grid (extended with G ghost layers per side): interior index i in [0, N),
- * extended side E = N + 2G, 2-D storage index (i1+G)*E + (i0+G) with axis 0
- * fastest.  A[ax][idx] is the coefficient on the face between cell idx and
- * idx + e_ax.  m_init is given on the whole extended grid.
+ * extended side E = N + 2G, storage index ((i2+G)*E + (i1+G))*E + (i0+G)
+ * (fewer terms for d < 3) with axis 0 fastest.  A[ax][idx] is the coefficient
+ * on the face between cell idx and idx + e_ax.  m_init is given on the whole
+ * extended grid.  d = 1, 2, 3 (the problem allows d <= 3, Section 2.1).
  */
 #include <math.h>
 #include <stdlib.h>
@@ -39,40 +40,53 @@ typedef struct {
     const double *minit; /* [3][E^d] */
 } grid_t;
 
-static long ext_index(const grid_t *g, int i0, int i1) {
+static long ext_index3(const grid_t *g, int i0, int i1, int i2) {
     if (g->d == 1) return (long)(i0 + GW);
-    return (long)(i1 + GW) * g->E + (i0 + GW);
+    if (g->d == 2) return (long)(i1 + GW) * g->E + (i0 + GW);
+    return ((long)(i2 + GW) * g->E + (i1 + GW)) * g->E + (i0 + GW);
 }
 
-static long axis_stride(const grid_t *g, int ax) { return ax == 0 ? 1 : g->E; }
+static long axis_stride(const grid_t *g, int ax) {
+    return ax == 0 ? 1 : (ax == 1 ? g->E : (long)g->E * g->E);
+}
 
-/* Fill the ghost layers of y (3 components, extended storage) from its interior. */
+/* interior extents along axes 1 and 2 (1 when the axis does not exist) */
+static int ext_n1(const grid_t *g) { return g->d >= 2 ? g->N : 1; }
+static int ext_n2(const grid_t *g) { return g->d >= 3 ? g->N : 1; }
+
+/* Fill the ghost layers of y (3 components, extended storage) from its interior:
+ * for each axis, the ghost points whose other coordinates are interior. */
 static void fill_ghosts(const grid_t *g, double *y) {
     const int N = g->N;
     for (int ax = 0; ax < g->d; ++ax) {
-        int other_n = (g->d == 1) ? 1 : N;
-        for (int o = 0; o < other_n; ++o) {
-            for (int gi = -GW; gi < N + GW; ++gi) {
-                if (gi >= 0 && gi < N) continue;
-                int wrap = ((gi % N) + N) % N;
-                long gidx, widx;
-                if (ax == 0) {
-                    gidx = ext_index(g, gi, o);
-                    widx = ext_index(g, wrap, o);
-                } else {
-                    gidx = ext_index(g, o, gi);
-                    widx = ext_index(g, o, wrap);
-                }
-                for (int c = 0; c < 3; ++c) {
-                    const double *mi = g->minit + c * g->cells_ext;
-                    double *yc = y + c * g->cells_ext;
-                    if (g->bc == 0) /* periodic perturbation m - m_init */
-                        yc[gidx] = yc[widx] + (mi[gidx] - mi[widx]);
-                    else            /* Dirichlet: m = m_init on ghosts */
-                        yc[gidx] = mi[gidx];
+        int na = (g->d >= 2) ? N : 1; /* first other axis */
+        int nb = (g->d >= 3) ? N : 1; /* second other axis */
+        for (int ob = 0; ob < nb; ++ob)
+            for (int oa = 0; oa < na; ++oa) {
+                for (int gi = -GW; gi < N + GW; ++gi) {
+                    if (gi >= 0 && gi < N) continue;
+                    int wrap = ((gi % N) + N) % N;
+                    long gidx, widx;
+                    if (ax == 0) {
+                        gidx = ext_index3(g, gi, oa, ob);
+                        widx = ext_index3(g, wrap, oa, ob);
+                    } else if (ax == 1) {
+                        gidx = ext_index3(g, oa, gi, ob);
+                        widx = ext_index3(g, oa, wrap, ob);
+                    } else {
+                        gidx = ext_index3(g, oa, ob, gi);
+                        widx = ext_index3(g, oa, ob, wrap);
+                    }
+                    for (int c = 0; c < 3; ++c) {
+                        const double *mi = g->minit + c * g->cells_ext;
+                        double *yc = y + c * g->cells_ext;
+                        if (g->bc == 0) /* periodic perturbation m - m_init */
+                            yc[gidx] = yc[widx] + (mi[gidx] - mi[widx]);
+                        else            /* Dirichlet: m = m_init on ghosts */
+                            yc[gidx] = mi[gidx];
+                    }
                 }
             }
-        }
     }
 }
 
@@ -116,126 +130,153 @@ static void cross(const double *a, const double *b, double *out) {
 /* H for every interior cell: H[c][ext idx].  y gets its ghosts filled first. */
 static void field_all(const grid_t *g, double *y, double *H) {
     fill_ghosts(g, y);
-    int n1 = (g->d == 1) ? 1 : g->N;
+    int n1 = ext_n1(g), n2 = ext_n2(g);
     for (int c = 0; c < 3; ++c)
-        for (int i1 = 0; i1 < n1; ++i1)
-            for (int i0 = 0; i0 < g->N; ++i0) {
-                long idx = ext_index(g, i0, i1);
-                H[c * g->cells_ext + idx] = field_at(g, y + c * g->cells_ext, idx);
-            }
+        for (int i2 = 0; i2 < n2; ++i2)
+            for (int i1 = 0; i1 < n1; ++i1)
+                for (int i0 = 0; i0 < g->N; ++i0) {
+                    long idx = ext_index3(g, i0, i1, i2);
+                    H[c * g->cells_ext + idx] = field_at(g, y + c * g->cells_ext, idx);
+                }
 }
 
 /* f(y) = -y x H - alpha y x (y x H) for every interior cell; also returns H. */
 static void rhs_all(const grid_t *g, double alpha, double *y, double *H, double *f) {
     field_all(g, y, H);
-    int n1 = (g->d == 1) ? 1 : g->N;
+    int n1 = ext_n1(g), n2 = ext_n2(g);
     long ce = g->cells_ext;
-    for (int i1 = 0; i1 < n1; ++i1)
-        for (int i0 = 0; i0 < g->N; ++i0) {
-            long idx = ext_index(g, i0, i1);
-            double m[3] = {y[idx], y[ce + idx], y[2 * ce + idx]};
-            double h[3] = {H[idx], H[ce + idx], H[2 * ce + idx]};
-            double mxh[3], mxmxh[3];
-            cross(m, h, mxh);
-            cross(m, mxh, mxmxh);
-            for (int c = 0; c < 3; ++c) f[c * ce + idx] = -mxh[c] - alpha * mxmxh[c];
-        }
+    for (int i2 = 0; i2 < n2; ++i2)
+        for (int i1 = 0; i1 < n1; ++i1)
+            for (int i0 = 0; i0 < g->N; ++i0) {
+                long idx = ext_index3(g, i0, i1, i2);
+                double m[3] = {y[idx], y[ce + idx], y[2 * ce + idx]};
+                double h[3] = {H[idx], H[ce + idx], H[2 * ce + idx]};
+                double mxh[3], mxmxh[3];
+                cross(m, h, mxh);
+                cross(m, mxh, mxmxh);
+                for (int c = 0; c < 3; ++c) f[c * ce + idx] = -mxh[c] - alpha * mxmxh[c];
+            }
 }
 
-/* Quantity sum at one time level: out3d[...] += wt * sum_j w_j Q_j. */
+/* Product weight of cell (i0, i1, i2): w_c along every axis except `face_ax`,
+ * where the east-face weight w_f is used (face_ax = -1: cell weight everywhere). */
+static double weight(const grid_t *g, const double *wc, const double *wf, int face_ax,
+                     int i0, int i1, int i2) {
+    const int idx[3] = {i0, i1, i2};
+    double w = 1.0;
+    for (int ax = 0; ax < g->d; ++ax) {
+        double f = (ax == face_ax) ? wf[idx[ax]] : wc[idx[ax]];
+        w = (ax == 0) ? f : w * f;
+    }
+    return w;
+}
+
+/* Quantity sum at one time level: out3d[...] += wt * sum_j w_j Q_j.  The boxes
+ * are cubes, so every axis uses the same cell weights wc and face weights wf. */
 static void accumulate(const grid_t *g, int quantity, double wt, double *y, double *H,
-                       const double *wx, const double *wy, const double *wfx,
-                       const double *wfy, double *out) {
+                       const double *wc, const double *wf, double *out) {
     field_all(g, y, H);
-    int n1 = (g->d == 1) ? 1 : g->N;
+    int n1 = ext_n1(g), n2 = ext_n2(g);
     long ce = g->cells_ext;
     if (quantity == 1) { /* flux model: a grad m on the east face of each cell */
         for (int ax = 0; ax < g->d; ++ax)
             for (int c = 0; c < 3; ++c) {
                 double s = 0.0;
-                for (int i1 = 0; i1 < n1; ++i1)
-                    for (int i0 = 0; i0 < g->N; ++i0) {
-                        long idx = ext_index(g, i0, i1);
-                        double w;
-                        if (g->d == 1) w = wfx[i0];
-                        else if (ax == 0) w = wfx[i0] * wy[i1];
-                        else w = wx[i0] * wfy[i1];
-                        s += w * face_flux(g, y + c * ce, idx, ax);
-                    }
+                for (int i2 = 0; i2 < n2; ++i2)
+                    for (int i1 = 0; i1 < n1; ++i1)
+                        for (int i0 = 0; i0 < g->N; ++i0) {
+                            long idx = ext_index3(g, i0, i1, i2);
+                            double w = weight(g, wc, wf, ax, i0, i1, i2);
+                            s += w * face_flux(g, y + c * ce, idx, ax);
+                        }
                 out[ax * 3 + c] += wt * s;
             }
         return;
     }
     for (int c = 0; c < 3; ++c) {
         double s = 0.0;
-        for (int i1 = 0; i1 < n1; ++i1)
-            for (int i0 = 0; i0 < g->N; ++i0) {
-                long idx = ext_index(g, i0, i1);
-                double w = (g->d == 1) ? wx[i0] : wx[i0] * wy[i1];
-                double q;
-                if (quantity == 0) {
-                    q = H[c * ce + idx];
-                } else { /* torque m x H */
-                    double m[3] = {y[idx], y[ce + idx], y[2 * ce + idx]};
-                    double h[3] = {H[idx], H[ce + idx], H[2 * ce + idx]};
-                    double t[3];
-                    cross(m, h, t);
-                    q = t[c];
+        for (int i2 = 0; i2 < n2; ++i2)
+            for (int i1 = 0; i1 < n1; ++i1)
+                for (int i0 = 0; i0 < g->N; ++i0) {
+                    long idx = ext_index3(g, i0, i1, i2);
+                    double w = weight(g, wc, wf, -1, i0, i1, i2);
+                    double q;
+                    if (quantity == 0) {
+                        q = H[c * ce + idx];
+                    } else { /* torque m x H */
+                        double m[3] = {y[idx], y[ce + idx], y[2 * ce + idx]};
+                        double h[3] = {H[idx], H[ce + idx], H[2 * ce + idx]};
+                        double t[3];
+                        cross(m, h, t);
+                        q = t[c];
+                    }
+                    s += w * q;
                 }
-                s += w * q;
-            }
         out[c] += wt * s;
     }
 }
 
 static double energy(const grid_t *g, double *y) {
     fill_ghosts(g, y);
-    int n1 = (g->d == 1) ? 1 : g->N;
+    int n1 = ext_n1(g), n2 = ext_n2(g);
     long ce = g->cells_ext;
     double e = 0.0;
     for (int ax = 0; ax < g->d; ++ax)
-        for (int i1 = 0; i1 < n1; ++i1)
-            for (int i0 = 0; i0 < g->N; ++i0) {
-                long idx = ext_index(g, i0, i1);
-                double a = g->A[ax * ce + idx];
-                for (int c = 0; c < 3; ++c) {
-                    double fl = face_flux(g, y + c * ce, idx, ax);
-                    /* fl = a * grad; energy density a |grad|^2 / 2 = fl^2 / (2a) */
-                    e += 0.5 * fl * fl / a;
+        for (int i2 = 0; i2 < n2; ++i2)
+            for (int i1 = 0; i1 < n1; ++i1)
+                for (int i0 = 0; i0 < g->N; ++i0) {
+                    long idx = ext_index3(g, i0, i1, i2);
+                    double a = g->A[ax * ce + idx];
+                    for (int c = 0; c < 3; ++c) {
+                        double fl = face_flux(g, y + c * ce, idx, ax);
+                        /* fl = a * grad; energy density a |grad|^2 / 2 = fl^2 / (2a) */
+                        e += 0.5 * fl * fl / a;
+                    }
                 }
-            }
     return e * pow(g->dx, g->d);
 }
 
 static double norm_dev(const grid_t *g, const double *y) {
-    int n1 = (g->d == 1) ? 1 : g->N;
+    int n1 = ext_n1(g), n2 = ext_n2(g);
     long ce = g->cells_ext;
     double dev = 0.0;
-    for (int i1 = 0; i1 < n1; ++i1)
-        for (int i0 = 0; i0 < g->N; ++i0) {
-            long idx = ext_index(g, i0, i1);
-            double n = sqrt(y[idx] * y[idx] + y[ce + idx] * y[ce + idx] + y[2 * ce + idx] * y[2 * ce + idx]);
-            double d = fabs(n - 1.0);
-            if (d > dev) dev = d;
-        }
+    for (int i2 = 0; i2 < n2; ++i2)
+        for (int i1 = 0; i1 < n1; ++i1)
+            for (int i0 = 0; i0 < g->N; ++i0) {
+                long idx = ext_index3(g, i0, i1, i2);
+                double n = sqrt(y[idx] * y[idx] + y[ce + idx] * y[ce + idx] + y[2 * ce + idx] * y[2 * ce + idx]);
+                double d = fabs(n - 1.0);
+                if (d > dev) dev = d;
+            }
     return dev;
+}
+
+static long cells_ext_of(int d, int E) {
+    return (d == 1) ? (long)E : (d == 2 ? (long)E * E : (long)E * E * E);
+}
+
+/* Copy the interior of an extended [3][E^d] array into a packed [3][N^d] one. */
+static void pack_interior(const grid_t *g, const double *src, double *dst) {
+    int n1 = ext_n1(g), n2 = ext_n2(g);
+    long nc = (long)g->N * n1 * n2;
+    for (int c = 0; c < 3; ++c)
+        for (int i2 = 0; i2 < n2; ++i2)
+            for (int i1 = 0; i1 < n1; ++i1)
+                for (int i0 = 0; i0 < g->N; ++i0)
+                    dst[c * nc + ((long)i2 * n1 + i1) * g->N + i0] =
+                        src[c * g->cells_ext + ext_index3(g, i0, i1, i2)];
 }
 
 /* Evaluate H(y) once; y_ext [3][E^d] (interior used, ghosts refilled), H_out [3][N^d]. */
 int oracle_eval_field(int d, int N, int order, int bc, double dx, const double *A,
                       const double *minit, const double *y_ext, double *H_out) {
     grid_t g = {d, N, N + 2 * GW, order, bc, 0, dx, A, minit};
-    g.cells_ext = (d == 1) ? g.E : (long)g.E * g.E;
+    g.cells_ext = cells_ext_of(d, g.E);
     double *y = malloc(sizeof(double) * 3 * g.cells_ext);
     double *H = calloc(3 * g.cells_ext, sizeof(double));
     memcpy(y, y_ext, sizeof(double) * 3 * g.cells_ext);
     field_all(&g, y, H);
-    int n1 = (d == 1) ? 1 : N;
-    long nc = (long)N * n1;
-    for (int c = 0; c < 3; ++c)
-        for (int i1 = 0; i1 < n1; ++i1)
-            for (int i0 = 0; i0 < N; ++i0)
-                H_out[c * nc + (long)i1 * N + i0] = H[c * g.cells_ext + ext_index(&g, i0, i1)];
+    pack_interior(&g, H, H_out);
     free(y);
     free(H);
     return 0;
@@ -245,19 +286,18 @@ int oracle_eval_field(int d, int N, int order, int bc, double dx, const double *
  * Solve one micro problem.
  *   integ: 1 = HeunP, 2 = RK4P; bc: 0 periodic m - m_init, 1 Dirichlet;
  *   quantity: 0 field, 1 flux, 2 torque; project: 1 normal, 0 off (tests only)
- *   wx, wy: per-axis cell weights [N]; wfx, wfy: per-axis east-face weights [N]
+ *   wc: cell weights [N]; wf: east-face weights [N] (the same on every axis)
  *   wt: time weights [M+1]
  *   out: [3] or [3d] (flux: [axis][component]); mfinal [3][N^d] (nullable);
  *   energy_out, normdev_out: [M+1] (nullable)
  */
 int oracle_solve_box(int d, int N, int order, int integ, int bc, int quantity, int project,
                      double dx, double alpha, double dt, int M,
-                     const double *A, const double *minit,
-                     const double *wx, const double *wy, const double *wfx, const double *wfy,
+                     const double *A, const double *minit, const double *wc, const double *wf,
                      const double *wt, double *out, double *mfinal,
                      double *energy_out, double *normdev_out) {
     grid_t g = {d, N, N + 2 * GW, order, bc, 0, dx, A, minit};
-    g.cells_ext = (d == 1) ? g.E : (long)g.E * g.E;
+    g.cells_ext = cells_ext_of(d, g.E);
     long ce = g.cells_ext;
     size_t bytes = sizeof(double) * 3 * ce;
     double *m = malloc(bytes), *y = malloc(bytes), *H = calloc(3 * ce, sizeof(double));
@@ -266,10 +306,10 @@ int oracle_solve_box(int d, int N, int order, int integ, int bc, int quantity, i
     memcpy(m, minit, bytes); /* interior = m_init; ghosts are refilled before use */
     int nq = (quantity == 1) ? 3 * d : 3;
     for (int q = 0; q < nq; ++q) out[q] = 0.0;
-    int n1 = (d == 1) ? 1 : N;
+    int n1 = ext_n1(&g), n2 = ext_n2(&g);
 
     for (int n = 0; n <= M; ++n) {
-        accumulate(&g, quantity, wt[n], m, H, wx, wy, wfx, wfy, out);
+        accumulate(&g, quantity, wt[n], m, H, wc, wf, out);
         if (energy_out) energy_out[n] = energy(&g, m);
         if (normdev_out) normdev_out[n] = norm_dev(&g, m);
         if (n == M) break;
@@ -290,22 +330,17 @@ int oracle_solve_box(int d, int N, int order, int integ, int bc, int quantity, i
                 m[t] = m[t] + dt / 6.0 * (k1[t] + 2.0 * k2[t] + 2.0 * k3[t] + k4[t]);
         }
         if (project) {
-            for (int i1 = 0; i1 < n1; ++i1)
-                for (int i0 = 0; i0 < N; ++i0) {
-                    long idx = ext_index(&g, i0, i1);
-                    double nr = sqrt(m[idx] * m[idx] + m[ce + idx] * m[ce + idx] +
-                                     m[2 * ce + idx] * m[2 * ce + idx]);
-                    for (int c = 0; c < 3; ++c) m[c * ce + idx] /= nr;
-                }
+            for (int i2 = 0; i2 < n2; ++i2)
+                for (int i1 = 0; i1 < n1; ++i1)
+                    for (int i0 = 0; i0 < N; ++i0) {
+                        long idx = ext_index3(&g, i0, i1, i2);
+                        double nr = sqrt(m[idx] * m[idx] + m[ce + idx] * m[ce + idx] +
+                                         m[2 * ce + idx] * m[2 * ce + idx]);
+                        for (int c = 0; c < 3; ++c) m[c * ce + idx] /= nr;
+                    }
         }
     }
-    if (mfinal) {
-        long nc = (long)N * n1;
-        for (int c = 0; c < 3; ++c)
-            for (int i1 = 0; i1 < n1; ++i1)
-                for (int i0 = 0; i0 < N; ++i0)
-                    mfinal[c * nc + (long)i1 * N + i0] = m[c * ce + ext_index(&g, i0, i1)];
-    }
+    if (mfinal) pack_interior(&g, m, mfinal);
     free(m); free(y); free(H); free(k1); free(k2); free(k3); free(k4);
     int bad = 0;
     for (int q = 0; q < nq; ++q) if (!isfinite(out[q])) bad = 1;

@@ -64,7 +64,7 @@ def _lib(variant="plain"):
     if variant not in _LIBS:
         L = ctypes.CDLL(build(variant=variant))
         dp = ctypes.POINTER(ctypes.c_double)
-        L.oracle_solve_box.argtypes = [ctypes.c_int] * 7 + [ctypes.c_double] * 3 + [ctypes.c_int] + [dp] * 11
+        L.oracle_solve_box.argtypes = [ctypes.c_int] * 7 + [ctypes.c_double] * 3 + [ctypes.c_int] + [dp] * 9
         L.oracle_solve_box.restype = ctypes.c_int
         L.oracle_eval_field.argtypes = [ctypes.c_int] * 4 + [ctypes.c_double] + [dp] * 4
         L.oracle_eval_field.restype = ctypes.c_int
@@ -94,10 +94,20 @@ def face_coefficients(box, coef):
     c = box["center"]
     if d == 1:
         return np.ascontiguousarray(coef(c[0] + xi + 0.5 * dx)[None, :]), dx
-    X0, X1 = np.meshgrid(c[0] + xi, c[1] + xi, indexing="xy")   # [i1][i0]
-    a0 = coef(X0 + 0.5 * dx, X1)
-    a1 = coef(X0, X1 + 0.5 * dx)
-    return np.ascontiguousarray(np.stack([a0, a1])), dx
+    if d == 2:
+        X0, X1 = np.meshgrid(c[0] + xi, c[1] + xi, indexing="xy")   # [i1][i0]
+        a0 = coef(X0 + 0.5 * dx, X1)
+        a1 = coef(X0, X1 + 0.5 * dx)
+        return np.ascontiguousarray(np.stack([a0, a1])), dx
+    X0, X1, X2 = grid3(c, xi)                                       # [i2][i1][i0]
+    a = [coef(X0 + 0.5 * dx, X1, X2), coef(X0, X1 + 0.5 * dx, X2), coef(X0, X1, X2 + 0.5 * dx)]
+    return np.ascontiguousarray(np.stack(a)), dx
+
+
+def grid3(c, xi):
+    """Absolute coordinates of the 3-D extended grid, each shaped [i2][i1][i0]."""
+    X2, X1, X0 = np.meshgrid(c[2] + xi, c[1] + xi, c[0] + xi, indexing="ij")
+    return X0, X1, X2
 
 
 def lagrange5(s):
@@ -117,10 +127,19 @@ def lagrange5(s):
 def q4_interpolant(macro, k, xi_axes):
     """Q_[4] at the tensor grid xi_axes (tuple of 1-D arrays) around macro node k.
 
-    macro: dict(n, dX, M[3, n(, n)]).  Returns [3] + grid shape (axis 0 fastest
-    in 2-D: shape [3, len(xi1), len(xi0)]).
+    macro: dict(n, dX, M[3, n(, n(, n))]).  Returns [3] + grid shape with axis 0
+    fastest: [3, len(xi1), len(xi0)] in 2-D, [3, len(xi2), len(xi1), len(xi0)] in 3-D.
     """
     n, dX, M = macro["n"], macro["dX"], np.asarray(macro["M"], dtype=np.float64)
+    if len(xi_axes) == 3:
+        Ls = [lagrange5(x / dX) for x in xi_axes]            # [5, n_a] per axis
+        ids = [[(k[a] + l) % n for l in range(-2, 3)] for a in range(3)]
+        vals = M[:, ids[0]][:, :, ids[1]][:, :, :, ids[2]]   # [3, l0, l1, l2]
+        # along x1, then x2, then x3
+        t0 = np.einsum("cabe,ai->cibe", vals, Ls[0])          # [3, n0, l1, l2]
+        t1 = np.einsum("cibe,bj->cije", t0, Ls[1])            # [3, n0, n1, l2]
+        P = np.einsum("cije,ek->ckji", t1, Ls[2])             # [3, n2, n1, n0]
+        return P / np.sqrt(np.sum(P * P, axis=0, keepdims=True))
     if len(xi_axes) == 1:
         L0 = lagrange5(xi_axes[0] / dX)                   # [5, n0]
         idx = [(k[0] + l) % n for l in range(-2, 3)]
@@ -145,7 +164,7 @@ def node_offsets(box, macro):
     the Lagrange arguments.  Offsets within 1e-9 dX of zero count as zero, so a
     centre given as i / n and the node 0 + i dX are the same point."""
     dX = macro["dX"]
-    x0 = macro.get("x0", (0.0, 0.0))
+    x0 = macro.get("x0", (0.0, 0.0, 0.0))
     out = []
     for a in range(box["dim"]):
         o = box["center"][a] - (x0[a] + box["macro_index"][a] * dX)
@@ -154,20 +173,23 @@ def node_offsets(box, macro):
 
 
 def initial_data(box, init_fn=None, macro=None):
-    """m_init on the extended grid, [3][E^d] (2-D storage: [3][i1][i0])."""
+    """m_init on the extended grid, [3][E^d] (2-D storage: [3][i1][i0], 3-D:
+    [3][i2][i1][i0])."""
     d, n = box["dim"], box["n"]
     xi, dx = grid_positions(n, box["mu_box"])
     c = box["center"]
     if box["init_mode"] == 1:
         k = box["macro_index"]
         off = node_offsets(box, macro)
-        axes = (xi + off[0],) if d == 1 else (xi + off[0], xi + off[1])
+        axes = tuple(xi + off[a] for a in range(d))
         mi = q4_interpolant(macro, k, axes)
     elif d == 1:
         mi = init_fn(c[0] + xi)
-    else:
+    elif d == 2:
         X0, X1 = np.meshgrid(c[0] + xi, c[1] + xi, indexing="xy")
         mi = init_fn(X0, X1)
+    else:
+        mi = init_fn(*grid3(c, xi))
     return np.ascontiguousarray(mi.reshape(3, -1), dtype=np.float64)
 
 
@@ -209,7 +231,7 @@ def solve_box(box, coef, init_fn=None, macro=None, kernel=(3, 7, 3, 7), project=
     nd = np.zeros(M + 1) if want_trace else None
     rc = _lib(variant).oracle_solve_box(d, n, box["order"], integ, box["bc"], box["quantity"],
                                  1 if project else 0, dx, box["alpha"], dt, M,
-                                 _ptr(A), _ptr(mi), _ptr(w), _ptr(w), _ptr(wf), _ptr(wf),
+                                 _ptr(A), _ptr(mi), _ptr(w), _ptr(wf),
                                  _ptr(wt), _ptr(out), _ptr(mfinal), _ptr(en), _ptr(nd))
     res = dict(out=out, M=M, dt=dt, integrator=integ, dx=dx, finite=(rc == 0))
     if want_state:

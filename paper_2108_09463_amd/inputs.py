@@ -117,6 +117,19 @@ def coef_ex2(eps):
                   a_min=0.2, a_max=1.6)
 
 
+def coef_layered3(eps):
+    """3-D laminate a = 1 + 0.5 sin(2 pi x1 / eps): its homogenized matrix is
+    diag(harmonic mean, mean, mean) = diag(sqrt(0.75), 1, 1)."""
+    f = 1.0 / eps
+    return SinSum(3, 1.0, [(0.5, [(f, 0.0), (0.0, 0.0), (0.0, 0.0)])], a_min=0.5, a_max=1.5)
+
+
+def coef_product3(eps):
+    """a = 1 + 0.5 sin(2 pi x1/eps) sin(2 pi x2/eps) sin(2 pi x3/eps)."""
+    f = 1.0 / eps
+    return SinSum(3, 1.0, [(0.5, [(f, 0.0), (f, 0.0), (f, 0.0)])], a_min=0.5, a_max=1.5)
+
+
 def coef_const(c, dim):
     return SinSum(dim, float(c), [], a_min=float(c), a_max=float(c))
 
@@ -171,6 +184,20 @@ class InitEX2:
             0.6 + np.exp(-0.3 * (c(TWO_PI * (x1 - 0.25)) + c(TWO_PI * (x2 - 0.12)))),
             0.5 + np.exp(-0.4 * (c(TWO_PI * x1) + c(TWO_PI * (x2 - 0.4)))),
             0.4 + np.exp(-0.2 * (c(TWO_PI * (x1 - 0.81)) + c(TWO_PI * (x2 - 0.73)))),
+        ])
+        return _normalize(v)
+
+
+@dataclass
+class InitSmooth3D:
+    """A smooth normalized 3-D field built like the EX2 data (Section 2.3)."""
+    def __call__(self, x1, x2, x3):
+        x1, x2, x3 = (np.asarray(v, dtype=np.float64) for v in (x1, x2, x3))
+        c = np.cos
+        v = np.stack([
+            0.6 + np.exp(-0.3 * (c(TWO_PI * (x1 - 0.25)) + c(TWO_PI * (x2 - 0.12)) + c(TWO_PI * x3))),
+            0.5 + np.exp(-0.4 * (c(TWO_PI * x1) + c(TWO_PI * (x2 - 0.4)) + c(TWO_PI * (x3 - 0.3)))),
+            0.4 + np.exp(-0.2 * (c(TWO_PI * (x1 - 0.81)) + c(TWO_PI * (x2 - 0.73)) + c(TWO_PI * (x3 - 0.6)))),
         ])
         return _normalize(v)
 

@@ -53,9 +53,13 @@ class Problem:
         if minit_ext is None:
             if d == 1:
                 minit_ext = init_fn(c[0] + self.xi)
-            else:
+            elif d == 2:
                 X, Y = np.meshgrid(c[0] + self.xi, c[1] + self.xi, indexing="xy")
                 minit_ext = init_fn(X, Y)
+            else:
+                # storage [i2][i1][i0]: the last meshgrid axis runs fastest
+                Z, Y, X = np.meshgrid(c[2] + self.xi, c[1] + self.xi, c[0] + self.xi, indexing="ij")
+                minit_ext = init_fn(X, Y, Z)
         self.mext0 = np.asarray(minit_ext, float).reshape(3, -1)
         ncell = n ** d
         next_ = self.E ** d
@@ -63,8 +67,8 @@ class Problem:
         P = np.zeros((next_, ncell))
         qv = np.zeros((3, next_))
         for e in range(next_):
-            idx = np.unravel_index(e, (self.E,) * d)[::-1] if d == 2 else (e,)
-            idx = [k - G for k in idx]             # (i0, i1) interior coordinates
+            idx = self._unravel(e, self.E)
+            idx = [k - G for k in idx]             # (i0, i1, ...) interior coordinates
             inside = all(0 <= k < n for k in idx)
             if inside:
                 P[e, self._cell(idx)] = 1.0
@@ -84,10 +88,10 @@ class Problem:
         self.div = np.zeros((ncell, next_))
         self.faceflux = []                          # per axis: matrix ext -> east-face flux of cells
         for ax in range(d):
-            s = 1 if ax == 0 else self.E
+            s = self.E ** ax
             A = np.zeros(next_)
             for e in range(next_):
-                idx = np.unravel_index(e, (self.E,) * d)[::-1] if d == 2 else (e,)
+                idx = self._unravel(e, self.E)
                 pos = [c[k] + self.xi[idx[k]] for k in range(d)]
                 pos[ax] += 0.5 * self.h
                 A[e] = coef(*pos)
@@ -103,8 +107,7 @@ class Problem:
                     for p, v in pts.items():
                         Gm[e, p] += v * scale
             F = A[:, None] * Gm                      # flux on faces
-            cells = [self._ext(list(np.unravel_index(ci, (n,) * d)[::-1]) if d == 2 else [ci])
-                     for ci in range(ncell)]
+            cells = [self._ext(list(self._unravel(ci, n))) for ci in range(ncell)]
             for ci, e in enumerate(cells):
                 if self.order == 2:
                     self.div[ci] += (F[e] - F[e - s]) / self.h
@@ -112,11 +115,15 @@ class Problem:
                     self.div[ci] += (27.0 * (F[e] - F[e - s]) - (F[e + s] - F[e - 2 * s])) / (24.0 * self.h)
             self.faceflux.append(np.array([F[e] for e in cells]))
 
+    def _unravel(self, e, size):
+        """(i0, i1, ...) of flat index e, axis 0 fastest."""
+        return tuple(int(v) for v in np.unravel_index(e, (size,) * self.d)[::-1])
+
     def _cell(self, idx):
-        return idx[0] if self.d == 1 else idx[1] * self.n + idx[0]
+        return sum(int(idx[k]) * self.n ** k for k in range(self.d))
 
     def _ext(self, idx):
-        return idx[0] + G if self.d == 1 else (idx[1] + G) * self.E + idx[0] + G
+        return sum((int(idx[k]) + G) * self.E ** k for k in range(self.d))
 
     def field(self, m):
         """H for interior state m [3, ncell]."""
@@ -127,8 +134,7 @@ class Problem:
 
     def interior0(self):
         n, d = self.n, self.d
-        return np.stack([np.array([self.mext0[c, self._ext(list(np.unravel_index(ci, (n,) * d)[::-1])
-                                                                if d == 2 else [ci])]
+        return np.stack([np.array([self.mext0[c, self._ext(list(self._unravel(ci, n)))]
                                    for ci in range(n ** d)]) for c in range(3)])
 
 
@@ -150,8 +156,16 @@ def solve(box, coef, init_fn=None, minit_ext=None, M=None, integ=None, kernel=(3
     xs = -box["mu_box"] + prob.h * np.arange(n)
     w1 = kernel_eval(cx, kernel[1], xs / box["mu"], False) * prob.h / box["mu"]
     wf1 = kernel_eval(cx, kernel[1], (xs + 0.5 * prob.h) / box["mu"], False) * prob.h / box["mu"]
-    wcell = w1 if d == 1 else np.outer(w1, w1).reshape(-1)          # [i1][i0] order
-    wflux = [wf1] if d == 1 else [np.outer(w1, wf1).reshape(-1), np.outer(wf1, w1).reshape(-1)]
+    def prod(ws):
+        """Product weight over the cells, flat in storage order (axis 0 fastest);
+        ws[a] is the weight vector along axis a."""
+        out = ws[0]
+        for a in range(1, d):
+            out = np.multiply.outer(ws[a], out)
+        return out.reshape(-1)
+
+    wcell = prod([w1] * d)
+    wflux = [prod([wf1 if a == ax else w1 for a in range(d)]) for ax in range(d)]
     wt = kernel_eval(ct, kernel[3], np.arange(M + 1) / M, True) / M
 
     def f(m):
