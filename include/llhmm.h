@@ -102,7 +102,10 @@ typedef struct {
     int32_t init_mode;    /* llhmm_init_mode */
     int32_t n_steps;      /* 0: stability rule picks M; > 0: forced M */
     int32_t coef_index;   /* index into the batch's llhmm_coef table */
-    int32_t macro_index[2]; /* INIT_MACRO_Q: macro node k of the box centre */
+    int32_t macro_index[2]; /* INIT_MACRO_Q: macro node k whose 5^d neighbours Q_[4] uses; the
+                               interpolant is evaluated at the absolute grid positions, so
+                               the centre may lie off the node (e.g. x_k + dX/2 e_j), at
+                               most one macro cell away per axis */
     int32_t pad_;
     double eps;           /* epsilon (informational; frequencies carry it) */
     double alpha;         /* micro damping alpha > 0 (artificial damping, Section 2.3) */
@@ -262,6 +265,34 @@ llhmm_status llhmm_macro_step(llhmm_ctx *ctx, int32_t npts, int32_t scheme, int3
                               int32_t stage, double dt, double alpha, double *M_dev,
                               const double *H_avg_dev, double *Y_dev, double *work_dev,
                               int32_t *next_stage_out, hipStream_t stream);
+
+/* Torque model eq. (macro_torque), dM/dt = -T_avg - alpha M x T_avg: one stage of
+ * HeunP or RK4P (scheme LLHMM_MACRO_HEUNP / LLHMM_MACRO_RK4P; the step ends with
+ * normalization, the projection of Section 3.1).  MPEA does not apply: the
+ * model has no cross product in its first term (Section 2.2).  T_avg_dev
+ * [npts][3] is the averaged torque (quantity LLHMM_Q_TORQUE) of the micro
+ * problems at the stage input; M_dev, Y_dev, work_dev and the stage protocol
+ * are those of llhmm_macro_step (work_dev needs [7][3][npts]). */
+llhmm_status llhmm_macro_step_torque(llhmm_ctx *ctx, int32_t npts, int32_t scheme, int32_t stage,
+                                     double dt, double alpha, double *M_dev, const double *T_avg_dev,
+                                     double *Y_dev, double *work_dev, int32_t *next_stage_out,
+                                     hipStream_t stream);
+
+/* Flux model eq. (macro_flux): the divergence of the averaged flux at the macro
+ * nodes, from fluxes at the staggered points x_i + dX/2 e_j (Section 2.2: the
+ * flux components belong at different grid locations).  Its result has the
+ * role of H_avg in llhmm_macro_step, since eq. (macro_flux) has the form of
+ * the field model.  FP64, asynchronous on `stream`.
+ *   F_dev  [dim * npts][ld]: row j * npts + p is the averaged flux (quantity
+ *          LLHMM_Q_FLUX, entries [axis][component]) of the micro problem centred
+ *          at x_p + dX/2 e_j, p the node index (i0 * n + i1 in 2-D); only its
+ *          axis-j entries are read.  ld >= 3 dim.
+ *   H_dev  [npts][3] out.
+ *   order  4: (27 (F_{i+1/2} - F_{i-1/2}) - (F_{i+3/2} - F_{i-3/2})) / (24 dX);
+ *          2: (F_{i+1/2} - F_{i-1/2}) / dX.  The macro grid is periodic. */
+llhmm_status llhmm_flux_divergence(llhmm_ctx *ctx, const llhmm_macro *macro, int32_t order,
+                                   const double *F_dev, int32_t ld, double *H_dev,
+                                   hipStream_t stream);
 
 /* Serving -----------------------------------------------------------------
  * A request loop for micro problems that arrive over time: in the HMM loop

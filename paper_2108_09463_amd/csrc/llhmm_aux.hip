@@ -5,7 +5,11 @@
 //              physical scale of the averaged quantity; writes a status word.
 //   k_macro:   one stage of the macro field model eq. (macro_disc) per macro
 //              point: MPEA (eqs. (h_mpea), (mpe_update)) or HeunP / RK4P
-//              start-up stages (Section 3.1).  FP64.
+//              start-up stages (Section 3.1); or one HeunP / RK4P stage of the
+//              torque model eq. (macro_torque).  FP64.
+//   k_flux_div: the divergence of the averaged flux of the flux model
+//              eq. (macro_flux) at the macro nodes from the fluxes at the
+//              staggered points x_i + dX/2 e_j.  FP64.
 #include "llhmm_internal.h"
 
 namespace llhmm {
@@ -54,9 +58,10 @@ __device__ __forceinline__ void ll_rhs(const double m[3], const double h[3], dou
     for (int i = 0; i < 3; ++i) f[i] = -c[i] - alpha * e[i];
 }
 
-__global__ void __launch_bounds__(256) k_macro(int npts, int scheme, int step, int stage, double dt,
-                                               double alpha, double *M, const double *H, double *Y,
-                                               double *work) {
+// model 0: field (and flux) model, H = H_avg; model 1: torque model, H = T_avg.
+__global__ void __launch_bounds__(256) k_macro(int npts, int model, int scheme, int step, int stage,
+                                               double dt, double alpha, double *M, const double *H,
+                                               double *Y, double *work) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= npts) return;
     const long np = npts;
@@ -67,7 +72,7 @@ __global__ void __launch_bounds__(256) k_macro(int npts, int scheme, int step, i
         h[c] = H[(long)i * 3 + c];
         y[c] = Y[c * np + i];
     }
-    if (stage == 0) {  // h^j = H_avg + alpha M^j x H_avg, eq. (h_term), kept for MPEA
+    if (stage == 0 && model == 0) {  // h^j = H_avg + alpha M^j x H_avg, eq. (h_term), kept for MPEA
         double mh[3];
         cross3(m, h, mh);
         for (int c = 0; c < 3; ++c) W(step % 3, c) = h[c] + alpha * mh[c];
@@ -91,7 +96,13 @@ __global__ void __launch_bounds__(256) k_macro(int npts, int scheme, int step, i
         return;
     }
     double k[3];
-    ll_rhs(stage == 0 ? m : y, h, alpha, k);
+    if (model == 0) {
+        ll_rhs(stage == 0 ? m : y, h, alpha, k);
+    } else {  // -T - alpha Y x T
+        double yt[3];
+        cross3(stage == 0 ? m : y, h, yt);
+        for (int c = 0; c < 3; ++c) k[c] = -h[c] - alpha * yt[c];
+    }
     const int nst = (scheme == LLHMM_MACRO_HEUNP) ? 2 : 4;
     if (stage < nst - 1) {
         for (int c = 0; c < 3; ++c) W(3 + stage, c) = k[c];
@@ -113,11 +124,49 @@ __global__ void __launch_bounds__(256) k_macro(int npts, int scheme, int step, i
     }
 }
 
-hipError_t launch_macro(int npts, int scheme, int step, int stage, double dt, double alpha,
+hipError_t launch_macro(int npts, int model, int scheme, int step, int stage, double dt, double alpha,
                         double *M, const double *H, double *Y, double *work, hipStream_t s) {
     if (npts <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_macro, dim3((npts + 255) / 256), dim3(256), 0, s, npts, scheme, step, stage,
-                       dt, alpha, M, H, Y, work);
+    hipLaunchKernelGGL(k_macro, dim3((npts + 255) / 256), dim3(256), 0, s, npts, model, scheme, step,
+                       stage, dt, alpha, M, H, Y, work);
+    return hipGetLastError();
+}
+
+// One thread per macro node i: H_i = sum_j D_j F_j with F_j at x_i + dX/2 e_j in
+// row j * npts + (staggered index) of F.  Node index p = i0 * n + i1 (2-D).
+__global__ void __launch_bounds__(256) k_flux_div(int dim, int n, double dX, int order, const double *F,
+                                                  int ld, double *H) {
+    const long npts = (dim == 1) ? (long)n : (long)n * n;
+    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npts) return;
+    const int i0 = (dim == 1) ? (int)p : (int)(p / n);
+    const int i1 = (dim == 1) ? 0 : (int)(p % n);
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int j = 0; j < dim; ++j) {
+        // F_j at staggered index i + k along axis j (periodic)
+        auto at = [&](int k, int c) -> double {
+            int a0 = i0, a1 = i1;
+            if (j == 0) a0 = ((i0 + k) % n + n) % n;
+            else a1 = ((i1 + k) % n + n) % n;
+            const long q = (dim == 1) ? (long)a0 : (long)a0 * n + a1;
+            return F[((long)j * npts + q) * ld + j * 3 + c];
+        };
+        for (int c = 0; c < 3; ++c) {
+            double v;
+            if (order == 4) v = (27.0 * (at(0, c) - at(-1, c)) - (at(1, c) - at(-2, c))) / (24.0 * dX);
+            else v = (at(0, c) - at(-1, c)) / dX;
+            acc[c] += v;
+        }
+    }
+    for (int c = 0; c < 3; ++c) H[p * 3 + c] = acc[c];
+}
+
+hipError_t launch_flux_div(int dim, int n, double dX, int order, const double *F, int ld, double *H,
+                           hipStream_t s) {
+    const long npts = (dim == 1) ? (long)n : (long)n * n;
+    if (npts <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_flux_div, dim3((unsigned)((npts + 255) / 256)), dim3(256), 0, s, dim, n, dX, order,
+                       F, ld, H);
     return hipGetLastError();
 }
 

@@ -104,6 +104,8 @@ llhmm_status validate_box(const llhmm_box &b, int i, int ncoefs) {
         return fail(LLHMM_E_INVALID, "box %d: non-finite centre", i);
     if (b.init_mode == LLHMM_INIT_EXPLICIT && b.init_offset < 0)
         return fail(LLHMM_E_INVALID, "box %d: negative init_offset", i);
+    if (b.init_mode == LLHMM_INIT_MACRO_Q && b.n + 2 * kGhost > (b.dim == 1 ? kLagMax : kLagMax2))
+        return fail(LLHMM_E_INVALID, "box %d: macro-interpolated data needs n <= %d", i, b.dim == 1 ? 256 : 128);
     return LLHMM_OK;
 }
 
@@ -831,10 +833,13 @@ static llhmm_status prologue_args(llhmm_batch *b, const double *m_init_dev, cons
             if (macro->dim != P.dim) return fail(LLHMM_E_INVALID, "box %d: macro dim differs", i);
             if (P.mi0 < 0 || P.mi0 >= macro->n || (P.dim == 2 && (P.mi1 < 0 || P.mi1 >= macro->n)))
                 return fail(LLHMM_E_INVALID, "box %d: macro_index out of range", i);
-            const double tol = 1e-9 * macro->dX;
+            // Q_[4] around node k is evaluated at the box's absolute positions; a
+            // centre off the node (staggered flux points) must stay within one
+            // macro cell of it
+            const double tol = (1.0 + 1e-9) * macro->dX;
             if (std::fabs(P.cx - (macro->x0[0] + P.mi0 * macro->dX)) > tol ||
                 (P.dim == 2 && std::fabs(P.cy - (macro->x0[1] + P.mi1 * macro->dX)) > tol))
-                return fail(LLHMM_E_INVALID, "box %d: centre is not its macro node", i);
+                return fail(LLHMM_E_INVALID, "box %d: centre more than one macro cell from its node", i);
         }
     }
     pa = PrologueArgs{};
@@ -1243,8 +1248,41 @@ llhmm_status llhmm_macro_step(llhmm_ctx *ctx, int32_t npts, int32_t scheme, int3
     }
     if (stage < 0 || stage >= nst) return fail(LLHMM_E_INVALID, "stage %d out of range", stage);
     HIP_TRY(hipSetDevice(ctx->device));
-    HIP_TRY(launch_macro(npts, scheme, step_index, stage, dt, alpha, M_dev, H_avg_dev, Y_dev, work_dev, stream));
+    HIP_TRY(launch_macro(npts, 0, scheme, step_index, stage, dt, alpha, M_dev, H_avg_dev, Y_dev, work_dev,
+                         stream));
     if (next_stage_out) *next_stage_out = (stage + 1 < nst) ? stage + 1 : 0;
+    return LLHMM_OK;
+}
+
+llhmm_status llhmm_macro_step_torque(llhmm_ctx *ctx, int32_t npts, int32_t scheme, int32_t stage, double dt,
+                                     double alpha, double *M_dev, const double *T_avg_dev, double *Y_dev,
+                                     double *work_dev, int32_t *next_stage_out, hipStream_t stream) {
+    if (!ctx) return fail(LLHMM_E_INVALID, "ctx is NULL");
+    if (npts <= 0 || !M_dev || !T_avg_dev || !Y_dev || !work_dev)
+        return fail(LLHMM_E_INVALID, "macro step: empty grid or NULL buffer");
+    if (!(dt > 0.0) || !(alpha >= 0.0)) return fail(LLHMM_E_INVALID, "macro step: dt > 0, alpha >= 0");
+    int nst;
+    if (scheme == LLHMM_MACRO_HEUNP) nst = 2;
+    else if (scheme == LLHMM_MACRO_RK4P) nst = 4;
+    else return fail(LLHMM_E_INVALID, "torque model: scheme must be HeunP or RK4P");
+    if (stage < 0 || stage >= nst) return fail(LLHMM_E_INVALID, "stage %d out of range", stage);
+    HIP_TRY(hipSetDevice(ctx->device));
+    HIP_TRY(launch_macro(npts, 1, scheme, 0, stage, dt, alpha, M_dev, T_avg_dev, Y_dev, work_dev, stream));
+    if (next_stage_out) *next_stage_out = (stage + 1 < nst) ? stage + 1 : 0;
+    return LLHMM_OK;
+}
+
+llhmm_status llhmm_flux_divergence(llhmm_ctx *ctx, const llhmm_macro *macro, int32_t order, const double *F_dev,
+                                   int32_t ld, double *H_dev, hipStream_t stream) {
+    if (!ctx || !macro) return fail(LLHMM_E_INVALID, "ctx/macro is NULL");
+    if ((macro->dim != 1 && macro->dim != 2) || macro->n < 5)
+        return fail(LLHMM_E_INVALID, "flux divergence: dim 1 or 2 and n >= 5 macro nodes");
+    if (!(macro->dX > 0.0)) return fail(LLHMM_E_INVALID, "flux divergence: dX > 0");
+    if (order != 2 && order != 4) return fail(LLHMM_E_INVALID, "flux divergence: order 2 or 4");
+    if (!F_dev || !H_dev) return fail(LLHMM_E_INVALID, "flux divergence: NULL buffer");
+    if (ld < 3 * macro->dim) return fail(LLHMM_E_INVALID, "flux divergence: ld %d < 3 dim", ld);
+    HIP_TRY(hipSetDevice(ctx->device));
+    HIP_TRY(launch_flux_div(macro->dim, macro->n, macro->dX, order, F_dev, ld, H_dev, stream));
     return LLHMM_OK;
 }
 

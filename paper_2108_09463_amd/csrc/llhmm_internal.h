@@ -93,6 +93,11 @@ struct CoefDev {
 };
 static_assert(sizeof(CoefDev) == sizeof(llhmm_coef), "coef layout");
 
+// Grid indices (with ghosts) of the largest box whose micro data the set-up
+// kernel interpolates from the macro field: 1-D boxes up to n = 256, 2-D up to 128.
+constexpr int kLagMax = 256 + 2 * kGhost;
+constexpr int kLagMax2 = 128 + 2 * kGhost;
+
 struct MacroDev {
     int32_t dim, n;
     double dX, x0[2];
@@ -188,8 +193,10 @@ hipError_t launch_prologue(int prec, const PrologueArgs &a, hipStream_t s);
 hipError_t launch_upscale(const double *partials, const int32_t *wave_status,
                           const double *box_const, const BoxPlan *plans, int nboxes, double *H, int ld,
                           int32_t *status, int32_t *status_out, hipStream_t s);
-hipError_t launch_macro(int npts, int scheme, int step_index, int stage, double dt,
+hipError_t launch_macro(int npts, int model, int scheme, int step_index, int stage, double dt,
                         double alpha, double *M, const double *H, double *Y,
                         double *work, hipStream_t s);
+hipError_t launch_flux_div(int dim, int n, double dX, int order, const double *F, int ld, double *H,
+                           hipStream_t s);
 
 }  // namespace llhmm

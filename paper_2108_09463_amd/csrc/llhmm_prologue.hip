@@ -94,10 +94,18 @@ __device__ void lagrange5(double s, double Lb[5]) {
 // and x2).  Built once per box in LDS by init_tables.
 struct InitTables {
     const double *Mloc;
-    const double *Lb;
+    const double *Lb;   // basis along x1
+    const double *Lb1;  // basis along x2 (2-D)
 };
 
-constexpr int kLagMax = 256 + 2 * kGhost;  // grid indices of the largest (1-D) box
+// Offset of the box centre from its macro node x_k = x0 + k dX along one axis.
+// Q_[4] is evaluated at absolute positions, so a centre between nodes (the
+// staggered flux points) shifts the Lagrange arguments; offsets within
+// 1e-9 dX of zero are taken as zero (a centre given as i / n is the node).
+__device__ double node_offset(double centre, double x0, int k, double dX) {
+    const double o = centre - (x0 + (double)k * dX);
+    return (fabs(o) <= 1e-9 * dX) ? 0.0 : o;
+}
 
 // m_init at grid point (i0, i1); ghost points allowed.
 __device__ void minit_at(const PrologueArgs &A, const BoxPlan &P, const InitTables &T, int i0, int i1,
@@ -119,7 +127,7 @@ __device__ void minit_at(const PrologueArgs &A, const BoxPlan &P, const InitTabl
         for (int l0 = 0; l0 < 5; ++l0)
             for (int c = 0; c < 3; ++c) p[c] = p[c] + T.Mloc[c * 5 + l0] * L0[l0];
     } else {
-        const double *L1 = T.Lb + (i1 + kGhost) * 5;
+        const double *L1 = T.Lb1 + (i1 + kGhost) * 5;
         for (int l1 = 0; l1 < 5; ++l1) {
             double q[3] = {0.0, 0.0, 0.0};
             for (int l0 = 0; l0 < 5; ++l0)  // along x1 first
@@ -278,8 +286,9 @@ __global__ void __launch_bounds__(256) k_prologue(PrologueArgs A) {
     __shared__ double s_red[4][kMaxQ];
     __shared__ double s_Mloc[75];
     __shared__ double s_Lb[kLagMax * 5];
+    __shared__ double s_Lb1[kLagMax2 * 5];
     __shared__ double s_sin[kCoefTabTerms * 4 * kTabLen];
-    InitTables IT{s_Mloc, s_Lb};
+    InitTables IT{s_Mloc, s_Lb, s_Lb1};
     CoefTables CT{nullptr};
     {
         const CoefDev &c = A.coefs[P.coef_index];
@@ -317,7 +326,14 @@ __global__ void __launch_bounds__(256) k_prologue(PrologueArgs A) {
                 s_Mloc[t] = A.M_macro[c * npts + (long)k0 * nm + k1];
             }
         }
-        for (int i = tid; i < N + 2 * kGhost; i += nth) lagrange5(grid_xi(P, i - kGhost) / A.macro.dX, s_Lb + i * 5);
+        const double dX = A.macro.dX;
+        const double o0 = node_offset(P.cx, A.macro.x0[0], P.mi0, dX);
+        for (int i = tid; i < N + 2 * kGhost; i += nth) lagrange5((grid_xi(P, i - kGhost) + o0) / dX, s_Lb + i * 5);
+        if (D == 2) {
+            const double o1 = node_offset(P.cy, A.macro.x0[1], P.mi1, dX);
+            for (int i = tid; i < N + 2 * kGhost; i += nth)
+                lagrange5((grid_xi(P, i - kGhost) + o1) / dX, s_Lb1 + i * 5);
+        }
     }
     __syncthreads();  // per-box tables written
 

@@ -1,13 +1,21 @@
-"""The HMM macro loop of eq. (macro_disc) on the GPU (Section 2.2, Section 3.1).
+"""The HMM macro loop on the GPU (Section 2.2, Section 3.1).
 
 One micro problem per macro node and stage: every stage of a macro step solves
 the whole batch at the stage input Y (micro initial data Q_[4] from Y, Section
-4.1), averages it to H_avg (eq. (upscaling)) and hands H_avg to
-llhmm_macro_step, which advances the macro state (HeunP start-up steps, then
-MPEA, eqs. (h_mpea), (mpe_update)).  The macro grid is periodic with nodes
-x_i = i dX (the unit interval or square); the macro state stays on the device
-and every stage is queued on one stream, the micro batch as a replayed HIP
-graph.
+4.1), averages it (eq. (upscaling)) and hands the average to the macro step.
+Three macro models (Section 2.2):
+
+* field, eq. (macro_disc): H_avg at the nodes; llhmm_macro_step (HeunP
+  start-up steps, then MPEA, eqs. (h_mpea), (mpe_update));
+* flux, eq. (macro_flux): the averaged flux of micro problems centred at the
+  staggered points x_i + dX/2 e_j (one batch of d * npts problems), its
+  divergence by llhmm_flux_divergence, then the field model's step;
+* torque, eq. (macro_torque): T_avg at the nodes; llhmm_macro_step_torque
+  (HeunP or RK4P with normalization; MPEA needs the cross-product form).
+
+The macro grid is periodic with nodes x_i = i dX (the unit interval or
+square); the macro state stays on the device and every stage is queued on one
+stream, the micro batch as a replayed HIP graph.
 """
 from __future__ import annotations
 
@@ -28,10 +36,16 @@ class HmmLoop:
     micro      box fields shared by every micro problem (n, eps, mu, mu_box, eta,
                alpha, bc, order, a_max, integrator, n_steps, quantity = field)
     alpha, dt  macro damping and time step
+    tune       run the band-mode autotuner once on the initial state
+    model      "field", "flux" or "torque" (see the module docstring)
+    flux_order order of the staggered divergence of the flux model (2 or 4)
+    startup    macro scheme of the start-up steps (field, flux) or of every step
+               (torque): llhmm.MACRO_HEUNP or llhmm.MACRO_RK4P
     """
 
     def __init__(self, n_macro, M_init, coef, micro, alpha, dt, precision=inputs.FP32,
-                 K=None, ctx=None, graph=True, startup=None):
+                 K=None, ctx=None, graph=True, startup=None, tune=False, model="field",
+                 flux_order=4):
         import torch
         self.torch = torch
         self.dev = torch.device("cuda", 0)
@@ -40,19 +54,32 @@ class HmmLoop:
         self.dim = M_init.ndim - 1
         if self.dim not in (1, 2) or any(s != n_macro for s in M_init.shape[1:]):
             raise ValueError("M_init must be [3, n] or [3, n, n] with n = n_macro")
+        if model not in ("field", "flux", "torque"):
+            raise ValueError("model must be field, flux or torque")
+        self.model = model
+        self.flux_order = flux_order
         self.n = n_macro
         self.npts = n_macro ** self.dim
         self.alpha, self.dt = float(alpha), float(dt)
-        self.startup = L.MACRO_HEUNP if startup is None else startup
+        if startup is None:
+            startup = L.MACRO_RK4P if model == "torque" else L.MACRO_HEUNP
+        self.startup = startup
         dX = 1.0 / n_macro
+        quantity = {"field": inputs.Q_FIELD, "flux": inputs.Q_FLUX, "torque": inputs.Q_TORQUE}[model]
+        # flux model: one block of boxes per axis j, centred at x_p + dX/2 e_j
+        shifts = [(0.5 * (j == 0), 0.5 * (j == 1)) for j in range(self.dim)] if model == "flux" \
+            else [(0.0, 0.0)]
         boxes = []
-        for p in range(self.npts):
-            idx = (p // n_macro, p % n_macro) if self.dim == 2 else (p, 0)
-            b = inputs.make_box(**copy.deepcopy(micro))
-            b.update(dim=self.dim, quantity=inputs.Q_FIELD, init_mode=inputs.INIT_MACRO_Q,
-                     coef_index=0, center=(idx[0] * dX, idx[1] * dX if self.dim == 2 else 0.0),
-                     macro_index=idx)
-            boxes.append(b)
+        for sh in shifts:
+            for p in range(self.npts):
+                idx = (p // n_macro, p % n_macro) if self.dim == 2 else (p, 0)
+                b = inputs.make_box(**copy.deepcopy(micro))
+                b.update(dim=self.dim, quantity=quantity, init_mode=inputs.INIT_MACRO_Q,
+                         coef_index=0,
+                         center=((idx[0] + sh[0]) * dX,
+                                 (idx[1] + sh[1]) * dX if self.dim == 2 else 0.0),
+                         macro_index=idx)
+                boxes.append(b)
         self.boxes = boxes
         self.macro = dict(dim=self.dim, n=n_macro, dX=dX, x0=(0.0, 0.0))
         self.batch = L.llhmm_batch_create(self.ctx, boxes, [L.to_coef(coef)], precision,
@@ -61,33 +88,44 @@ class HmmLoop:
         f64 = dict(dtype=torch.float64, device=self.dev)
         self.M = torch.from_numpy(np.ascontiguousarray(M_init.reshape(3, -1))).to(self.dev)
         self.Y = self.M.clone()
-        self.H = torch.zeros((self.npts, 3), **f64)
+        self.ld = 3 * self.dim if model == "flux" else 3
+        self.Q = torch.zeros((len(boxes), self.ld), **f64)     # micro averages
+        self.H = self.Q if model != "flux" else torch.zeros((self.npts, 3), **f64)
         self.work = torch.zeros(7 * 3 * self.npts, **f64)
-        self.status = torch.zeros(self.npts, dtype=torch.int32, device=self.dev)
-        self.bad = torch.zeros(self.npts, dtype=torch.int32, device=self.dev)
+        self.status = torch.zeros(len(boxes), dtype=torch.int32, device=self.dev)
+        self.bad = torch.zeros(len(boxes), dtype=torch.int32, device=self.dev)
         self.step_index = 0
         self.stages = 0
+        if tune:
+            # band boxes: pick the tile variant and steps per launch on this batch
+            L.llhmm_batch_tune(self.ctx, self.batch, None, self.macro, self.Y, None, 1)
 
     def cell_steps_per_stage(self):
         return self.batch.cell_steps()
 
     def _micro(self):
         if self.graph:
-            L.llhmm_batch_run_graph(self.ctx, self.batch, self.H, 3, self.status, None,
+            L.llhmm_batch_run_graph(self.ctx, self.batch, self.Q, self.ld, self.status, None,
                                     self.macro, self.Y)
         else:
             L.llhmm_micro_batch(self.ctx, self.batch, None, self.macro, self.Y)
-            L.llhmm_upscale(self.ctx, self.batch, self.H, 3, self.status, False)
+            L.llhmm_upscale(self.ctx, self.batch, self.Q, self.ld, self.status, False)
         self.bad |= self.status
+        if self.model == "flux":
+            L.llhmm_flux_divergence(self.ctx, self.macro, self.flux_order, self.Q, self.ld, self.H)
 
     def step(self):
         """One macro step: as many micro batches and macro stages as the scheme has."""
-        scheme = self.startup if self.step_index < 2 else L.MACRO_MPEA
         stage = 0
         while True:
             self._micro()
-            stage = L.llhmm_macro_step(self.ctx, self.npts, scheme, self.step_index, stage,
-                                       self.dt, self.alpha, self.M, self.H, self.Y, self.work)
+            if self.model == "torque":
+                stage = L.llhmm_macro_step_torque(self.ctx, self.npts, self.startup, stage, self.dt,
+                                                  self.alpha, self.M, self.H, self.Y, self.work)
+            else:
+                scheme = self.startup if self.step_index < 2 else L.MACRO_MPEA
+                stage = L.llhmm_macro_step(self.ctx, self.npts, scheme, self.step_index, stage,
+                                           self.dt, self.alpha, self.M, self.H, self.Y, self.work)
             self.stages += 1
             if stage == 0:
                 break

@@ -118,6 +118,14 @@ _SYMBOLS = {
                                         ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p]),
+    "llhmm_macro_step_torque": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                               ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                               ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
+                                               ctypes.c_void_p]),
+    "llhmm_flux_divergence": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Macro), ctypes.c_int32,
+                                             ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                             ctypes.c_void_p]),
 }
 
 
@@ -354,6 +362,19 @@ def llhmm_macro_step(ctx, npts, scheme, step_index, stage, dt, alpha, M, H_avg, 
                                   _ptr(H_avg), _ptr(Y), _ptr(work), ctypes.byref(nxt),
                                   _stream(stream)))
     return nxt.value
+
+
+def llhmm_macro_step_torque(ctx, npts, scheme, stage, dt, alpha, M, T_avg, Y, work, stream=None):
+    nxt = ctypes.c_int32()
+    _check(lib().llhmm_macro_step_torque(ctx.h, npts, scheme, stage, dt, alpha, _ptr(M), _ptr(T_avg),
+                                         _ptr(Y), _ptr(work), ctypes.byref(nxt), _stream(stream)))
+    return nxt.value
+
+
+def llhmm_flux_divergence(ctx, macro, order, F, ld, H, stream=None):
+    ms = _macro_struct(macro)
+    _check(lib().llhmm_flux_divergence(ctx.h, ms[0] if ms else None, order, _ptr(F), ld, _ptr(H),
+                                       _stream(stream)))
 
 
 # ---------------------------------------------------------------- input packing

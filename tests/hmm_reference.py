@@ -67,22 +67,33 @@ def ideal_loop(n_macro, ppe, T):
     return M.reshape(3, n_macro, n_macro)
 
 
-def oracle_loop(n_macro, setup, steps, dt, threads=None):
-    """`steps` macro steps with every stage's H_avg from the C oracle."""
+def oracle_loop(n_macro, setup, steps, dt, threads=None, model="field"):
+    """`steps` macro steps with every stage's average from the C oracle's micro
+    solves: H_avg at the nodes (field; HeunP start-up, MPEA), the fourth-order
+    staggered divergence of the fluxes at x_i + dX/2 e_j (flux; same stepping),
+    or T_avg at the nodes (torque; RK4P)."""
     from concurrent.futures import ThreadPoolExecutor
     threads = threads or min(16, os.cpu_count() or 1)
     tmpl = inputs.hmm_micro(setup)
     coef = inputs.coef_ex2(tmpl["eps"])
     dX = 1.0 / n_macro
-    boxes = [inputs.make_box(dim=2, quantity=inputs.Q_FIELD, init_mode=inputs.INIT_MACRO_Q,
-                             center=(i * dX, j * dX), macro_index=(i, j), **tmpl)
-             for i in range(n_macro) for j in range(n_macro)]
+    q = {"field": inputs.Q_FIELD, "flux": inputs.Q_FLUX, "torque": inputs.Q_TORQUE}[model]
+    shifts = [(0.5, 0.0), (0.0, 0.5)] if model == "flux" else [(0.0, 0.0)]
+    boxes = [inputs.make_box(dim=2, quantity=q, init_mode=inputs.INIT_MACRO_Q,
+                             center=((i + sh[0]) * dX, (j + sh[1]) * dX), macro_index=(i, j), **tmpl)
+             for sh in shifts for i in range(n_macro) for j in range(n_macro)]
 
-    def field(Y):
+    def average(Y):
         mac = dict(n=n_macro, dX=dX, M=Y.reshape(3, n_macro, n_macro))
         with ThreadPoolExecutor(threads) as ex:
-            out = list(ex.map(lambda b: micro.solve_box(b, coef, macro=mac)["out"], boxes))
-        return np.ascontiguousarray(np.stack(out).T)
+            out = np.stack(list(ex.map(lambda b: micro.solve_box(b, coef, macro=mac)["out"], boxes)))
+        if model != "flux":
+            return np.ascontiguousarray(out.T)
+        npts = n_macro * n_macro
+        F = [out[j * npts:(j + 1) * npts, 3 * j:3 * j + 3].T.reshape(3, n_macro, n_macro)
+             for j in range(2)]
+        return hg.staggered_divergence(F, dX, 4).reshape(3, -1)
 
-    return hg.run_loop(inputs.ex2_macro(n_macro), field, ALPHA, dt, steps).reshape(
+    kw = dict(startup="rk4p", model="torque") if model == "torque" else {}
+    return hg.run_loop(inputs.ex2_macro(n_macro), average, ALPHA, dt, steps, **kw).reshape(
         3, n_macro, n_macro)

@@ -29,6 +29,7 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--out", default=None)
     ap.add_argument("--no-ideal", action="store_true")
+    ap.add_argument("--tune", action="store_true")
     args = ap.parse_args()
     prec = inputs.FP32 if args.precision == "fp32" else inputs.FP64
     ctx = L.llhmm_create(0)
@@ -41,7 +42,7 @@ def main():
             steps, dt = R.steps_for(n, args.T)
             tmpl = inputs.hmm_micro(setup)
             loop = HmmLoop(n, inputs.ex2_macro(n), inputs.coef_ex2(tmpl["eps"]), tmpl, R.ALPHA,
-                           dt, precision=prec, ctx=ctx)
+                           dt, precision=prec, ctx=ctx, tune=args.tune)
             t0 = time.perf_counter()
             loop.run(steps, progress=lambda k: print(
                 f"  {setup} n={n} step {k}/{steps} {time.perf_counter() - t0:.1f}s", flush=True),

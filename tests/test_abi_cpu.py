@@ -88,3 +88,15 @@ def test_unstable_rule_bounds():
          for n in (32, 64, 128)]
     M, _, _ = L.llhmm_plan(b)
     assert abs(M[1] / M[0] - 4) < 0.05 and abs(M[2] / M[1] - 4) < 0.02
+
+
+def test_macro_interpolated_box_size_limit():
+    """Q_[4] micro data is tabulated per grid index in the set-up kernel: 2-D boxes
+    up to n = 128, 1-D up to 256; larger ones are rejected before any launch."""
+    ok = inputs.make_box(dim=2, n=128, init_mode=1, eps=0.01, mu=0.03, mu_box=0.03, eta=1e-4)
+    L.llhmm_plan([ok])
+    for d, n in ((2, 130), (1, 258)):
+        b = inputs.make_box(dim=d, n=n, init_mode=1, eps=0.01, mu=0.03, mu_box=0.03, eta=1e-4)
+        with pytest.raises(L.LlhmmError) as ei:
+            L.llhmm_plan([b])
+        assert ei.value.code == L.E_INVALID and "n <=" in str(ei.value)

@@ -33,13 +33,13 @@ def ctx():
     return L.llhmm_create(0)
 
 
-def gpu_loop(ctx, n_macro, setup, steps, dt, precision=inputs.FP32):
+def gpu_loop(ctx, n_macro, setup, steps, dt, precision=inputs.FP32, model="field"):
     tmpl = inputs.hmm_micro(setup)
     loop = HmmLoop(n_macro, inputs.ex2_macro(n_macro), inputs.coef_ex2(tmpl["eps"]), tmpl,
-                   R.ALPHA, dt, precision=precision, ctx=ctx)
+                   R.ALPHA, dt, precision=precision, ctx=ctx, model=model)
     try:
-        print(f"hmm loop n_macro={n_macro} setup={setup} steps={steps} prec={precision}",
-              flush=True)
+        print(f"hmm loop model={model} n_macro={n_macro} setup={setup} steps={steps} "
+              f"prec={precision}", flush=True)
         loop.run(steps)
         return loop.state(), loop.stages
     finally:
@@ -81,3 +81,60 @@ def test_loop_converges_to_homogenized_solution(ctx):
     assert errs["s5", 24] < 3.0 * ideal[24]
     assert errs["s1", 12] / errs["s1", 24] < 2.0
     assert max(errs.values()) < naive
+
+
+@pytest.mark.parametrize("precision", [inputs.FP64, inputs.FP32])
+@pytest.mark.parametrize("model", ["flux", "torque"])
+def test_flux_and_torque_loops_match_oracle_loops(ctx, model, precision):
+    """Flux model (boxes at the staggered points, fourth-order divergence,
+    HeunP then MPEA) and torque model (RK4P) over four macro steps against the
+    same loops driven by the oracle.  Bar as for the field model, with the
+    averaged quantity's own size: the flux divergence weighs a flux error by
+    at most 2 (27 + 1) / (24 dX) per axis."""
+    from oracle import homogenized as hg
+    n, steps = 12, 4
+    _, dt = R.steps_for(n, 0.1)
+    Mg, stages = gpu_loop(ctx, n, "s1", steps, dt, precision, model=model)
+    Mo = R.oracle_loop(n, "s1", steps, dt, model=model)
+    M0 = inputs.ex2_macro(n)
+    A = R.discrete_AH(6)
+    tol = 1e-5 if precision == inputs.FP32 else 3e-11
+    if model == "flux":
+        Fmax = 2.0 * max(np.abs(hg.q4_stagger_flux(M0, A, 1.0 / n, j)).max() for j in range(2))
+        dH = 2 * (2 * 28.0 / 24.0 * n) * tol * Fmax
+        weight = 44.0 / 12.0
+    else:
+        dH = tol * 2.0 * np.abs(hg.q4_node_torque(M0, A, 1.0 / n)).max()
+        weight = 1.0
+    bound = stages * dt * (1 + R.ALPHA) * weight * dH
+    err = np.abs(Mg - Mo).max()
+    print("loop parity", model, precision, err, bound)
+    assert stages == (6 if model == "flux" else 16)
+    assert err <= bound, (err, bound)
+    assert np.abs(Mg - M0).max() > 1e3 * bound
+
+
+@pytest.mark.parametrize("model", ["flux", "torque"])
+def test_flux_and_torque_loops_converge(ctx, model):
+    """With the low-averaging-error setup both models follow their E_avg = 0
+    loops against M0 and converge like dX^4."""
+    from oracle import homogenized as hg
+    T = 0.01
+    ref = R.M0(5, T)
+    A = R.discrete_AH(5)
+    errs, ideal = {}, {}
+    for n in (12, 24):
+        steps, dt = R.steps_for(n, T)
+        M, _ = gpu_loop(ctx, n, "s5", steps, dt, model=model)
+        errs[n] = R.l2_err(M, ref)
+        if model == "flux":
+            f = lambda Y: hg.q4_flux_field(Y.reshape(3, n, n), A, 1.0 / n).reshape(3, -1)
+            kw = {}
+        else:
+            f = lambda Y: hg.q4_node_torque(Y.reshape(3, n, n), A, 1.0 / n).reshape(3, -1)
+            kw = dict(startup="rk4p", model="torque")
+        Mi = hg.run_loop(inputs.ex2_macro(n), f, R.ALPHA, dt, steps, **kw).reshape(3, n, n)
+        ideal[n] = R.l2_err(Mi, ref)
+    print(model, "errors", errs, "ideal", ideal)
+    assert errs[12] / errs[24] > 8.0
+    assert errs[24] < 3.0 * ideal[24]
