@@ -30,6 +30,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP32 = 157.3e12   # MI355X vector FP32 (packed), published
 PEAK_FP64 = 78.6e12    # MI355X vector FP64, published
+PEAK_HBM = 8.0e12      # MI355X HBM3E bandwidth, published (bytes/s)
 
 # Sources that define the time-stepping kernel: HBM traffic measured with PMC
 # counters is reported only while these are unchanged since the measurement.
@@ -277,7 +278,38 @@ WORKLOADS = {
                      "field average"),
     "one_d_batch": ("one_d_batch: 16384 1-D boxes of 256 points, mu=mu'=4eps, eps=0.01, alpha=0.01 RK4P, "
                     "eta=eps^2, seeded phases, flux average"),
+    "three_d_batch": ("three_d_batch: 512 3-D boxes of 32^3, eps=1/200, mu=mu'=3eps, eta=eps^2, "
+                      "alpha=0.1 RK4P, periodic m - m_init, a = 1 + 0.5 sin sin sin, FP64, field average"),
 }
+
+# d = 3 kernel: bytes streamed through HBM per cell and stage (FP64): stage input
+# y 24, face coefficients 24 (three unique faces per cell), slope written and
+# read back 48, state m 24, Runge-Kutta sum read and written 48, next stage
+# input written 24
+BYTES_PER_CELL_STAGE_3D = 192.0
+
+
+def three_d_record(steps, warmup, with_cpu):
+    """The d = 3 batch in FP64 with its HBM roofline."""
+    from paper_2108_09463_amd import inputs
+    from paper_2108_09463_amd import llhmm as L
+    w3 = inputs.three_d_batch()
+    r = measure(w3, inputs.FP64, steps, warmup)
+    M, _, integ = L.llhmm_plan(w3.boxes)
+    cell_stages = sum(int(m) * (4 if int(ig) == 2 else 2) * b["n"] ** 3 for b, m, ig in zip(w3.boxes, M, integ))
+    achieved = BYTES_PER_CELL_STAGE_3D * cell_stages / (r["kernel_ms"] * 1e-3)
+    rec = {"workload": WORKLOADS["three_d_batch"], "dtype": "f64", "value": r["rate"],
+           "unit": "cell-steps/s", "ms_per_step": r["ms_per_step"], "cell_steps_per_step": r["cell_steps"],
+           "latency_ms": {"p50": r["p50_ms"], "p99": r["p99_ms"]},
+           "phase_ms": {"setup": r["setup_ms"], "time_stepping": r["kernel_ms"]},
+           "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                        "frac": achieved / PEAK_HBM, "traffic": None, "kernel": "k_micro3d",
+                        "kernel_ms": r["kernel_ms"], "bytes_per_cell_stage": BYTES_PER_CELL_STAGE_3D,
+                        "bytes_per_launch": BYTES_PER_CELL_STAGE_3D * cell_stages},
+           "status_ok": r["status_ok"]}
+    if with_cpu:
+        rec["cpu_baseline"], rec["max_rel_err_vs_oracle"] = cpu_baseline(w3, 16, {"fp64": r["H"]})
+    return rec
 
 
 def main():
@@ -375,6 +407,7 @@ def main():
              line["uneven_batch"]["max_rel_err_vs_oracle"]) = cpu_baseline(wu, 64, {"fp32": u["H"]})
         if args.served_stages > 0:
             line["served"] = served(args.served_stages, with_cpu=not args.no_cpu)
+        line["three_d_batch"] = three_d_record(3, 1, not args.no_cpu)
     print(json.dumps(line), flush=True)
 
 

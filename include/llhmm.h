@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define LLHMM_ABI_VERSION 1
+#define LLHMM_ABI_VERSION 2
 #define LLHMM_GHOST 3
 #define LLHMM_MAX_TERMS 8
 
@@ -87,14 +87,16 @@ typedef struct {
     int32_t dim, n_terms, sampled, pad_;
     double c0;
     double amp[LLHMM_MAX_TERMS];
-    double freq[LLHMM_MAX_TERMS][2];
-    double phase[LLHMM_MAX_TERMS][2];
+    double freq[LLHMM_MAX_TERMS][3];
+    double phase[LLHMM_MAX_TERMS][3];
 } llhmm_coef;
 
-/* One micro problem (eq. (micro)). */
+/* One micro problem (eq. (micro)).  d = 3 boxes (the problem allows d <= 3,
+ * Section 2.1) are supported in FP64 with the second-order stencil and the
+ * field or torque quantity; other d = 3 combinations return LLHMM_E_NOTSUP. */
 typedef struct {
-    int32_t dim;          /* d in {1, 2} */
-    int32_t n;            /* grid points per axis (square boxes in 2-D), >= 8 */
+    int32_t dim;          /* d in {1, 2, 3} */
+    int32_t n;            /* grid points per axis (square / cubic boxes), >= 8 */
     int32_t order;        /* spatial order of the stencil: 2 or 4 */
     int32_t integrator;   /* llhmm_integrator */
     int32_t bc;           /* llhmm_bc */
@@ -102,27 +104,28 @@ typedef struct {
     int32_t init_mode;    /* llhmm_init_mode */
     int32_t n_steps;      /* 0: stability rule picks M; > 0: forced M */
     int32_t coef_index;   /* index into the batch's llhmm_coef table */
-    int32_t macro_index[2]; /* INIT_MACRO_Q: macro node k whose 5^d neighbours Q_[4] uses; the
+    int32_t macro_index[3]; /* INIT_MACRO_Q: macro node k whose 5^d neighbours Q_[4] uses; the
                                interpolant is evaluated at the absolute grid positions, so
                                the centre may lie off the node (e.g. x_k + dX/2 e_j), at
                                most one macro cell away per axis */
-    int32_t pad_;
     double eps;           /* epsilon (informational; frequencies carry it) */
     double alpha;         /* micro damping alpha > 0 (artificial damping, Section 2.3) */
     double mu;            /* averaging half-width, 0 < mu <= mu_box */
     double mu_box;        /* box half-width mu' */
     double eta;           /* averaging time, > 0 */
     double a_max;         /* (A1) upper bound of a^eps, used by the stability rule */
-    double center[2];     /* x_b, absolute coordinates of the box centre */
+    double center[3];     /* x_b, absolute coordinates of the box centre (first d used) */
     int64_t init_offset;  /* INIT_EXPLICIT: element offset of this box's m_init */
     int64_t coef_offset;  /* sampled coefficient: element offset of this box's faces */
 } llhmm_box;
 
-/* Periodic macro grid x_i = x0 + i dX, i in [0, n)^dim (eq. (macro_disc)). */
+/* Periodic macro grid x_i = x0 + i dX, i in [0, n)^dim (eq. (macro_disc)); the
+ * field M is component-major [3][n^dim] with the last index fastest
+ * (node (i0, i1, i2) at ((i0 * n) + i1) * n + i2). */
 typedef struct {
     int32_t dim, n;
     double dX;
-    double x0[2];
+    double x0[3];
 } llhmm_macro;
 
 typedef struct llhmm_ctx llhmm_ctx;
@@ -189,7 +192,8 @@ llhmm_status llhmm_batch_timing(llhmm_batch *batch, int32_t back, float *setup_m
  *                layout [dim][E^dim] at coef_offset, entry (axis, j) = a^eps on
  *                the face between point j and j + e_axis.  Nullable otherwise.
  *   m_final_dev  nullable: FP64 final micro state, [nboxes][3][n^dim] packed
- *                with the largest n of the batch as stride (tests only).
+ *                with stride 3 n_max^d_max per box (largest n and d of the
+ *                batch), axis 0 fastest (tests only).
  * The result stays in the batch until llhmm_upscale. */
 llhmm_status llhmm_micro_batch(llhmm_ctx *ctx, llhmm_batch *batch, const double *m_init_dev,
                                const llhmm_macro *macro, const double *M_macro_dev,

@@ -26,6 +26,7 @@ SOURCES = [
     "llhmm_tiles_f32_1d.hip",
     "llhmm_tiles_f64_1d.hip",
     "llhmm_tiles_band.hip",
+    "llhmm_micro3d.hip",
 ]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,

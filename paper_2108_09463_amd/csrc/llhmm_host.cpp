@@ -10,6 +10,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <map>
 #include <string>
 #include <tuple>
@@ -80,7 +81,7 @@ int resolve_integrator(int integ, double alpha) {
 
 llhmm_status validate_box(const llhmm_box &b, int i, int ncoefs) {
     auto finite = [](double v) { return std::isfinite(v); };
-    if (b.dim != 1 && b.dim != 2) return fail(LLHMM_E_INVALID, "box %d: dim must be 1 or 2", i);
+    if (b.dim < 1 || b.dim > 3) return fail(LLHMM_E_INVALID, "box %d: dim must be 1, 2 or 3", i);
     if (b.n < 8 || (b.n & 1)) return fail(LLHMM_E_INVALID, "box %d: n must be even and >= 8", i);
     if (b.order != 2 && b.order != 4) return fail(LLHMM_E_INVALID, "box %d: order must be 2 or 4", i);
     if (b.integrator < 0 || b.integrator > 2) return fail(LLHMM_E_INVALID, "box %d: bad integrator", i);
@@ -100,12 +101,14 @@ llhmm_status validate_box(const llhmm_box &b, int i, int ncoefs) {
     if (!(finite(b.eta) && b.eta > 0.0)) return fail(LLHMM_E_INVALID, "box %d: need eta > 0", i);
     if (!(finite(b.a_max) && b.a_max > 0.0))
         return fail(LLHMM_E_INVALID, "box %d: need a_max > 0 (assumption A1)", i);
-    if (!finite(b.center[0]) || !finite(b.center[1]))
+    if (!finite(b.center[0]) || !finite(b.center[1]) || !finite(b.center[2]))
         return fail(LLHMM_E_INVALID, "box %d: non-finite centre", i);
     if (b.init_mode == LLHMM_INIT_EXPLICIT && b.init_offset < 0)
         return fail(LLHMM_E_INVALID, "box %d: negative init_offset", i);
     if (b.init_mode == LLHMM_INIT_MACRO_Q && b.n + 2 * kGhost > (b.dim == 1 ? kLagMax : kLagMax2))
         return fail(LLHMM_E_INVALID, "box %d: macro-interpolated data needs n <= %d", i, b.dim == 1 ? 256 : 128);
+    if (b.dim == 3 && b.n > kMaxN3)
+        return fail(LLHMM_E_INVALID, "box %d: d = 3 boxes need n <= %d", i, kMaxN3);
     return LLHMM_OK;
 }
 
@@ -391,6 +394,10 @@ struct llhmm_batch {
     void *state[2] = {nullptr, nullptr};  // band boxes' state, ping-pong between launches
     void *refbuf[2] = {nullptr, nullptr}; // FP32 band boxes' reference tables, ping-pong
     int32_t *box_ids = nullptr;
+    int32_t *box3_ids = nullptr;                  // the d = 3 boxes
+    int nbox3 = 0;
+    double cost3 = 0.0;
+    double *work3d = nullptr;                     // their work areas (work3d_size doubles each)
     CoefDev *coefs = nullptr;
     void *tabs = nullptr;
     double *wts = nullptr, *wt = nullptr, *partials = nullptr, *box_const = nullptr, *scratch64 = nullptr;
@@ -543,7 +550,7 @@ static void batch_free(llhmm_batch *b) {
     if (!b) return;
     void *ptrs[] = {b->plans, b->box_ids, b->coefs, b->tabs, b->wts, b->wt, b->partials,
                     b->wave_status, b->status, b->box_const, b->scratch64, b->jobs,
-                    b->state[0], b->state[1], b->refbuf[0], b->refbuf[1]};
+                    b->state[0], b->state[1], b->refbuf[0], b->refbuf[1], b->box3_ids, b->work3d};
     for (void *p : ptrs) bfree(b, p);
     for (auto &slot : b->ev)
         for (hipEvent_t e : slot)
@@ -581,7 +588,7 @@ static llhmm_status batch_create_impl(llhmm_ctx *ctx, const llhmm_box *boxes, in
     if (K->p_x > 7 || K->p_t > 7) return fail(LLHMM_E_INVALID, "kernel order p must be <= 7");
     for (int c = 0; c < ncoefs; ++c) {
         const llhmm_coef &cf = coefs[c];
-        if (cf.n_terms < 0 || cf.n_terms > LLHMM_MAX_TERMS || cf.dim < 1 || cf.dim > 2)
+        if (cf.n_terms < 0 || cf.n_terms > LLHMM_MAX_TERMS || cf.dim < 1 || cf.dim > 3)
             return fail(LLHMM_E_INVALID, "coef %d: bad dim / n_terms", c);
     }
     HIP_TRY(hipSetDevice(ctx->device));
@@ -614,7 +621,8 @@ static llhmm_status batch_create_impl(llhmm_ctx *ctx, const llhmm_box *boxes, in
     }
     b->dim_max = dim_max;
     b->nmax = nmax;
-    int64_t tab_off = 0, w_off = 0, s64_off = 0, part_off = 0, state_off = 0, ref_off = 0;
+    int64_t tab_off = 0, w_off = 0, s64_off = 0, part_off = 0, state_off = 0, ref_off = 0, work3_off = 0;
+    std::vector<int32_t> ids3;
     std::map<int, int64_t> wt_off_of_M;
     std::vector<double> wt_h;
     int64_t cell_steps = 0;
@@ -628,6 +636,12 @@ static llhmm_status batch_create_impl(llhmm_ctx *ctx, const llhmm_box *boxes, in
         if (st != LLHMM_OK) {
             delete b;
             return st;
+        }
+        if (bx.dim == 3 && (precision != LLHMM_FP64 || bx.order != 2 || bx.quantity == LLHMM_Q_FLUX ||
+                            coefs[bx.coef_index].sampled)) {
+            delete b;
+            return fail(LLHMM_E_NOTSUP, "box %d: d = 3 boxes need FP64, order 2, a closed-form coefficient "
+                        "and the field or torque quantity", i);
         }
         auto it = reg.find(TileKey{precision, bx.dim, bx.n, bx.order, bx.bc, bx.quantity});
         const BandTileInfo *bt = nullptr;
@@ -651,14 +665,14 @@ static llhmm_status batch_create_impl(llhmm_ctx *ctx, const llhmm_box *boxes, in
                 band_slots = band_max_slots(bit->second, bx.n, stages);
             }
         }
-        if (it == reg.end() && !bt) {
+        if (it == reg.end() && !bt && bx.dim != 3) {
             delete b;
             return fail(LLHMM_E_NOTSUP,
                         "box %d: no kernel for precision %s, dim %d, n %d, order %d, bc %d, quantity %d",
                         i, precision == LLHMM_FP32 ? "fp32" : "fp64", bx.dim, bx.n, bx.order, bx.bc,
                         bx.quantity);
         }
-        tile_of[i] = bt ? nullptr : it->second;
+        tile_of[i] = (bt || bx.dim == 3) ? nullptr : it->second;
         b->band_tile[i] = bt;
         b->band_s[i] = band_s;
         BoxPlan &P = b->plans_h[i];
@@ -674,6 +688,7 @@ static llhmm_status batch_create_impl(llhmm_ctx *ctx, const llhmm_box *boxes, in
         P.coef_index = bx.coef_index;
         P.mi0 = bx.macro_index[0];
         P.mi1 = bx.macro_index[1];
+        P.mi2 = bx.macro_index[2];
         P.nq = (bx.quantity == LLHMM_Q_FLUX) ? 3 * bx.dim : 3;
         P.coef_sampled = coefs[bx.coef_index].sampled ? 1 : 0;
         int64_t slots;
@@ -682,6 +697,9 @@ static llhmm_status batch_create_impl(llhmm_ctx *ctx, const llhmm_box *boxes, in
             // slots of the largest strip count any choice can give
             P.band = 1;
             slots = band_slots;
+        } else if (bx.dim == 3) {
+            P.nwaves = 1;
+            slots = 1;
         } else {
             P.nwaves = (bx.dim == 2) ? it->second->threads / 64 : 1;
             slots = P.nwaves;
@@ -696,6 +714,7 @@ static llhmm_status batch_create_impl(llhmm_ctx *ctx, const llhmm_box *boxes, in
         }
         P.prec = precision;
         P.form = (precision == LLHMM_FP32 || P.band) ? 1 : 0;
+        if (bx.dim == 3) P.form = 0;
         P.dt = pl.dt;
         P.alpha = bx.alpha;
         P.dx = 2.0 * bx.mu_box / bx.n;
@@ -705,11 +724,21 @@ static llhmm_status batch_create_impl(llhmm_ctx *ctx, const llhmm_box *boxes, in
         P.out_scale = (bx.quantity == LLHMM_Q_FLUX) ? ((bx.order == 2) ? P.dx : 24.0 * P.dx) : 1.0;
         P.cx = bx.center[0];
         P.cy = bx.center[1];
+        P.cz = bx.center[2];
         P.init_offset = bx.init_offset;
         P.coef_offset = bx.coef_offset;
-        P.mfinal_offset = (int64_t)i * 3 * (bx.dim == 1 ? (int64_t)nmax : (int64_t)nmax * nmax);
-        P.tab_offset = tab_off;
-        tab_off += tab_layout(bx.dim, bx.n, P.form).size;
+        // per-box stride 3 nmax^dim_max (largest n and d of the batch)
+        P.mfinal_offset = (int64_t)i * 3 *
+                          (dim_max == 1 ? (int64_t)nmax : (dim_max == 2 ? (int64_t)nmax * nmax : (int64_t)nmax * nmax * nmax));
+        if (bx.dim == 3) {
+            P.tab_offset = work3_off;  // in the 3-D work buffer
+            work3_off += work3d_size(bx.n);
+            ids3.push_back(i);
+            b->cost3 += (double)pl.M * P.stages * bx.n * bx.n * bx.n;
+        } else {
+            P.tab_offset = tab_off;
+            tab_off += tab_layout(bx.dim, bx.n, P.form).size;
+        }
         P.w_offset = w_off;
         w_off += 2 * bx.n;
         P.s64_offset = s64_off;
@@ -733,7 +762,8 @@ static llhmm_status batch_create_impl(llhmm_ctx *ctx, const llhmm_box *boxes, in
         double ws = 0.0;
         for (int n = 0; n <= pl.M; ++n) ws += wt_h[P.wt_offset + n];
         P.wsum = ws;
-        cell_steps += (int64_t)pl.M * (bx.dim == 1 ? bx.n : (int64_t)bx.n * bx.n);
+        cell_steps += (int64_t)pl.M * (bx.dim == 1 ? bx.n : (bx.dim == 2 ? (int64_t)bx.n * bx.n
+                                                                          : (int64_t)bx.n * bx.n * bx.n));
         b->any_explicit |= (bx.init_mode == LLHMM_INIT_EXPLICIT);
         b->any_macro |= (bx.init_mode == LLHMM_INIT_MACRO_Q);
         b->any_sampled |= (P.coef_sampled != 0);
@@ -789,6 +819,9 @@ static llhmm_status batch_create_impl(llhmm_ctx *ctx, const llhmm_box *boxes, in
     if (e == hipSuccess) e = balloc(b, (void **)&b->status, sizeof(int32_t) * (size_t)nboxes);
     if (e == hipSuccess) e = balloc(b, (void **)&b->box_const, sizeof(double) * (size_t)nboxes * kMaxQ);
     if (e == hipSuccess) e = balloc(b, (void **)&b->scratch64, sizeof(double) * std::max<int64_t>(s64_off, 1));
+    b->nbox3 = (int)ids3.size();
+    if (e == hipSuccess && b->nbox3 > 0) e = bupload(b, &b->box3_ids, ids3.data(), ids3.size());
+    if (e == hipSuccess && work3_off > 0) e = balloc(b, (void **)&b->work3d, sizeof(double) * work3_off);
     if (e != hipSuccess) {
         batch_free(b);
         return fail(e == hipErrorOutOfMemory ? LLHMM_E_NOMEM : LLHMM_E_HIP, "batch allocation: %s",
@@ -827,18 +860,21 @@ static llhmm_status prologue_args(llhmm_batch *b, const double *m_init_dev, cons
         md.dX = macro->dX;
         md.x0[0] = macro->x0[0];
         md.x0[1] = macro->x0[1];
+        md.x0[2] = macro->x0[2];
         for (int i = 0; i < b->nboxes; ++i) {
             const BoxPlan &P = b->plans_h[i];
             if (P.init_mode != LLHMM_INIT_MACRO_Q) continue;
             if (macro->dim != P.dim) return fail(LLHMM_E_INVALID, "box %d: macro dim differs", i);
-            if (P.mi0 < 0 || P.mi0 >= macro->n || (P.dim == 2 && (P.mi1 < 0 || P.mi1 >= macro->n)))
+            if (P.mi0 < 0 || P.mi0 >= macro->n || (P.dim >= 2 && (P.mi1 < 0 || P.mi1 >= macro->n)) ||
+                (P.dim == 3 && (P.mi2 < 0 || P.mi2 >= macro->n)))
                 return fail(LLHMM_E_INVALID, "box %d: macro_index out of range", i);
             // Q_[4] around node k is evaluated at the box's absolute positions; a
             // centre off the node (staggered flux points) must stay within one
             // macro cell of it
             const double tol = (1.0 + 1e-9) * macro->dX;
             if (std::fabs(P.cx - (macro->x0[0] + P.mi0 * macro->dX)) > tol ||
-                (P.dim == 2 && std::fabs(P.cy - (macro->x0[1] + P.mi1 * macro->dX)) > tol))
+                (P.dim >= 2 && std::fabs(P.cy - (macro->x0[1] + P.mi1 * macro->dX)) > tol) ||
+                (P.dim == 3 && std::fabs(P.cz - (macro->x0[2] + P.mi2 * macro->dX)) > tol))
                 return fail(LLHMM_E_INVALID, "box %d: centre more than one macro cell from its node", i);
         }
     }
@@ -945,6 +981,28 @@ static llhmm_status run_batch(llhmm_ctx *ctx, llhmm_batch *b, const double *m_in
     hipEvent_t *ev = b->ev[b->timed % LLHMM_TIMING_SLOTS];
     if (timed) HIP_TRY(hipEventRecord(ev[0], stream));
     HIP_TRY(launch_prologue(b->prec, pa, stream));
+    Micro3dArgs a3{};
+    if (b->nbox3 > 0) {
+        a3.plans = b->plans;
+        a3.box_ids = b->box3_ids;
+        a3.nbox = b->nbox3;
+        a3.mode = mode;
+        a3.coefs = b->coefs;
+        a3.m_init = m_init_dev;
+        a3.M_macro = M_macro_dev;
+        a3.macro = pa.macro;
+        a3.work = b->work3d;
+        a3.wts = b->wts;
+        a3.wt = b->wt;
+        a3.partials = b->partials;
+        a3.wave_status = b->wave_status;
+        a3.box_const = b->box_const;
+        a3.out_field = field_dev;
+        memcpy(a3.kc, b->kc, sizeof a3.kc);
+        a3.kp = b->kp;
+        a3.kq = b->kq;
+        HIP_TRY(launch_setup3d(a3, stream));
+    }
     if (timed) HIP_TRY(hipEventRecord(ev[1], stream));
 
     // work items: resident classes (index >= 0) and band classes (~index)
@@ -952,6 +1010,8 @@ static llhmm_status run_batch(llhmm_ctx *ctx, llhmm_batch *b, const double *m_in
     std::vector<Item> items;
     for (size_t i = 0; i < b->classes.size(); ++i) items.push_back({b->classes[i].cost, (int)i});
     for (size_t i = 0; i < b->bands.size(); ++i) items.push_back({b->bands[i].cost, ~(int)i});
+    constexpr int kItem3d = std::numeric_limits<int>::max();
+    if (b->nbox3 > 0) items.push_back({b->cost3, kItem3d});
     std::stable_sort(items.begin(), items.end(), [](const Item &x, const Item &y) { return x.cost > y.cost; });
     const int lanes = std::min<int>((int)items.size(), b->max_lanes);
     if (lanes > 1) {
@@ -965,6 +1025,10 @@ static llhmm_status run_batch(llhmm_ctx *ctx, llhmm_batch *b, const double *m_in
         const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
         load[l] += it.cost;
         hipStream_t s = (l == 0) ? stream : b->side[l - 1];
+        if (it.idx == kItem3d) {
+            HIP_TRY(launch_micro3d(a3, s));
+            continue;
+        }
         st = (it.idx >= 0) ? launch_resident(b, b->classes[it.idx], mode, field_dev, s)
                            : launch_band_class(b, b->bands[~it.idx], mode, field_dev, s);
         if (st != LLHMM_OK) return st;
@@ -1361,6 +1425,13 @@ static llhmm_status request_bytes(const llhmm_server *sv, const llhmm_box &bx, i
     const int prec = sv->cfg.precision;
     const int64_t tsize = (prec == LLHMM_FP32) ? 4 : 8;
     const int stages = (pl.integ == LLHMM_RK4P) ? 4 : 2;
+    if (bx.dim == 3) {
+        if (prec != LLHMM_FP64 || bx.order != 2 || bx.quantity == LLHMM_Q_FLUX)
+            return fail(LLHMM_E_NOTSUP, "request %d: d = 3 needs FP64, order 2, field or torque", i);
+        bytes = work3d_size(bx.n) * 8 + 2 * bx.n * 8 + (kMaxQ * 8 + 4) + 2 * (int64_t)(pl.M + 1) * 8 +
+                (int64_t)sizeof(BoxPlan) + 4 + kMaxQ * 8 + 4 + kMaxQ * 8 + 4 + (int64_t)sizeof(CoefDev) + 3 * 256;
+        return LLHMM_OK;
+    }
     auto it = registry().find(TileKey{prec, bx.dim, bx.n, bx.order, bx.bc, bx.quantity});
     const BandTileInfo *bt = nullptr;
     int64_t band_slots = 0;

@@ -21,10 +21,11 @@ struct BoxPlan {
     int32_t bc, quantity, init_mode, M;  // M: number of time steps
     int32_t coef_index, mi0, mi1, nq;    // macro node; nq = outputs per box
     int32_t coef_sampled, nwaves, prec, form;   // form: 0 direct, 1 reference + perturbation
-    int32_t band, strips, pad0_, pad1_;  // band: box advanced in row strips (large boxes)
+    int32_t band, strips, mi2, pad1_;    // band: box advanced in row strips (large boxes); mi2: 3-D node
     double dt, alpha, dx, mu;
     double mu_box, a_scale, out_scale, cx;
     double cy, wsum;                     // wsum = sum_n w^n (time weights)
+    double cz, pad2_;                    // 3-D: centre along x3
     int64_t init_offset, coef_offset, wt_offset, mfinal_offset;
     int64_t tab_offset;                  // element offset (in T) of the box's tables
     int64_t w_offset;                    // element offset (double) of the space weights
@@ -88,8 +89,8 @@ struct CoefDev {
     int32_t dim, n_terms, sampled, pad_;
     double c0;
     double amp[LLHMM_MAX_TERMS];
-    double freq[LLHMM_MAX_TERMS][2];
-    double phase[LLHMM_MAX_TERMS][2];
+    double freq[LLHMM_MAX_TERMS][3];
+    double phase[LLHMM_MAX_TERMS][3];
 };
 static_assert(sizeof(CoefDev) == sizeof(llhmm_coef), "coef layout");
 
@@ -97,10 +98,11 @@ static_assert(sizeof(CoefDev) == sizeof(llhmm_coef), "coef layout");
 // kernel interpolates from the macro field: 1-D boxes up to n = 256, 2-D up to 128.
 constexpr int kLagMax = 256 + 2 * kGhost;
 constexpr int kLagMax2 = 128 + 2 * kGhost;
+constexpr int kMaxN3 = 64;  // largest d = 3 box (points per axis)
 
 struct MacroDev {
     int32_t dim, n;
-    double dX, x0[2];
+    double dX, x0[3];
 };
 
 struct PrologueArgs {
@@ -132,6 +134,30 @@ struct MicroArgs {
     int32_t *wave_status;      // [slots]
     double *out_field;         // m_final or H (nullable)
 };
+
+// d = 3 boxes (FP64, second-order stencil): one block per box, arrays in a
+// per-box work area of work3d_size(n) doubles at plan.tab_offset.
+struct Micro3dArgs {
+    const BoxPlan *plans;
+    const int32_t *box_ids;    // the batch's 3-D boxes
+    int32_t nbox, mode;        // mode 0 solve, 1 evaluate H(m_init) only
+    const CoefDev *coefs;
+    const double *m_init;      // explicit initial data (extended grid, LLHMM_GHOST layers)
+    const double *M_macro;     // macro field [3][n^3]
+    MacroDev macro;
+    double *work;              // 3-D work buffer (doubles)
+    double *wts;               // space weights (written by the set-up)
+    const double *wt;          // time-weight table
+    double *partials;          // [slots][kMaxQ]
+    int32_t *wave_status;      // [slots]
+    double *box_const;         // [nboxes][kMaxQ] (zeroed for 3-D boxes)
+    double *out_field;         // m_final or H (nullable)
+    double kc[8];              // space kernel coefficients c_0..c_p
+    int32_t kp, kq;
+};
+hipError_t launch_setup3d(const Micro3dArgs &a, hipStream_t s);
+hipError_t launch_micro3d(const Micro3dArgs &a, hipStream_t s);
+int64_t work3d_size(int n);
 
 // Large 2-D boxes are advanced in full-width row strips ("band" mode): a block
 // holds a window of rows = its strip's own rows plus h halo rows on each side,

@@ -274,6 +274,7 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_prologue(PrologueArgs A) {
     const int box = blockIdx.x;
     const BoxPlan P = A.plans[box];
+    if (P.dim == 3) return;  // d = 3 boxes have their own set-up kernel (k_setup3d)
     const int D = P.dim, N = P.n;
     const int lines = (D == 1) ? 1 : N;
     const long cells = (long)N * lines;

@@ -37,8 +37,8 @@ class Coef(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("n_terms", ctypes.c_int32),
                 ("sampled", ctypes.c_int32), ("pad_", ctypes.c_int32),
                 ("c0", ctypes.c_double), ("amp", ctypes.c_double * MAX_TERMS),
-                ("freq", (ctypes.c_double * 2) * MAX_TERMS),
-                ("phase", (ctypes.c_double * 2) * MAX_TERMS)]
+                ("freq", (ctypes.c_double * 3) * MAX_TERMS),
+                ("phase", (ctypes.c_double * 3) * MAX_TERMS)]
 
 
 class Box(ctypes.Structure):
@@ -46,16 +46,16 @@ class Box(ctypes.Structure):
                 ("integrator", ctypes.c_int32), ("bc", ctypes.c_int32),
                 ("quantity", ctypes.c_int32), ("init_mode", ctypes.c_int32),
                 ("n_steps", ctypes.c_int32), ("coef_index", ctypes.c_int32),
-                ("macro_index", ctypes.c_int32 * 2), ("pad_", ctypes.c_int32),
+                ("macro_index", ctypes.c_int32 * 3),
                 ("eps", ctypes.c_double), ("alpha", ctypes.c_double), ("mu", ctypes.c_double),
                 ("mu_box", ctypes.c_double), ("eta", ctypes.c_double), ("a_max", ctypes.c_double),
-                ("center", ctypes.c_double * 2), ("init_offset", ctypes.c_int64),
+                ("center", ctypes.c_double * 3), ("init_offset", ctypes.c_int64),
                 ("coef_offset", ctypes.c_int64)]
 
 
 class Macro(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("n", ctypes.c_int32), ("dX", ctypes.c_double),
-                ("x0", ctypes.c_double * 2)]
+                ("x0", ctypes.c_double * 3)]
 
 
 class ServerCfg(ctypes.Structure):
@@ -160,8 +160,10 @@ def to_box(d):
     for k in ("dim", "n", "order", "integrator", "bc", "quantity", "init_mode", "n_steps",
               "coef_index", "eps", "alpha", "mu", "mu_box", "eta", "a_max"):
         setattr(b, k, d[k])
-    b.macro_index[0], b.macro_index[1] = d.get("macro_index", (0, 0))
-    b.center[0], b.center[1] = d.get("center", (0.0, 0.0))
+    mi = tuple(d.get("macro_index", (0, 0))) + (0, 0, 0)
+    ce = tuple(d.get("center", (0.0, 0.0))) + (0.0, 0.0, 0.0)
+    b.macro_index[0], b.macro_index[1], b.macro_index[2] = mi[:3]
+    b.center[0], b.center[1], b.center[2] = ce[:3]
     b.init_offset = int(d.get("init_offset", 0))
     b.coef_offset = int(d.get("coef_offset", 0))
     return b
@@ -304,7 +306,8 @@ def _macro_struct(macro):
     m.dim = macro["dim"]
     m.n = macro["n"]
     m.dX = macro["dX"]
-    m.x0[0], m.x0[1] = macro.get("x0", (0.0, 0.0))
+    x0 = (tuple(macro.get("x0", (0.0, 0.0))) + (0.0, 0.0, 0.0))[:3]
+    m.x0[0], m.x0[1], m.x0[2] = x0
     return ctypes.byref(m), m
 
 
@@ -390,13 +393,17 @@ def pack_explicit_init(boxes, init_of):
     chunks, offs, off = [], [], 0
     for i, b in enumerate(boxes):
         xi = extended_positions(b["n"], b["mu_box"])
-        cx, cy = b.get("center", (0.0, 0.0))
+        cx, cy, cz = (tuple(b.get("center", (0.0, 0.0))) + (0.0, 0.0, 0.0))[:3]
         f = init_of(i)
         if b["dim"] == 1:
             v = f(cx + xi)
-        else:
+        elif b["dim"] == 2:
             X0, X1 = np.meshgrid(cx + xi, cy + xi, indexing="xy")
             v = f(X0, X1)
+        else:
+            # storage [i2][i1][i0], axis 0 fastest
+            X2, X1, X0 = np.meshgrid(cz + xi, cy + xi, cx + xi, indexing="ij")
+            v = f(X0, X1, X2)
         v = np.ascontiguousarray(v, dtype=np.float64).reshape(-1)
         chunks.append(v)
         offs.append(off)
@@ -405,7 +412,7 @@ def pack_explicit_init(boxes, init_of):
 
 
 def macro_dict(macro, dim=2):
-    return dict(dim=dim, n=macro["n"], dX=macro["dX"], x0=macro.get("x0", (0.0, 0.0)))
+    return dict(dim=dim, n=macro["n"], dX=macro["dX"], x0=macro.get("x0", (0.0, 0.0, 0.0)))
 
 
 # ---------------------------------------------------------------- serving

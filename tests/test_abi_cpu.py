@@ -28,7 +28,7 @@ def test_exports_every_declared_symbol(lib):
     assert len(names) >= 12
     for n in sorted(names):
         assert hasattr(lib, n), n
-    assert L.llhmm_abi_version() == 1
+    assert L.llhmm_abi_version() == 2
 
 
 def _all_boxes():
@@ -62,7 +62,7 @@ def test_kernel_coefficients_match_oracle():
 
 
 @pytest.mark.parametrize("field,value,msg", [
-    ("dim", 3, "dim"), ("n", 7, "even"), ("order", 3, "order"), ("alpha", 0.0, "alpha"),
+    ("dim", 4, "dim"), ("n", 7, "even"), ("order", 3, "order"), ("alpha", 0.0, "alpha"),
     ("mu", 0.0, "mu"), ("eta", -1.0, "eta"), ("a_max", 0.0, "a_max"), ("eps", 1.5, "eps"),
     ("bc", 5, "bc"), ("quantity", 9, "quantity"), ("n_steps", -2, "n_steps"),
 ])
@@ -100,3 +100,18 @@ def test_macro_interpolated_box_size_limit():
         with pytest.raises(L.LlhmmError) as ei:
             L.llhmm_plan([b])
         assert ei.value.code == L.E_INVALID and "n <=" in str(ei.value)
+
+
+def test_3d_plan_matches_oracle_and_size_limit():
+    """d = 3 boxes: the step rule (with d = 3 in omega) matches the oracle; boxes
+    above n = 64 are rejected before any launch."""
+    from oracle import micro
+    b = inputs.make_box(dim=3, n=24, eps=0.01, alpha=0.1, mu=0.03, mu_box=0.03, eta=1e-4, a_max=1.5,
+                        center=(0.1, 0.2, 0.3), macro_index=(0, 0, 0))
+    M, dt, integ = L.llhmm_plan([b])
+    oi, oM, odt = micro.plan(b)
+    assert (M[0], integ[0]) == (oM, oi) and dt[0] == pytest.approx(odt, rel=1e-15)
+    big = dict(b, n=66)
+    with pytest.raises(L.LlhmmError) as ei:
+        L.llhmm_plan([big])
+    assert ei.value.code == L.E_INVALID and "n <= 64" in str(ei.value)
