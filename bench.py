@@ -283,10 +283,9 @@ WORKLOADS = {
 }
 
 # d = 3 kernel: bytes streamed through HBM per cell and stage (FP64): stage input
-# y 24, face coefficients 24 (three unique faces per cell), slope written and
-# read back 48, state m 24, Runge-Kutta sum read and written 48, next stage
-# input written 24
-BYTES_PER_CELL_STAGE_3D = 192.0
+# read 24, face coefficients 24 (three unique faces per cell), state m read 24,
+# Runge-Kutta sum read and written 48, next stage input written 24
+BYTES_PER_CELL_STAGE_3D = 144.0
 
 
 def hbm_roofline_3d(boxes, kernel_ms):

@@ -3,19 +3,20 @@
 //
 // A 3-D box does not fit on one compute unit (a 32^3 box holds 0.8 MB of
 // FP64 state per stage buffer), so one block per box streams its arrays
-// through the caches: the stage input y with one ghost layer, the state m, the
-// stage slope and the running Runge-Kutta sum live in HBM, the block walks all
-// cells per stage (consecutive threads on consecutive x1 points, so loads
-// coalesce) and block barriers separate the phases.  The kernel is HBM-bound.
+// through the caches: the stage input with one ghost layer (two buffers, read
+// one and write the other), the state m and the running Runge-Kutta sum live
+// in HBM, the block walks all cells per stage (consecutive threads on
+// consecutive x1 points, so loads coalesce) and block barriers separate the
+// phases.  The kernel is HBM-bound.
 //
 // Per box (doubles, at plan.tab_offset in the 3-D work buffer), E = n + 2,
 // X = E^3 (one ghost layer per side), C = n^3, storage index
 // ((i2 + 1) E + (i1 + 1)) E + (i0 + 1) (interior: ((i2 n) + i1) n + i0):
-//   A  [3][X]  a^eps on the face between point idx and idx + e_axis, times 1/dx^2
-//   G  [3][X]  ghost data: m_init (Dirichlet) or m_init(ghost) - m_init(wrapped
-//              interior point) (periodic m - m_init), on the face ghost points
-//   y  [3][X]  stage input with its ghosts
-//   m  [3][C]  state;  acc [3][C] running sum of b_s k_s;  kb [3][C] stage slope
+//   A   [3][X]  a^eps on the face between point idx and idx + e_axis, times 1/dx^2
+//   G   [3][X]  ghost data: m_init (Dirichlet) or m_init(ghost) - m_init(wrapped
+//               interior point) (periodic m - m_init), on the face ghost points
+//   y0, y1 [3][X]  stage inputs with their ghosts (ping-pong)
+//   m   [3][C]  state;  acc [3][C] running sum of b_s k_s
 #include "llhmm_internal.h"
 
 namespace llhmm {
@@ -70,16 +71,16 @@ __device__ double node_offset3(double centre, double x0, int k, double dX) {
 struct Box3 {
     int n, E;
     long C, X;
-    double *A, *G, *y, *m, *acc, *kb;
+    double *A, *G, *y, *y1, *m, *acc;
     __device__ Box3(double *base, int n_) : n(n_), E(n_ + 2) {
         C = (long)n * n * n;
         X = (long)E * E * E;
         A = base;
         G = A + 3 * X;
         y = G + 3 * X;
-        m = y + 3 * X;
+        y1 = y + 3 * X;
+        m = y1 + 3 * X;
         acc = m + 3 * C;
-        kb = acc + 3 * C;
     }
     // extended index of grid point (i0, i1, i2), ghosts at -1 and n
     __device__ long ext(int i0, int i1, int i2) const { return ((long)(i2 + 1) * E + (i1 + 1)) * E + (i0 + 1); }
@@ -234,7 +235,9 @@ __global__ void __launch_bounds__(kThreads3d) k_setup3d(Micro3dArgs A) {
 
 // One block per 3-D box: the whole time loop (HeunP / RK4P with projection),
 // the weighted space/time average of the field (or torque) at stage 1 of every
-// step, and m_final; mode 1 evaluates H(m_init) once.
+// step, and m_final; mode 1 evaluates H(m_init) once.  Each stage reads one
+// stage-input buffer and writes the next stage input into the other, so a
+// point's slope never goes through memory.
 __global__ void __launch_bounds__(kThreads3d) k_micro3d(Micro3dArgs A) {
     const int box = A.box_ids[blockIdx.x];
     const BoxPlan P = A.plans[box];
@@ -246,14 +249,24 @@ __global__ void __launch_bounds__(kThreads3d) k_micro3d(Micro3dArgs A) {
     const double alpha = P.alpha, dt = P.dt;
     const bool rk4 = (P.stages == 4);
     const long s1 = B.stride(1), s2 = B.stride(2);
+    // this thread's points t = tid + k nth, walked with incremental coordinates
+    const int d0 = nth % n, d1 = (nth / n) % n, d2 = (int)(nth / nn);
+    const int b0 = tid % n, b1 = (tid / n) % n, b2 = (int)(tid / nn);
+    auto advance = [&](int &i0, int &i1, int &i2) {
+        i0 += d0;
+        if (i0 >= n) { i0 -= n; ++i1; }
+        i1 += d1;
+        if (i1 >= n) { i1 -= n; ++i2; }
+        i2 += d2;
+    };
 
-    // H = div(a grad y) at the interior point (i0, i1, i2): returns H[3]
-    auto field = [&](long e, double H[3]) {
+    // H = div(a grad y) at the interior point with extended index e
+    auto field = [&](const double *y, long e, double H[3]) {
         const double ae0 = B.A[e], aw0 = B.A[e - 1];
         const double ae1 = B.A[X + e], aw1 = B.A[X + e - s1];
         const double ae2 = B.A[2 * X + e], aw2 = B.A[2 * X + e - s2];
         for (int c = 0; c < 3; ++c) {
-            const double *yc = B.y + c * X;
+            const double *yc = y + c * X;
             const double v = yc[e];
             double h = ae0 * (yc[e + 1] - v) - aw0 * (v - yc[e - 1]);
             h += ae1 * (yc[e + s1] - v) - aw1 * (v - yc[e - s1]);
@@ -263,10 +276,10 @@ __global__ void __launch_bounds__(kThreads3d) k_micro3d(Micro3dArgs A) {
     };
 
     if (A.mode == 1) {
-        for (long t = tid; t < C; t += nth) {
-            const int i0 = (int)(t % n), i1 = (int)((t / n) % n), i2 = (int)(t / nn);
+        int i0 = b0, i1 = b1, i2 = b2;
+        for (long t = tid; t < C; t += nth, advance(i0, i1, i2)) {
             double H[3];
-            field(B.ext(i0, i1, i2), H);
+            field(B.y, B.ext(i0, i1, i2), H);
             for (int c = 0; c < 3; ++c) A.out_field[P.mfinal_offset + c * C + t] = H[c];
         }
         return;
@@ -274,16 +287,18 @@ __global__ void __launch_bounds__(kThreads3d) k_micro3d(Micro3dArgs A) {
 
     double sum[3] = {0.0, 0.0, 0.0};   // this thread's share of the average
     const int nst = rk4 ? 4 : 2;
+    double *ycur = B.y, *ynext = B.y1;
     for (int step = 0; step <= P.M; ++step) {
         const double wn = wt[step];
         for (int s = 0; s < nst; ++s) {
-            // phase A: slope of the stage input at every own point (and the average at stage 1)
-            for (long t = tid; t < C; t += nth) {
-                const int i0 = (int)(t % n), i1 = (int)((t / n) % n), i2 = (int)(t / nn);
+            const double bs = rk4 ? ((s == 0 || s == 3) ? 1.0 / 6.0 : 1.0 / 3.0) : 0.5;
+            const double cnext = rk4 ? ((s < 2) ? 0.5 : 1.0) : 1.0;
+            int i0 = b0, i1 = b1, i2 = b2;
+            for (long t = tid; t < C; t += nth, advance(i0, i1, i2)) {
                 const long e = B.ext(i0, i1, i2);
                 double H[3];
-                field(e, H);
-                const double yv[3] = {B.y[e], B.y[X + e], B.y[2 * X + e]};
+                field(ycur, e, H);
+                const double yv[3] = {ycur[e], ycur[X + e], ycur[2 * X + e]};
                 double c1[3], c2[3];
                 c1[0] = yv[1] * H[2] - yv[2] * H[1];
                 c1[1] = yv[2] * H[0] - yv[0] * H[2];
@@ -299,33 +314,26 @@ __global__ void __launch_bounds__(kThreads3d) k_micro3d(Micro3dArgs A) {
                 c2[0] = yv[1] * c1[2] - yv[2] * c1[1];
                 c2[1] = yv[2] * c1[0] - yv[0] * c1[2];
                 c2[2] = yv[0] * c1[1] - yv[1] * c1[0];
-                for (int c = 0; c < 3; ++c) B.kb[c * C + t] = -c1[c] - alpha * c2[c];
-            }
-            if (step == P.M) break;
-            __syncthreads();
-            // phase B: next stage input (or the end of the step) at every own point
-            const double bs = rk4 ? ((s == 0 || s == 3) ? 1.0 / 6.0 : 1.0 / 3.0) : 0.5;
-            const double cnext = rk4 ? ((s < 2) ? 0.5 : 1.0) : 1.0;
-            for (long t = tid; t < C; t += nth) {
-                const int i0 = (int)(t % n), i1 = (int)((t / n) % n), i2 = (int)(t / nn);
-                const long e = B.ext(i0, i1, i2);
                 if (s < nst - 1) {
                     for (int c = 0; c < 3; ++c) {
-                        const double k = B.kb[c * C + t];
+                        const double k = -c1[c] - alpha * c2[c];
                         B.acc[c * C + t] = (s == 0) ? bs * k : B.acc[c * C + t] + bs * k;
-                        B.y[c * X + e] = B.m[c * C + t] + cnext * dt * k;
+                        ynext[c * X + e] = B.m[c * C + t] + cnext * dt * k;
                     }
                 } else {
                     double v[3];
-                    for (int c = 0; c < 3; ++c)
-                        v[c] = B.m[c * C + t] + dt * (B.acc[c * C + t] + bs * B.kb[c * C + t]);
+                    for (int c = 0; c < 3; ++c) {
+                        const double k = -c1[c] - alpha * c2[c];
+                        v[c] = B.m[c * C + t] + dt * (B.acc[c * C + t] + bs * k);
+                    }
                     const double nr = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
                     for (int c = 0; c < 3; ++c) {
                         B.m[c * C + t] = v[c] / nr;
-                        B.y[c * X + e] = v[c] / nr;
+                        ynext[c * X + e] = v[c] / nr;
                     }
                 }
             }
+            if (step == P.M) break;
             __syncthreads();
             // ghosts of the new stage input
             for (long g = tid; g < 6 * nn; g += nth) {
@@ -333,10 +341,13 @@ __global__ void __launch_bounds__(kThreads3d) k_micro3d(Micro3dArgs A) {
                 int q0, q1, q2;
                 ghost_point(B, g, gi, wi, q0, q1, q2);
                 for (int c = 0; c < 3; ++c)
-                    B.y[c * X + gi] = (P.bc == LLHMM_BC_DIRICHLET) ? B.G[c * X + gi]
-                                                                   : B.y[c * X + wi] + B.G[c * X + gi];
+                    ynext[c * X + gi] = (P.bc == LLHMM_BC_DIRICHLET) ? B.G[c * X + gi]
+                                                                     : ynext[c * X + wi] + B.G[c * X + gi];
             }
             __syncthreads();
+            double *tmp = ycur;
+            ycur = ynext;
+            ynext = tmp;
         }
     }
 
@@ -379,7 +390,7 @@ hipError_t launch_micro3d(const Micro3dArgs &a, hipStream_t s) {
 
 int64_t work3d_size(int n) {
     const int64_t E = n + 2;
-    return 9 * E * E * E + 9 * (int64_t)n * n * n;
+    return 12 * E * E * E + 6 * (int64_t)n * n * n;
 }
 
 }  // namespace llhmm
