@@ -289,8 +289,9 @@ llhmm_status llhmm_macro_step_torque(llhmm_ctx *ctx, int32_t npts, int32_t schem
  * the field model.  FP64, asynchronous on `stream`.
  *   F_dev  [dim * npts][ld]: row j * npts + p is the averaged flux (quantity
  *          LLHMM_Q_FLUX, entries [axis][component]) of the micro problem centred
- *          at x_p + dX/2 e_j, p the node index (i0 * n + i1 in 2-D); only its
- *          axis-j entries are read.  ld >= 3 dim.
+ *          at x_p + dX/2 e_j, p the node index (last coordinate fastest:
+ *          i0 * n + i1 in 2-D, (i0 * n + i1) * n + i2 in 3-D); only its axis-j
+ *          entries are read.  ld >= 3 dim.
  *   H_dev  [npts][3] out.
  *   order  4: (27 (F_{i+1/2} - F_{i-1/2}) - (F_{i+3/2} - F_{i-3/2})) / (24 dX);
  *          2: (F_{i+1/2} - F_{i-1/2}) / dX.  The macro grid is periodic. */

@@ -133,22 +133,30 @@ hipError_t launch_macro(int npts, int model, int scheme, int step, int stage, do
 }
 
 // One thread per macro node i: H_i = sum_j D_j F_j with F_j at x_i + dX/2 e_j in
-// row j * npts + (staggered index) of F.  Node index p = i0 * n + i1 (2-D).
+// row j * npts + (staggered index) of F.  Node index: the last coordinate
+// runs fastest, p = (i0 * n + i1) * n + i2 in 3-D.
 __global__ void __launch_bounds__(256) k_flux_div(int dim, int n, double dX, int order, const double *F,
                                                   int ld, double *H) {
-    const long npts = (dim == 1) ? (long)n : (long)n * n;
+    long npts = n;
+    for (int d = 1; d < dim; ++d) npts *= n;
     const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= npts) return;
-    const int i0 = (dim == 1) ? (int)p : (int)(p / n);
-    const int i1 = (dim == 1) ? 0 : (int)(p % n);
+    int idx[3] = {0, 0, 0};
+    {
+        long r = p;
+        for (int d = dim - 1; d >= 0; --d) {
+            idx[d] = (int)(r % n);
+            r /= n;
+        }
+    }
     double acc[3] = {0.0, 0.0, 0.0};
     for (int j = 0; j < dim; ++j) {
         // F_j at staggered index i + k along axis j (periodic)
         auto at = [&](int k, int c) -> double {
-            int a0 = i0, a1 = i1;
-            if (j == 0) a0 = ((i0 + k) % n + n) % n;
-            else a1 = ((i1 + k) % n + n) % n;
-            const long q = (dim == 1) ? (long)a0 : (long)a0 * n + a1;
+            int a[3] = {idx[0], idx[1], idx[2]};
+            a[j] = ((a[j] + k) % n + n) % n;
+            long q = 0;
+            for (int d = 0; d < dim; ++d) q = q * n + a[d];
             return F[((long)j * npts + q) * ld + j * 3 + c];
         };
         for (int c = 0; c < 3; ++c) {
@@ -163,7 +171,8 @@ __global__ void __launch_bounds__(256) k_flux_div(int dim, int n, double dX, int
 
 hipError_t launch_flux_div(int dim, int n, double dX, int order, const double *F, int ld, double *H,
                            hipStream_t s) {
-    const long npts = (dim == 1) ? (long)n : (long)n * n;
+    long npts = n;
+    for (int d = 1; d < dim; ++d) npts *= n;
     if (npts <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_flux_div, dim3((unsigned)((npts + 255) / 256)), dim3(256), 0, s, dim, n, dX, order,
                        F, ld, H);

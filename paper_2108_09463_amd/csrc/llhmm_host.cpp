@@ -1339,8 +1339,8 @@ llhmm_status llhmm_macro_step_torque(llhmm_ctx *ctx, int32_t npts, int32_t schem
 llhmm_status llhmm_flux_divergence(llhmm_ctx *ctx, const llhmm_macro *macro, int32_t order, const double *F_dev,
                                    int32_t ld, double *H_dev, hipStream_t stream) {
     if (!ctx || !macro) return fail(LLHMM_E_INVALID, "ctx/macro is NULL");
-    if ((macro->dim != 1 && macro->dim != 2) || macro->n < 5)
-        return fail(LLHMM_E_INVALID, "flux divergence: dim 1 or 2 and n >= 5 macro nodes");
+    if (macro->dim < 1 || macro->dim > 3 || macro->n < 5)
+        return fail(LLHMM_E_INVALID, "flux divergence: dim 1, 2 or 3 and n >= 5 macro nodes");
     if (!(macro->dX > 0.0)) return fail(LLHMM_E_INVALID, "flux divergence: dX > 0");
     if (order != 2 && order != 4) return fail(LLHMM_E_INVALID, "flux divergence: order 2 or 4");
     if (!F_dev || !H_dev) return fail(LLHMM_E_INVALID, "flux divergence: NULL buffer");

@@ -13,8 +13,9 @@ Three macro models (Section 2.2):
 * torque, eq. (macro_torque): T_avg at the nodes; llhmm_macro_step_torque
   (HeunP or RK4P with normalization; MPEA needs the cross-product form).
 
-The macro grid is periodic with nodes x_i = i dX (the unit interval or
-square); the macro state stays on the device and every stage is queued on one
+The macro grid is periodic with nodes x_i = i dX (the unit interval, square
+or cube; d = 3 micro problems are FP64, field or torque); the macro state stays
+on the device and every stage is queued on one
 stream, the micro batch as a replayed HIP graph.
 """
 from __future__ import annotations
@@ -31,7 +32,7 @@ class HmmLoop:
     """Runs eq. (macro_disc) with H_avg from the library's micro batches.
 
     n_macro    macro nodes per axis (dX = 1 / n_macro)
-    M_init     macro initial data, [3, n_macro] or [3, n_macro, n_macro]
+    M_init     macro initial data, [3] + [n_macro] * d, d = 1, 2, 3
     coef       the material coefficient a^eps (an inputs.SinSum)
     micro      box fields shared by every micro problem (n, eps, mu, mu_box, eta,
                alpha, bc, order, a_max, integrator, n_steps, quantity = field)
@@ -52,8 +53,8 @@ class HmmLoop:
         self.ctx = ctx or L.llhmm_create(0)
         M_init = np.asarray(M_init, dtype=np.float64)
         self.dim = M_init.ndim - 1
-        if self.dim not in (1, 2) or any(s != n_macro for s in M_init.shape[1:]):
-            raise ValueError("M_init must be [3, n] or [3, n, n] with n = n_macro")
+        if self.dim not in (1, 2, 3) or any(s != n_macro for s in M_init.shape[1:]):
+            raise ValueError("M_init must be [3] + [n_macro] * d, d = 1, 2 or 3")
         if model not in ("field", "flux", "torque"):
             raise ValueError("model must be field, flux or torque")
         self.model = model
@@ -67,21 +68,26 @@ class HmmLoop:
         dX = 1.0 / n_macro
         quantity = {"field": inputs.Q_FIELD, "flux": inputs.Q_FLUX, "torque": inputs.Q_TORQUE}[model]
         # flux model: one block of boxes per axis j, centred at x_p + dX/2 e_j
-        shifts = [(0.5 * (j == 0), 0.5 * (j == 1)) for j in range(self.dim)] if model == "flux" \
-            else [(0.0, 0.0)]
+        shifts = [tuple(0.5 * (a == j) for a in range(3)) for j in range(self.dim)] \
+            if model == "flux" else [(0.0, 0.0, 0.0)]
         boxes = []
         for sh in shifts:
             for p in range(self.npts):
-                idx = (p // n_macro, p % n_macro) if self.dim == 2 else (p, 0)
+                # node index p: the last coordinate runs fastest
+                idx = [0, 0, 0]
+                r = p
+                for a in range(self.dim - 1, -1, -1):
+                    idx[a] = r % n_macro
+                    r //= n_macro
                 b = inputs.make_box(**copy.deepcopy(micro))
                 b.update(dim=self.dim, quantity=quantity, init_mode=inputs.INIT_MACRO_Q,
                          coef_index=0,
-                         center=((idx[0] + sh[0]) * dX,
-                                 (idx[1] + sh[1]) * dX if self.dim == 2 else 0.0),
-                         macro_index=idx)
+                         center=tuple((idx[a] + sh[a]) * dX if a < self.dim else 0.0
+                                      for a in range(3)),
+                         macro_index=tuple(idx))
                 boxes.append(b)
         self.boxes = boxes
-        self.macro = dict(dim=self.dim, n=n_macro, dX=dX, x0=(0.0, 0.0))
+        self.macro = dict(dim=self.dim, n=n_macro, dX=dX, x0=(0.0, 0.0, 0.0))
         self.batch = L.llhmm_batch_create(self.ctx, boxes, [L.to_coef(coef)], precision,
                                           K or L.kernel())
         self.graph = graph

@@ -67,33 +67,42 @@ def ideal_loop(n_macro, ppe, T):
     return M.reshape(3, n_macro, n_macro)
 
 
-def oracle_loop(n_macro, setup, steps, dt, threads=None, model="field"):
+def oracle_loop(n_macro, setup, steps, dt, threads=None, model="field", tmpl=None, coef=None,
+                M_init=None):
     """`steps` macro steps with every stage's average from the C oracle's micro
     solves: H_avg at the nodes (field; HeunP start-up, MPEA), the fourth-order
     staggered divergence of the fluxes at x_i + dX/2 e_j (flux; same stepping),
-    or T_avg at the nodes (torque; RK4P)."""
+    or T_avg at the nodes (torque; RK4P).  By default the EX2 setup `setup` on
+    the unit square; tmpl / coef / M_init ([3] + [n_macro] * d) override it."""
     from concurrent.futures import ThreadPoolExecutor
     threads = threads or min(16, os.cpu_count() or 1)
-    tmpl = inputs.hmm_micro(setup)
-    coef = inputs.coef_ex2(tmpl["eps"])
+    tmpl = tmpl or inputs.hmm_micro(setup)
+    coef = coef or inputs.coef_ex2(tmpl["eps"])
+    M_init = inputs.ex2_macro(n_macro) if M_init is None else np.asarray(M_init, dtype=np.float64)
+    d = M_init.ndim - 1
     dX = 1.0 / n_macro
     q = {"field": inputs.Q_FIELD, "flux": inputs.Q_FLUX, "torque": inputs.Q_TORQUE}[model]
-    shifts = [(0.5, 0.0), (0.0, 0.5)] if model == "flux" else [(0.0, 0.0)]
-    boxes = [inputs.make_box(dim=2, quantity=q, init_mode=inputs.INIT_MACRO_Q,
-                             center=((i + sh[0]) * dX, (j + sh[1]) * dX), macro_index=(i, j), **tmpl)
-             for sh in shifts for i in range(n_macro) for j in range(n_macro)]
+    shifts = [tuple(0.5 * (a == j) for a in range(3)) for j in range(d)] if model == "flux" \
+        else [(0.0, 0.0, 0.0)]
+    nodes = list(np.ndindex(*(n_macro,) * d))           # last coordinate fastest
+    boxes = []
+    for sh in shifts:
+        for k in nodes:
+            k3 = tuple(k) + (0,) * (3 - d)
+            boxes.append(inputs.make_box(**dict(tmpl, dim=d, quantity=q, init_mode=inputs.INIT_MACRO_Q,
+                                                center=tuple((k3[a] + sh[a]) * dX for a in range(3)),
+                                                macro_index=k3)))
 
     def average(Y):
-        mac = dict(n=n_macro, dX=dX, M=Y.reshape(3, n_macro, n_macro))
+        mac = dict(n=n_macro, dX=dX, M=Y.reshape((3,) + (n_macro,) * d))
         with ThreadPoolExecutor(threads) as ex:
             out = np.stack(list(ex.map(lambda b: micro.solve_box(b, coef, macro=mac)["out"], boxes)))
         if model != "flux":
             return np.ascontiguousarray(out.T)
-        npts = n_macro * n_macro
-        F = [out[j * npts:(j + 1) * npts, 3 * j:3 * j + 3].T.reshape(3, n_macro, n_macro)
-             for j in range(2)]
+        npts = n_macro ** d
+        F = [out[j * npts:(j + 1) * npts, 3 * j:3 * j + 3].T.reshape((3,) + (n_macro,) * d)
+             for j in range(d)]
         return hg.staggered_divergence(F, dX, 4).reshape(3, -1)
 
     kw = dict(startup="rk4p", model="torque") if model == "torque" else {}
-    return hg.run_loop(inputs.ex2_macro(n_macro), average, ALPHA, dt, steps, **kw).reshape(
-        3, n_macro, n_macro)
+    return hg.run_loop(M_init, average, ALPHA, dt, steps, **kw).reshape((3,) + (n_macro,) * d)

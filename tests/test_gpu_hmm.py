@@ -138,3 +138,40 @@ def test_flux_and_torque_loops_converge(ctx, model):
     print(model, "errors", errs, "ideal", ideal)
     assert errs[12] / errs[24] > 8.0
     assert errs[24] < 3.0 * ideal[24]
+
+
+@pytest.mark.parametrize("model", ["field", "torque"])
+def test_3d_loops_match_oracle_loops(ctx, model):
+    """The loop on a 6^3 periodic macro grid with d = 3 micro boxes (FP64): field
+    model (HeunP start-up, MPEA) and torque model (RK4P) against the loops driven
+    by the oracle.  The bar propagates a micro bar of 1e-9 relative (3-D averages
+    carry rounding noise up to 1e-10, see test_gpu_3d)."""
+    from oracle import micro
+    n, eps = 6, 1.0 / 48.0
+    x = np.arange(n) / n
+    M0 = inputs.InitSmooth3D()(*np.meshgrid(x, x, x, indexing="ij"))
+    tmpl = dict(n=16, order=2, integrator=inputs.HEUNP, bc=inputs.BC_DIRICHLET, eps=eps,
+                alpha=1.2, mu=3.5 * eps, mu_box=4 * eps, eta=eps ** 2, a_max=1.5)
+    coef = inputs.coef_product3(eps)
+    dt = 0.03 / n ** 2
+    steps = 3 if model == "field" else 2
+    loop = HmmLoop(n, M0, coef, tmpl, R.ALPHA, dt, precision=inputs.FP64, ctx=ctx, model=model)
+    try:
+        print(f"3-D hmm loop model={model}", flush=True)
+        loop.run(steps)
+        Mg, stages = loop.state(), loop.stages
+    finally:
+        loop.close()
+    Mo = R.oracle_loop(n, None, steps, dt, model=model, tmpl=tmpl, coef=coef, M_init=M0)
+    mac = dict(n=n, dX=1.0 / n, M=M0)
+    q = inputs.Q_FIELD if model == "field" else inputs.Q_TORQUE
+    Hmax = 2.0 * max(np.abs(micro.solve_box(inputs.make_box(**dict(
+        tmpl, dim=3, quantity=q, init_mode=1, center=(k[0] / n, k[1] / n, k[2] / n), macro_index=k)),
+        coef, macro=mac)["out"]).max() for k in [(0, 0, 0), (2, 3, 1), (5, 1, 4)])
+    weight = 44.0 / 12.0 if model == "field" else 1.0
+    bound = stages * dt * (1 + R.ALPHA) * weight * 1e-9 * Hmax
+    err = np.abs(Mg - Mo).max()
+    print("3-D loop parity", model, err, bound, flush=True)
+    assert stages == (5 if model == "field" else 8)
+    assert err <= bound, (err, bound)
+    assert np.abs(Mg - M0).max() > 1e3 * bound
