@@ -40,14 +40,19 @@ KERNEL_SOURCES = ["paper_2108_09463_amd/csrc/llhmm_micro_impl.h",
                   "paper_2108_09463_amd/csrc/llhmm_tiles_f32_2d.hip",
                   "paper_2108_09463_amd/csrc/llhmm_tiles_f64_2d.hip",
                   "paper_2108_09463_amd/build.py"]
+KERNEL_SOURCES_3D = ["paper_2108_09463_amd/csrc/llhmm_micro3d.hip",
+                     "paper_2108_09463_amd/csrc/llhmm_micro3d.h",
+                     "paper_2108_09463_amd/csrc/llhmm_internal.h",
+                     "paper_2108_09463_amd/build.py"]
 TRAFFIC_FILES = {"fp32": "profiles/k_micro_f32_two_d_batch_traffic.txt",
-                 "fp64": "profiles/k_micro_f64_two_d_batch_traffic.txt"}
+                 "fp64": "profiles/k_micro_f64_two_d_batch_traffic.txt",
+                 "3d": "profiles/k_micro3d_three_d_batch_traffic.txt"}
 
 
-def kernel_source_hash():
+def kernel_source_hash(sources=None):
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in sources or KERNEL_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -64,7 +69,8 @@ def measured_traffic(name):
         if ":" in line and not line.startswith(" "):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("kernel_sources_sha256_16") != kernel_source_hash():
+    sources = KERNEL_SOURCES_3D if name == "3d" else KERNEL_SOURCES
+    if kv.get("kernel_sources_sha256_16") != kernel_source_hash(sources):
         return None
     try:
         return float(kv["hbm_bytes_per_launch"])
@@ -295,7 +301,8 @@ def hbm_roofline_3d(boxes, kernel_ms):
     cell_stages = sum(int(m) * (4 if int(ig) == 2 else 2) * b["n"] ** 3 for b, m, ig in zip(boxes, M, integ))
     achieved = BYTES_PER_CELL_STAGE_3D * cell_stages / (kernel_ms * 1e-3)
     return {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
-            "frac": achieved / PEAK_HBM, "traffic": None, "kernel": "k_micro3d", "kernel_ms": kernel_ms,
+            "frac": achieved / PEAK_HBM, "traffic": measured_traffic("3d"), "kernel": "k_micro3d",
+            "kernel_ms": kernel_ms,
             "bytes_per_cell_stage": BYTES_PER_CELL_STAGE_3D,
             "bytes_per_launch": BYTES_PER_CELL_STAGE_3D * cell_stages}
 

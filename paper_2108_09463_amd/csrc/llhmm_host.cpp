@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "llhmm_internal.h"
+#include "llhmm_micro3d.h"
 
 using namespace llhmm;
 
@@ -395,7 +396,7 @@ struct llhmm_batch {
     void *refbuf[2] = {nullptr, nullptr}; // FP32 band boxes' reference tables, ping-pong
     int32_t *box_ids = nullptr;
     int32_t *box3_ids = nullptr;                  // the d = 3 boxes
-    int nbox3 = 0;
+    int nbox3 = 0, nmax3 = 0;
     double cost3 = 0.0;
     double *work3d = nullptr;                     // their work areas (work3d_size doubles each)
     CoefDev *coefs = nullptr;
@@ -734,6 +735,7 @@ static llhmm_status batch_create_impl(llhmm_ctx *ctx, const llhmm_box *boxes, in
             P.tab_offset = work3_off;  // in the 3-D work buffer
             work3_off += work3d_size(bx.n);
             ids3.push_back(i);
+            b->nmax3 = std::max(b->nmax3, bx.n);
             b->cost3 += (double)pl.M * P.stages * bx.n * bx.n * bx.n;
         } else {
             P.tab_offset = tab_off;
@@ -986,6 +988,7 @@ static llhmm_status run_batch(llhmm_ctx *ctx, llhmm_batch *b, const double *m_in
         a3.plans = b->plans;
         a3.box_ids = b->box3_ids;
         a3.nbox = b->nbox3;
+        a3.nmax = b->nmax3;
         a3.mode = mode;
         a3.coefs = b->coefs;
         a3.m_init = m_init_dev;

@@ -135,30 +135,6 @@ struct MicroArgs {
     double *out_field;         // m_final or H (nullable)
 };
 
-// d = 3 boxes (FP64, second-order stencil): one block per box, arrays in a
-// per-box work area of work3d_size(n) doubles at plan.tab_offset.
-struct Micro3dArgs {
-    const BoxPlan *plans;
-    const int32_t *box_ids;    // the batch's 3-D boxes
-    int32_t nbox, mode;        // mode 0 solve, 1 evaluate H(m_init) only
-    const CoefDev *coefs;
-    const double *m_init;      // explicit initial data (extended grid, LLHMM_GHOST layers)
-    const double *M_macro;     // macro field [3][n^3]
-    MacroDev macro;
-    double *work;              // 3-D work buffer (doubles)
-    double *wts;               // space weights (written by the set-up)
-    const double *wt;          // time-weight table
-    double *partials;          // [slots][kMaxQ]
-    int32_t *wave_status;      // [slots]
-    double *box_const;         // [nboxes][kMaxQ] (zeroed for 3-D boxes)
-    double *out_field;         // m_final or H (nullable)
-    double kc[8];              // space kernel coefficients c_0..c_p
-    int32_t kp, kq;
-};
-hipError_t launch_setup3d(const Micro3dArgs &a, hipStream_t s);
-hipError_t launch_micro3d(const Micro3dArgs &a, hipStream_t s);
-int64_t work3d_size(int n);
-
 // Large 2-D boxes are advanced in full-width row strips ("band" mode): a block
 // holds a window of rows = its strip's own rows plus h halo rows on each side,
 // runs `steps` time steps on it without exchanging data with other blocks

@@ -17,7 +17,7 @@
 //               interior point) (periodic m - m_init), on the face ghost points
 //   y0, y1 [3][X]  stage inputs with their ghosts (ping-pong)
 //   m   [3][C]  state;  acc [3][C] running sum of b_s k_s
-#include "llhmm_internal.h"
+#include "llhmm_micro3d.h"
 
 namespace llhmm {
 
@@ -233,11 +233,12 @@ __global__ void __launch_bounds__(kThreads3d) k_setup3d(Micro3dArgs A) {
 
 #pragma clang fp contract(on)
 
-// One block per 3-D box: the whole time loop (HeunP / RK4P with projection),
-// the weighted space/time average of the field (or torque) at stage 1 of every
-// step, and m_final; mode 1 evaluates H(m_init) once.  Each stage reads one
-// stage-input buffer and writes the next stage input into the other, so a
-// point's slope never goes through memory.
+// One block per 3-D box, point by point: the whole time loop (HeunP / RK4P with
+// projection), the weighted space/time average of the field (or torque) at
+// stage 1 of every step, and m_final; mode 1 evaluates H(m_init) once.  Each
+// stage reads one stage-input buffer and writes the next stage input into the
+// other, so a point's slope never goes through memory.  The solve uses the
+// plane-walking kernel below; this one serves the field evaluation.
 __global__ void __launch_bounds__(kThreads3d) k_micro3d(Micro3dArgs A) {
     const int box = A.box_ids[blockIdx.x];
     const BoxPlan P = A.plans[box];
@@ -376,6 +377,214 @@ __global__ void __launch_bounds__(kThreads3d) k_micro3d(Micro3dArgs A) {
     }
 }
 
+// The time loop walking each stage plane by plane (mode 0).  A block owns the
+// whole (x1, x2) plane of its box at once (PT points per thread); the stage
+// input of the plane below, the plane itself and the x3 face below stay in
+// registers from one plane to the next, and the plane with its ghost ring is
+// staged in LDS for the x1 / x2 neighbours.  NT threads per block, one point of
+// the plane per thread (n <= 22: 512 threads, n <= 32: 1024).  Every array element then crosses
+// HBM once per stage: the streamed bytes are the algorithmic ones.
+template <int NMAX, int NT>
+__global__ void __launch_bounds__(NT, 1) k_micro3d_planes(Micro3dArgs A) {
+    constexpr int PT = (NMAX * NMAX + NT - 1) / NT;
+    constexpr int PLMAX = (NMAX + 2) * (NMAX + 2);
+    __shared__ double s_plane[3 * PLMAX];
+    __shared__ double s_red[NT][3];
+    const int box = A.box_ids[blockIdx.x];
+    const BoxPlan P = A.plans[box];
+    const int n = P.n, tid = threadIdx.x;
+    Box3 B(A.work + P.tab_offset, n);
+    const long C = B.C, X = B.X, nn = (long)n * n;
+    const int E = B.E, PL = E * E;
+    const long s1 = B.stride(1), s2 = B.stride(2);
+    const double *w = A.wts + P.w_offset;
+    const double *wt = A.wt + P.wt_offset;
+    const double alpha = P.alpha, dt = P.dt;
+    const bool rk4 = (P.stages == 4);
+    const int nst = rk4 ? 4 : 2;
+    // this thread's points of a plane: q = tid + j * threads, (i0, i1) = (q % n, q / n)
+    int q0[PT], q1[PT], gside[PT];   // gside: -1 / +1 at the x1 ends of a row, else 0
+    bool act[PT];
+#pragma unroll
+    for (int j = 0; j < PT; ++j) {
+        const int q = tid + j * NT;
+        act[j] = q < nn;
+        q0[j] = act[j] ? q % n : 0;
+        q1[j] = act[j] ? q / n : 0;
+        gside[j] = (q0[j] == 0) ? -1 : (q0[j] == n - 1 ? 1 : 0);
+    }
+    double sum[3] = {0.0, 0.0, 0.0};
+    double *ycur = B.y, *ynext = B.y1;
+    for (int step = 0; step <= P.M; ++step) {
+        const double wn = wt[step];
+        for (int s = 0; s < nst; ++s) {
+            const double bs = rk4 ? ((s == 0 || s == 3) ? 1.0 / 6.0 : 1.0 / 3.0) : 0.5;
+            const double cnext = rk4 ? ((s < 2) ? 0.5 : 1.0) : 1.0;
+            const bool last_level = (step == P.M);
+            // per point: the stage input of the plane below (ylo) and of the
+            // plane itself (yc), the x3 face below (aw2) and, for points at the
+            // x1 ends of a row, the row's ghost value (gx; it shares the cache
+            // line that brings the point itself)
+            double ylo[PT][3], yc[PT][3], aw2[PT], gx[PT][3];
+#pragma unroll
+            for (int j = 0; j < PT; ++j) {
+                if (!act[j]) continue;
+                const long elo = B.ext(q0[j], q1[j], -1), e0 = B.ext(q0[j], q1[j], 0);
+                const long eg = e0 + gside[j];
+                for (int c = 0; c < 3; ++c) {
+                    ylo[j][c] = ycur[c * X + elo];
+                    yc[j][c] = ycur[c * X + e0];
+                    gx[j][c] = gside[j] ? ycur[c * X + eg] : 0.0;
+                }
+                aw2[j] = B.A[2 * X + elo];
+            }
+            for (int i2 = 0; i2 < n; ++i2) {
+                // this plane's loads from memory (the plane above and the faces)
+                // are issued before the staging barrier, so they are in flight
+                // while the block synchronizes
+                double yhi[PT][3], ghi[PT][3], fa[PT][5];
+#pragma unroll
+                for (int j = 0; j < PT; ++j) {
+                    if (!act[j]) continue;
+                    const long e = B.ext(q0[j], q1[j], i2);
+                    for (int c = 0; c < 3; ++c) {
+                        yhi[j][c] = ycur[c * X + e + s2];
+                        ghi[j][c] = gside[j] ? ycur[c * X + e + s2 + gside[j]] : 0.0;
+                    }
+                    fa[j][0] = B.A[e];
+                    fa[j][1] = B.A[e - 1];
+                    fa[j][2] = B.A[X + e];
+                    fa[j][3] = B.A[X + e - s1];
+                    fa[j][4] = B.A[2 * X + e];
+                }
+                // the plane's stage input into LDS: own points and the x1 ghosts
+                // from registers, the x2 ghost rows from memory
+#pragma unroll
+                for (int j = 0; j < PT; ++j) {
+                    if (!act[j]) continue;
+                    const int l = (q1[j] + 1) * E + (q0[j] + 1);
+                    for (int c = 0; c < 3; ++c) s_plane[c * PL + l] = yc[j][c];
+                    if (gside[j])
+                        for (int c = 0; c < 3; ++c) s_plane[c * PL + l + gside[j]] = gx[j][c];
+                }
+                for (int g = tid; g < 2 * n; g += NT) {
+                    const int i0 = g % n, i1 = (g < n) ? -1 : n;
+                    const long e = B.ext(i0, i1, i2);
+                    const int l = (i1 + 1) * E + (i0 + 1);
+                    for (int c = 0; c < 3; ++c) s_plane[c * PL + l] = ycur[c * X + e];
+                }
+                __syncthreads();
+#pragma unroll
+                for (int j = 0; j < PT; ++j) {
+                    if (!act[j]) continue;
+                    const int i0 = q0[j], i1 = q1[j];
+                    const long e = B.ext(i0, i1, i2);
+                    const long t = ((long)i2 * n + i1) * n + i0;
+                    const int l = (i1 + 1) * E + (i0 + 1);
+                    const double ae0 = fa[j][0], aw0 = fa[j][1];
+                    const double ae1 = fa[j][2], aw1 = fa[j][3];
+                    const double ae2 = fa[j][4];
+                    double H[3];
+                    for (int c = 0; c < 3; ++c) {
+                        const double *pl = s_plane + c * PL;
+                        const double v = yc[j][c];
+                        double h = ae0 * (pl[l + 1] - v) - aw0 * (v - pl[l - 1]);
+                        h += ae1 * (pl[l + E] - v) - aw1 * (v - pl[l - E]);
+                        h += ae2 * (yhi[j][c] - v) - aw2[j] * (v - ylo[j][c]);
+                        H[c] = h;
+                    }
+                    const double yv[3] = {yc[j][0], yc[j][1], yc[j][2]};
+                    double c1[3], c2[3];
+                    c1[0] = yv[1] * H[2] - yv[2] * H[1];
+                    c1[1] = yv[2] * H[0] - yv[0] * H[2];
+                    c1[2] = yv[0] * H[1] - yv[1] * H[0];
+                    if (s == 0) {
+                        const double wc = w[i0] * w[i1] * w[i2] * wn;
+                        if (P.quantity == LLHMM_Q_TORQUE)
+                            for (int c = 0; c < 3; ++c) sum[c] += wc * c1[c];
+                        else
+                            for (int c = 0; c < 3; ++c) sum[c] += wc * H[c];
+                    }
+                    if (!last_level) {
+                        c2[0] = yv[1] * c1[2] - yv[2] * c1[1];
+                        c2[1] = yv[2] * c1[0] - yv[0] * c1[2];
+                        c2[2] = yv[0] * c1[1] - yv[1] * c1[0];
+                        if (s == 0) {
+                            for (int c = 0; c < 3; ++c) {
+                                const double k = -c1[c] - alpha * c2[c];
+                                B.acc[c * C + t] = bs * k;
+                                ynext[c * X + e] = B.m[c * C + t] + cnext * dt * k;
+                            }
+                        } else if (s < nst - 1) {
+                            for (int c = 0; c < 3; ++c) {
+                                const double k = -c1[c] - alpha * c2[c];
+                                B.acc[c * C + t] = B.acc[c * C + t] + bs * k;
+                                ynext[c * X + e] = B.m[c * C + t] + cnext * dt * k;
+                            }
+                        } else {
+                            double v[3];
+                            for (int c = 0; c < 3; ++c) {
+                                const double k = -c1[c] - alpha * c2[c];
+                                v[c] = B.m[c * C + t] + dt * (B.acc[c * C + t] + bs * k);
+                            }
+                            const double nr = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+                            for (int c = 0; c < 3; ++c) {
+                                B.m[c * C + t] = v[c] / nr;
+                                ynext[c * X + e] = v[c] / nr;
+                            }
+                        }
+                    }
+                    // move up one plane
+                    for (int c = 0; c < 3; ++c) {
+                        ylo[j][c] = yc[j][c];
+                        yc[j][c] = yhi[j][c];
+                        gx[j][c] = ghi[j][c];
+                    }
+                    aw2[j] = ae2;
+                }
+                __syncthreads();  // the plane buffer is rewritten next
+            }
+            if (last_level) break;
+            // ghosts of the new stage input
+            for (long g = tid; g < 6 * nn; g += NT) {
+                long gi, wi;
+                int r0, r1, r2;
+                ghost_point(B, g, gi, wi, r0, r1, r2);
+                for (int c = 0; c < 3; ++c)
+                    ynext[c * X + gi] = (P.bc == LLHMM_BC_DIRICHLET) ? B.G[c * X + gi]
+                                                                     : ynext[c * X + wi] + B.G[c * X + gi];
+            }
+            __syncthreads();
+            double *tmp = ycur;
+            ycur = ynext;
+            ynext = tmp;
+        }
+    }
+
+    // the box's average: fixed-order block reduction into its partial-sum slot
+    for (int c = 0; c < 3; ++c) s_red[tid][c] = sum[c];
+    __syncthreads();
+    for (int half = NT / 2; half > 0; half >>= 1) {
+        if (tid < half)
+            for (int c = 0; c < 3; ++c) s_red[tid][c] = s_red[tid][c] + s_red[tid + half][c];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        double *dst = A.partials + P.part_offset * kMaxQ;
+        int bad = 0;
+        for (int q = 0; q < kMaxQ; ++q) {
+            const double v = (q < 3) ? s_red[0][q] : 0.0;
+            dst[q] = v;
+            if (!__builtin_isfinite(v)) bad = 1;
+        }
+        A.wave_status[P.part_offset] = bad;
+    }
+    if (A.out_field) {
+        for (long t = tid; t < C; t += NT)
+            for (int c = 0; c < 3; ++c) A.out_field[P.mfinal_offset + c * C + t] = B.m[c * C + t];
+    }
+}
+
 hipError_t launch_setup3d(const Micro3dArgs &a, hipStream_t s) {
     if (a.nbox <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_setup3d, dim3(a.nbox), dim3(kThreads3d), 0, s, a);
@@ -384,7 +593,15 @@ hipError_t launch_setup3d(const Micro3dArgs &a, hipStream_t s) {
 
 hipError_t launch_micro3d(const Micro3dArgs &a, hipStream_t s) {
     if (a.nbox <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_micro3d, dim3(a.nbox), dim3(kThreads3d), 0, s, a);
+    // field evaluation, and boxes above 32 points per axis (whose plane would take
+    // 4 or more points per thread and spill): the point-by-point kernel
+    if (a.mode == 1 || a.nmax > 32) {
+        hipLaunchKernelGGL(k_micro3d, dim3(a.nbox), dim3(kThreads3d), 0, s, a);
+    } else if (a.nmax <= 22) {
+        hipLaunchKernelGGL((k_micro3d_planes<22, 512>), dim3(a.nbox), dim3(512), 0, s, a);
+    } else {
+        hipLaunchKernelGGL((k_micro3d_planes<32, 1024>), dim3(a.nbox), dim3(1024), 0, s, a);
+    }
     return hipGetLastError();
 }
 

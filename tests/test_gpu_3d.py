@@ -112,6 +112,16 @@ def test_3d_parity(ctx, bc, q, integ):
     check(ctx, wl)
 
 
+@pytest.mark.parametrize("ns", [(8, 16), (20, 32), (40,)])
+def test_3d_kernel_paths(ctx, ns):
+    """Each time-stepping path: the plane-walking kernel for n <= 22 and n <= 32
+    (one and two points of a plane per thread) and the point-by-point kernel
+    above 32 points per axis."""
+    print(f"3-D kernel path n={ns}", flush=True)
+    wl = workload(boxes3(ns, 1, 0, 2, seed=41 + ns[0], n_steps=6))
+    check(ctx, wl)
+
+
 def test_3d_stability_rule_and_laminate(ctx):
     """Step counts from the rule (d = 3 in omega) and the laminate coefficient."""
     wl = workload(boxes3((16, 24), 1, 0, 0, seed=5, eta=1.0), coef=inputs.coef_layered3(0.01))
