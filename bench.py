@@ -291,20 +291,33 @@ WORKLOADS = {
 # d = 3 kernel: bytes streamed through HBM per cell and stage (FP64): stage input
 # read 24, face coefficients 24 (three unique faces per cell), state m read 24,
 # Runge-Kutta sum read and written 48, next stage input written 24
-BYTES_PER_CELL_STAGE_3D = 144.0
+# Boxes of the cpu_baseline sample per workload, sized for about 10-30 s on 16
+# host threads (all 512 boxes of the d = 3 batch take about 41 s, all 1024 of
+# the 2-D batch about 14 s).
+DEFAULT_CPU_SAMPLE = {"three_d_batch": 256}
+
+# Bytes per cell that one stage of the d = 3 time loop must move through HBM:
+# read the stage input, the state and the running sum, write the running sum
+# (the state at the last stage) and the next stage input, 24 bytes each; the
+# first stage of a step has no running sum to read.
+BYTES_PER_CELL_STAGE_3D = 120.0
+BYTES_FIRST_STAGE_SAVING_3D = 24.0
 
 
 def hbm_roofline_3d(boxes, kernel_ms):
     """Roofline of k_micro3d: streamed bytes per launch over its duration."""
     from paper_2108_09463_amd import llhmm as L
     M, _, integ = L.llhmm_plan(boxes)
-    cell_stages = sum(int(m) * (4 if int(ig) == 2 else 2) * b["n"] ** 3 for b, m, ig in zip(boxes, M, integ))
-    achieved = BYTES_PER_CELL_STAGE_3D * cell_stages / (kernel_ms * 1e-3)
+    nbytes = 0.0
+    for b, m, ig in zip(boxes, M, integ):
+        stages = 4 if int(ig) == 2 else 2
+        nbytes += int(m) * b["n"] ** 3 * (stages * BYTES_PER_CELL_STAGE_3D - BYTES_FIRST_STAGE_SAVING_3D)
+    achieved = nbytes / (kernel_ms * 1e-3)
     return {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
             "frac": achieved / PEAK_HBM, "traffic": measured_traffic("3d"), "kernel": "k_micro3d",
             "kernel_ms": kernel_ms,
             "bytes_per_cell_stage": BYTES_PER_CELL_STAGE_3D,
-            "bytes_per_launch": BYTES_PER_CELL_STAGE_3D * cell_stages}
+            "bytes_per_launch": nbytes}
 
 
 def three_d_record(steps, warmup, with_cpu):
@@ -329,7 +342,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
-    ap.add_argument("--cpu-sample", type=int, default=1024)
+    ap.add_argument("--cpu-sample", type=int, default=None,
+                    help="boxes the oracle solves for cpu_baseline (default: about 10-30 s of host work)")
     ap.add_argument("--precision", choices=["both", "fp32", "fp64"], default="both")
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="two_d_batch")
     ap.add_argument("--no-extra", action="store_true",
@@ -362,7 +376,8 @@ def main():
     cpu = None
     errs = {}
     if not args.no_cpu:
-        cpu, errs = cpu_baseline(wl, min(args.cpu_sample, len(wl.boxes)), gpu_H)
+        sample = args.cpu_sample or DEFAULT_CPU_SAMPLE.get(args.workload, 1024)
+        cpu, errs = cpu_baseline(wl, min(sample, len(wl.boxes)), gpu_H)
     head = "fp32" if "fp32" in res else "fp64"
     r = res[head]
     line = {

@@ -1,18 +1,20 @@
 // d = 3 micro boxes (the problem allows d <= 3, Section 2.1), FP64, second-
-// order stencil: set-up and time stepping.
+// order stencil: set-up, time stepping and field evaluation.
 //
 // A 3-D box does not fit on one compute unit (a 32^3 box holds 0.8 MB of
 // FP64 state per stage buffer), so one block per box streams its arrays
 // through the caches: the stage input with one ghost layer (two buffers, read
 // one and write the other), the state m and the running Runge-Kutta sum live
-// in HBM, the block walks all cells per stage (consecutive threads on
-// consecutive x1 points, so loads coalesce) and block barriers separate the
-// phases.  The kernel is HBM-bound.
+// in HBM; each thread walks x3 columns (consecutive threads on consecutive x1
+// points, so loads coalesce) and one block barrier ends each stage.  The time
+// loop is HBM-bound.
 //
 // Per box (doubles, at plan.tab_offset in the 3-D work buffer), E = n + 2,
 // X = E^3 (one ghost layer per side), C = n^3, storage index
 // ((i2 + 1) E + (i1 + 1)) E + (i0 + 1) (interior: ((i2 n) + i1) n + i0):
-//   A   [3][X]  a^eps on the face between point idx and idx + e_axis, times 1/dx^2
+//   A   [3][X]  a^eps on the face between point idx and idx + e_axis, times
+//               1/dx^2 (read by the field evaluation; the time loop forms the
+//               same values from per-axis factor tables)
 //   G   [3][X]  ghost data: m_init (Dirichlet) or m_init(ghost) - m_init(wrapped
 //               interior point) (periodic m - m_init), on the face ghost points
 //   y0, y1 [3][X]  stage inputs with their ghosts (ping-pong)
@@ -28,18 +30,51 @@ constexpr int kThreads3d = 512;
 
 __device__ __forceinline__ double xi_of(const BoxPlan &P, int idx) { return -P.mu_box + (double)idx * P.dx; }
 
-// a^eps at absolute (x0, x1, x2): c0 + sum_t amp_t prod_axis s_{t,axis}
-__device__ double coef3(const CoefDev &c, double x0, double x1, double x2) {
+// The factor of term t along axis ax at coordinate x: sin(2 pi f x + phase),
+// or exactly 1 where the term does not vary along that axis.
+__device__ __forceinline__ double axis_factor(const CoefDev &c, int t, int ax, double x) {
     const double two_pi = 6.283185307179586;
+    if (ax >= c.dim || c.freq[t][ax] == 0.0) return 1.0;
+    return sin(two_pi * c.freq[t][ax] * x + c.phase[t][ax]);
+}
+
+// a^eps at absolute (x0, x1, x2): c0 + sum_t amp_t prod_axis s_{t,axis}
+// (a factor of exactly 1 leaves the product's bits unchanged)
+__device__ double coef3(const CoefDev &c, double x0, double x1, double x2) {
     const double x[3] = {x0, x1, x2};
     double a = c.c0;
     for (int t = 0; t < c.n_terms; ++t) {
         double p = c.amp[t];
-        for (int ax = 0; ax < c.dim; ++ax)
-            if (c.freq[t][ax] != 0.0) p = p * sin(two_pi * c.freq[t][ax] * x[ax] + c.phase[t][ax]);
+        for (int ax = 0; ax < 3; ++ax) p = p * axis_factor(c, t, ax, x[ax]);
         a = a + p;
     }
     return a;
+}
+
+// Coordinates along one axis as the set-up kernel forms them: grid point i,
+// and the face between points f and f + 1.
+__device__ __forceinline__ double point_pos(const BoxPlan &P, double centre, int i) {
+    return centre + xi_of(P, i);
+}
+__device__ __forceinline__ double face_pos(const BoxPlan &P, double centre, int f) {
+    const double x = centre + xi_of(P, f);
+    return x + 0.5 * P.dx;
+}
+
+// A face coefficient a^eps / dx^2 from the per-axis factor tables: the
+// products and sums of coef3 in its order, so the same bits as the set-up
+// kernel's stored faces.  t0, t1, t2: term 0's entries along each axis (term t
+// at + t * ts); the axis-0 tables hold amp_t times the factor, the first
+// product coef3 forms.
+__device__ __forceinline__ double face_from_factors(double c0, int nterms, const double *t0, const double *t1,
+                                                    const double *t2, int ts, double sc) {
+    double a = c0;
+    for (int t = 0; t < nterms; ++t) {
+        double p = t0[t * ts] * t1[t * ts];
+        p = p * t2[t * ts];
+        a = a + p;
+    }
+    return a * sc;
 }
 
 __device__ double kernel_space3(const Micro3dArgs &A, double x) {
@@ -233,328 +268,232 @@ __global__ void __launch_bounds__(kThreads3d) k_setup3d(Micro3dArgs A) {
 
 #pragma clang fp contract(on)
 
-// One block per 3-D box, point by point: the whole time loop (HeunP / RK4P with
-// projection), the weighted space/time average of the field (or torque) at
-// stage 1 of every step, and m_final; mode 1 evaluates H(m_init) once.  Each
-// stage reads one stage-input buffer and writes the next stage input into the
-// other, so a point's slope never goes through memory.  The solve uses the
-// plane-walking kernel below; this one serves the field evaluation.
-__global__ void __launch_bounds__(kThreads3d) k_micro3d(Micro3dArgs A) {
+// One block per 3-D box: H(m_init) = div(a grad m_init) at every point (mode 1,
+// the field evaluation), from the stored faces and the stage input with its
+// ghosts as the set-up kernel leaves them.
+__global__ void __launch_bounds__(kThreads3d) k_field3d(Micro3dArgs A) {
     const int box = A.box_ids[blockIdx.x];
     const BoxPlan P = A.plans[box];
     const int n = P.n, tid = threadIdx.x, nth = blockDim.x;
     Box3 B(A.work + P.tab_offset, n);
     const long C = B.C, X = B.X, nn = (long)n * n;
-    const double *w = A.wts + P.w_offset;
-    const double *wt = A.wt + P.wt_offset;
-    const double alpha = P.alpha, dt = P.dt;
-    const bool rk4 = (P.stages == 4);
     const long s1 = B.stride(1), s2 = B.stride(2);
-    // this thread's points t = tid + k nth, walked with incremental coordinates
-    const int d0 = nth % n, d1 = (nth / n) % n, d2 = (int)(nth / nn);
-    const int b0 = tid % n, b1 = (tid / n) % n, b2 = (int)(tid / nn);
-    auto advance = [&](int &i0, int &i1, int &i2) {
-        i0 += d0;
-        if (i0 >= n) { i0 -= n; ++i1; }
-        i1 += d1;
-        if (i1 >= n) { i1 -= n; ++i2; }
-        i2 += d2;
-    };
-
-    // H = div(a grad y) at the interior point with extended index e
-    auto field = [&](const double *y, long e, double H[3]) {
+    for (long t = tid; t < C; t += nth) {
+        const int i0 = (int)(t % n), i1 = (int)((t / n) % n), i2 = (int)(t / nn);
+        const long e = B.ext(i0, i1, i2);
         const double ae0 = B.A[e], aw0 = B.A[e - 1];
         const double ae1 = B.A[X + e], aw1 = B.A[X + e - s1];
         const double ae2 = B.A[2 * X + e], aw2 = B.A[2 * X + e - s2];
         for (int c = 0; c < 3; ++c) {
-            const double *yc = y + c * X;
+            const double *yc = B.y + c * X;
             const double v = yc[e];
             double h = ae0 * (yc[e + 1] - v) - aw0 * (v - yc[e - 1]);
             h += ae1 * (yc[e + s1] - v) - aw1 * (v - yc[e - s1]);
             h += ae2 * (yc[e + s2] - v) - aw2 * (v - yc[e - s2]);
-            H[c] = h;
+            A.out_field[P.mfinal_offset + c * C + t] = h;
         }
-    };
-
-    if (A.mode == 1) {
-        int i0 = b0, i1 = b1, i2 = b2;
-        for (long t = tid; t < C; t += nth, advance(i0, i1, i2)) {
-            double H[3];
-            field(B.y, B.ext(i0, i1, i2), H);
-            for (int c = 0; c < 3; ++c) A.out_field[P.mfinal_offset + c * C + t] = H[c];
-        }
-        return;
-    }
-
-    double sum[3] = {0.0, 0.0, 0.0};   // this thread's share of the average
-    const int nst = rk4 ? 4 : 2;
-    double *ycur = B.y, *ynext = B.y1;
-    for (int step = 0; step <= P.M; ++step) {
-        const double wn = wt[step];
-        for (int s = 0; s < nst; ++s) {
-            const double bs = rk4 ? ((s == 0 || s == 3) ? 1.0 / 6.0 : 1.0 / 3.0) : 0.5;
-            const double cnext = rk4 ? ((s < 2) ? 0.5 : 1.0) : 1.0;
-            int i0 = b0, i1 = b1, i2 = b2;
-            for (long t = tid; t < C; t += nth, advance(i0, i1, i2)) {
-                const long e = B.ext(i0, i1, i2);
-                double H[3];
-                field(ycur, e, H);
-                const double yv[3] = {ycur[e], ycur[X + e], ycur[2 * X + e]};
-                double c1[3], c2[3];
-                c1[0] = yv[1] * H[2] - yv[2] * H[1];
-                c1[1] = yv[2] * H[0] - yv[0] * H[2];
-                c1[2] = yv[0] * H[1] - yv[1] * H[0];
-                if (s == 0) {
-                    const double wc = w[i0] * w[i1] * w[i2] * wn;
-                    if (P.quantity == LLHMM_Q_TORQUE)
-                        for (int c = 0; c < 3; ++c) sum[c] += wc * c1[c];
-                    else
-                        for (int c = 0; c < 3; ++c) sum[c] += wc * H[c];
-                }
-                if (step == P.M) continue;
-                c2[0] = yv[1] * c1[2] - yv[2] * c1[1];
-                c2[1] = yv[2] * c1[0] - yv[0] * c1[2];
-                c2[2] = yv[0] * c1[1] - yv[1] * c1[0];
-                if (s < nst - 1) {
-                    for (int c = 0; c < 3; ++c) {
-                        const double k = -c1[c] - alpha * c2[c];
-                        B.acc[c * C + t] = (s == 0) ? bs * k : B.acc[c * C + t] + bs * k;
-                        ynext[c * X + e] = B.m[c * C + t] + cnext * dt * k;
-                    }
-                } else {
-                    double v[3];
-                    for (int c = 0; c < 3; ++c) {
-                        const double k = -c1[c] - alpha * c2[c];
-                        v[c] = B.m[c * C + t] + dt * (B.acc[c * C + t] + bs * k);
-                    }
-                    const double nr = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-                    for (int c = 0; c < 3; ++c) {
-                        B.m[c * C + t] = v[c] / nr;
-                        ynext[c * X + e] = v[c] / nr;
-                    }
-                }
-            }
-            if (step == P.M) break;
-            __syncthreads();
-            // ghosts of the new stage input
-            for (long g = tid; g < 6 * nn; g += nth) {
-                long gi, wi;
-                int q0, q1, q2;
-                ghost_point(B, g, gi, wi, q0, q1, q2);
-                for (int c = 0; c < 3; ++c)
-                    ynext[c * X + gi] = (P.bc == LLHMM_BC_DIRICHLET) ? B.G[c * X + gi]
-                                                                     : ynext[c * X + wi] + B.G[c * X + gi];
-            }
-            __syncthreads();
-            double *tmp = ycur;
-            ycur = ynext;
-            ynext = tmp;
-        }
-    }
-
-    // the box's average: fixed-order block reduction into its partial-sum slot
-    __shared__ double s_red[kThreads3d][3];
-    for (int c = 0; c < 3; ++c) s_red[tid][c] = sum[c];
-    __syncthreads();
-    for (int half = kThreads3d / 2; half > 0; half >>= 1) {
-        if (tid < half)
-            for (int c = 0; c < 3; ++c) s_red[tid][c] = s_red[tid][c] + s_red[tid + half][c];
-        __syncthreads();
-    }
-    if (tid == 0) {
-        double *dst = A.partials + P.part_offset * kMaxQ;
-        int bad = 0;
-        for (int q = 0; q < kMaxQ; ++q) {
-            const double v = (q < 3) ? s_red[0][q] : 0.0;
-            dst[q] = v;
-            if (!__builtin_isfinite(v)) bad = 1;
-        }
-        A.wave_status[P.part_offset] = bad;
-    }
-    if (A.out_field) {
-        for (long t = tid; t < C; t += nth)
-            for (int c = 0; c < 3; ++c) A.out_field[P.mfinal_offset + c * C + t] = B.m[c * C + t];
     }
 }
 
-// The time loop walking each stage plane by plane (mode 0).  A block owns the
-// whole (x1, x2) plane of its box at once (PT points per thread); the stage
-// input of the plane below, the plane itself and the x3 face below stay in
-// registers from one plane to the next, and the plane with its ghost ring is
-// staged in LDS for the x1 / x2 neighbours.  NT threads per block, one point of
-// the plane per thread (n <= 22: 512 threads, n <= 32: 1024).  Every array element then crosses
-// HBM once per stage: the streamed bytes are the algorithmic ones.
-template <int NMAX, int NT>
-__global__ void __launch_bounds__(NT, 1) k_micro3d_planes(Micro3dArgs A) {
-    constexpr int PT = (NMAX * NMAX + NT - 1) / NT;
-    constexpr int PLMAX = (NMAX + 2) * (NMAX + 2);
-    __shared__ double s_plane[3 * PLMAX];
+// Loads and stores at a byte offset from a block-uniform base: the base stays
+// in scalar registers and each address costs one 32-bit vector register.
+__device__ __forceinline__ double ldo(const double *base, uint32_t off) {
+    return *reinterpret_cast<const double *>(reinterpret_cast<const char *>(base) + off);
+}
+__device__ __forceinline__ void sto(double *base, uint32_t off, double v) {
+    *reinterpret_cast<double *>(reinterpret_cast<char *>(base) + off) = v;
+}
+// Streaming loads (data not read again within the stage): non-temporal, so
+// they do not push the stage input's reusable lines out of L2.
+__device__ __forceinline__ double ldo_nt(const double *base, uint32_t off) {
+    return __builtin_nontemporal_load(reinterpret_cast<const double *>(reinterpret_cast<const char *>(base) + off));
+}
+
+// The time loop (mode 0; boxes with n >= 8), walking columns.  Thread t owns the
+// x3 columns (i0, i1) = (q % n, q / n), q = t + j NT, and walks each from
+// x3 = 0 to n - 1 in every stage:
+//  * the stage input below, at and above the point and the x3 face below stay
+//    in registers from one point to the next; the x1 / x2 neighbours come from
+//    the caches, where the waves holding the neighbouring columns brought
+//    them a moment earlier;
+//  * the face coefficients a^eps / dx^2 of the (closed-form) coefficient are
+//    formed from per-axis factor tables in LDS, bit for bit the values the
+//    set-up kernel stores, which takes a sixth of the streamed bytes off
+//    every stage;
+//  * no wave waits for another inside a stage (stage inputs are read-only
+//    there and every other array is touched only at the thread's own
+//    points), and all loads of a point are issued together;
+//  * a point on a box face also writes the face ghosts of the next stage
+//    input that wrap to it (periodic image plus offset, or the Dirichlet
+//    datum), their ghost data loaded with the point's other operands, so a
+//    stage ends with a single barrier.
+template <int NT>
+__global__ void __launch_bounds__(NT, 1) k_micro3d(Micro3dArgs A) {
     __shared__ double s_red[NT][3];
+    // factor tables [term][axis][TR]: points 0..n-1, faces -1/2..n-1/2 (index f + 1)
+    constexpr int TR = kMaxN3 + 1;
+    __shared__ double s_pt[LLHMM_MAX_TERMS * 3 * TR];
+    __shared__ double s_fc[LLHMM_MAX_TERMS * 3 * TR];
     const int box = A.box_ids[blockIdx.x];
     const BoxPlan P = A.plans[box];
-    const int n = P.n, tid = threadIdx.x;
+    const int n = P.n, tid = threadIdx.x, nn = n * n;
     Box3 B(A.work + P.tab_offset, n);
-    const long C = B.C, X = B.X, nn = (long)n * n;
-    const int E = B.E, PL = E * E;
-    const long s1 = B.stride(1), s2 = B.stride(2);
+    const long C = B.C, X = B.X;
+    const uint32_t s1b = (uint32_t)B.stride(1) * 8, s2b = (uint32_t)B.stride(2) * 8;
+    const int32_t n8 = n * 8, ns1 = n * (int32_t)s1b, ns2 = n * (int32_t)s2b;
     const double *w = A.wts + P.w_offset;
     const double *wt = A.wt + P.wt_offset;
     const double alpha = P.alpha, dt = P.dt;
-    const bool rk4 = (P.stages == 4);
+    const bool rk4 = (P.stages == 4), dirichlet = (P.bc == LLHMM_BC_DIRICHLET);
     const int nst = rk4 ? 4 : 2;
-    // this thread's points of a plane: q = tid + j * threads, (i0, i1) = (q % n, q / n)
-    int q0[PT], q1[PT], gside[PT];   // gside: -1 / +1 at the x1 ends of a row, else 0
-    bool act[PT];
-#pragma unroll
-    for (int j = 0; j < PT; ++j) {
-        const int q = tid + j * NT;
-        act[j] = q < nn;
-        q0[j] = act[j] ? q % n : 0;
-        q1[j] = act[j] ? q / n : 0;
-        gside[j] = (q0[j] == 0) ? -1 : (q0[j] == n - 1 ? 1 : 0);
+    const CoefDev &cf = A.coefs[P.coef_index];
+    const double sc = 1.0 / (P.dx * P.dx);
+    const double c0 = cf.c0;
+    const int nterms = cf.n_terms;
+    {
+        const double cen[3] = {P.cx, P.cy, P.cz};
+        for (int k = tid; k < nterms * 3 * (2 * n + 1); k += NT) {
+            const int t = k / (3 * (2 * n + 1)), r = k % (3 * (2 * n + 1));
+            const int ax = r / (2 * n + 1), i = r % (2 * n + 1);
+            const double pre = (ax == 0) ? cf.amp[t] : 1.0;   // amp_t times the axis-0 factor
+            if (i < n) {
+                s_pt[(t * 3 + ax) * TR + i] = pre * axis_factor(cf, t, ax, point_pos(P, cen[ax], i));
+            } else {
+                const int f = i - n - 1;   // face between points f and f + 1, f = -1..n-1
+                s_fc[(t * 3 + ax) * TR + f + 1] = pre * axis_factor(cf, t, ax, face_pos(P, cen[ax], f));
+            }
+        }
+        __syncthreads();
     }
+    constexpr int TS = 3 * TR;   // term stride of both tables
+    const double *Gb[3] = {B.G, B.G + X, B.G + 2 * X};
+    double *mb[3] = {B.m, B.m + C, B.m + 2 * C};
+    double *ab[3] = {B.acc, B.acc + C, B.acc + 2 * C};
     double sum[3] = {0.0, 0.0, 0.0};
     double *ycur = B.y, *ynext = B.y1;
     for (int step = 0; step <= P.M; ++step) {
         const double wn = wt[step];
+        const bool last_level = (step == P.M);
         for (int s = 0; s < nst; ++s) {
             const double bs = rk4 ? ((s == 0 || s == 3) ? 1.0 / 6.0 : 1.0 / 3.0) : 0.5;
             const double cnext = rk4 ? ((s < 2) ? 0.5 : 1.0) : 1.0;
-            const bool last_level = (step == P.M);
-            // per point: the stage input of the plane below (ylo) and of the
-            // plane itself (yc), the x3 face below (aw2) and, for points at the
-            // x1 ends of a row, the row's ghost value (gx; it shares the cache
-            // line that brings the point itself)
-            double ylo[PT][3], yc[PT][3], aw2[PT], gx[PT][3];
-#pragma unroll
-            for (int j = 0; j < PT; ++j) {
-                if (!act[j]) continue;
-                const long elo = B.ext(q0[j], q1[j], -1), e0 = B.ext(q0[j], q1[j], 0);
-                const long eg = e0 + gside[j];
+            const double *yb[3] = {ycur, ycur + X, ycur + 2 * X};
+            double *nb[3] = {ynext, ynext + X, ynext + 2 * X};
+            // the running sum is not read at the first stage: its load then repeats
+            // the state's (same lines, no extra traffic)
+            const double *const *accr = (s == 0) ? (const double *const *)mb : (const double *const *)ab;
+            for (int q = tid; q < nn; q += NT) {
+                const int i0 = q % n, i1 = q / n;
+                uint32_t eb = (uint32_t)B.ext(i0, i1, -1) * 8;
+                uint32_t tb = (uint32_t)q * 8;
+                double ylo[3], yc[3];
                 for (int c = 0; c < 3; ++c) {
-                    ylo[j][c] = ycur[c * X + elo];
-                    yc[j][c] = ycur[c * X + e0];
-                    gx[j][c] = gside[j] ? ycur[c * X + eg] : 0.0;
+                    ylo[c] = ldo(yb[c], eb);
+                    yc[c] = ldo(yb[c], eb + s2b);
                 }
-                aw2[j] = B.A[2 * X + elo];
-            }
-            for (int i2 = 0; i2 < n; ++i2) {
-                // this plane's loads from memory (the plane above and the faces)
-                // are issued before the staging barrier, so they are in flight
-                // while the block synchronizes
-                double yhi[PT][3], ghi[PT][3], fa[PT][5];
-#pragma unroll
-                for (int j = 0; j < PT; ++j) {
-                    if (!act[j]) continue;
-                    const long e = B.ext(q0[j], q1[j], i2);
+                // factor table rows of this column (term 0)
+                const double *p0 = s_pt + i0, *p1 = s_pt + TR + i1, *p2 = s_pt + 2 * TR;
+                const double *f0 = s_fc + i0 + 1, *f1 = s_fc + TR + i1 + 1, *f2 = s_fc + 2 * TR;
+                double aw2 = face_from_factors(c0, nterms, p0, p1, f2, TS, sc);
+                const double wxy = w[i0] * w[i1];
+                // byte offsets from a point of this column to the face ghosts that
+                // wrap to it (0: none): x1 (slot a), x2 (slot b; x3 when the column
+                // is not on an x2 face)
+                const int32_t da = (i0 == n - 1) ? -n8 : ((i0 == 0) ? n8 : 0);
+                const int32_t dy = (i1 == n - 1) ? -ns1 : ((i1 == 0) ? ns1 : 0);
+                for (int i2 = 0; i2 < n; ++i2, tb += (uint32_t)nn * 8) {
+                    eb += s2b;
+                    const int32_t dz = (i2 == n - 1) ? -ns2 : ((i2 == 0) ? ns2 : 0);
+                    const int32_t db = dy ? dy : dz;
+                    const uint32_t ga = da ? eb + da : 0u, gb = db ? eb + db : 0u;
+                    // every load of the point first, so they are in flight together
+                    double yhi[3], ye[3], yw[3], yn[3], ys[3], mo[3], ao[3], gav[3], gbv[3];
                     for (int c = 0; c < 3; ++c) {
-                        yhi[j][c] = ycur[c * X + e + s2];
-                        ghi[j][c] = gside[j] ? ycur[c * X + e + s2 + gside[j]] : 0.0;
+                        const double *yp = yb[c];
+                        yhi[c] = ldo(yp, eb + s2b);
+                        ye[c] = ldo(yp, eb + 8);
+                        yw[c] = ldo(yp, eb - 8);
+                        yn[c] = ldo(yp, eb + s1b);
+                        ys[c] = ldo(yp, eb - s1b);
                     }
-                    fa[j][0] = B.A[e];
-                    fa[j][1] = B.A[e - 1];
-                    fa[j][2] = B.A[X + e];
-                    fa[j][3] = B.A[X + e - s1];
-                    fa[j][4] = B.A[2 * X + e];
-                }
-                // the plane's stage input into LDS: own points and the x1 ghosts
-                // from registers, the x2 ghost rows from memory
-#pragma unroll
-                for (int j = 0; j < PT; ++j) {
-                    if (!act[j]) continue;
-                    const int l = (q1[j] + 1) * E + (q0[j] + 1);
-                    for (int c = 0; c < 3; ++c) s_plane[c * PL + l] = yc[j][c];
-                    if (gside[j])
-                        for (int c = 0; c < 3; ++c) s_plane[c * PL + l + gside[j]] = gx[j][c];
-                }
-                for (int g = tid; g < 2 * n; g += NT) {
-                    const int i0 = g % n, i1 = (g < n) ? -1 : n;
-                    const long e = B.ext(i0, i1, i2);
-                    const int l = (i1 + 1) * E + (i0 + 1);
-                    for (int c = 0; c < 3; ++c) s_plane[c * PL + l] = ycur[c * X + e];
-                }
-                __syncthreads();
-#pragma unroll
-                for (int j = 0; j < PT; ++j) {
-                    if (!act[j]) continue;
-                    const int i0 = q0[j], i1 = q1[j];
-                    const long e = B.ext(i0, i1, i2);
-                    const long t = ((long)i2 * n + i1) * n + i0;
-                    const int l = (i1 + 1) * E + (i0 + 1);
-                    const double ae0 = fa[j][0], aw0 = fa[j][1];
-                    const double ae1 = fa[j][2], aw1 = fa[j][3];
-                    const double ae2 = fa[j][4];
+                    for (int c = 0; c < 3; ++c) {
+                        mo[c] = ldo_nt(mb[c], tb);
+                        ao[c] = ldo_nt(accr[c], tb);
+                        gav[c] = ldo(Gb[c], ga);
+                        gbv[c] = ldo(Gb[c], gb);
+                    }
+                    const double wz = w[i2];
+                    // keep the scheduler from splitting the loads into dependent groups
+                    __builtin_amdgcn_sched_barrier(0);
+                    const double ae0 = face_from_factors(c0, nterms, f0, p1, p2 + i2, TS, sc);
+                    const double aw0 = face_from_factors(c0, nterms, f0 - 1, p1, p2 + i2, TS, sc);
+                    const double ae1 = face_from_factors(c0, nterms, p0, f1, p2 + i2, TS, sc);
+                    const double aw1 = face_from_factors(c0, nterms, p0, f1 - 1, p2 + i2, TS, sc);
+                    const double ae2 = face_from_factors(c0, nterms, p0, p1, f2 + i2 + 1, TS, sc);
                     double H[3];
                     for (int c = 0; c < 3; ++c) {
-                        const double *pl = s_plane + c * PL;
-                        const double v = yc[j][c];
-                        double h = ae0 * (pl[l + 1] - v) - aw0 * (v - pl[l - 1]);
-                        h += ae1 * (pl[l + E] - v) - aw1 * (v - pl[l - E]);
-                        h += ae2 * (yhi[j][c] - v) - aw2[j] * (v - ylo[j][c]);
+                        const double v = yc[c];
+                        double h = ae0 * (ye[c] - v) - aw0 * (v - yw[c]);
+                        h += ae1 * (yn[c] - v) - aw1 * (v - ys[c]);
+                        h += ae2 * (yhi[c] - v) - aw2 * (v - ylo[c]);
                         H[c] = h;
                     }
-                    const double yv[3] = {yc[j][0], yc[j][1], yc[j][2]};
                     double c1[3], c2[3];
-                    c1[0] = yv[1] * H[2] - yv[2] * H[1];
-                    c1[1] = yv[2] * H[0] - yv[0] * H[2];
-                    c1[2] = yv[0] * H[1] - yv[1] * H[0];
+                    c1[0] = yc[1] * H[2] - yc[2] * H[1];
+                    c1[1] = yc[2] * H[0] - yc[0] * H[2];
+                    c1[2] = yc[0] * H[1] - yc[1] * H[0];
                     if (s == 0) {
-                        const double wc = w[i0] * w[i1] * w[i2] * wn;
+                        const double wc = wxy * wz * wn;
                         if (P.quantity == LLHMM_Q_TORQUE)
                             for (int c = 0; c < 3; ++c) sum[c] += wc * c1[c];
                         else
                             for (int c = 0; c < 3; ++c) sum[c] += wc * H[c];
                     }
                     if (!last_level) {
-                        c2[0] = yv[1] * c1[2] - yv[2] * c1[1];
-                        c2[1] = yv[2] * c1[0] - yv[0] * c1[2];
-                        c2[2] = yv[0] * c1[1] - yv[1] * c1[0];
-                        if (s == 0) {
+                        c2[0] = yc[1] * c1[2] - yc[2] * c1[1];
+                        c2[1] = yc[2] * c1[0] - yc[0] * c1[2];
+                        c2[2] = yc[0] * c1[1] - yc[1] * c1[0];
+                        double vn[3];
+                        if (s < nst - 1) {
                             for (int c = 0; c < 3; ++c) {
                                 const double k = -c1[c] - alpha * c2[c];
-                                B.acc[c * C + t] = bs * k;
-                                ynext[c * X + e] = B.m[c * C + t] + cnext * dt * k;
-                            }
-                        } else if (s < nst - 1) {
-                            for (int c = 0; c < 3; ++c) {
-                                const double k = -c1[c] - alpha * c2[c];
-                                B.acc[c * C + t] = B.acc[c * C + t] + bs * k;
-                                ynext[c * X + e] = B.m[c * C + t] + cnext * dt * k;
+                                sto(ab[c], tb, (s == 0) ? bs * k : ao[c] + bs * k);
+                                vn[c] = mo[c] + cnext * dt * k;
                             }
                         } else {
                             double v[3];
                             for (int c = 0; c < 3; ++c) {
                                 const double k = -c1[c] - alpha * c2[c];
-                                v[c] = B.m[c * C + t] + dt * (B.acc[c * C + t] + bs * k);
+                                v[c] = mo[c] + dt * (ao[c] + bs * k);
                             }
                             const double nr = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
                             for (int c = 0; c < 3; ++c) {
-                                B.m[c * C + t] = v[c] / nr;
-                                ynext[c * X + e] = v[c] / nr;
+                                vn[c] = v[c] / nr;
+                                sto(mb[c], tb, vn[c]);
                             }
                         }
+                        for (int c = 0; c < 3; ++c) sto(nb[c], eb, vn[c]);
+                        if (da)
+                            for (int c = 0; c < 3; ++c) sto(nb[c], eb + da, dirichlet ? gav[c] : vn[c] + gav[c]);
+                        if (db)
+                            for (int c = 0; c < 3; ++c) sto(nb[c], eb + db, dirichlet ? gbv[c] : vn[c] + gbv[c]);
+                        // the x3 ghost of a point on an edge shared by an x2 face and an
+                        // x3 face (slot b holds its x2 ghost)
+                        if (dy && dz)
+                            for (int c = 0; c < 3; ++c) {
+                                const double g = ldo(Gb[c], eb + dz);
+                                sto(nb[c], eb + dz, dirichlet ? g : vn[c] + g);
+                            }
                     }
-                    // move up one plane
                     for (int c = 0; c < 3; ++c) {
-                        ylo[j][c] = yc[j][c];
-                        yc[j][c] = yhi[j][c];
-                        gx[j][c] = ghi[j][c];
+                        ylo[c] = yc[c];
+                        yc[c] = yhi[c];
                     }
-                    aw2[j] = ae2;
+                    aw2 = ae2;
                 }
-                __syncthreads();  // the plane buffer is rewritten next
             }
             if (last_level) break;
-            // ghosts of the new stage input
-            for (long g = tid; g < 6 * nn; g += NT) {
-                long gi, wi;
-                int r0, r1, r2;
-                ghost_point(B, g, gi, wi, r0, r1, r2);
-                for (int c = 0; c < 3; ++c)
-                    ynext[c * X + gi] = (P.bc == LLHMM_BC_DIRICHLET) ? B.G[c * X + gi]
-                                                                     : ynext[c * X + wi] + B.G[c * X + gi];
-            }
-            __syncthreads();
+            __syncthreads();   // the next stage input is complete, ghosts included
             double *tmp = ycur;
             ycur = ynext;
             ynext = tmp;
@@ -585,6 +524,11 @@ __global__ void __launch_bounds__(NT, 1) k_micro3d_planes(Micro3dArgs A) {
     }
 }
 
+template <int NT>
+static void launch_cols(const Micro3dArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL((k_micro3d<NT>), dim3(a.nbox), dim3(NT), 0, s, a);
+}
+
 hipError_t launch_setup3d(const Micro3dArgs &a, hipStream_t s) {
     if (a.nbox <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_setup3d, dim3(a.nbox), dim3(kThreads3d), 0, s, a);
@@ -593,14 +537,15 @@ hipError_t launch_setup3d(const Micro3dArgs &a, hipStream_t s) {
 
 hipError_t launch_micro3d(const Micro3dArgs &a, hipStream_t s) {
     if (a.nbox <= 0) return hipSuccess;
-    // field evaluation, and boxes above 32 points per axis (whose plane would take
-    // 4 or more points per thread and spill): the point-by-point kernel
-    if (a.mode == 1 || a.nmax > 32) {
-        hipLaunchKernelGGL(k_micro3d, dim3(a.nbox), dim3(kThreads3d), 0, s, a);
-    } else if (a.nmax <= 22) {
-        hipLaunchKernelGGL((k_micro3d_planes<22, 512>), dim3(a.nbox), dim3(512), 0, s, a);
+    if (a.mode == 1) {
+        hipLaunchKernelGGL(k_field3d, dim3(a.nbox), dim3(kThreads3d), 0, s, a);
     } else {
-        hipLaunchKernelGGL((k_micro3d_planes<32, 1024>), dim3(a.nbox), dim3(1024), 0, s, a);
+        // threads per block: the columns of the largest box, rounded up (larger
+        // boxes take several passes over their columns)
+        const int cols = a.nmax * a.nmax;
+        if (cols <= 256) launch_cols<256>(a, s);
+        else if (cols <= 512) launch_cols<512>(a, s);
+        else launch_cols<1024>(a, s);
     }
     return hipGetLastError();
 }
