@@ -33,8 +33,6 @@ for d in (1, 2):
 @pytest.mark.parametrize("d,order,bc,q,integ", CASES)
 def test_oracle_matches_bruteforce(d, order, bc, q, integ):
     """P1: O1-O12 end to end against a dense-operator implementation."""
-    if d == 2 and (order == 4) and integ == 1:
-        pytest.skip("covered by the other 2-D fourth-order cases")
     eps = 0.05
     n = 12 if d == 1 else 10
     b = box(dim=d, n=n, order=order, bc=bc, quantity=q, integrator=integ, eps=eps, alpha=0.3,
