@@ -122,6 +122,26 @@ def test_3d_kernel_paths(ctx, ns):
     check(ctx, wl)
 
 
+def coef_three_terms3(eps):
+    """A three-term closed-form coefficient: terms that vary along all, two and
+    one axes, nonzero phases and different frequencies (a in [0.55, 1.85])."""
+    f = 1.0 / eps
+    return inputs.SinSum(3, 1.2, [(0.3, [(f, 0.1), (f, 0.0), (f, 0.7)]),
+                                  (0.2, [(2.0 * f, 0.0), (0.0, 0.0), (f, 0.3)]),
+                                  (0.15, [(0.0, 0.0), (3.0 * f, 0.5), (0.0, 0.0)])],
+                         a_min=0.55, a_max=1.85)
+
+
+@pytest.mark.parametrize("bc", [0, 1])
+def test_3d_multi_term_coefficient(ctx, bc):
+    """The time loop forms the faces from per-axis factor tables, term by term:
+    several terms, factors that are exactly 1 on some axes, and phases."""
+    print(f"3-D three-term coefficient bc={bc}", flush=True)
+    wl = workload(boxes3((12, 16), bc, inputs.Q_FIELD, 2, seed=77 + bc, n_steps=8),
+                  coef=coef_three_terms3(0.01))
+    check(ctx, wl)
+
+
 def test_3d_stability_rule_and_laminate(ctx):
     """Step counts from the rule (d = 3 in omega) and the laminate coefficient."""
     wl = workload(boxes3((16, 24), 1, 0, 0, seed=5, eta=1.0), coef=inputs.coef_layered3(0.01))
