@@ -308,6 +308,9 @@ __device__ __forceinline__ void sto(double *base, uint32_t off, double v) {
 __device__ __forceinline__ double ldo_nt(const double *base, uint32_t off) {
     return __builtin_nontemporal_load(reinterpret_cast<const double *>(reinterpret_cast<const char *>(base) + off));
 }
+__device__ __forceinline__ void sto_nt(double *base, uint32_t off, double v) {
+    __builtin_nontemporal_store(v, reinterpret_cast<double *>(reinterpret_cast<char *>(base) + off));
+}
 
 // The time loop (mode 0; boxes with n >= 8), walking columns.  Thread t owns the
 // x3 columns (i0, i1) = (q % n, q / n), q = t + j NT, and walks each from
@@ -457,7 +460,7 @@ __global__ void __launch_bounds__(NT, 1) k_micro3d(Micro3dArgs A) {
                         if (s < nst - 1) {
                             for (int c = 0; c < 3; ++c) {
                                 const double k = -c1[c] - alpha * c2[c];
-                                sto(ab[c], tb, (s == 0) ? bs * k : ao[c] + bs * k);
+                                sto_nt(ab[c], tb, (s == 0) ? bs * k : ao[c] + bs * k);
                                 vn[c] = mo[c] + cnext * dt * k;
                             }
                         } else {
@@ -469,7 +472,7 @@ __global__ void __launch_bounds__(NT, 1) k_micro3d(Micro3dArgs A) {
                             const double nr = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
                             for (int c = 0; c < 3; ++c) {
                                 vn[c] = v[c] / nr;
-                                sto(mb[c], tb, vn[c]);
+                                sto_nt(mb[c], tb, vn[c]);
                             }
                         }
                         for (int c = 0; c < 3; ++c) sto(nb[c], eb, vn[c]);
