@@ -529,7 +529,9 @@ __global__ void __launch_bounds__(L * NG, MINW) k_micro(MicroArgs A) {
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int wave = tid >> 6;
+    // the wavefront index is uniform across the wave: in a scalar register, the
+    // row group of a 64-lane group and everything derived from it are too
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int j = (L == 16) ? (lane & 15) : lane;
     Lane S;
     S.g = (L == 16) ? (wave * 4 + (lane >> 4)) : wave;
@@ -752,7 +754,7 @@ __global__ void __launch_bounds__(L * NG, MINW) k_band(BandArgs A) {
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int wave = tid >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: scalar register
     const int j = (L == 16) ? (lane & 15) : lane;
     const BandJob job = A.jobs[blockIdx.x];
     const BoxPlan &P = A.plans[job.box];
