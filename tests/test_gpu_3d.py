@@ -112,11 +112,12 @@ def test_3d_parity(ctx, bc, q, integ):
     check(ctx, wl)
 
 
-@pytest.mark.parametrize("ns", [(8, 16), (20, 32), (40,)])
+@pytest.mark.parametrize("ns", [(8,), (8, 16), (20, 32), (40,), (64,)])
 def test_3d_kernel_paths(ctx, ns):
     """Each launch shape of the time loop: 256, 512 and 1024 threads per block
-    (one column per thread up to n = 32) and several passes over the columns
-    above 32 points per axis; boxes of different n in one launch."""
+    (one column per thread up to n = 32), several passes over the columns
+    above 32 points per axis (n = 64: the largest box, four passes), the
+    smallest box alone, and boxes of different n in one launch."""
     print(f"3-D kernel path n={ns}", flush=True)
     wl = workload(boxes3(ns, 1, 0, 2, seed=41 + ns[0], n_steps=6))
     check(ctx, wl)
