@@ -143,6 +143,18 @@ def test_3d_multi_term_coefficient(ctx, bc):
     check(ctx, wl)
 
 
+def test_3d_mixed_classes_one_launch(ctx):
+    """One time-stepping launch carries every d = 3 box of the batch: periodic
+    and Dirichlet, field and torque, HeunP and RK4P boxes of different n
+    together (each block reads its box's own plan)."""
+    print("3-D mixed classes in one launch", flush=True)
+    boxes = (boxes3((12,), 0, inputs.Q_FIELD, 2, seed=91, n_steps=7)
+             + boxes3((16,), 1, inputs.Q_TORQUE, 1, seed=92, n_steps=9)
+             + boxes3((10,), 1, inputs.Q_FIELD, 2, seed=93, n_steps=5)
+             + boxes3((14,), 0, inputs.Q_TORQUE, 1, seed=94, n_steps=6))
+    check(ctx, workload(boxes))
+
+
 def test_3d_stability_rule_and_laminate(ctx):
     """Step counts from the rule (d = 3 in omega) and the laminate coefficient."""
     wl = workload(boxes3((16, 24), 1, 0, 0, seed=5, eta=1.0), coef=inputs.coef_layered3(0.01))
