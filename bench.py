@@ -354,8 +354,9 @@ def main():
                     help="only run a plain 1 GiB device copy (PMC counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: the micro boxes shard across GPUs without "
-              "communication, and multi-GPU runs are not part of this build", file=sys.stderr)
+        print("bench.py measures one GPU (--gpus 1): the boxes of a batch are independent, so "
+              "N GPUs would each solve 1/N of them with no communication; this script does not "
+              "launch several", file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()

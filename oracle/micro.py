@@ -216,7 +216,7 @@ def weights(box, kernel, M):
     return (np.ascontiguousarray(w), np.ascontiguousarray(wf), np.ascontiguousarray(wt))
 
 
-# ---------------------------------------------------------------- driver
+# ---------------------------------------------------------------- solving a box
 def solve_box(box, coef, init_fn=None, macro=None, kernel=(3, 7, 3, 7), project=True,
               want_state=False, want_trace=False, variant="plain"):
     d, n = box["dim"], box["n"]
