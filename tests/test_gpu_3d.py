@@ -155,6 +155,36 @@ def test_3d_mixed_classes_one_launch(ctx):
     check(ctx, workload(boxes))
 
 
+def test_full_three_d_batch_sampled(ctx):
+    """512 boxes of 32^3 (194 RK4P steps) in the launch configuration the bench
+    times; 4 boxes checked one by one against the oracle (average and final
+    state), with the noise-run bars of the small cases."""
+    print("3-D full batch, sampled boxes", flush=True)
+    wl = inputs.three_d_batch()
+    idx = [0, 171, 342, 511]
+    p = Prepared(wl, precision=inputs.FP64, ctx=ctx)
+    out = p.solve(want_state=True)
+    assert (out["status"] == 0).all()
+    ora = run_oracle(wl, idx, want_state=True, threads=4)
+    noise = [run_oracle(wl, idx, want_state=True, variant="fma", threads=4)]
+    for d in range(3):
+        wlp = copy.copy(wl)
+        wlp.coefs = [UlpCoef(c, 7 + 31 * d + k) for k, c in enumerate(wl.coefs)]
+        noise.append(run_oracle(wlp, idx, want_state=True, threads=4))
+    Ho = np.stack([r["out"] for r in ora])
+    spread = np.max([rel_err(np.stack([r["out"] for r in run]), Ho) for run in noise], axis=0)
+    err = rel_err(out["H"][idx, :3], Ho)
+    print("3-D full batch rel err", err, "spread", spread, flush=True)
+    assert np.all(err <= np.maximum(1e-12, SPREAD_FACTOR * spread))
+    for j, i in enumerate(idx):
+        mg = box_state(out["m_final"], i, wl.boxes[i], p.batch.n_max, p.batch.dim_max)
+        sp = max(np.abs(run[j]["mfinal"] - ora[j]["mfinal"]).max() for run in noise)
+        dev = np.abs(mg - ora[j]["mfinal"]).max()
+        print("state", i, dev, sp, flush=True)
+        assert dev <= max(1e-13, SPREAD_FACTOR * sp), (i, dev, sp)
+    p.batch.close()
+
+
 def test_3d_stability_rule_and_laminate(ctx):
     """Step counts from the rule (d = 3 in omega) and the laminate coefficient."""
     wl = workload(boxes3((16, 24), 1, 0, 0, seed=5, eta=1.0), coef=inputs.coef_layered3(0.01))
