@@ -384,3 +384,51 @@ def test_macro_time_order(scheme, order):
         errs.append(np.abs(st.M - exact(T)).max())
     rate = math.log2(errs[1] / errs[2])
     assert abs(rate - order) < 0.3, (errs, rate)
+
+
+# ----------------------------------------------------------------- closed form: discrete plane wave
+@pytest.mark.parametrize("d", [1, 2, 3])
+@pytest.mark.parametrize("integ,order", [(1, 2), (2, 4)])
+def test_discrete_plane_wave_closed_form(d, integ, order):
+    """With a constant coefficient a, a plane wave that is periodic on the box
+    is an eigenvector of the second-order stencil: D m_perp = -lam_h m_perp with
+    lam_h = sum_i 4 sin^2(k_i dx / 2) / dx^2.  The semi-discrete equation (micro)
+    is then solved exactly by the damped precessing plane wave of the
+    homogenized equation with k^T A k replaced by a lam_h.  The oracle's final
+    state must converge to it at the integrator's order (HeunP 2, RK4P 4) as
+    dt is halved: this pins the signs of the precession and damping terms, the
+    stencil's eigenvalue, the periodic ghosts and the stage weights."""
+    from oracle import homogenized as hg
+    a, alpha, th0, ph0 = 1.3, 0.3, 0.7, 0.2
+    n = 16 if d < 3 else 8
+    mu_box = 0.5
+    xi, dx = micro.grid_positions(n, mu_box)
+    x = xi[micro.GW:micro.GW + n]
+    centre = (0.13, 0.29, 0.41)
+    kint = (1, 2, 1)[:d]
+    k = [2.0 * math.pi * j / (n * dx) for j in kint]
+    Aeff = np.diag([a * (2.0 * math.sin(ki * dx / 2.0) / (ki * dx)) ** 2 for ki in k])
+    # interior grid in storage order [i2][i1][i0] (x1 fastest)
+    axes = [centre[i] + x for i in range(d)]
+    grids = np.meshgrid(*axes[::-1], indexing="ij")[::-1]
+
+    def wave(t, X):
+        return hg.plane_wave(tuple(X), k, Aeff, alpha, th0, ph0, t)
+
+    T = 0.01 * (3 - d) if d < 3 else 0.01    # about the same phase advance on every d
+    M0 = int(round((400 if integ == 1 else 50) * T / 0.01))   # errors well above rounding
+    errs = []
+    for M in (M0, 2 * M0):
+        b = inputs.make_box(dim=d, n=n, order=2, bc=0, quantity=inputs.Q_FIELD, integrator=integ,
+                            n_steps=M, eps=0.05, alpha=alpha, mu=mu_box, mu_box=mu_box, eta=T,
+                            a_max=a, center=centre, macro_index=(0, 0, 0))
+        r = micro.solve_box(b, inputs.coef_const(a, d), init_fn=lambda *X: wave(0.0, X), want_state=True)
+        want = wave(T, grids)
+        errs.append(np.abs(r["mfinal"] - want).max())
+    # the wave really moved: precession by tens of degrees and a visible tilt
+    moved = np.abs(wave(T, grids) - wave(0.0, grids)).max()
+    assert moved > 0.3
+    ratio = errs[0] / errs[1]
+    print(d, integ, errs, ratio)
+    assert 0.8 * 2 ** order <= ratio <= 1.25 * 2 ** order
+    assert errs[1] <= (1e-5 if integ == 1 else 1e-8)
