@@ -92,8 +92,10 @@ typedef struct {
 } llhmm_coef;
 
 /* One micro problem (eq. (micro)).  d = 3 boxes (the problem allows d <= 3,
- * Section 2.1) are supported in FP64 with the second-order stencil and the
- * field or torque quantity; other d = 3 combinations return LLHMM_E_NOTSUP. */
+ * Section 2.1) are supported in FP64 with the second-order stencil and a
+ * closed-form coefficient, for the field, torque and flux quantities (flux:
+ * nine outputs, [axis][component]); other d = 3 combinations return
+ * LLHMM_E_NOTSUP.  The serving loop takes d = 3 field and torque requests. */
 typedef struct {
     int32_t dim;          /* d in {1, 2, 3} */
     int32_t n;            /* grid points per axis (square / cubic boxes), >= 8 */

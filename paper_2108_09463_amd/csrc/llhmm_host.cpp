@@ -397,6 +397,7 @@ struct llhmm_batch {
     int32_t *box_ids = nullptr;
     int32_t *box3_ids = nullptr;                  // the d = 3 boxes
     int nbox3 = 0, nmax3 = 0;
+    int nq3 = 3;                                  // largest number of outputs of a d = 3 box
     double cost3 = 0.0;
     double *work3d = nullptr;                     // their work areas (work3d_size doubles each)
     CoefDev *coefs = nullptr;
@@ -638,11 +639,10 @@ static llhmm_status batch_create_impl(llhmm_ctx *ctx, const llhmm_box *boxes, in
             delete b;
             return st;
         }
-        if (bx.dim == 3 && (precision != LLHMM_FP64 || bx.order != 2 || bx.quantity == LLHMM_Q_FLUX ||
-                            coefs[bx.coef_index].sampled)) {
+        if (bx.dim == 3 && (precision != LLHMM_FP64 || bx.order != 2 || coefs[bx.coef_index].sampled)) {
             delete b;
-            return fail(LLHMM_E_NOTSUP, "box %d: d = 3 boxes need FP64, order 2, a closed-form coefficient "
-                        "and the field or torque quantity", i);
+            return fail(LLHMM_E_NOTSUP, "box %d: d = 3 boxes need FP64, order 2 and a closed-form coefficient",
+                        i);
         }
         auto it = reg.find(TileKey{precision, bx.dim, bx.n, bx.order, bx.bc, bx.quantity});
         const BandTileInfo *bt = nullptr;
@@ -736,6 +736,7 @@ static llhmm_status batch_create_impl(llhmm_ctx *ctx, const llhmm_box *boxes, in
             work3_off += work3d_size(bx.n);
             ids3.push_back(i);
             b->nmax3 = std::max(b->nmax3, bx.n);
+            b->nq3 = std::max(b->nq3, P.nq);
             b->cost3 += (double)pl.M * P.stages * bx.n * bx.n * bx.n;
         } else {
             P.tab_offset = tab_off;
@@ -989,6 +990,7 @@ static llhmm_status run_batch(llhmm_ctx *ctx, llhmm_batch *b, const double *m_in
         a3.box_ids = b->box3_ids;
         a3.nbox = b->nbox3;
         a3.nmax = b->nmax3;
+        a3.nq_max = b->nq3;
         a3.mode = mode;
         a3.coefs = b->coefs;
         a3.m_init = m_init_dev;
@@ -1372,9 +1374,13 @@ struct ServeReq {
     int64_t bytes;                   // device memory its share of a micro-batch needs (upper bound)
 };
 
+// Results per request in the serving API: stride 6 (3 * dim for flux in 2-D;
+// d = 3 flux requests are not served).
+constexpr int kServeQ = 6;
+
 struct ServeDone {
     int64_t id;
-    double H[kMaxQ];
+    double H[kServeQ];
     int32_t status;
     double latency_us;
 };
@@ -1406,7 +1412,7 @@ struct llhmm_server {
     std::deque<ServeReq> queue;
     std::vector<ServeFlight> slots;
     std::vector<hipStream_t> streams;
-    double *H_host = nullptr;    // pinned [slots][max_batch_boxes][kMaxQ]
+    double *H_host = nullptr;    // pinned [slots][max_batch_boxes][kServeQ]
     int32_t *st_host = nullptr;  // pinned [slots][max_batch_boxes]
     std::deque<ServeDone> done;
     int64_t reserved = 0, seq = 0;
@@ -1490,7 +1496,7 @@ static llhmm_status serve_complete(llhmm_server *sv) {
         for (size_t r = 0; r < f.reqs.size(); ++r) {
             ServeDone d;
             d.id = f.reqs[r].id;
-            memcpy(d.H, sv->H_host + ((size_t)k * mb + r) * kMaxQ, sizeof d.H);
+            memcpy(d.H, sv->H_host + ((size_t)k * mb + r) * kServeQ, sizeof d.H);
             d.status = sv->st_host[(size_t)k * mb + r];
             d.latency_us = (t - f.reqs[r].t_submit) * 1e6;
             sv->done.push_back(d);
@@ -1556,7 +1562,7 @@ static llhmm_status serve_admit(llhmm_server *sv) {
             serve_fail_front(sv, n, st);
             continue;
         }
-        f.H_dev = (double *)sv->arena.alloc(n * kMaxQ * sizeof(double));
+        f.H_dev = (double *)sv->arena.alloc(n * kServeQ * sizeof(double));
         f.st_dev = (int32_t *)sv->arena.alloc(n * sizeof(int32_t));
         f.bytes = bytes + kBatchSlack;
         sv->reserved += f.bytes;
@@ -1576,8 +1582,8 @@ static llhmm_status serve_admit(llhmm_server *sv) {
             continue;
         }
         HIP_TRY(launch_upscale(f.batch->partials, f.batch->wave_status, f.batch->box_const, f.batch->plans,
-                               (int)n, f.H_dev, kMaxQ, f.batch->status, f.st_dev, s));
-        HIP_TRY(hipMemcpyAsync(sv->H_host + (size_t)slot * mb * kMaxQ, f.H_dev, n * kMaxQ * sizeof(double),
+                               (int)n, f.H_dev, kServeQ, f.batch->status, f.st_dev, s));
+        HIP_TRY(hipMemcpyAsync(sv->H_host + (size_t)slot * mb * kServeQ, f.H_dev, n * kServeQ * sizeof(double),
                                hipMemcpyDeviceToHost, s));
         HIP_TRY(hipMemcpyAsync(sv->st_host + (size_t)slot * mb, f.st_dev, n * sizeof(int32_t),
                                hipMemcpyDeviceToHost, s));
@@ -1623,7 +1629,7 @@ llhmm_status llhmm_server_create(llhmm_ctx *ctx, const llhmm_server_cfg *cfg, co
     sv->coefs.assign(coefs, coefs + ncoefs);
     hipError_t e = sv->arena.init((size_t)cfg->device_bytes);
     const size_t mb = (size_t)cfg->max_batch_boxes;
-    if (e == hipSuccess) e = hipHostMalloc((void **)&sv->H_host, sizeof(double) * cfg->max_inflight * mb * kMaxQ);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&sv->H_host, sizeof(double) * cfg->max_inflight * mb * kServeQ);
     if (e == hipSuccess) e = hipHostMalloc((void **)&sv->st_host, sizeof(int32_t) * cfg->max_inflight * mb);
     sv->slots.resize(cfg->max_inflight);
     sv->streams.assign(cfg->max_inflight, nullptr);
@@ -1691,7 +1697,7 @@ llhmm_status llhmm_server_poll(llhmm_server *sv, int32_t wait, int32_t max, int6
     while (k < max && !sv->done.empty()) {
         const ServeDone &d = sv->done.front();
         if (ids_out) ids_out[k] = d.id;
-        if (H_out) memcpy(H_out + (size_t)k * kMaxQ, d.H, sizeof d.H);
+        if (H_out) memcpy(H_out + (size_t)k * kServeQ, d.H, sizeof d.H);
         if (status_out) status_out[k] = d.status;
         if (latency_us_out) latency_us_out[k] = d.latency_us;
         sv->done.pop_front();

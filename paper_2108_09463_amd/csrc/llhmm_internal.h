@@ -9,7 +9,7 @@ namespace llhmm {
 
 constexpr int kGhost = LLHMM_GHOST;
 constexpr int kMaxWaves = 16;  // waves per block of the resident kernels
-constexpr int kMaxQ = 6;       // outputs per box (flux in 2-D)
+constexpr int kMaxQ = 9;       // outputs per box (flux in 3-D: 3 axes x 3 components)
 constexpr int kFaceHalo = 3;   // faces -2 .. n stored per line: n + 3 entries
 // FP32 reference + perturbation form: every kRerefSteps time steps the state
 // is re-expressed around a new reference r' = fl(r + u) (MicroLane::rereference).

@@ -12,7 +12,7 @@ struct Micro3dArgs {
     const BoxPlan *plans;
     const int32_t *box_ids;    // the batch's 3-D boxes
     int32_t nbox, mode;        // mode 0 solve, 1 evaluate H(m_init) only
-    int32_t nmax, pad_;        // largest n of the 3-D boxes
+    int32_t nmax, nq_max;      // largest n of the 3-D boxes; largest outputs per box (9: flux)
     const CoefDev *coefs;
     const double *m_init;      // explicit initial data (extended grid, LLHMM_GHOST layers)
     const double *M_macro;     // macro field [3][n^3]

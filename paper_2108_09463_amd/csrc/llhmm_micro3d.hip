@@ -330,9 +330,9 @@ __device__ __forceinline__ void sto_nt(double *base, uint32_t off, double v) {
 //    input that wrap to it (periodic image plus offset, or the Dirichlet
 //    datum), their ghost data loaded with the point's other operands, so a
 //    stage ends with a single barrier.
-template <int NT>
+template <int NT, int NQ>
 __global__ void __launch_bounds__(NT, 1) k_micro3d(Micro3dArgs A) {
-    __shared__ double s_red[NT][3];
+    __shared__ double s_red[NT][NQ];
     // factor tables [term][axis][TR]: points 0..n-1, faces -1/2..n-1/2 (index f + 1)
     constexpr int TR = kMaxN3 + 1;
     __shared__ double s_pt[LLHMM_MAX_TERMS * 3 * TR];
@@ -372,7 +372,19 @@ __global__ void __launch_bounds__(NT, 1) k_micro3d(Micro3dArgs A) {
     const double *Gb[3] = {B.G, B.G + X, B.G + 2 * X};
     double *mb[3] = {B.m, B.m + C, B.m + 2 * C};
     double *ab[3] = {B.acc, B.acc + C, B.acc + 2 * C};
-    double sum[3] = {0.0, 0.0, 0.0};
+    const bool flux = (NQ == 9) && (P.quantity == LLHMM_Q_FLUX);
+    // this thread's share of the average: in registers (3 sums), or with nine
+    // sums in its row of the reduction buffer (registers would spill)
+    constexpr bool SUM_LDS = (NQ == 9);
+    double sum[SUM_LDS ? 1 : NQ];
+    for (int q = 0; q < NQ; ++q) {
+        if (SUM_LDS) s_red[tid][q] = 0.0;
+        else sum[SUM_LDS ? 0 : q] = 0.0;
+    }
+    auto add_sum = [&](int q, double v) {
+        if (SUM_LDS) s_red[tid][q] += v;
+        else sum[SUM_LDS ? 0 : q] += v;
+    };
     double *ycur = B.y, *ynext = B.y1;
     for (int step = 0; step <= P.M; ++step) {
         const double wn = wt[step];
@@ -399,6 +411,10 @@ __global__ void __launch_bounds__(NT, 1) k_micro3d(Micro3dArgs A) {
                 const double *f0 = s_fc + i0 + 1, *f1 = s_fc + TR + i1 + 1, *f2 = s_fc + 2 * TR;
                 double aw2 = face_from_factors(c0, nterms, p0, p1, f2, TS, sc);
                 const double wxy = w[i0] * w[i1];
+                // flux: the face weight along the flux axis, point weights along the
+                // others (axis 0 first), as products over the axes
+                const double wfx = (NQ == 9) ? w[n + i0] * w[i1] : 0.0;
+                const double wfy = (NQ == 9) ? w[i0] * w[n + i1] : 0.0;
                 // byte offsets from a point of this column to the face ghosts that
                 // wrap to it (0: none): x1 (slot a), x2 (slot b; x3 when the column
                 // is not on an x2 face)
@@ -426,6 +442,7 @@ __global__ void __launch_bounds__(NT, 1) k_micro3d(Micro3dArgs A) {
                         gbv[c] = ldo(Gb[c], gb);
                     }
                     const double wz = w[i2];
+                    const double wfz = (NQ == 9) ? w[n + i2] : 0.0;
                     // keep the scheduler from splitting the loads into dependent groups
                     __builtin_amdgcn_sched_barrier(0);
                     const double ae0 = face_from_factors(c0, nterms, f0, p1, p2 + i2, TS, sc);
@@ -445,12 +462,21 @@ __global__ void __launch_bounds__(NT, 1) k_micro3d(Micro3dArgs A) {
                     c1[0] = yc[1] * H[2] - yc[2] * H[1];
                     c1[1] = yc[2] * H[0] - yc[0] * H[2];
                     c1[2] = yc[0] * H[1] - yc[1] * H[0];
-                    if (s == 0) {
+                    if (s == 0 && flux) {
+                        // a grad m on the east face of the point along each axis
+                        // ([axis][component]; a / dx^2 here, times dx at the upscale)
+                        const double w0 = wfx * wz * wn, w1 = wfy * wz * wn, w2 = wxy * wfz * wn;
+                        for (int c = 0; c < 3; ++c) {
+                            add_sum(c, w0 * (ae0 * (ye[c] - yc[c])));
+                            add_sum(3 + c, w1 * (ae1 * (yn[c] - yc[c])));
+                            add_sum(6 + c, w2 * (ae2 * (yhi[c] - yc[c])));
+                        }
+                    } else if (s == 0) {
                         const double wc = wxy * wz * wn;
                         if (P.quantity == LLHMM_Q_TORQUE)
-                            for (int c = 0; c < 3; ++c) sum[c] += wc * c1[c];
+                            for (int c = 0; c < 3; ++c) add_sum(c, wc * c1[c]);
                         else
-                            for (int c = 0; c < 3; ++c) sum[c] += wc * H[c];
+                            for (int c = 0; c < 3; ++c) add_sum(c, wc * H[c]);
                     }
                     if (!last_level) {
                         c2[0] = yc[1] * c1[2] - yc[2] * c1[1];
@@ -504,18 +530,19 @@ __global__ void __launch_bounds__(NT, 1) k_micro3d(Micro3dArgs A) {
     }
 
     // the box's average: fixed-order block reduction into its partial-sum slot
-    for (int c = 0; c < 3; ++c) s_red[tid][c] = sum[c];
+    if (!SUM_LDS)
+        for (int c = 0; c < NQ; ++c) s_red[tid][c] = sum[SUM_LDS ? 0 : c];
     __syncthreads();
     for (int half = NT / 2; half > 0; half >>= 1) {
         if (tid < half)
-            for (int c = 0; c < 3; ++c) s_red[tid][c] = s_red[tid][c] + s_red[tid + half][c];
+            for (int c = 0; c < NQ; ++c) s_red[tid][c] = s_red[tid][c] + s_red[tid + half][c];
         __syncthreads();
     }
     if (tid == 0) {
         double *dst = A.partials + P.part_offset * kMaxQ;
         int bad = 0;
         for (int q = 0; q < kMaxQ; ++q) {
-            const double v = (q < 3) ? s_red[0][q] : 0.0;
+            const double v = (q < NQ) ? s_red[0][q] : 0.0;
             dst[q] = v;
             if (!__builtin_isfinite(v)) bad = 1;
         }
@@ -529,7 +556,10 @@ __global__ void __launch_bounds__(NT, 1) k_micro3d(Micro3dArgs A) {
 
 template <int NT>
 static void launch_cols(const Micro3dArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL((k_micro3d<NT>), dim3(a.nbox), dim3(NT), 0, s, a);
+    if (a.nq_max > 3)   // a flux box in the batch: nine sums per thread
+        hipLaunchKernelGGL((k_micro3d<NT, 9>), dim3(a.nbox), dim3(NT), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_micro3d<NT, 3>), dim3(a.nbox), dim3(NT), 0, s, a);
 }
 
 hipError_t launch_setup3d(const Micro3dArgs &a, hipStream_t s) {

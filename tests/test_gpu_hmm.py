@@ -140,12 +140,15 @@ def test_flux_and_torque_loops_converge(ctx, model):
     assert errs[24] < 3.0 * ideal[24]
 
 
-@pytest.mark.parametrize("model", ["field", "torque"])
+@pytest.mark.parametrize("model", ["field", "torque", "flux"])
 def test_3d_loops_match_oracle_loops(ctx, model):
     """The loop on a 6^3 periodic macro grid with d = 3 micro boxes (FP64): field
-    model (HeunP start-up, MPEA) and torque model (RK4P) against the loops driven
-    by the oracle.  The bar propagates a micro bar of 1e-9 relative (3-D averages
-    carry rounding noise up to 1e-10, see test_gpu_3d)."""
+    model (HeunP start-up, MPEA), torque model (RK4P) and flux model (boxes at
+    the staggered points of all three axes, fourth-order divergence) against
+    the loops driven by the oracle.  The bar propagates a micro bar of 1e-9
+    relative (3-D averages carry rounding noise up to 1e-10, see test_gpu_3d);
+    the flux divergence weighs a flux error by at most 2 (27 + 1) / (24 dX) per
+    axis."""
     from oracle import micro
     n, eps = 6, 1.0 / 48.0
     x = np.arange(n) / n
@@ -164,14 +167,18 @@ def test_3d_loops_match_oracle_loops(ctx, model):
         loop.close()
     Mo = R.oracle_loop(n, None, steps, dt, model=model, tmpl=tmpl, coef=coef, M_init=M0)
     mac = dict(n=n, dX=1.0 / n, M=M0)
-    q = inputs.Q_FIELD if model == "field" else inputs.Q_TORQUE
+    q = {"field": inputs.Q_FIELD, "torque": inputs.Q_TORQUE, "flux": inputs.Q_FLUX}[model]
+    sh = (0.5, 0.0, 0.0) if model == "flux" else (0.0, 0.0, 0.0)
     Hmax = 2.0 * max(np.abs(micro.solve_box(inputs.make_box(**dict(
-        tmpl, dim=3, quantity=q, init_mode=1, center=(k[0] / n, k[1] / n, k[2] / n), macro_index=k)),
+        tmpl, dim=3, quantity=q, init_mode=1,
+        center=tuple((k[a] + sh[a]) / n for a in range(3)), macro_index=k)),
         coef, macro=mac)["out"]).max() for k in [(0, 0, 0), (2, 3, 1), (5, 1, 4)])
-    weight = 44.0 / 12.0 if model == "field" else 1.0
+    if model == "flux":
+        Hmax *= 3 * (2 * 28.0 / 24.0 * n)   # three axes of the staggered divergence
+    weight = 1.0 if model == "torque" else 44.0 / 12.0
     bound = stages * dt * (1 + R.ALPHA) * weight * 1e-9 * Hmax
     err = np.abs(Mg - Mo).max()
     print("3-D loop parity", model, err, bound, flush=True)
-    assert stages == (5 if model == "field" else 8)
+    assert stages == {"field": 5, "torque": 8, "flux": 4}[model]   # HeunP start-up: 2 stages a step
     assert err <= bound, (err, bound)
     assert np.abs(Mg - M0).max() > 1e3 * bound
