@@ -398,6 +398,7 @@ struct llhmm_batch {
     int32_t *box3_ids = nullptr;                  // the d = 3 boxes
     int nbox3 = 0, nmax3 = 0;
     int nq3 = 3;                                  // largest number of outputs of a d = 3 box
+    int orders3 = 0;                              // stencil orders of the d = 3 boxes (bit 0: 2, bit 1: 4)
     double cost3 = 0.0;
     double *work3d = nullptr;                     // their work areas (work3d_size doubles each)
     CoefDev *coefs = nullptr;
@@ -639,10 +640,9 @@ static llhmm_status batch_create_impl(llhmm_ctx *ctx, const llhmm_box *boxes, in
             delete b;
             return st;
         }
-        if (bx.dim == 3 && (precision != LLHMM_FP64 || bx.order != 2 || coefs[bx.coef_index].sampled)) {
+        if (bx.dim == 3 && (precision != LLHMM_FP64 || coefs[bx.coef_index].sampled)) {
             delete b;
-            return fail(LLHMM_E_NOTSUP, "box %d: d = 3 boxes need FP64, order 2 and a closed-form coefficient",
-                        i);
+            return fail(LLHMM_E_NOTSUP, "box %d: d = 3 boxes need FP64 and a closed-form coefficient", i);
         }
         auto it = reg.find(TileKey{precision, bx.dim, bx.n, bx.order, bx.bc, bx.quantity});
         const BandTileInfo *bt = nullptr;
@@ -733,7 +733,8 @@ static llhmm_status batch_create_impl(llhmm_ctx *ctx, const llhmm_box *boxes, in
                           (dim_max == 1 ? (int64_t)nmax : (dim_max == 2 ? (int64_t)nmax * nmax : (int64_t)nmax * nmax * nmax));
         if (bx.dim == 3) {
             P.tab_offset = work3_off;  // in the 3-D work buffer
-            work3_off += work3d_size(bx.n);
+            work3_off += work3d_size(bx.n, bx.order);
+            b->orders3 |= (bx.order == 4) ? 2 : 1;
             ids3.push_back(i);
             b->nmax3 = std::max(b->nmax3, bx.n);
             b->nq3 = std::max(b->nq3, P.nq);
@@ -991,6 +992,7 @@ static llhmm_status run_batch(llhmm_ctx *ctx, llhmm_batch *b, const double *m_in
         a3.nbox = b->nbox3;
         a3.nmax = b->nmax3;
         a3.nq_max = b->nq3;
+        a3.orders = b->orders3;
         a3.mode = mode;
         a3.coefs = b->coefs;
         a3.m_init = m_init_dev;
@@ -1437,7 +1439,7 @@ static llhmm_status request_bytes(const llhmm_server *sv, const llhmm_box &bx, i
     if (bx.dim == 3) {
         if (prec != LLHMM_FP64 || bx.order != 2 || bx.quantity == LLHMM_Q_FLUX)
             return fail(LLHMM_E_NOTSUP, "request %d: d = 3 needs FP64, order 2, field or torque", i);
-        bytes = work3d_size(bx.n) * 8 + 2 * bx.n * 8 + (kMaxQ * 8 + 4) + 2 * (int64_t)(pl.M + 1) * 8 +
+        bytes = work3d_size(bx.n, bx.order) * 8 + 2 * bx.n * 8 + (kMaxQ * 8 + 4) + 2 * (int64_t)(pl.M + 1) * 8 +
                 (int64_t)sizeof(BoxPlan) + 4 + kMaxQ * 8 + 4 + kMaxQ * 8 + 4 + (int64_t)sizeof(CoefDev) + 3 * 256;
         return LLHMM_OK;
     }

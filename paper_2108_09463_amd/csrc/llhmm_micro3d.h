@@ -6,13 +6,14 @@
 
 namespace llhmm {
 
-// One block per box, arrays in a per-box work area of work3d_size(n) doubles
+// One block per box, arrays in a per-box work area of work3d_size(n, order) doubles
 // at plan.tab_offset.
 struct Micro3dArgs {
     const BoxPlan *plans;
     const int32_t *box_ids;    // the batch's 3-D boxes
     int32_t nbox, mode;        // mode 0 solve, 1 evaluate H(m_init) only
     int32_t nmax, nq_max;      // largest n of the 3-D boxes; largest outputs per box (9: flux)
+    int32_t orders, pad_;      // stencil orders present: bit 0 second, bit 1 fourth
     const CoefDev *coefs;
     const double *m_init;      // explicit initial data (extended grid, LLHMM_GHOST layers)
     const double *M_macro;     // macro field [3][n^3]
@@ -29,6 +30,6 @@ struct Micro3dArgs {
 };
 hipError_t launch_setup3d(const Micro3dArgs &a, hipStream_t s);
 hipError_t launch_micro3d(const Micro3dArgs &a, hipStream_t s);
-int64_t work3d_size(int n);
+int64_t work3d_size(int n, int order);
 
 }  // namespace llhmm

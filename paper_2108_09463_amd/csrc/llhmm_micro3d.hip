@@ -104,10 +104,10 @@ __device__ double node_offset3(double centre, double x0, int k, double dX) {
 }
 
 struct Box3 {
-    int n, E;
+    int n, gw, E;   // gw ghost layers per side: 1 (second order) or 3 (fourth order)
     long C, X;
     double *A, *G, *y, *y1, *m, *acc;
-    __device__ Box3(double *base, int n_) : n(n_), E(n_ + 2) {
+    __device__ Box3(double *base, int n_, int gw_ = 1) : n(n_), gw(gw_), E(n_ + 2 * gw_) {
         C = (long)n * n * n;
         X = (long)E * E * E;
         A = base;
@@ -117,20 +117,25 @@ struct Box3 {
         m = y1 + 3 * X;
         acc = m + 3 * C;
     }
-    // extended index of grid point (i0, i1, i2), ghosts at -1 and n
-    __device__ long ext(int i0, int i1, int i2) const { return ((long)(i2 + 1) * E + (i1 + 1)) * E + (i0 + 1); }
+    // extended index of grid point (i0, i1, i2), ghosts at -gw..-1 and n..n+gw-1
+    __device__ long ext(int i0, int i1, int i2) const {
+        return ((long)(i2 + gw) * E + (i1 + gw)) * E + (i0 + gw);
+    }
     __device__ long stride(int ax) const { return ax == 0 ? 1 : (ax == 1 ? (long)E : (long)E * E); }
 };
 
-// The g-th face ghost point (6 n^2 of them): its extended index and the index
-// of the interior point it wraps to (periodic images).
+// The g-th face ghost point (6 gw n^2 of them: per face of the box, gw layers
+// of n^2 points; the 7-point and 13-point stencils reach no edge or corner
+// ghost): its extended index and the index of the interior point it wraps to
+// (periodic images).
 __device__ void ghost_point(const Box3 &B, long g, long &gi, long &wi, int &c0, int &c1, int &c2) {
     const int n = B.n;
     const long nn = (long)n * n;
-    const int face = (int)(g / nn);
+    const int face = (int)(g / (nn * B.gw));
+    const int l = (int)((g / nn) % B.gw) + 1;   // layer 1..gw
     const int a = (int)(g % n), b = (int)((g / n) % n);
     const int ax = face >> 1, side = face & 1;
-    const int p = side ? n : -1, w = side ? 0 : n - 1;
+    const int p = side ? n - 1 + l : -l, w = side ? l - 1 : n - l;
     int q[3], r[3];
     if (ax == 0) { q[0] = p; q[1] = a; q[2] = b; }
     else if (ax == 1) { q[0] = a; q[1] = p; q[2] = b; }
@@ -156,10 +161,11 @@ __device__ void minit3(const Micro3dArgs &A, const BoxPlan &P, const double *L, 
         return;
     }
     // Q_[4]: tensor-product Lagrange interpolation along x1, then x2, then x3
-    const int EL = P.n + 2;                 // basis rows for grid indices -1 .. n
-    const double *L0 = L + (i0 + 1) * 5;
-    const double *L1 = L + (EL + i1 + 1) * 5;
-    const double *L2 = L + (2 * EL + i2 + 1) * 5;
+    const int gw = (P.order == 4) ? 3 : 1;
+    const int EL = P.n + 2 * gw;            // basis rows for grid indices -gw .. n+gw-1
+    const double *L0 = L + (i0 + gw) * 5;
+    const double *L1 = L + (EL + i1 + gw) * 5;
+    const double *L2 = L + (2 * EL + i2 + gw) * 5;
     const double *Mloc = L + 3 * EL * 5;    // [c][l0][l1][l2]
     double p[3] = {0.0, 0.0, 0.0};
     for (int l2 = 0; l2 < 5; ++l2) {
@@ -186,18 +192,19 @@ __global__ void __launch_bounds__(kThreads3d) k_setup3d(Micro3dArgs A) {
     const int box = A.box_ids[blockIdx.x];
     const BoxPlan P = A.plans[box];
     const int n = P.n, tid = threadIdx.x, nth = blockDim.x;
-    Box3 B(A.work + P.tab_offset, n);
+    const int gw = (P.order == 4) ? 3 : 1;
+    Box3 B(A.work + P.tab_offset, n, gw);
     const CoefDev &cf = A.coefs[P.coef_index];
-    // Lagrange bases per axis for grid indices -1..n, then the 5^3 x 3 macro values
+    // Lagrange bases per axis for grid indices -gw..n+gw-1, then the 5^3 x 3 macro values
     __shared__ double s_L[3 * (kLagMax2 - 4) * 5 + 375];
     if (P.init_mode == LLHMM_INIT_MACRO_Q) {
-        const int nm = A.macro.n, EL = n + 2;
+        const int nm = A.macro.n, EL = n + 2 * gw;
         const long npts = (long)nm * nm * nm;
         const double dX = A.macro.dX;
         const double cen[3] = {P.cx, P.cy, P.cz};
         const int mi[3] = {P.mi0, P.mi1, P.mi2};
         for (int t = tid; t < 3 * EL; t += nth) {
-            const int ax = t / EL, i = t % EL - 1;
+            const int ax = t / EL, i = t % EL - gw;
             const double o = node_offset3(cen[ax], A.macro.x0[ax], mi[ax], dX);
             lagrange5_3((xi_of(P, i) + o) / dX, s_L + t * 5);
         }
@@ -213,12 +220,13 @@ __global__ void __launch_bounds__(kThreads3d) k_setup3d(Micro3dArgs A) {
     __syncthreads();
     // faces: a at the midpoint between (i0,i1,i2) and its +e_axis neighbour, for
     // every point of the extended grid whose face an interior stencil reads
-    const double sc = 1.0 / (P.dx * P.dx);
+    // scaled by 1/dx^2 (second order) or 1/(24 dx)^2 (fourth order)
+    const double sc = (P.order == 4) ? P.a_scale : 1.0 / (P.dx * P.dx);
     const int E = B.E;
     for (long t = tid; t < 3 * B.X; t += nth) {
         const int ax = (int)(t / B.X);
         const long e = t % B.X;
-        const int i0 = (int)(e % E) - 1, i1 = (int)((e / E) % E) - 1, i2 = (int)(e / ((long)E * E)) - 1;
+        const int i0 = (int)(e % E) - gw, i1 = (int)((e / E) % E) - gw, i2 = (int)(e / ((long)E * E)) - gw;
         double x0 = P.cx + xi_of(P, i0), x1 = P.cy + xi_of(P, i1), x2 = P.cz + xi_of(P, i2);
         if (ax == 0) x0 = x0 + 0.5 * P.dx;
         else if (ax == 1) x1 = x1 + 0.5 * P.dx;
@@ -238,7 +246,7 @@ __global__ void __launch_bounds__(kThreads3d) k_setup3d(Micro3dArgs A) {
     }
     __syncthreads();
     // ghost data and the ghosts of y (as the periodic / Dirichlet rule fills them)
-    const long ng = 6L * n * n;
+    const long ng = 6L * gw * n * n;
     for (long g = tid; g < ng; g += nth) {
         long gi, wi;
         int q0, q1, q2;
@@ -268,6 +276,23 @@ __global__ void __launch_bounds__(kThreads3d) k_setup3d(Micro3dArgs A) {
 
 #pragma clang fp contract(on)
 
+// Fourth-order part of H along one axis at extended index e (stride st): the
+// staggered fluxes F = a' (27 (y_{i+1} - y_i) - (y_{i+2} - y_{i-1})) on the
+// faces between points i and i+1, i = j-2..j+1 (faces pre-scaled by
+// 1/(24 dx)^2), combined as 27 (F_{j+1/2} - F_{j-1/2}) - (F_{j+3/2} - F_{j-3/2}).
+// f_east: the flux on the east face j+1/2.
+__device__ __forceinline__ double axis_o4(const double *yc, const double *Aax, long e, long st,
+                                          double &f_east) {
+    double F[4];
+    for (int k = -2; k <= 1; ++k) {
+        const long f = e + k * st;
+        const double g = 27.0 * (yc[f + st] - yc[f]) - (yc[f + 2 * st] - yc[f - st]);
+        F[k + 2] = Aax[f] * g;
+    }
+    f_east = F[2];
+    return 27.0 * (F[2] - F[1]) - (F[3] - F[0]);
+}
+
 // One block per 3-D box: H(m_init) = div(a grad m_init) at every point (mode 1,
 // the field evaluation), from the stored faces and the stage input with its
 // ghosts as the set-up kernel leaves them.
@@ -275,12 +300,22 @@ __global__ void __launch_bounds__(kThreads3d) k_field3d(Micro3dArgs A) {
     const int box = A.box_ids[blockIdx.x];
     const BoxPlan P = A.plans[box];
     const int n = P.n, tid = threadIdx.x, nth = blockDim.x;
-    Box3 B(A.work + P.tab_offset, n);
+    const bool o4 = (P.order == 4);
+    Box3 B(A.work + P.tab_offset, n, o4 ? 3 : 1);
     const long C = B.C, X = B.X, nn = (long)n * n;
     const long s1 = B.stride(1), s2 = B.stride(2);
     for (long t = tid; t < C; t += nth) {
         const int i0 = (int)(t % n), i1 = (int)((t / n) % n), i2 = (int)(t / nn);
         const long e = B.ext(i0, i1, i2);
+        if (o4) {
+            for (int c = 0; c < 3; ++c) {
+                const double *yc = B.y + c * X;
+                double fe, h = 0.0;
+                for (int ax = 0; ax < 3; ++ax) h += axis_o4(yc, B.A + ax * X, e, B.stride(ax), fe);
+                A.out_field[P.mfinal_offset + c * C + t] = h;
+            }
+            continue;
+        }
         const double ae0 = B.A[e], aw0 = B.A[e - 1];
         const double ae1 = B.A[X + e], aw1 = B.A[X + e - s1];
         const double ae2 = B.A[2 * X + e], aw2 = B.A[2 * X + e - s2];
@@ -292,6 +327,124 @@ __global__ void __launch_bounds__(kThreads3d) k_field3d(Micro3dArgs A) {
             h += ae2 * (yc[e + s2] - v) - aw2 * (v - yc[e - s2]);
             A.out_field[P.mfinal_offset + c * C + t] = h;
         }
+    }
+}
+
+// The time loop of fourth-order boxes (mode 0), point by point: each stage
+// reads the stage input with three ghost layers, writes the next one, and the
+// ghost layers of the new input are filled between two block barriers.  The
+// wider stencil (13 points, four staggered fluxes per axis) is read through
+// the caches; this path favours simplicity over speed.
+__global__ void __launch_bounds__(kThreads3d) k_micro3d_o4(Micro3dArgs A) {
+    __shared__ double s_red[kThreads3d][9];
+    const int box = A.box_ids[blockIdx.x];
+    const BoxPlan P = A.plans[box];
+    if (P.order != 4) return;   // second-order boxes: the column kernel
+    const int n = P.n, tid = threadIdx.x, nth = kThreads3d;
+    Box3 B(A.work + P.tab_offset, n, 3);
+    const long C = B.C, X = B.X, nn = (long)n * n;
+    const double *w = A.wts + P.w_offset;
+    const double *wt = A.wt + P.wt_offset;
+    const double alpha = P.alpha, dt = P.dt;
+    const bool rk4 = (P.stages == 4), dirichlet = (P.bc == LLHMM_BC_DIRICHLET);
+    const bool flux = (P.quantity == LLHMM_Q_FLUX), torque = (P.quantity == LLHMM_Q_TORQUE);
+    const int nst = rk4 ? 4 : 2;
+    for (int q = 0; q < 9; ++q) s_red[tid][q] = 0.0;   // this thread's share of the average
+    double *ycur = B.y, *ynext = B.y1;
+    for (int step = 0; step <= P.M; ++step) {
+        const double wn = wt[step];
+        const bool last_level = (step == P.M);
+        for (int s = 0; s < nst; ++s) {
+            const double bs = rk4 ? ((s == 0 || s == 3) ? 1.0 / 6.0 : 1.0 / 3.0) : 0.5;
+            const double cnext = rk4 ? ((s < 2) ? 0.5 : 1.0) : 1.0;
+            for (long t = tid; t < C; t += nth) {
+                const int i0 = (int)(t % n), i1 = (int)((t / n) % n), i2 = (int)(t / nn);
+                const long e = B.ext(i0, i1, i2);
+                double H[3], Fe[3][3];
+                for (int c = 0; c < 3; ++c) {
+                    const double *yc = ycur + c * X;
+                    double h = 0.0;
+                    for (int ax = 0; ax < 3; ++ax) h += axis_o4(yc, B.A + ax * X, e, B.stride(ax), Fe[ax][c]);
+                    H[c] = h;
+                }
+                const double yv[3] = {ycur[e], ycur[X + e], ycur[2 * X + e]};
+                double c1[3], c2[3];
+                c1[0] = yv[1] * H[2] - yv[2] * H[1];
+                c1[1] = yv[2] * H[0] - yv[0] * H[2];
+                c1[2] = yv[0] * H[1] - yv[1] * H[0];
+                if (s == 0) {
+                    if (flux) {
+                        // a grad m on the east face of each axis: the face weight along
+                        // that axis, point weights along the others
+                        const double wax[3] = {w[n + i0] * w[i1] * w[i2] * wn, w[i0] * w[n + i1] * w[i2] * wn,
+                                               w[i0] * w[i1] * w[n + i2] * wn};
+                        for (int ax = 0; ax < 3; ++ax)
+                            for (int c = 0; c < 3; ++c) s_red[tid][ax * 3 + c] += wax[ax] * Fe[ax][c];
+                    } else {
+                        const double wc = w[i0] * w[i1] * w[i2] * wn;
+                        for (int c = 0; c < 3; ++c) s_red[tid][c] += wc * (torque ? c1[c] : H[c]);
+                    }
+                }
+                if (last_level) continue;
+                c2[0] = yv[1] * c1[2] - yv[2] * c1[1];
+                c2[1] = yv[2] * c1[0] - yv[0] * c1[2];
+                c2[2] = yv[0] * c1[1] - yv[1] * c1[0];
+                if (s < nst - 1) {
+                    for (int c = 0; c < 3; ++c) {
+                        const double k = -c1[c] - alpha * c2[c];
+                        B.acc[c * C + t] = (s == 0) ? bs * k : B.acc[c * C + t] + bs * k;
+                        ynext[c * X + e] = B.m[c * C + t] + cnext * dt * k;
+                    }
+                } else {
+                    double v[3];
+                    for (int c = 0; c < 3; ++c) {
+                        const double k = -c1[c] - alpha * c2[c];
+                        v[c] = B.m[c * C + t] + dt * (B.acc[c * C + t] + bs * k);
+                    }
+                    const double nr = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+                    for (int c = 0; c < 3; ++c) {
+                        B.m[c * C + t] = v[c] / nr;
+                        ynext[c * X + e] = v[c] / nr;
+                    }
+                }
+            }
+            if (last_level) break;
+            __syncthreads();
+            // the three ghost layers of the new stage input
+            for (long g = tid; g < 18 * nn; g += nth) {
+                long gi, wi;
+                int q0, q1, q2;
+                ghost_point(B, g, gi, wi, q0, q1, q2);
+                for (int c = 0; c < 3; ++c)
+                    ynext[c * X + gi] = dirichlet ? B.G[c * X + gi] : ynext[c * X + wi] + B.G[c * X + gi];
+            }
+            __syncthreads();
+            double *tmp = ycur;
+            ycur = ynext;
+            ynext = tmp;
+        }
+    }
+
+    // the box's average: fixed-order block reduction into its partial-sum slot
+    __syncthreads();
+    for (int half = kThreads3d / 2; half > 0; half >>= 1) {
+        if (tid < half)
+            for (int c = 0; c < 9; ++c) s_red[tid][c] = s_red[tid][c] + s_red[tid + half][c];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        double *dst = A.partials + P.part_offset * kMaxQ;
+        int bad = 0;
+        for (int q = 0; q < kMaxQ; ++q) {
+            const double v = (q < 9) ? s_red[0][q] : 0.0;
+            dst[q] = v;
+            if (!__builtin_isfinite(v)) bad = 1;
+        }
+        A.wave_status[P.part_offset] = bad;
+    }
+    if (A.out_field) {
+        for (long t = tid; t < C; t += nth)
+            for (int c = 0; c < 3; ++c) A.out_field[P.mfinal_offset + c * C + t] = B.m[c * C + t];
     }
 }
 
@@ -339,6 +492,7 @@ __global__ void __launch_bounds__(NT, 1) k_micro3d(Micro3dArgs A) {
     __shared__ double s_fc[LLHMM_MAX_TERMS * 3 * TR];
     const int box = A.box_ids[blockIdx.x];
     const BoxPlan P = A.plans[box];
+    if (P.order != 2) return;   // fourth-order boxes: k_micro3d_o4
     const int n = P.n, tid = threadIdx.x, nn = n * n;
     Box3 B(A.work + P.tab_offset, n);
     const long C = B.C, X = B.X;
@@ -573,18 +727,21 @@ hipError_t launch_micro3d(const Micro3dArgs &a, hipStream_t s) {
     if (a.mode == 1) {
         hipLaunchKernelGGL(k_field3d, dim3(a.nbox), dim3(kThreads3d), 0, s, a);
     } else {
-        // threads per block: the columns of the largest box, rounded up (larger
-        // boxes take several passes over their columns)
-        const int cols = a.nmax * a.nmax;
-        if (cols <= 256) launch_cols<256>(a, s);
-        else if (cols <= 512) launch_cols<512>(a, s);
-        else launch_cols<1024>(a, s);
+        // second-order boxes: threads per block = the columns of the largest box,
+        // rounded up (larger boxes take several passes over their columns)
+        if (a.orders & 1) {
+            const int cols = a.nmax * a.nmax;
+            if (cols <= 256) launch_cols<256>(a, s);
+            else if (cols <= 512) launch_cols<512>(a, s);
+            else launch_cols<1024>(a, s);
+        }
+        if (a.orders & 2) hipLaunchKernelGGL(k_micro3d_o4, dim3(a.nbox), dim3(kThreads3d), 0, s, a);
     }
     return hipGetLastError();
 }
 
-int64_t work3d_size(int n) {
-    const int64_t E = n + 2;
+int64_t work3d_size(int n, int order) {
+    const int64_t E = n + ((order == 4) ? 6 : 2);
     return 12 * E * E * E + 6 * (int64_t)n * n * n;
 }
 

@@ -1,4 +1,4 @@
-"""d = 3 micro boxes on the GPU (FP64, second-order stencil) against the FP64
+"""d = 3 micro boxes on the GPU (FP64, second- and fourth-order stencils) against the FP64
 oracle: upscaled field, torque and flux, final states and one field evaluation,
 both boundary conditions, HeunP and RK4P, explicit and Q_[4] macro data (on
 and off the node), a mixed 2-D / 3-D batch, graph replay, and the
@@ -31,12 +31,12 @@ def ctx():
     return L.llhmm_create(0)
 
 
-def boxes3(ns, bc, q, integ, seed, n_steps=0, eta=0.3):
+def boxes3(ns, bc, q, integ, seed, n_steps=0, eta=0.3, order=2):
     eps = 1.0 / 100.0
     rng = np.random.default_rng(seed)
     out = []
     for n in ns:
-        out.append(inputs.make_box(dim=3, n=n, order=2, bc=bc, quantity=q, integrator=integ,
+        out.append(inputs.make_box(dim=3, n=n, order=order, bc=bc, quantity=q, integrator=integ,
                                    n_steps=n_steps, eps=eps, alpha=float(rng.uniform(0.05, 1.2)),
                                    mu=(2.5 if bc else 3.0) * eps, mu_box=3 * eps,
                                    eta=eta * eps ** 2, a_max=1.5,
@@ -119,6 +119,29 @@ def test_3d_parity(ctx, bc, q, integ):
     check(ctx, wl)
 
 
+@pytest.mark.parametrize("bc", [0, 1])
+@pytest.mark.parametrize("q", [inputs.Q_FIELD, inputs.Q_TORQUE, inputs.Q_FLUX])
+@pytest.mark.parametrize("integ", [1, 2])
+def test_3d_parity_fourth_order(ctx, bc, q, integ):
+    """The fourth-order stencil (three ghost layers, staggered (27, -1) fluxes)
+    on boxes of several sizes, every BC, quantity and integrator."""
+    print(f"3-D fourth-order parity bc={bc} q={q} integ={integ}", flush=True)
+    wl = workload(boxes3((8, 12, 20), bc, q, integ, seed=131 + bc + 2 * q + 4 * integ, n_steps=8,
+                         order=4))
+    check(ctx, wl)
+
+
+def test_3d_both_orders_one_batch(ctx):
+    """Second- and fourth-order boxes in one batch (two time-stepping kernels on
+    the same work buffer, each skipping the other's boxes)."""
+    print("3-D both stencil orders in one batch", flush=True)
+    boxes = (boxes3((12,), 0, inputs.Q_FIELD, 2, seed=141, n_steps=6)
+             + boxes3((10,), 1, inputs.Q_FLUX, 2, seed=142, n_steps=5, order=4)
+             + boxes3((16,), 1, inputs.Q_TORQUE, 1, seed=143, n_steps=7)
+             + boxes3((8,), 0, inputs.Q_FIELD, 1, seed=144, n_steps=6, order=4))
+    check(ctx, workload(boxes))
+
+
 @pytest.mark.parametrize("ns", [(8,), (8, 16), (20, 32), (40,), (64,)])
 def test_3d_kernel_paths(ctx, ns):
     """Each launch shape of the time loop: 256, 512 and 1024 threads per block
@@ -199,8 +222,9 @@ def test_3d_stability_rule_and_laminate(ctx):
     check(ctx, wl, want_state=False)
 
 
-def test_3d_field_evaluation(ctx):
-    wl = workload(boxes3((12, 16), 0, 0, 2, seed=9, n_steps=4))
+@pytest.mark.parametrize("order", [2, 4])
+def test_3d_field_evaluation(ctx, order):
+    wl = workload(boxes3((12, 16), 0, 0, 2, seed=9, n_steps=4, order=order))
     p = Prepared(wl, precision=inputs.FP64, ctx=ctx)
     Hf = p.eval_field()
     for i, b in enumerate(wl.boxes):
@@ -262,12 +286,10 @@ def test_mixed_2d_3d_batch_and_graph(ctx):
     p.batch.close()
 
 
-@pytest.mark.parametrize("what", ["fp32", "order4"])
+@pytest.mark.parametrize("what", ["fp32"])
 def test_3d_unsupported_combinations(ctx, what):
     b = boxes3((16,), 0, 0, 2, seed=3, n_steps=4)[0]
-    if what == "order4":
-        b["order"] = 4
-    prec = inputs.FP32 if what == "fp32" else inputs.FP64
+    prec = inputs.FP32
     with pytest.raises(L.LlhmmError) as ei:
         L.llhmm_batch_create(ctx, [b], [L.to_coef(inputs.coef_product3(0.01))], prec)
     assert ei.value.code == L.E_NOTSUP
