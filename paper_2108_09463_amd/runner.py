@@ -15,7 +15,10 @@ from . import llhmm as L
 class Prepared:
     """A workload planned and uploaded once; `solve()` can be called repeatedly."""
 
-    def __init__(self, wl, precision=None, ctx=None, device=0, boxes=None, K=None):
+    def __init__(self, wl, precision=None, ctx=None, device=0, boxes=None, K=None, coef_samples=None):
+        """coef_samples: optional FP64 face values of a sampled coefficient, packed
+        as llhmm_micro_batch's coef_dev (each box's block at its coef_offset);
+        the workload's coefficients are then passed as sampled."""
         import torch
         self.torch = torch
         self.wl = wl
@@ -34,7 +37,10 @@ class Prepared:
             self.macro = L.macro_dict(wl.macro, dim=boxes[0]["dim"])
             self.M_macro = torch.from_numpy(np.ascontiguousarray(wl.macro["M"], dtype=np.float64)
                                             .reshape(3, -1)).to(self.dev)
-        coefs = [L.to_coef(c) for c in wl.coefs]
+        sampled = coef_samples is not None
+        coefs = [L.to_coef(c, sampled=sampled) for c in wl.coefs]
+        self.coef_dev = (torch.from_numpy(np.ascontiguousarray(coef_samples, dtype=np.float64)).to(self.dev)
+                         if sampled else None)
         prec = wl.precision if precision is None else precision
         self.precision = prec
         self.batch = L.llhmm_batch_create(self.ctx, boxes, coefs, prec,
@@ -44,7 +50,7 @@ class Prepared:
         self.status = torch.zeros(len(boxes), dtype=torch.int32, device=self.dev)
 
     def launch(self, m_final=None, stream=None):
-        L.llhmm_micro_batch(self.ctx, self.batch, self.m_init, self.macro, self.M_macro, None,
+        L.llhmm_micro_batch(self.ctx, self.batch, self.m_init, self.macro, self.M_macro, self.coef_dev,
                             m_final, stream)
         L.llhmm_upscale(self.ctx, self.batch, self.H, self.ld, self.status, False, stream)
 
@@ -52,10 +58,10 @@ class Prepared:
         """The same solve + upscale as one captured HIP graph (replayed while the
         arguments stay the same)."""
         L.llhmm_batch_run_graph(self.ctx, self.batch, self.H, self.ld, self.status, self.m_init,
-                                self.macro, self.M_macro, None, None, stream)
+                                self.macro, self.M_macro, self.coef_dev, None, stream)
 
     def tune(self, reps=2):
-        L.llhmm_batch_tune(self.ctx, self.batch, self.m_init, self.macro, self.M_macro, None, reps)
+        L.llhmm_batch_tune(self.ctx, self.batch, self.m_init, self.macro, self.M_macro, self.coef_dev, reps)
         return L.llhmm_batch_band_steps(self.batch)
 
     def solve(self, want_state=False):
@@ -77,7 +83,7 @@ class Prepared:
         d = self.batch.dim_max
         Hf = torch.zeros(len(self.boxes) * 3 * self.batch.n_max ** d, dtype=torch.float64,
                          device=self.dev)
-        L.llhmm_eval_field(self.ctx, self.batch, Hf, self.m_init, self.macro, self.M_macro)
+        L.llhmm_eval_field(self.ctx, self.batch, Hf, self.m_init, self.macro, self.M_macro, self.coef_dev)
         torch.cuda.synchronize(self.dev)
         return Hf.cpu().numpy()
 
