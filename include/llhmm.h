@@ -92,11 +92,11 @@ typedef struct {
 } llhmm_coef;
 
 /* One micro problem (eq. (micro)).  d = 3 boxes (the problem allows d <= 3,
- * Section 2.1) are supported in FP64 with a closed-form coefficient, with the
- * second- or fourth-order stencil, for the field, torque and flux quantities
- * (flux: nine outputs, [axis][component]); d = 3 in FP32 or with a sampled
- * coefficient returns LLHMM_E_NOTSUP.  The serving loop takes d = 3
- * second-order field and torque requests. */
+ * Section 2.1) are supported in FP64 with a closed-form or sampled
+ * coefficient, the second- or fourth-order stencil, and the field, torque and
+ * flux quantities (flux: nine outputs, [axis][component]); d = 3 in FP32
+ * returns LLHMM_E_NOTSUP.  The serving loop takes d = 3 second-order field
+ * and torque requests with a closed-form coefficient. */
 typedef struct {
     int32_t dim;          /* d in {1, 2, 3} */
     int32_t n;            /* grid points per axis (square / cubic boxes), >= 8 */

@@ -399,6 +399,7 @@ struct llhmm_batch {
     int nbox3 = 0, nmax3 = 0;
     int nq3 = 3;                                  // largest number of outputs of a d = 3 box
     int orders3 = 0;                              // stencil orders of the d = 3 boxes (bit 0: 2, bit 1: 4)
+    int sampled3 = 0;                             // a d = 3 box's coefficient is sampled
     double cost3 = 0.0;
     double *work3d = nullptr;                     // their work areas (work3d_size doubles each)
     CoefDev *coefs = nullptr;
@@ -640,9 +641,9 @@ static llhmm_status batch_create_impl(llhmm_ctx *ctx, const llhmm_box *boxes, in
             delete b;
             return st;
         }
-        if (bx.dim == 3 && (precision != LLHMM_FP64 || coefs[bx.coef_index].sampled)) {
+        if (bx.dim == 3 && precision != LLHMM_FP64) {
             delete b;
-            return fail(LLHMM_E_NOTSUP, "box %d: d = 3 boxes need FP64 and a closed-form coefficient", i);
+            return fail(LLHMM_E_NOTSUP, "box %d: d = 3 boxes need FP64", i);
         }
         auto it = reg.find(TileKey{precision, bx.dim, bx.n, bx.order, bx.bc, bx.quantity});
         const BandTileInfo *bt = nullptr;
@@ -735,6 +736,7 @@ static llhmm_status batch_create_impl(llhmm_ctx *ctx, const llhmm_box *boxes, in
             P.tab_offset = work3_off;  // in the 3-D work buffer
             work3_off += work3d_size(bx.n, bx.order);
             b->orders3 |= (bx.order == 4) ? 2 : 1;
+            b->sampled3 |= P.coef_sampled;
             ids3.push_back(i);
             b->nmax3 = std::max(b->nmax3, bx.n);
             b->nq3 = std::max(b->nq3, P.nq);
@@ -993,6 +995,8 @@ static llhmm_status run_batch(llhmm_ctx *ctx, llhmm_batch *b, const double *m_in
         a3.nmax = b->nmax3;
         a3.nq_max = b->nq3;
         a3.orders = b->orders3;
+        a3.sampled = b->sampled3;
+        a3.coef_samples = pa.coef_samples;
         a3.mode = mode;
         a3.coefs = b->coefs;
         a3.m_init = m_init_dev;

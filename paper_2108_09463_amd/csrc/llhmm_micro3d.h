@@ -13,7 +13,8 @@ struct Micro3dArgs {
     const int32_t *box_ids;    // the batch's 3-D boxes
     int32_t nbox, mode;        // mode 0 solve, 1 evaluate H(m_init) only
     int32_t nmax, nq_max;      // largest n of the 3-D boxes; largest outputs per box (9: flux)
-    int32_t orders, pad_;      // stencil orders present: bit 0 second, bit 1 fourth
+    int32_t orders, sampled;   // stencil orders present (bit 0 second, bit 1 fourth); a box's coefficient is sampled
+    const double *coef_samples;   // sampled coefficients: face values [3][E6^3] per box at coef_offset, E6 = n + 6
     const CoefDev *coefs;
     const double *m_init;      // explicit initial data (extended grid, LLHMM_GHOST layers)
     const double *M_macro;     // macro field [3][n^3]

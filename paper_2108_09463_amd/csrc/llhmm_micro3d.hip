@@ -228,6 +228,12 @@ __global__ void __launch_bounds__(kThreads3d) k_setup3d(Micro3dArgs A) {
         const long e = t % B.X;
         const int i0 = (int)(e % E) - gw, i1 = (int)((e / E) % E) - gw, i2 = (int)(e / ((long)E * E)) - gw;
         double x0 = P.cx + xi_of(P, i0), x1 = P.cy + xi_of(P, i1), x2 = P.cz + xi_of(P, i2);
+        if (P.coef_sampled) {   // the caller's face values, [axis][E6^3] on the grid with 3 ghost layers
+            const int E6 = n + 2 * kGhost;
+            const long si = (long)ax * E6 * E6 * E6 + ((long)(i2 + kGhost) * E6 + (i1 + kGhost)) * E6 + (i0 + kGhost);
+            B.A[t] = A.coef_samples[P.coef_offset + si] * sc;
+            continue;
+        }
         if (ax == 0) x0 = x0 + 0.5 * P.dx;
         else if (ax == 1) x1 = x1 + 0.5 * P.dx;
         else x2 = x2 + 0.5 * P.dx;
@@ -472,10 +478,11 @@ __device__ __forceinline__ void sto_nt(double *base, uint32_t off, double v) {
 //    in registers from one point to the next; the x1 / x2 neighbours come from
 //    the caches, where the waves holding the neighbouring columns brought
 //    them a moment earlier;
-//  * the face coefficients a^eps / dx^2 of the (closed-form) coefficient are
+//  * the face coefficients a^eps / dx^2 of a closed-form coefficient are
 //    formed from per-axis factor tables in LDS, bit for bit the values the
 //    set-up kernel stores, which takes a sixth of the streamed bytes off
-//    every stage;
+//    every stage (STORED, for a batch with a sampled coefficient: the stored
+//    faces are read with the point's other operands);
 //  * no wave waits for another inside a stage (stage inputs are read-only
 //    there and every other array is touched only at the thread's own
 //    points), and all loads of a point are issued together;
@@ -483,13 +490,14 @@ __device__ __forceinline__ void sto_nt(double *base, uint32_t off, double v) {
 //    input that wrap to it (periodic image plus offset, or the Dirichlet
 //    datum), their ghost data loaded with the point's other operands, so a
 //    stage ends with a single barrier.
-template <int NT, int NQ>
+template <int NT, int NQ, bool STORED>
 __global__ void __launch_bounds__(NT, 1) k_micro3d(Micro3dArgs A) {
     __shared__ double s_red[NT][NQ];
-    // factor tables [term][axis][TR]: points 0..n-1, faces -1/2..n-1/2 (index f + 1)
+    // factor tables [term][axis][TR]: points 0..n-1, faces -1/2..n-1/2 (index f + 1);
+    // STORED (a sampled coefficient in the batch): the faces the set-up stored
     constexpr int TR = kMaxN3 + 1;
-    __shared__ double s_pt[LLHMM_MAX_TERMS * 3 * TR];
-    __shared__ double s_fc[LLHMM_MAX_TERMS * 3 * TR];
+    __shared__ double s_pt[STORED ? 1 : LLHMM_MAX_TERMS * 3 * TR];
+    __shared__ double s_fc[STORED ? 1 : LLHMM_MAX_TERMS * 3 * TR];
     const int box = A.box_ids[blockIdx.x];
     const BoxPlan P = A.plans[box];
     if (P.order != 2) return;   // fourth-order boxes: k_micro3d_o4
@@ -507,7 +515,7 @@ __global__ void __launch_bounds__(NT, 1) k_micro3d(Micro3dArgs A) {
     const double sc = 1.0 / (P.dx * P.dx);
     const double c0 = cf.c0;
     const int nterms = cf.n_terms;
-    {
+    if (!STORED) {
         const double cen[3] = {P.cx, P.cy, P.cz};
         for (int k = tid; k < nterms * 3 * (2 * n + 1); k += NT) {
             const int t = k / (3 * (2 * n + 1)), r = k % (3 * (2 * n + 1));
@@ -523,6 +531,7 @@ __global__ void __launch_bounds__(NT, 1) k_micro3d(Micro3dArgs A) {
         __syncthreads();
     }
     constexpr int TS = 3 * TR;   // term stride of both tables
+    const double *Ab[3] = {B.A, B.A + X, B.A + 2 * X};
     const double *Gb[3] = {B.G, B.G + X, B.G + 2 * X};
     double *mb[3] = {B.m, B.m + C, B.m + 2 * C};
     double *ab[3] = {B.acc, B.acc + C, B.acc + 2 * C};
@@ -563,7 +572,7 @@ __global__ void __launch_bounds__(NT, 1) k_micro3d(Micro3dArgs A) {
                 // factor table rows of this column (term 0)
                 const double *p0 = s_pt + i0, *p1 = s_pt + TR + i1, *p2 = s_pt + 2 * TR;
                 const double *f0 = s_fc + i0 + 1, *f1 = s_fc + TR + i1 + 1, *f2 = s_fc + 2 * TR;
-                double aw2 = face_from_factors(c0, nterms, p0, p1, f2, TS, sc);
+                double aw2 = STORED ? ldo(Ab[2], eb) : face_from_factors(c0, nterms, p0, p1, f2, TS, sc);
                 const double wxy = w[i0] * w[i1];
                 // flux: the face weight along the flux axis, point weights along the
                 // others (axis 0 first), as products over the axes
@@ -597,13 +606,21 @@ __global__ void __launch_bounds__(NT, 1) k_micro3d(Micro3dArgs A) {
                     }
                     const double wz = w[i2];
                     const double wfz = (NQ == 9) ? w[n + i2] : 0.0;
+                    double sae0 = 0.0, saw0 = 0.0, sae1 = 0.0, saw1 = 0.0, sae2 = 0.0;
+                    if (STORED) {
+                        sae0 = ldo(Ab[0], eb);
+                        saw0 = ldo(Ab[0], eb - 8);
+                        sae1 = ldo(Ab[1], eb);
+                        saw1 = ldo(Ab[1], eb - s1b);
+                        sae2 = ldo(Ab[2], eb);
+                    }
                     // keep the scheduler from splitting the loads into dependent groups
                     __builtin_amdgcn_sched_barrier(0);
-                    const double ae0 = face_from_factors(c0, nterms, f0, p1, p2 + i2, TS, sc);
-                    const double aw0 = face_from_factors(c0, nterms, f0 - 1, p1, p2 + i2, TS, sc);
-                    const double ae1 = face_from_factors(c0, nterms, p0, f1, p2 + i2, TS, sc);
-                    const double aw1 = face_from_factors(c0, nterms, p0, f1 - 1, p2 + i2, TS, sc);
-                    const double ae2 = face_from_factors(c0, nterms, p0, p1, f2 + i2 + 1, TS, sc);
+                    const double ae0 = STORED ? sae0 : face_from_factors(c0, nterms, f0, p1, p2 + i2, TS, sc);
+                    const double aw0 = STORED ? saw0 : face_from_factors(c0, nterms, f0 - 1, p1, p2 + i2, TS, sc);
+                    const double ae1 = STORED ? sae1 : face_from_factors(c0, nterms, p0, f1, p2 + i2, TS, sc);
+                    const double aw1 = STORED ? saw1 : face_from_factors(c0, nterms, p0, f1 - 1, p2 + i2, TS, sc);
+                    const double ae2 = STORED ? sae2 : face_from_factors(c0, nterms, p0, p1, f2 + i2 + 1, TS, sc);
                     double H[3];
                     for (int c = 0; c < 3; ++c) {
                         const double v = yc[c];
@@ -708,12 +725,18 @@ __global__ void __launch_bounds__(NT, 1) k_micro3d(Micro3dArgs A) {
     }
 }
 
+template <int NT, bool STORED>
+static void launch_cols_faces(const Micro3dArgs &a, hipStream_t s) {
+    if (a.nq_max > 3)   // a flux box in the batch: nine sums per thread
+        hipLaunchKernelGGL((k_micro3d<NT, 9, STORED>), dim3(a.nbox), dim3(NT), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_micro3d<NT, 3, STORED>), dim3(a.nbox), dim3(NT), 0, s, a);
+}
+
 template <int NT>
 static void launch_cols(const Micro3dArgs &a, hipStream_t s) {
-    if (a.nq_max > 3)   // a flux box in the batch: nine sums per thread
-        hipLaunchKernelGGL((k_micro3d<NT, 9>), dim3(a.nbox), dim3(NT), 0, s, a);
-    else
-        hipLaunchKernelGGL((k_micro3d<NT, 3>), dim3(a.nbox), dim3(NT), 0, s, a);
+    if (a.sampled) launch_cols_faces<NT, true>(a, s);   // a sampled coefficient: the stored faces
+    else launch_cols_faces<NT, false>(a, s);
 }
 
 hipError_t launch_setup3d(const Micro3dArgs &a, hipStream_t s) {

@@ -60,3 +60,39 @@ def test_sampled_coefficient_parity(ctx, dim, sizes, prec):
     print("sampled", dim, prec, err, tol, flush=True)
     assert np.all(err <= tol)
     p.batch.close()
+
+
+def test_sampled_coefficient_3d(ctx):
+    """d = 3 boxes with sampled faces (the time loop then reads the stored faces
+    instead of forming them): second and fourth order, both BCs, field and
+    flux, in one batch."""
+    print("sampled coefficient d=3", flush=True)
+    eps = 0.01
+    coef = inputs.coef_product3(eps)
+    rng = np.random.default_rng(5)
+    boxes, blocks, off = [], [], 0
+    for i, (n, order, q) in enumerate([(12, 2, inputs.Q_FIELD), (16, 2, inputs.Q_FLUX),
+                                       (10, 4, inputs.Q_FIELD), (12, 4, inputs.Q_FLUX)]):
+        b = inputs.make_box(dim=3, n=n, order=order, bc=i % 2, quantity=q, integrator=2, n_steps=0,
+                            eps=eps, alpha=float(rng.uniform(0.05, 0.5)), mu=(2.5 if i % 2 else 3.0) * eps,
+                            mu_box=3 * eps, eta=0.1 * eps ** 2, a_max=1.5,
+                            center=tuple(float(v) for v in rng.random(3)), macro_index=(0, 0, 0))
+        A, _ = micro.face_coefficients(b, coef)
+        b["coef_offset"] = off
+        blocks.append(A.reshape(-1))
+        off += A.size
+        boxes.append(b)
+    wl = inputs.Workload("sampled3", 3, boxes, [coef], init=inputs.InitSmooth3D(), precision=inputs.FP64)
+    p = Prepared(wl, precision=inputs.FP64, ctx=ctx, coef_samples=np.concatenate(blocks))
+    out = p.solve()
+    assert (out["status"] == 0).all()
+    ora = run_oracle(wl)
+    width = max(len(r["out"]) for r in ora)
+    Ho = np.stack([np.pad(r["out"], (0, width - len(r["out"]))) for r in ora])
+    err = rel_err(out["H"][:, :width], Ho)
+    fma = run_oracle(wl, variant="fma")
+    Hf = np.stack([np.pad(r["out"], (0, width - len(r["out"]))) for r in fma])
+    tol = np.maximum(TOL[inputs.FP64], 4.0 * rel_err(Hf, Ho))
+    print("sampled 3-D", err, tol, flush=True)
+    assert np.all(err <= tol)
+    p.batch.close()
