@@ -426,6 +426,14 @@ struct MicroLane {
                         for (int c = 0; c < 3; ++c) sq[(D == 2 ? 3 : 0) + c] = fma(w2, (double)Fy_north[c], sq[(D == 2 ? 3 : 0) + c]);
                     }
                 }
+                if constexpr (sizeof(T) == 8 && AVG >= AVG_FIELD && AVG <= AVG_FLUX) {
+                    // FP64: the averages are finished point by point.  Left free, the
+                    // scheduler moves the serial FMA chain of each sum to the end of
+                    // the stage and keeps every point's field live until then, which
+                    // spills to scratch in the 64-point-wide boxes.
+#pragma unroll
+                    for (int q = 0; q < NQ; ++q) asm volatile("" : "+v"(sq[q]));
+                }
                 if (!LAST) {
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
