@@ -2,7 +2,7 @@
 GPU HMM loop against the homogenized reference M0, per micro setup and macro
 grid, beside the E_avg = 0 loop and the naive average coefficient.
 
-  python tests/hmm_study.py --setups s1 s2 --dX 12 24 --out gpurun_out/hmm.json
+  python tests/hmm_study.py --setups s1 s2 --dX 12 24 --out hmm.json
 """
 import argparse
 import json

@@ -10,7 +10,7 @@ period corner, so the discrete micro operator has the discrete homogenized
 matrix of oracle.cell at P points per period; E_avg is measured against that
 matrix (the continuous A^H differs by the micro discretization error).
 
-  python tests/micro_sweep.py --out gpurun_out/sweep.json
+  python tests/micro_sweep.py --out sweep.json
 """
 from __future__ import annotations
 
