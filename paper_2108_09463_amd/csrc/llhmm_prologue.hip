@@ -128,6 +128,9 @@ __device__ void minit_at(const PrologueArgs &A, const BoxPlan &P, const InitTabl
             for (int c = 0; c < 3; ++c) p[c] = p[c] + T.Mloc[c * 5 + l0] * L0[l0];
     } else {
         const double *L1 = T.Lb1 + (i1 + kGhost) * 5;
+        // kept rolled: unrolled, the 75 macro values and the basis stay live at
+        // once and the kernel needs 300-400 VGPRs (one block per CU instead of three)
+#pragma unroll 1
         for (int l1 = 0; l1 < 5; ++l1) {
             double q[3] = {0.0, 0.0, 0.0};
             for (int l0 = 0; l0 < 5; ++l0)  // along x1 first
