@@ -286,7 +286,10 @@ WORKLOADS = {
                     "eta=eps^2, seeded phases, flux average"),
     "three_d_batch": ("three_d_batch: 512 3-D boxes of 32^3, eps=1/200, mu=mu'=3eps, eta=eps^2, "
                       "alpha=0.1 RK4P, periodic m - m_init, a = 1 + 0.5 sin sin sin, FP64, field average"),
+    "three_d_batch_o4": ("three_d_batch_o4: the 512 3-D boxes of 32^3 of three_d_batch with the "
+                         "fourth-order conservative stencil, FP64, field average"),
 }
+THREE_D = ("three_d_batch", "three_d_batch_o4")
 
 # d = 3 kernel: bytes streamed through HBM per cell and stage (FP64): stage input
 # read 24, face coefficients 24 (three unique faces per cell), state m read 24,
@@ -294,7 +297,7 @@ WORKLOADS = {
 # Boxes of the cpu_baseline sample per workload, sized for about 10-30 s on 16
 # host threads (all 512 boxes of the d = 3 batch take about 41 s, all 1024 of
 # the 2-D batch about 14 s).
-DEFAULT_CPU_SAMPLE = {"three_d_batch": 256}
+DEFAULT_CPU_SAMPLE = {"three_d_batch": 256, "three_d_batch_o4": 128}
 
 # Bytes per cell that one stage of the d = 3 time loop must move through HBM:
 # read the stage input, the state and the running sum, write the running sum
@@ -302,6 +305,8 @@ DEFAULT_CPU_SAMPLE = {"three_d_batch": 256}
 # first stage of a step has no running sum to read.
 BYTES_PER_CELL_STAGE_3D = 120.0
 BYTES_FIRST_STAGE_SAVING_3D = 24.0
+# The fourth-order kernel also reads the three stored faces of each cell (24 bytes).
+BYTES_FACES_3D_O4 = 24.0
 
 
 def hbm_roofline_3d(boxes, kernel_ms):
@@ -311,12 +316,15 @@ def hbm_roofline_3d(boxes, kernel_ms):
     nbytes = 0.0
     for b, m, ig in zip(boxes, M, integ):
         stages = 4 if int(ig) == 2 else 2
-        nbytes += int(m) * b["n"] ** 3 * (stages * BYTES_PER_CELL_STAGE_3D - BYTES_FIRST_STAGE_SAVING_3D)
+        per_stage = BYTES_PER_CELL_STAGE_3D + (BYTES_FACES_3D_O4 if b["order"] == 4 else 0.0)
+        nbytes += int(m) * b["n"] ** 3 * (stages * per_stage - BYTES_FIRST_STAGE_SAVING_3D)
+    o4 = all(b["order"] == 4 for b in boxes)
     achieved = nbytes / (kernel_ms * 1e-3)
     return {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
-            "frac": achieved / PEAK_HBM, "traffic": measured_traffic("3d"), "kernel": "k_micro3d",
+            "frac": achieved / PEAK_HBM, "traffic": None if o4 else measured_traffic("3d"),
+            "kernel": "k_micro3d_o4" if o4 else "k_micro3d",
             "kernel_ms": kernel_ms,
-            "bytes_per_cell_stage": BYTES_PER_CELL_STAGE_3D,
+            "bytes_per_cell_stage": BYTES_PER_CELL_STAGE_3D + (BYTES_FACES_3D_O4 if o4 else 0.0),
             "bytes_per_launch": nbytes}
 
 
@@ -368,10 +376,10 @@ def main():
     precs = {"fp32": inputs.FP32, "fp64": inputs.FP64}
     if args.precision != "both":
         precs = {args.precision: precs[args.precision]}
-    if args.workload == "three_d_batch":
+    if args.workload in THREE_D:
         precs = {"fp64": inputs.FP64}          # d = 3 boxes are built in FP64
     res = {name: measure(wl, prec, args.steps, args.warmup) for name, prec in precs.items()}
-    if args.workload == "three_d_batch":
+    if args.workload in THREE_D:
         res["fp64"]["roofline"] = hbm_roofline_3d(wl.boxes, res["fp64"]["kernel_ms"])
     gpu_H = {k: v["H"] for k, v in res.items()}
     cpu = None

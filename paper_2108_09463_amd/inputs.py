@@ -28,6 +28,7 @@ external data set):
 * ``three_d_batch``  512 boxes of 32^3 (d = 3), mu = mu' = 3 eps, eps = 1/200,
   a = 1 + 0.5 sin(2pi x1/eps) sin(2pi x2/eps) sin(2pi x3/eps), alpha = 0.1,
   eta = eps^2, smooth 3-D initial data at seeded centres, FP64.
+* ``three_d_batch_o4``  the same boxes with the fourth-order stencil.
 * HMM loop setups (Section 4.5, fig:hmm_err_ex3): EX2 on the periodic unit
   square, alpha = 0.01, T = 0.1, alpha_micro = 1.2, mu = 3.9 eps, Dirichlet
   micro boxes, averaging kernels p = 3, q = 7.  eps = 1/384 (the paper: 1/400)
@@ -321,18 +322,25 @@ def two_d_batch(n_macro=32, seed=2, precision=FP64, order=2, n=64, integrator=IN
                     precision=precision)
 
 
-def three_d_batch(nboxes=512, seed=6, n=32, precision=FP64):
+def three_d_batch(nboxes=512, seed=6, n=32, precision=FP64, order=2):
     """512 boxes of 32^3 (d = 3): eps = 1/200, mu = mu' = 3 eps, eta = eps^2,
     alpha = 0.1 (RK4P), periodic m - m_init, a = 1 + 0.5 prod_k sin(2 pi x_k / eps),
     explicit smooth 3-D initial data at seeded centres; field average."""
     eps = 1.0 / 200.0
     centres = np.random.default_rng(seed).random((nboxes, 3))
-    boxes = [make_box(dim=3, n=n, order=2, quantity=Q_FIELD, eps=eps, alpha=0.1, mu=3 * eps,
+    boxes = [make_box(dim=3, n=n, order=order, quantity=Q_FIELD, eps=eps, alpha=0.1, mu=3 * eps,
                       mu_box=3 * eps, eta=eps ** 2, a_max=1.5,
                       center=tuple(float(v) for v in centres[b]), macro_index=(0, 0, 0))
              for b in range(nboxes)]
     return Workload("three_d_batch", 3, boxes, [coef_product3(eps)], init=InitSmooth3D(),
                     precision=precision)
+
+
+def three_d_batch_o4(nboxes=512, seed=6, n=32, precision=FP64):
+    """The d = 3 batch above with the fourth-order conservative stencil."""
+    wl = three_d_batch(nboxes, seed, n, precision, order=4)
+    wl.name = "three_d_batch_o4"
+    return wl
 
 
 UNEVEN_SIZES = (32, 48, 64, 96, 128)

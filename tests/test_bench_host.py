@@ -44,6 +44,25 @@ def test_three_d_roofline_bytes():
     assert r["achieved"] == pytest.approx(want / 2.0e-3 / 1e9, rel=1e-12)
 
 
+def test_three_d_roofline_bytes_fourth_order():
+    """Fourth order also reads the three stored faces of each cell: 144 bytes
+    per stage, less 24 at a step's first stage (RK4P 552 per step); the PMC
+    traffic of the second-order kernel is not reported for it."""
+    eps = 0.01
+    boxes = [inputs.make_box(dim=3, n=n, order=4, bc=0, quantity=inputs.Q_FIELD, integrator=2,
+                             n_steps=4 + n, eps=eps, alpha=0.3, mu=3 * eps, mu_box=3 * eps,
+                             eta=0.3 * eps ** 2, a_max=1.5, center=(0.1, 0.2, 0.3), macro_index=(0, 0, 0))
+             for n in (8, 16)]
+    M, _, ig = L.llhmm_plan(boxes)
+    assert all(int(g) == 2 for g in ig)
+    want = sum(int(m) * b["n"] ** 3 * (4 * 144 - 24) for b, m in zip(boxes, M))
+    r = bench.hbm_roofline_3d(boxes, kernel_ms=4.0)
+    assert r["bytes_per_launch"] == pytest.approx(want, rel=0, abs=0.5)
+    assert r["bytes_per_cell_stage"] == 144.0
+    assert r["kernel"] == "k_micro3d_o4" and r["traffic"] is None
+    assert r["frac"] == pytest.approx(want / 4.0e-3 / 8.0e12, rel=1e-12)
+
+
 def test_traffic_reported_only_for_the_measured_sources(tmp_path, monkeypatch):
     src = tmp_path / "kernel.hip"
     src.write_text("// kernel v1\n")
