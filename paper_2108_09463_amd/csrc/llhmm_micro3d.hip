@@ -336,11 +336,11 @@ __global__ void __launch_bounds__(kThreads3d) k_field3d(Micro3dArgs A) {
     }
 }
 
-// The time loop of fourth-order boxes (mode 0), point by point: each stage
-// reads the stage input with three ghost layers, writes the next one, and the
-// ghost layers of the new input are filled between two block barriers.  The
-// wider stencil (13 points, four staggered fluxes per axis) is read through
-// the caches; this path favours simplicity over speed.
+// The time loop of fourth-order boxes (mode 0): each stage reads the stage
+// input with three ghost layers and writes the next one, walking x3 columns
+// (x3 values and face fluxes roll in registers, the x1/x2 parts of the
+// 13-point stencil come through the caches); the ghost layers of the new
+// input are filled between two block barriers.
 __global__ void __launch_bounds__(kThreads3d) k_micro3d_o4(Micro3dArgs A) {
     __shared__ double s_red[kThreads3d][9];
     const int box = A.box_ids[blockIdx.x];
@@ -363,54 +363,90 @@ __global__ void __launch_bounds__(kThreads3d) k_micro3d_o4(Micro3dArgs A) {
         for (int s = 0; s < nst; ++s) {
             const double bs = rk4 ? ((s == 0 || s == 3) ? 1.0 / 6.0 : 1.0 / 3.0) : 0.5;
             const double cnext = rk4 ? ((s < 2) ? 0.5 : 1.0) : 1.0;
-            for (long t = tid; t < C; t += nth) {
-                const int i0 = (int)(t % n), i1 = (int)((t / n) % n), i2 = (int)(t / nn);
-                const long e = B.ext(i0, i1, i2);
-                double H[3], Fe[3][3];
+            // Column walk: a thread owns the x3 columns (i0, i1) = col and walks
+            // them upwards.  The stage input at planes i2 .. i2+3 and the fluxes on
+            // the x3 faces i2-2 .. i2 (face j between planes j and j+1) roll along
+            // in registers, so each point loads one new value and one new face
+            // along x3; the x1/x2 stencils are read through the caches.
+            const double *A2 = B.A + 2 * X;
+            const long s3 = B.stride(2);
+            for (long col = tid; col < nn; col += nth) {
+                const int i0 = (int)(col % n), i1 = (int)(col / n);
+                const long e0 = B.ext(i0, i1, 0);
+                double yw[3][4], F3[3][3];
                 for (int c = 0; c < 3; ++c) {
                     const double *yc = ycur + c * X;
-                    double h = 0.0;
-                    for (int ax = 0; ax < 3; ++ax) h += axis_o4(yc, B.A + ax * X, e, B.stride(ax), Fe[ax][c]);
-                    H[c] = h;
+                    const double ym3 = yc[e0 - 3 * s3], ym2 = yc[e0 - 2 * s3], ym1 = yc[e0 - s3];
+                    for (int k = 0; k < 4; ++k) yw[c][k] = yc[e0 + k * s3];
+                    F3[c][0] = A2[e0 - 2 * s3] * (27.0 * (ym1 - ym2) - (yw[c][0] - ym3));
+                    F3[c][1] = A2[e0 - s3] * (27.0 * (yw[c][0] - ym1) - (yw[c][1] - ym2));
+                    F3[c][2] = A2[e0] * (27.0 * (yw[c][1] - yw[c][0]) - (yw[c][2] - ym1));
                 }
-                const double yv[3] = {ycur[e], ycur[X + e], ycur[2 * X + e]};
-                double c1[3], c2[3];
-                c1[0] = yv[1] * H[2] - yv[2] * H[1];
-                c1[1] = yv[2] * H[0] - yv[0] * H[2];
-                c1[2] = yv[0] * H[1] - yv[1] * H[0];
-                if (s == 0) {
-                    if (flux) {
-                        // a grad m on the east face of each axis: the face weight along
-                        // that axis, point weights along the others
-                        const double wax[3] = {w[n + i0] * w[i1] * w[i2] * wn, w[i0] * w[n + i1] * w[i2] * wn,
-                                               w[i0] * w[i1] * w[n + i2] * wn};
-                        for (int ax = 0; ax < 3; ++ax)
-                            for (int c = 0; c < 3; ++c) s_red[tid][ax * 3 + c] += wax[ax] * Fe[ax][c];
+#pragma unroll 1
+                for (int i2 = 0; i2 < n; ++i2) {
+                    // opaque to the optimizer: otherwise every stencil address becomes
+                    // its own pointer stepped along x3, and the registers overflow
+                    long e = e0 + i2 * s3;
+                    asm volatile("" : "+v"(e));
+                    const long t = (long)i2 * nn + col;
+                    double H[3], Fe[3][3];
+                    for (int c = 0; c < 3; ++c) {
+                        const double *yc = ycur + c * X;
+                        double h = 0.0;
+                        for (int ax = 0; ax < 2; ++ax) h += axis_o4(yc, B.A + ax * X, e, B.stride(ax), Fe[ax][c]);
+                        const double f1 = A2[e + s3] * (27.0 * (yw[c][2] - yw[c][1]) - (yw[c][3] - yw[c][0]));
+                        h += 27.0 * (F3[c][2] - F3[c][1]) - (f1 - F3[c][0]);
+                        Fe[2][c] = F3[c][2];
+                        F3[c][0] = F3[c][1];
+                        F3[c][1] = F3[c][2];
+                        F3[c][2] = f1;
+                        H[c] = h;
+                    }
+                    const double yv[3] = {yw[0][0], yw[1][0], yw[2][0]};
+                    for (int c = 0; c < 3; ++c) {   // next point's window: planes i2+1 .. i2+4
+                        yw[c][0] = yw[c][1];
+                        yw[c][1] = yw[c][2];
+                        yw[c][2] = yw[c][3];
+                        yw[c][3] = (i2 + 1 < n) ? ycur[c * X + e + 4 * s3] : 0.0;
+                    }
+                    double c1[3], c2[3];
+                    c1[0] = yv[1] * H[2] - yv[2] * H[1];
+                    c1[1] = yv[2] * H[0] - yv[0] * H[2];
+                    c1[2] = yv[0] * H[1] - yv[1] * H[0];
+                    if (s == 0) {
+                        if (flux) {
+                            // a grad m on the east face of each axis: the face weight along
+                            // that axis, point weights along the others
+                            const double wax[3] = {w[n + i0] * w[i1] * w[i2] * wn, w[i0] * w[n + i1] * w[i2] * wn,
+                                                   w[i0] * w[i1] * w[n + i2] * wn};
+                            for (int ax = 0; ax < 3; ++ax)
+                                for (int c = 0; c < 3; ++c) s_red[tid][ax * 3 + c] += wax[ax] * Fe[ax][c];
+                        } else {
+                            const double wc = w[i0] * w[i1] * w[i2] * wn;
+                            for (int c = 0; c < 3; ++c) s_red[tid][c] += wc * (torque ? c1[c] : H[c]);
+                        }
+                    }
+                    if (last_level) continue;
+                    c2[0] = yv[1] * c1[2] - yv[2] * c1[1];
+                    c2[1] = yv[2] * c1[0] - yv[0] * c1[2];
+                    c2[2] = yv[0] * c1[1] - yv[1] * c1[0];
+                    if (s < nst - 1) {
+                        for (int c = 0; c < 3; ++c) {
+                            const double k = -c1[c] - alpha * c2[c];
+                            B.acc[c * C + t] = (s == 0) ? bs * k : B.acc[c * C + t] + bs * k;
+                            ynext[c * X + e] = B.m[c * C + t] + cnext * dt * k;
+                        }
                     } else {
-                        const double wc = w[i0] * w[i1] * w[i2] * wn;
-                        for (int c = 0; c < 3; ++c) s_red[tid][c] += wc * (torque ? c1[c] : H[c]);
-                    }
-                }
-                if (last_level) continue;
-                c2[0] = yv[1] * c1[2] - yv[2] * c1[1];
-                c2[1] = yv[2] * c1[0] - yv[0] * c1[2];
-                c2[2] = yv[0] * c1[1] - yv[1] * c1[0];
-                if (s < nst - 1) {
-                    for (int c = 0; c < 3; ++c) {
-                        const double k = -c1[c] - alpha * c2[c];
-                        B.acc[c * C + t] = (s == 0) ? bs * k : B.acc[c * C + t] + bs * k;
-                        ynext[c * X + e] = B.m[c * C + t] + cnext * dt * k;
-                    }
-                } else {
-                    double v[3];
-                    for (int c = 0; c < 3; ++c) {
-                        const double k = -c1[c] - alpha * c2[c];
-                        v[c] = B.m[c * C + t] + dt * (B.acc[c * C + t] + bs * k);
-                    }
-                    const double nr = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-                    for (int c = 0; c < 3; ++c) {
-                        B.m[c * C + t] = v[c] / nr;
-                        ynext[c * X + e] = v[c] / nr;
+                        double v[3];
+                        for (int c = 0; c < 3; ++c) {
+                            const double k = -c1[c] - alpha * c2[c];
+                            v[c] = B.m[c * C + t] + dt * (B.acc[c * C + t] + bs * k);
+                        }
+                        const double nr = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+                        for (int c = 0; c < 3; ++c) {
+                            B.m[c * C + t] = v[c] / nr;
+                            ynext[c * X + e] = v[c] / nr;
+                        }
                     }
                 }
             }
