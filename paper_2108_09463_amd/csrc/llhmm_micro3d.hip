@@ -433,18 +433,20 @@ __global__ void __launch_bounds__(kThreads3d) k_micro3d_o4(Micro3dArgs A) {
                     if (s < nst - 1) {
                         for (int c = 0; c < 3; ++c) {
                             const double k = -c1[c] - alpha * c2[c];
-                            B.acc[c * C + t] = (s == 0) ? bs * k : B.acc[c * C + t] + bs * k;
-                            ynext[c * X + e] = B.m[c * C + t] + cnext * dt * k;
+                            double *pa = B.acc + c * C + t;
+                            __builtin_nontemporal_store((s == 0) ? bs * k : __builtin_nontemporal_load(pa) + bs * k, pa);
+                            ynext[c * X + e] = __builtin_nontemporal_load(B.m + c * C + t) + cnext * dt * k;
                         }
                     } else {
                         double v[3];
                         for (int c = 0; c < 3; ++c) {
                             const double k = -c1[c] - alpha * c2[c];
-                            v[c] = B.m[c * C + t] + dt * (B.acc[c * C + t] + bs * k);
+                            v[c] = __builtin_nontemporal_load(B.m + c * C + t) +
+                                   dt * (__builtin_nontemporal_load(B.acc + c * C + t) + bs * k);
                         }
                         const double nr = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
                         for (int c = 0; c < 3; ++c) {
-                            B.m[c * C + t] = v[c] / nr;
+                            __builtin_nontemporal_store(v[c] / nr, B.m + c * C + t);
                             ynext[c * X + e] = v[c] / nr;
                         }
                     }
@@ -484,9 +486,12 @@ __global__ void __launch_bounds__(kThreads3d) k_micro3d_o4(Micro3dArgs A) {
         }
         A.wave_status[P.part_offset] = bad;
     }
-    if (A.out_field) {
-        for (long t = tid; t < C; t += nth)
-            for (int c = 0; c < 3; ++c) A.out_field[P.mfinal_offset + c * C + t] = B.m[c * C + t];
+    if (A.out_field) {   // the columns this thread walked
+        for (long col = tid; col < nn; col += nth)
+            for (int i2 = 0; i2 < n; ++i2) {
+                const long t = (long)i2 * nn + col;
+                for (int c = 0; c < 3; ++c) A.out_field[P.mfinal_offset + c * C + t] = B.m[c * C + t];
+            }
     }
 }
 
