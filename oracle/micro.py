@@ -24,6 +24,7 @@ from __future__ import annotations
 import ctypes
 import os
 import subprocess
+import threading
 
 import numpy as np
 
@@ -32,6 +33,7 @@ from . import kernels, stability
 GW = 3
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIBS = {}
+_BUILD_LOCK = threading.Lock()   # threads of one process share the build
 
 # Build variants of the same C source.  "plain": no FMA contraction (the
 # oracle).  "fma": identical algorithm with a*b+c contracted to fused
@@ -53,7 +55,7 @@ def build(force=False, variant="plain"):
     if not force and os.path.exists(out) and os.path.getmtime(out) >= os.path.getmtime(src):
         return out
     os.makedirs(os.path.dirname(out), exist_ok=True)
-    tmp = out + ".tmp%d" % os.getpid()
+    tmp = out + ".tmp%d_%d" % (os.getpid(), threading.get_ident())
     subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared"] + _VARIANTS[variant] +
                           ["-o", tmp, src, "-lm"])
     os.replace(tmp, out)
@@ -61,6 +63,11 @@ def build(force=False, variant="plain"):
 
 
 def _lib(variant="plain"):
+    with _BUILD_LOCK:
+        return _lib_locked(variant)
+
+
+def _lib_locked(variant):
     if variant not in _LIBS:
         L = ctypes.CDLL(build(variant=variant))
         dp = ctypes.POINTER(ctypes.c_double)
