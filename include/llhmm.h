@@ -227,6 +227,35 @@ llhmm_status llhmm_batch_run_graph(llhmm_ctx *ctx, llhmm_batch *batch, const dou
                                    const double *coef_dev, double *m_final_dev, double *H_avg_dev,
                                    int32_t ld, int32_t *status_dev, hipStream_t stream);
 
+/* Allocation-free solve, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  It is llhmm_batch_create + llhmm_micro_batch + llhmm_upscale
+ * (check = 0) in one call, with every buffer the kernels need beyond the
+ * caller's inputs and outputs (box descriptors, per-box tables, band state,
+ * partial sums, status words) placed in a static device array of
+ * LLHMM_NOALLOC_BYTES per GPU.  Each GPU the library runs on holds that array
+ * from the first llhmm_create on it until the process ends.  The call makes no
+ * hipMalloc, hipFree or other device allocation; host-side planning uses the
+ * host heap.
+ *   Arguments: boxes .. precision as in llhmm_batch_create; m_init_dev, macro,
+ *   M_macro_dev, coef_dev as in llhmm_micro_batch; H_avg_dev, ld, status_dev as
+ *   in llhmm_upscale.  Host arrays are consumed before the call returns; the
+ *   work is enqueued on `stream` (one stream: the classes of the batch are not
+ *   spread over side streams).
+ *   Errors: as llhmm_batch_create, and LLHMM_E_BUDGET when the batch does not
+ *   fit the array (nothing is enqueued then).  About 230 FP32 or 300 FP64
+ *   boxes of 64x64 fit.
+ *   Every call on a GPU uses the same array, and the array keeps the last
+ *   call's contents: calls on one GPU must be ordered (same stream, or
+ *   synchronized); calls that overlap on one GPU race. */
+#define LLHMM_NOALLOC_BYTES (64LL << 20)
+int64_t llhmm_noalloc_bytes(void);
+llhmm_status llhmm_solve_noalloc(llhmm_ctx *ctx, const llhmm_box *boxes, int32_t nboxes,
+                                 const llhmm_kernel *K, const llhmm_coef *coefs, int32_t ncoefs,
+                                 int32_t precision, const double *m_init_dev, const llhmm_macro *macro,
+                                 const double *M_macro_dev, const double *coef_dev, double *H_avg_dev,
+                                 int32_t ld, int32_t *status_dev, hipStream_t stream);
+
 /* Autotuner for the large boxes of a batch (2-D, n = 96 or 128, advanced in
  * row strips).  For every class (precision, n, bc, quantity, integrator) it
  * times the class alone, `reps` times after one warm-up, for each number of

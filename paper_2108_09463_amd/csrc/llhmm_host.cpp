@@ -12,6 +12,7 @@
 #include <cstring>
 #include <limits>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -313,6 +314,15 @@ struct Arena {
         free_[0] = bytes;
         return hipSuccess;
     }
+    // Hands out memory the caller already owns (base must be kAlign-aligned).
+    void init_external(char *mem, size_t bytes) {
+        base = mem;
+        size = bytes / kAlign * kAlign;
+        used = 0;
+        free_.clear();
+        taken_.clear();
+        free_[0] = size;
+    }
     void *alloc(size_t bytes) {
         bytes = std::max<size_t>(kAlign, (bytes + kAlign - 1) / kAlign * kAlign);
         for (auto it = free_.begin(); it != free_.end(); ++it) {
@@ -352,6 +362,7 @@ struct Arena {
 
 struct llhmm_ctx {
     int device;
+    char *scratch = nullptr;           // this device's copy of the allocation-free solve's scratch array
     std::map<TuneKey, TuneVal> tuned;  // band classes: variant and steps per launch from llhmm_batch_tune
 };
 
@@ -410,6 +421,8 @@ struct llhmm_batch {
     hipStream_t side[kSideStreams] = {};          // created on first use, default priority
     hipEvent_t fork = nullptr, join[kSideStreams] = {};
     Arena *arena = nullptr;                       // device memory source (nullptr: hipMalloc)
+    bool async_upload = false;                    // host tables go up with hipMemcpyAsync on upload_stream
+    hipStream_t upload_stream = nullptr;
     int max_lanes = 1 + kSideStreams;             // streams the classes may spread over
     hipStream_t cap_stream = nullptr;             // capture stream of llhmm_batch_run_graph
     hipGraphExec_t exec = nullptr;
@@ -429,6 +442,13 @@ static hipError_t balloc(llhmm_batch *b, void **p, size_t bytes) {
     return hipMalloc(p, bytes);
 }
 
+// Host -> device copy of batch tables: synchronous, or ordered on the batch's
+// upload stream (pageable source: consumed before the call returns).
+static hipError_t bcopy_h2d(llhmm_batch *b, void *dst, const void *src, size_t bytes) {
+    if (b->async_upload) return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, b->upload_stream);
+    return hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
+}
+
 static void bfree(llhmm_batch *b, void *p) {
     if (!p) return;
     if (b->arena) b->arena->release(p);
@@ -441,7 +461,7 @@ static hipError_t bupload(llhmm_batch *b, T **dst, const T *src, size_t count) {
     if (count == 0) return hipSuccess;
     hipError_t e = balloc(b, (void **)dst, sizeof(T) * count);
     if (e != hipSuccess) return e;
-    return hipMemcpy(*dst, src, sizeof(T) * count, hipMemcpyHostToDevice);
+    return bcopy_h2d(b, *dst, src, sizeof(T) * count);
 }
 
 // Band boxes: strip geometry from each box's steps per launch, classes by
@@ -497,13 +517,15 @@ static llhmm_status rebuild_bands(llhmm_batch *b) {
         if (e == hipErrorOutOfMemory) return fail(LLHMM_E_NOMEM, "band jobs: out of memory");
         HIP_TRY(e);
     }
-    HIP_TRY(hipMemcpy(b->plans, b->plans_h.data(), sizeof(BoxPlan) * b->plans_h.size(), hipMemcpyHostToDevice));
+    HIP_TRY(bcopy_h2d(b, b->plans, b->plans_h.data(), sizeof(BoxPlan) * b->plans_h.size()));
     if (b->exec) {
         HIP_TRY(hipGraphExecDestroy(b->exec));
         b->exec = nullptr;
     }
     return LLHMM_OK;
 }
+
+static llhmm_status scratch_address(int device, char **out);
 
 extern "C" {
 
@@ -517,7 +539,11 @@ llhmm_status llhmm_create(llhmm_ctx **ctx, int32_t device) {
     HIP_TRY(hipGetDeviceCount(&n));
     if (device < 0 || device >= n) return fail(LLHMM_E_INVALID, "device %d out of range (%d)", device, n);
     HIP_TRY(hipSetDevice(device));
+    char *scratch_dev = nullptr;
+    const llhmm_status st = scratch_address(device, &scratch_dev);
+    if (st != LLHMM_OK) return st;
     *ctx = new llhmm_ctx{device};
+    (*ctx)->scratch = scratch_dev;
     return LLHMM_OK;
 }
 
@@ -571,7 +597,8 @@ static void batch_free(llhmm_batch *b) {
 
 static llhmm_status batch_create_impl(llhmm_ctx *ctx, const llhmm_box *boxes, int32_t nboxes,
                                       const llhmm_kernel *K, const llhmm_coef *coefs, int32_t ncoefs,
-                                      int32_t precision, Arena *arena, int max_lanes, llhmm_batch **out);
+                                      int32_t precision, Arena *arena, int max_lanes, llhmm_batch **out,
+                                      hipStream_t upload_stream = nullptr, bool async_upload = false);
 
 llhmm_status llhmm_batch_create(llhmm_ctx *ctx, const llhmm_box *boxes, int32_t nboxes,
                                 const llhmm_kernel *K, const llhmm_coef *coefs, int32_t ncoefs,
@@ -583,7 +610,8 @@ llhmm_status llhmm_batch_create(llhmm_ctx *ctx, const llhmm_box *boxes, int32_t 
 
 static llhmm_status batch_create_impl(llhmm_ctx *ctx, const llhmm_box *boxes, int32_t nboxes,
                                       const llhmm_kernel *K, const llhmm_coef *coefs, int32_t ncoefs,
-                                      int32_t precision, Arena *arena, int max_lanes, llhmm_batch **out) {
+                                      int32_t precision, Arena *arena, int max_lanes, llhmm_batch **out,
+                                      hipStream_t upload_stream, bool async_upload) {
     if (!ctx || !out) return fail(LLHMM_E_INVALID, "ctx/out is NULL");
     *out = nullptr;
     if (nboxes <= 0 || !boxes) return fail(LLHMM_E_INVALID, "empty batch");
@@ -599,6 +627,8 @@ static llhmm_status batch_create_impl(llhmm_ctx *ctx, const llhmm_box *boxes, in
     double dcoef[8] = {0};
     llhmm_batch *b = new llhmm_batch();
     b->arena = arena;
+    b->upload_stream = upload_stream;
+    b->async_upload = async_upload;
     b->max_lanes = std::max(1, std::min(max_lanes, 1 + kSideStreams));
     b->nboxes = nboxes;
     b->prec = precision;
@@ -1724,6 +1754,84 @@ llhmm_status llhmm_server_stats(const llhmm_server *sv, int64_t *queued, int64_t
     if (bytes_in_use) *bytes_in_use = (int64_t)sv->arena.used;
     if (bytes_total) *bytes_total = (int64_t)sv->arena.size;
     return LLHMM_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------ allocation-free solve
+// The scratch memory of llhmm_solve_noalloc: one array per device, holding a
+// whole batch's descriptors, tables, band state and partial sums.  In host code
+// `scratch` names a host-side stand-in, never the device memory: its device
+// address is taken once per device with hipGetSymbolAddress (with that device
+// current) and only that address is used.
+static __device__ __align__(256) char scratch[LLHMM_NOALLOC_BYTES];
+
+static std::mutex g_scratch_mu;
+static std::map<int, char *> g_scratch_of_device;
+
+static llhmm_status scratch_address(int device, char **out) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    auto it = g_scratch_of_device.find(device);
+    if (it != g_scratch_of_device.end()) {
+        *out = it->second;
+        return LLHMM_OK;
+    }
+    int cur = 0;
+    HIP_TRY(hipGetDevice(&cur));
+    HIP_TRY(hipSetDevice(device));
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    (void)hipSetDevice(cur);
+    if (e != hipSuccess || !p)
+        return fail(LLHMM_E_HIP, "scratch array of device %d: hipGetSymbolAddress: %s", device,
+                    hipGetErrorString(e));
+    if ((uintptr_t)p % Arena::kAlign)
+        return fail(LLHMM_E_HIP, "scratch array of device %d is not %zu-byte aligned", device, Arena::kAlign);
+    g_scratch_of_device[device] = (char *)p;
+    *out = (char *)p;
+    return LLHMM_OK;
+}
+
+extern "C" {
+
+int64_t llhmm_noalloc_bytes(void) { return (int64_t)LLHMM_NOALLOC_BYTES; }
+
+llhmm_status llhmm_solve_noalloc(llhmm_ctx *ctx, const llhmm_box *boxes, int32_t nboxes,
+                                 const llhmm_kernel *K, const llhmm_coef *coefs, int32_t ncoefs,
+                                 int32_t precision, const double *m_init_dev, const llhmm_macro *macro,
+                                 const double *M_macro_dev, const double *coef_dev, double *H_avg_dev,
+                                 int32_t ld, int32_t *status_dev, hipStream_t stream) {
+    if (!ctx) return fail(LLHMM_E_INVALID, "ctx is NULL");
+    if (!ctx->scratch) return fail(LLHMM_E_HIP, "context has no scratch array");
+    // The batch lives in the scratch array: a fresh first-fit arena over it per
+    // call, one stream (no side streams, events or graphs), tables uploaded in
+    // stream order so that a previous call still reading the array is not
+    // overtaken.
+    Arena arena;
+    arena.init_external(ctx->scratch, (size_t)LLHMM_NOALLOC_BYTES);
+    llhmm_batch *b = nullptr;
+    llhmm_status st = batch_create_impl(ctx, boxes, nboxes, K, coefs, ncoefs, precision, &arena, 1, &b,
+                                        stream, true);
+    if (st == LLHMM_E_NOMEM)
+        return fail(LLHMM_E_BUDGET, "batch does not fit the %lld-byte scratch array of the allocation-free "
+                    "solve (%d boxes); use llhmm_batch_create or split the batch",
+                    (long long)LLHMM_NOALLOC_BYTES, nboxes);
+    if (st != LLHMM_OK) return st;
+    if (H_avg_dev) {
+        for (const BoxPlan &P : b->plans_h)
+            if (P.nq > ld) {
+                batch_free(b);
+                return fail(LLHMM_E_INVALID, "ld %d smaller than the outputs per box", ld);
+            }
+    }
+    st = run_batch(ctx, b, m_init_dev, macro, M_macro_dev, coef_dev, nullptr, 0, stream);
+    if (st == LLHMM_OK) {
+        const hipError_t e = launch_upscale(b->partials, b->wave_status, b->box_const, b->plans, b->nboxes,
+                                            H_avg_dev, ld, b->status, status_dev, stream);
+        if (e != hipSuccess) st = fail(LLHMM_E_HIP, "upscale launch: %s", hipGetErrorString(e));
+    }
+    batch_free(b);  // host bookkeeping only: the arena hands the array back, nothing is freed on the device
+    return st;
 }
 
 }  // extern "C"

@@ -96,6 +96,12 @@ _SYMBOLS = {
                                              ctypes.POINTER(Macro), ctypes.c_void_p, ctypes.c_void_p,
                                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                              ctypes.c_void_p, ctypes.c_void_p]),
+    "llhmm_noalloc_bytes": (ctypes.c_int64, []),
+    "llhmm_solve_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Box), ctypes.c_int32,
+                                           ctypes.POINTER(Kernel), ctypes.POINTER(Coef), ctypes.c_int32,
+                                           ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(Macro),
+                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
     "llhmm_batch_tune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.POINTER(Macro), ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_int32, ctypes.c_void_p]),
@@ -329,6 +335,23 @@ def llhmm_batch_run_graph(ctx, batch, H_avg, ld, status=None, m_init=None, macro
     _check(lib().llhmm_batch_run_graph(ctx.h, batch.h, _ptr(m_init), ms[0] if ms else None,
                                        _ptr(M_macro), _ptr(coef), _ptr(m_final), _ptr(H_avg), ld,
                                        _ptr(status), _stream(stream)))
+
+
+def llhmm_noalloc_bytes():
+    return int(lib().llhmm_noalloc_bytes())
+
+
+def llhmm_solve_noalloc(ctx, boxes, coefs, precision, H_avg, ld, status=None, m_init=None, macro=None,
+                        M_macro=None, coef=None, K=None, stream=None):
+    """Create + solve + upscale in the library's static scratch array (no device
+    allocation).  coefs: llhmm_coef structs (see to_coef)."""
+    arr = box_array(boxes)
+    carr = (Coef * len(coefs))(*coefs)
+    Kp = K or kernel()
+    ms = _macro_struct(macro)
+    _check(lib().llhmm_solve_noalloc(ctx.h, arr, len(boxes), ctypes.byref(Kp), carr, len(coefs), precision,
+                                     _ptr(m_init), ms[0] if ms else None, _ptr(M_macro), _ptr(coef),
+                                     _ptr(H_avg), ld, _ptr(status), _stream(stream)))
 
 
 def llhmm_batch_tune(ctx, batch, m_init=None, macro=None, M_macro=None, coef=None, reps=2,
