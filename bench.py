@@ -78,6 +78,34 @@ def measured_traffic(name):
         return None
 
 
+COUNTER_FILES = {"fp32": "profiles/k_micro_f32_two_d_batch_counters.txt",
+                 "fp64": "profiles/k_micro_f64_two_d_batch_counters.txt"}
+
+
+def measured_counters(name):
+    """VALU issue utilisation and LDS bank-conflict rate of the time-stepping
+    kernel from the committed PMC summary, or None when absent or taken on
+    other kernel sources."""
+    path = os.path.join(ROOT, COUNTER_FILES[name])
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(" "):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip().split()[0] if v.strip() else ""
+    if kv.get("kernel_sources_sha256_16") != kernel_source_hash(KERNEL_SOURCES):
+        return None
+    try:
+        return {"valu_issue_utilisation": float(kv["valu_issue_utilisation"]),
+                "valu_busy": float(kv["valu_busy"]),
+                "lds_bank_conflict_rate": float(kv["lds_bank_conflict_rate"]),
+                "hardware_over_algorithmic_flops": float(kv["hardware_over_algorithmic"]),
+                "source": COUNTER_FILES[name]}
+    except (KeyError, ValueError):
+        return None
+
+
 def copy_calibration(nbytes=1 << 30, reps=3):
     """A plain device-to-device copy of known size, for scaling the PMC
     FETCH_SIZE / WRITE_SIZE counters to bytes (run under rocprofv3 --pmc)."""
@@ -225,6 +253,7 @@ def measure(wl, precision, steps, warmup, tune=False, graph=False):
                 roofline=dict(bound="alu", achieved=achieved / 1e12, peak=peak / 1e12,
                               unit="TFLOP/s", frac=achieved / peak,
                               traffic=measured_traffic(name) if wl.name == "two_d_batch" else None,
+                              counters=measured_counters(name) if wl.name == "two_d_batch" else None,
                               kernel="time-stepping kernels", kernel_ms=t["kernel_ms"],
                               flops_per_cell_step=flops / cs, flops_per_launch=flops))
 
