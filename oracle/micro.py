@@ -40,7 +40,13 @@ _BUILD_LOCK = threading.Lock()   # threads of one process share the build
 # multiply-adds; the spread between the two measures the FP64 rounding floor
 # of a result, which bounds how closely any other correct FP64 implementation
 # can be expected to agree with the oracle.
-_VARIANTS = {"plain": ["-ffp-contract=off"], "fma": ["-ffp-contract=fast", "-mfma"]}
+_VARIANTS = {"plain": ["-ffp-contract=off"], "fma": ["-ffp-contract=fast", "-mfma"],
+             "ld": ["-ffp-contract=off", "-DORACLE_LONG_DOUBLE"],
+             "quad": ["-ffp-contract=off", "-DORACLE_QUAD"]}
+# "ld" (x87 extended precision) and "quad" (binary128, libquadmath): the same
+# algorithm in higher precision on the same FP64 inputs, the answers against
+# which FP64 results are measured.  "ld" is the one the parity tests use (about
+# three times the FP64 cost); "quad" (about 150 times) pins it on small boxes.
 
 
 def lib_path(variant="plain"):
@@ -56,8 +62,9 @@ def build(force=False, variant="plain"):
         return out
     os.makedirs(os.path.dirname(out), exist_ok=True)
     tmp = out + ".tmp%d_%d" % (os.getpid(), threading.get_ident())
-    subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared"] + _VARIANTS[variant] +
-                          ["-o", tmp, src, "-lm"])
+    libs = ["-lquadmath", "-lm"] if variant == "quad" else ["-lm"]
+    subprocess.check_call(["gcc", "-O2", "-std=gnu99", "-fPIC", "-shared"] + _VARIANTS[variant] +
+                          ["-o", tmp, src] + libs)
     os.replace(tmp, out)
     return out
 

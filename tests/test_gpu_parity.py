@@ -1,10 +1,19 @@
 """GPU parity: the HIP path (libllhmm through its C-ABI) against the FP64 CPU
 oracle on the same seeded inputs.
 
-Bars (per box, relative error ||H_gpu - H_oracle||_2 / max(||H_oracle||_2,
-1e-3 median_boxes ||H_oracle||_2)):
-  FP64 path  <= 1e-12
-  FP32 path  <= 1e-5
+Bars (per box, relative error ||H_gpu - H_ref||_2 / max(||H_ref||_2,
+1e-3 median_boxes ||H_ref||_2)):
+  FP32 path  <= 1e-5 against the FP64 oracle.
+  FP64 path  against the truth H_t, the same oracle algorithm computed in x87
+             extended precision (oracle variant "ld", pinned to binary128 in
+             tests/test_oracle_precision.py) on the same FP64 inputs:
+             |H_gpu - H_t| <= TRUTH_FACTOR * max(e_plain, e_fma, 1e-12), where
+             e_plain and e_fma are the errors against H_t of two correct FP64
+             implementations, the oracle built without and with FMA
+             contraction.  Where the average cancels few digits the bar is
+             4e-12; where it cancels many, the FP64 oracle itself is further
+             than 1e-12 from H_t and the bar follows.  The measured ratio
+             |H_gpu - H_t| / max(e_plain, e_fma) is printed.
 Field evaluations (one stencil application) are compared element by element.
 """
 import copy
@@ -21,11 +30,9 @@ from paper_2108_09463_amd import llhmm as L
 pytestmark = pytest.mark.gpu
 
 TOL = {inputs.FP64: 1e-12, inputs.FP32: 1e-5}
-# FP64: the bar is 1e-12, or 4x the oracle's own rounding spread over the
-# workload's boxes (the same oracle built with FMA contraction), whichever is
-# larger; on the 2-D workloads that spread reaches 6e-12, so no correct FP64
-# implementation can be held to 1e-12 there.
-SPREAD_FACTOR = 4.0
+# FP64: the GPU's error against the extended-precision truth may be this many
+# times the larger of the two FP64 oracle builds' errors against it.
+TRUTH_FACTOR = 4.0
 
 
 @pytest.fixture(scope="module")
@@ -66,14 +73,32 @@ def run_oracle(wl, idx=None, want_state=False, variant="plain", threads=1):
         return list(ex.map(one, idx))
 
 
-def tolerance(wl, precision, Ho, idx=None):
-    """Per-box bar: FP32 1e-5; FP64 max(1e-12, SPREAD_FACTOR x oracle self-spread)."""
-    if precision == inputs.FP32:
-        return np.full(len(Ho), TOL[inputs.FP32])
-    Hf = np.stack([r["out"] for r in run_oracle(wl, idx, variant="fma")])
-    spread = rel_err(Hf, Ho)
-    print("oracle fma/plain spread", spread)
-    return np.full(len(Ho), max(TOL[inputs.FP64], SPREAD_FACTOR * spread.max()))
+def outs(runs):
+    """Averages of oracle runs, one row per box, zero-padded to the widest box."""
+    width = max(len(r["out"]) for r in runs)
+    return np.stack([np.pad(r["out"], (0, width - len(r["out"]))) for r in runs])
+
+
+def fp64_truth(wl, idx=None, want_state=False, plain=None, extra=(), threads=16):
+    """Truth and FP64 reference errors for the FP64 bar.  Returns (truth runs,
+    H_truth, e_ref per box, reference runs); the references are the plain and
+    FMA oracle builds (plus `extra` runs of other legal FP64 roundings)."""
+    truth = run_oracle(wl, idx, want_state=want_state, variant="ld", threads=threads)
+    refs = [plain if plain is not None else run_oracle(wl, idx, want_state=want_state, threads=threads),
+            run_oracle(wl, idx, want_state=want_state, variant="fma", threads=threads)] + list(extra)
+    Ht = outs(truth)
+    e_ref = np.max([rel_err(outs(r)[:, :Ht.shape[1]], Ht) for r in refs], axis=0)
+    return truth, Ht, e_ref, refs
+
+
+def assert_fp64(Hg, Ht, e_ref, label=""):
+    """|H_gpu - H_truth| <= TRUTH_FACTOR max(e_ref, 1e-12) per box."""
+    err = rel_err(Hg[:, :Ht.shape[1]], Ht)
+    bar = TRUTH_FACTOR * np.maximum(e_ref, 1e-12)
+    print(label, "fp64 err vs truth", err.max(), "oracle builds vs truth", e_ref.max(),
+          "ratio", (err / np.maximum(e_ref, 1e-300)).max(), "bar", bar.max(), flush=True)
+    assert np.all(err <= bar), (err, bar)
+    return err
 
 
 def small_1d(n, order, bc, qty, nboxes=5, seed=11):
@@ -111,15 +136,23 @@ def small_2d(n, order, bc, qty, nboxes=3, seed=12, init_mode=0):
                            macro=mac)
 
 
+def assert_parity(wl, precision, Hg, ora, idx=None, label=""):
+    """FP32: <= 1e-5 against the oracle runs `ora`; FP64: the truth bar."""
+    Ho = outs(ora)
+    err = rel_err(Hg[:, :Ho.shape[1]], Ho)
+    print(label or wl.name, "rel err vs oracle", err, "precision", precision, flush=True)
+    if precision == inputs.FP32:
+        assert np.all(err <= TOL[inputs.FP32]), err
+    else:
+        _, Ht, e_ref, _ = fp64_truth(wl, idx, plain=ora)
+        assert_fp64(Hg, Ht, e_ref, label or wl.name)
+    return err
+
+
 def check(ctx, wl, precision, want_state=False):
     _, out = run_gpu(ctx, wl, precision, want_state)
     ora = run_oracle(wl, want_state=want_state)
-    nq = len(ora[0]["out"])
-    Ho = np.stack([r["out"] for r in ora])
-    err = rel_err(out["H"][:, :nq], Ho)
-    tol = tolerance(wl, precision, Ho)
-    print("rel err", err, "bar", tol, "precision", precision)
-    assert np.all(err <= tol), (err, tol)
+    assert_parity(wl, precision, out["H"], ora)
     return out, ora
 
 
@@ -185,14 +218,17 @@ def test_full_two_d_batch_sampled(ctx):
     times; 4 boxes checked against the oracle one by one."""
     wl = inputs.two_d_batch()
     idx = [0, 341, 682, 1023]
-    ora = run_oracle(wl, idx)
+    ora = run_oracle(wl, idx, threads=4)
     Ho = np.stack([r["out"] for r in ora])
+    _, Ht, e_ref, _ = fp64_truth(wl, idx, plain=ora)
     for prec in (inputs.FP64, inputs.FP32):
         _, out = run_gpu(ctx, wl, prec)
         err = rel_err(out["H"][idx, :3], Ho)
-        tol = tolerance(wl, prec, Ho, idx)
-        print("two_d_batch", prec, err, tol)
-        assert np.all(err <= tol)
+        print("two_d_batch", prec, "err vs oracle", err)
+        if prec == inputs.FP32:
+            assert np.all(err <= TOL[inputs.FP32])
+        else:
+            assert_fp64(out["H"][idx], Ht, e_ref, "two_d_batch")
 
 
 def test_full_one_d(ctx):

@@ -10,7 +10,7 @@ import pytest
 from oracle import micro
 from paper_2108_09463_amd import inputs
 from paper_2108_09463_amd.runner import Prepared
-from test_gpu_parity import TOL, rel_err, run_oracle, tolerance
+from test_gpu_parity import assert_fp64, assert_parity, fp64_truth, rel_err, run_oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -54,11 +54,7 @@ def test_sampled_coefficient_parity(ctx, dim, sizes, prec):
     out = p.solve()
     assert (out["status"] == 0).all()
     ora = run_oracle(wl)
-    Ho = np.stack([r["out"] for r in ora])
-    err = rel_err(out["H"][:, :3], Ho)
-    tol = tolerance(wl, prec, Ho)
-    print("sampled", dim, prec, err, tol, flush=True)
-    assert np.all(err <= tol)
+    assert_parity(wl, prec, out["H"], ora, label="sampled d=%d" % dim)
     p.batch.close()
 
 
@@ -86,13 +82,6 @@ def test_sampled_coefficient_3d(ctx):
     p = Prepared(wl, precision=inputs.FP64, ctx=ctx, coef_samples=np.concatenate(blocks))
     out = p.solve()
     assert (out["status"] == 0).all()
-    ora = run_oracle(wl)
-    width = max(len(r["out"]) for r in ora)
-    Ho = np.stack([np.pad(r["out"], (0, width - len(r["out"]))) for r in ora])
-    err = rel_err(out["H"][:, :width], Ho)
-    fma = run_oracle(wl, variant="fma")
-    Hf = np.stack([np.pad(r["out"], (0, width - len(r["out"]))) for r in fma])
-    tol = np.maximum(TOL[inputs.FP64], 4.0 * rel_err(Hf, Ho))
-    print("sampled 3-D", err, tol, flush=True)
-    assert np.all(err <= tol)
+    _, Ht, e_ref, _ = fp64_truth(wl)
+    assert_fp64(out["H"], Ht, e_ref, "sampled 3-D")
     p.batch.close()
