@@ -51,6 +51,17 @@ extern "C" {
 #endif
 
 #define LLHMM_ABI_VERSION 2
+/* FP32 domain: FP32 boxes wider than LLHMM_FP32_MAX_WIDTH_EPS eps (mu' / eps)
+ * need alpha >= LLHMM_FP32_MIN_ALPHA_WIDE, and every FP32 box needs an
+ * averaging radius mu >= LLHMM_FP32_MIN_MU_EPS eps; others return
+ * LLHMM_E_NOTSUP (solve them in FP64).  Outside these bounds the FP32
+ * roundings of the scheme (state, stencil, right-hand side, stored tables)
+ * move the upscaled average by about 1e-5 relative or more: on weakly damped
+ * wide boxes the average cancels many digits, and below mu = 2 eps too few
+ * points enter it for the rounding noise to average out. */
+#define LLHMM_FP32_MAX_WIDTH_EPS 8.0
+#define LLHMM_FP32_MIN_ALPHA_WIDE 0.5
+#define LLHMM_FP32_MIN_MU_EPS 2.0
 #define LLHMM_GHOST 3
 #define LLHMM_MAX_TERMS 8
 
@@ -152,6 +163,16 @@ llhmm_status llhmm_destroy(llhmm_ctx *ctx);
 llhmm_status llhmm_plan(const llhmm_box *boxes, int32_t nboxes, int32_t *n_steps_out,
                         double *dt_out, int32_t *integrator_out);
 
+/* Host-only check of a batch before any device work: every box is validated
+ * as in llhmm_batch_create (assumptions A1-A3 of eq. (prob), the contract
+ * above, the stability rule of Section 3.2), and its class (precision, dim, n,
+ * order, bc, quantity) must have a kernel and lie in the FP32 domain above.
+ * Returns LLHMM_OK, or the status llhmm_batch_create would return for the
+ * first failing box, whose index goes to *first_bad (nullable; -1 when all
+ * pass).  Needs no context and no GPU. */
+llhmm_status llhmm_check_boxes(const llhmm_box *boxes, int32_t nboxes, int32_t ncoefs, int32_t precision,
+                               int32_t *first_bad);
+
 /* Exact-in-double coefficients of the averaging kernels (Definition 2.3 reading:
  * K(x) = (1-x^2)^(q+1) sum_{i<=p} c_i x^i, K0(t) = t^(q+1)(1-t)^(q+1) sum_{i<=p} d_i t^i,
  * moments fixed by int K x^r = delta_r0, r = 0..p).  c, d: host arrays of p+1. */
@@ -161,7 +182,8 @@ llhmm_status llhmm_kernel_coeffs(const llhmm_kernel *K, double *c_space, double 
  * Plans the boxes (as llhmm_plan), chooses a kernel tile class per box,
  * uploads the per-box descriptors and allocates the per-box FP64 partial sums.
  * Host-synchronous.  Errors: LLHMM_E_INVALID (bad box), LLHMM_E_NOTSUP (no
- * kernel for a box class), LLHMM_E_NOMEM. */
+ * kernel for a box class, or an FP32 box outside the FP32 domain defined at
+ * LLHMM_FP32_MAX_WIDTH_EPS), LLHMM_E_NOMEM. */
 llhmm_status llhmm_batch_create(llhmm_ctx *ctx, const llhmm_box *boxes, int32_t nboxes,
                                 const llhmm_kernel *K, const llhmm_coef *coefs,
                                 int32_t ncoefs, int32_t precision, llhmm_batch **batch);

@@ -114,6 +114,29 @@ llhmm_status validate_box(const llhmm_box &b, int i, int ncoefs) {
     return LLHMM_OK;
 }
 
+// FP32 domain.  The FP32 path rounds its state, stencil, right-hand side and
+// stored tables to FP32.  The upscaled average sums these roundings over the
+// averaging region and the time steps; on wide, weakly damped boxes the average
+// cancels so many digits that each rounding alone moves it by about 1e-5
+// relative, and with an averaging radius below 2 eps too few points enter it
+// for the rounding noise to average out (CPU emulation of the kernel's
+// arithmetic).  No FP32 arrangement of the scheme holds the 1e-5 bar there, so
+// such boxes are refused in FP32 (they are solved in FP64).
+llhmm_status check_fp32_domain(const llhmm_box &b, int i, int precision) {
+    if (precision != LLHMM_FP32) return LLHMM_OK;
+    if (b.mu_box > LLHMM_FP32_MAX_WIDTH_EPS * b.eps * (1.0 + 1e-12) && b.alpha < LLHMM_FP32_MIN_ALPHA_WIDE)
+        return fail(LLHMM_E_NOTSUP,
+                    "box %d: FP32 cannot hold the 1e-5 bar on a weakly damped wide box (mu' = %.4g eps > %g eps "
+                    "with alpha = %.3g < %g); solve it in FP64",
+                    i, b.mu_box / b.eps, (double)LLHMM_FP32_MAX_WIDTH_EPS, b.alpha, (double)LLHMM_FP32_MIN_ALPHA_WIDE);
+    if (b.mu < LLHMM_FP32_MIN_MU_EPS * b.eps * (1.0 - 1e-12))
+        return fail(LLHMM_E_NOTSUP,
+                    "box %d: FP32 cannot hold the 1e-5 bar with an averaging radius mu = %.4g eps < %g eps; "
+                    "solve it in FP64",
+                    i, b.mu / b.eps, (double)LLHMM_FP32_MIN_MU_EPS);
+    return LLHMM_OK;
+}
+
 struct Planned {
     int integ, M;
     double dt;
@@ -568,6 +591,33 @@ llhmm_status llhmm_plan(const llhmm_box *boxes, int32_t nboxes, int32_t *n_steps
     return LLHMM_OK;
 }
 
+llhmm_status llhmm_check_boxes(const llhmm_box *boxes, int32_t nboxes, int32_t ncoefs, int32_t precision,
+                               int32_t *first_bad) {
+    if (first_bad) *first_bad = -1;
+    if (nboxes <= 0 || !boxes) return fail(LLHMM_E_INVALID, "empty batch");
+    if (precision != LLHMM_FP64 && precision != LLHMM_FP32) return fail(LLHMM_E_INVALID, "bad precision");
+    for (int i = 0; i < nboxes; ++i) {
+        const llhmm_box &bx = boxes[i];
+        llhmm_status s = validate_box(bx, i, ncoefs);
+        Planned p;
+        if (s == LLHMM_OK) s = plan_one(bx, i, p);
+        if (s == LLHMM_OK && bx.dim == 3 && precision != LLHMM_FP64)
+            s = fail(LLHMM_E_NOTSUP, "box %d: d = 3 boxes need FP64", i);
+        if (s == LLHMM_OK) s = check_fp32_domain(bx, i, precision);
+        if (s == LLHMM_OK && bx.dim != 3 &&
+            registry().find(TileKey{precision, bx.dim, bx.n, bx.order, bx.bc, bx.quantity}) == registry().end() &&
+            !(bx.dim == 2 && bx.order == 2 &&
+              band_registry().find(BandKey{precision, bx.n, bx.bc, bx.quantity}) != band_registry().end()))
+            s = fail(LLHMM_E_NOTSUP, "box %d: no kernel for precision %s, dim %d, n %d, order %d, bc %d, quantity %d",
+                     i, precision == LLHMM_FP32 ? "fp32" : "fp64", bx.dim, bx.n, bx.order, bx.bc, bx.quantity);
+        if (s != LLHMM_OK) {
+            if (first_bad) *first_bad = i;
+            return s;
+        }
+    }
+    return LLHMM_OK;
+}
+
 llhmm_status llhmm_kernel_coeffs(const llhmm_kernel *K, double *c_space, double *d_time) {
     if (!K) return fail(LLHMM_E_INVALID, "kernel is NULL");
     llhmm_status s = LLHMM_OK;
@@ -674,6 +724,11 @@ static llhmm_status batch_create_impl(llhmm_ctx *ctx, const llhmm_box *boxes, in
         if (bx.dim == 3 && precision != LLHMM_FP64) {
             delete b;
             return fail(LLHMM_E_NOTSUP, "box %d: d = 3 boxes need FP64", i);
+        }
+        st = check_fp32_domain(bx, i, precision);
+        if (st != LLHMM_OK) {
+            delete b;
+            return st;
         }
         auto it = reg.find(TileKey{precision, bx.dim, bx.n, bx.order, bx.bc, bx.quantity});
         const BandTileInfo *bt = nullptr;
@@ -1468,6 +1523,8 @@ static llhmm_status request_bytes(const llhmm_server *sv, const llhmm_box &bx, i
     st = plan_one(bx, i, pl);
     if (st != LLHMM_OK) return st;
     const int prec = sv->cfg.precision;
+    st = check_fp32_domain(bx, i, prec);
+    if (st != LLHMM_OK) return st;
     const int64_t tsize = (prec == LLHMM_FP32) ? 4 : 8;
     const int stages = (pl.integ == LLHMM_RK4P) ? 4 : 2;
     if (bx.dim == 3) {

@@ -13,7 +13,7 @@ constexpr int kMaxQ = 9;       // outputs per box (flux in 3-D: 3 axes x 3 compo
 constexpr int kFaceHalo = 3;   // faces -2 .. n stored per line: n + 3 entries
 // FP32 reference + perturbation form: every kRerefSteps time steps the state
 // is re-expressed around a new reference r' = fl(r + u) (MicroLane::rereference).
-constexpr int kRerefSteps = 32;
+constexpr int kRerefSteps = 8;
 
 // Per-box plan as the kernels read it.
 struct BoxPlan {

@@ -72,6 +72,8 @@ _SYMBOLS = {
     "llhmm_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "llhmm_plan": (ctypes.c_int, [ctypes.POINTER(Box), ctypes.c_int32, ctypes.c_void_p,
                                   ctypes.c_void_p, ctypes.c_void_p]),
+    "llhmm_check_boxes": (ctypes.c_int, [ctypes.POINTER(Box), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.POINTER(ctypes.c_int32)]),
     "llhmm_kernel_coeffs": (ctypes.c_int, [ctypes.POINTER(Kernel), ctypes.c_void_p, ctypes.c_void_p]),
     "llhmm_batch_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Box), ctypes.c_int32,
                                           ctypes.POINTER(Kernel), ctypes.POINTER(Coef),
@@ -216,6 +218,19 @@ def llhmm_plan(boxes):
     integ = np.zeros(n, np.int32)
     _check(lib().llhmm_plan(arr, n, M.ctypes.data, dt.ctypes.data, integ.ctypes.data))
     return M, dt, integ
+
+
+FP32_MAX_WIDTH_EPS = 8.0      # LLHMM_FP32_MAX_WIDTH_EPS
+FP32_MIN_ALPHA_WIDE = 0.5      # LLHMM_FP32_MIN_ALPHA_WIDE
+FP32_MIN_MU_EPS = 2.0          # LLHMM_FP32_MIN_MU_EPS
+
+
+def llhmm_check_boxes(boxes, precision, ncoefs=1 << 30):
+    """(status, first failing box index or -1, message); host only."""
+    arr = box_array(boxes)
+    bad = ctypes.c_int32(-1)
+    st = lib().llhmm_check_boxes(arr, len(boxes), ncoefs, precision, ctypes.byref(bad))
+    return st, bad.value, ("" if st == OK else lib().llhmm_last_error().decode())
 
 
 def llhmm_kernel_coeffs(p_x=3, q_x=7, p_t=3, q_t=7):

@@ -118,10 +118,15 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--quick", action="store_true")
     ap.add_argument("--out", default=None)
+    ap.add_argument("--fp32", action="store_true",
+                    help="FP32 (only the points inside the library's FP32 domain); default FP64")
     args = ap.parse_args()
     pts = sweeps(args.quick)
+    if args.fp32:
+        from paper_2108_09463_amd import llhmm as L
+        pts = [p for p in pts if L.llhmm_check_boxes([p[1]], inputs.FP32)[0] == L.OK]
     print(f"{len(pts)} sweep points", flush=True)
-    wl, H = run_gpu(pts)
+    wl, H = run_gpu(pts, precision=inputs.FP32 if args.fp32 else inputs.FP64)
     rows = []
     for (lab, _, _), h in zip(pts, H):
         rows.append(dict(lab, E_avg=e_avg(lab, h)))
