@@ -12,7 +12,7 @@ grid point advanced one full time step); the FP64 path is timed on the same
 batch and reported beside it, with p50/p99 batch latency, the roofline of the
 time-stepping kernel (from the library's HIP events on the launch stream), the
 oracle timed on the host cores, and the 4096-box uneven FP32 batch (sizes 32
-to 128, large boxes in band mode) as a nested record.
+to 128, large boxes in slab mode) as a nested record.
 """
 from __future__ import annotations
 
@@ -223,7 +223,7 @@ def algorithmic_flops(boxes):
 
 def measure(wl, precision, steps, warmup, tune=False, graph=False):
     """Times one workload at one precision; returns rates, latencies and the
-    roofline of the time-stepping phase.  tune: run the band-mode autotuner
+    roofline of the time-stepping phase.  tune: run the slab-mode autotuner
     first; graph: launch the whole solve as one captured HIP graph (the
     library's events then time the whole call as time stepping)."""
     import torch
@@ -232,10 +232,11 @@ def measure(wl, precision, steps, warmup, tune=False, graph=False):
     prep = Prepared(wl, precision=precision)
     cs = prep.cell_steps()
     flops = algorithmic_flops(prep.boxes)
-    steps_per_launch = None
+    slabs = None
     if tune:
-        sp = prep.tune(reps=1)
-        steps_per_launch = {int(n): int(k) for n, k in {b["n"]: k for b, k in zip(prep.boxes, sp) if k}.items()}
+        sp, spe = prep.tune(reps=1)
+        slabs = {int(b["n"]): dict(slabs=int(k), steps_per_exchange=int(e))
+                 for b, k, e in zip(prep.boxes, sp, spe) if k}
     t = time_batch(prep, steps, warmup, graph=graph)
     torch.cuda.synchronize()
     H = prep.H.cpu().numpy()
@@ -247,7 +248,7 @@ def measure(wl, precision, steps, warmup, tune=False, graph=False):
     achieved = flops / (t["kernel_ms"] * 1e-3)
     peak = PEAK_FP32 if precision == inputs.FP32 else PEAK_FP64
     name = "fp32" if precision == inputs.FP32 else "fp64"
-    return dict(cell_steps=cs, ms_per_step=t["ms_per_step"], rate=rate, steps_per_launch=steps_per_launch,
+    return dict(cell_steps=cs, ms_per_step=t["ms_per_step"], rate=rate, slabs=slabs,
                 p50_ms=pct(t["lat_ms"], 50), p99_ms=pct(t["lat_ms"], 99),
                 setup_ms=t["setup_ms"], kernel_ms=t["kernel_ms"], H=H, status_ok=bool((st == 0).all()),
                 roofline=dict(bound="alu", achieved=achieved / 1e12, peak=peak / 1e12,
@@ -258,33 +259,59 @@ def measure(wl, precision, steps, warmup, tune=False, graph=False):
                               flops_per_cell_step=flops / cs, flops_per_launch=flops))
 
 
-def served(stages, with_cpu=False):
-    """The served HMM run on a 128x128 macro grid: each macro stage issues
-    16384 micro requests (n in {32..128}, eps in {1/100, 1/200, 1/400},
-    alpha_micro = 1.2, HeunP, Q_[4] data), released in shuffled bursts of
-    256-4096 back to back (closed loop) into the request loop."""
+def _served_mode(stages, arrival, gap_mean_s=0.0):
+    """`stages` macro stages of the served run with one arrival mode; per-stage
+    request-latency percentiles and the stage records' summary."""
     import torch
     from paper_2108_09463_amd.serve import ServedRun
     run = ServedRun(n_macro=128, max_inflight=4, max_batch_boxes=2048, device_bytes=24 << 30)
     recs = []
     k = 0
-    for step in range(1 << 30):
+    step = 0
+    while len(recs) < stages:
         stage = 0
         while len(recs) < stages:
-            rec = run.stage(run.Y, k)
+            rec = run.stage(run.Y, k, arrival, gap_mean_s)
             k += 1
-            stage = run.macro_stage(step, stage, rec["H"])
+            stage = run.macro_stage(step, stage, rec)
             recs.append(rec)
             if stage == 0:
                 break
-        if len(recs) >= stages:
-            break
+        step += 1
     torch.cuda.synchronize()
-    lat = np.concatenate([r["latency_us"] for r in recs]) * 1e-3
-    bl = np.concatenate([np.array(r["burst_s"]) for r in recs]) * 1e3
-    st = np.array([r["stage_s"] for r in recs])
-    ok = all(bool((r["status"] == 0).all()) for r in recs)
+    cell_steps = run.cell_steps
     run.close()
+    st = np.array([r["stage_s"] for r in recs])
+    p50 = [pct(list(r["latency_us"] * 1e-3), 50) for r in recs]
+    p99 = [pct(list(r["latency_us"] * 1e-3), 99) for r in recs]
+    bl = np.concatenate([np.array(r["burst_s"]) for r in recs]) * 1e3
+    nb = np.array([len(r["bursts"]) for r in recs])
+    return recs, {
+        "arrival": arrival, "stages": len(recs), "value": cell_steps * len(recs) / st.sum(),
+        "unit": "cell-steps/s",
+        "request_latency_ms_per_stage": {"p50": p50, "p99": p99},
+        "request_latency_ms": {"p50_median_over_stages": float(np.median(p50)),
+                               "p99_max_over_stages": float(np.max(p99))},
+        "burst_latency_ms": {"p50": pct(list(bl), 50), "p99": pct(list(bl), 99)},
+        "stage_latency_ms": {"p50": pct(list(st * 1e3), 50), "p99": pct(list(st * 1e3), 99)},
+        "burst_service_ms": float((st / nb).mean() * 1e3),
+        "status_ok": all(bool((r["status"] == 0).all()) for r in recs)}, cell_steps
+
+
+def served(stages, with_cpu=False):
+    """The served HMM run on a 128x128 macro grid: each macro stage issues
+    16384 micro requests (n in {32..128}, eps in {1/100, 1/200, 1/400},
+    alpha_micro = 1.2, HeunP, Q_[4] data), released in shuffled bursts of
+    256-4096 into the request loop, in three arrival modes: saturating (back to
+    back), open loop (exponential gaps of mean 0.8 x the saturating run's
+    service time per burst) and closed loop (next burst after the previous
+    one has completed, at most 4 stages).  The macro stage reads the averages
+    where the micro-batches left them on the device."""
+    recs, sat, cell_steps = _served_mode(stages, "saturating")
+    gap = 0.8 * sat["burst_service_ms"] * 1e-3
+    _, opn, _ = _served_mode(stages, "open", gap)
+    opn["gap_mean_ms"] = gap * 1e3
+    _, clo, _ = _served_mode(min(stages, 4), "closed")
     extra = {}
     if with_cpu:
         # first stage: requests at the initial macro field; oracle on a sample of them
@@ -295,14 +322,14 @@ def served(stages, with_cpu=False):
         extra["cpu_baseline"], extra["max_rel_err_vs_oracle"] = cpu_baseline(wl, 32, {"fp32": recs[0]["H"]})
     return {"workload": "served: 128x128 macro grid (EX2 macro data), 16384 requests per macro stage, "
                         "n in {32,48,64,96,128}, eps in {1/100,1/200,1/400}, mu=mu'=3eps, eta=eps^2, "
-                        "alpha_micro=1.2 HeunP, Q4 init, FP32; bursts of 256-4096 released back to back; "
-                        "4 micro-batch slots of up to 2048 requests",
-            "stages": len(recs), "value": run.cell_steps * len(recs) / st.sum(), "unit": "cell-steps/s",
-            "cell_steps_per_stage": run.cell_steps,
-            "request_latency_ms": {"p50": pct(list(lat), 50), "p99": pct(list(lat), 99)},
-            "burst_latency_ms": {"p50": pct(list(bl), 50), "p99": pct(list(bl), 99)},
-            "stage_latency_ms": {"p50": pct(list(st * 1e3), 50), "p99": pct(list(st * 1e3), 99)},
-            "status_ok": ok, **extra}
+                        "alpha_micro=1.2 HeunP, Q4 init, FP32; bursts of 256-4096; "
+                        "4 micro-batch slots of up to 2048 requests; H_avg kept on the device",
+            "stages": sat["stages"], "value": sat["value"], "unit": "cell-steps/s",
+            "cell_steps_per_stage": cell_steps,
+            "request_latency_ms": sat["request_latency_ms"],
+            "stage_latency_ms": sat["stage_latency_ms"],
+            "modes": {"saturating": sat, "open": opn, "closed": clo},
+            "status_ok": sat["status_ok"] and opn["status_ok"] and clo["status_ok"], **extra}
 
 
 WORKLOADS = {
@@ -385,7 +412,7 @@ def main():
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="two_d_batch")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the uneven-batch and served measurements added to the default line")
-    ap.add_argument("--served-stages", type=int, default=1,
+    ap.add_argument("--served-stages", type=int, default=10,
                     help="macro stages of the served 128x128 run in the default line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (PMC counter calibration)")
@@ -463,12 +490,12 @@ def main():
         line["one_d_batch"] = rec
         wu = inputs.uneven_batch()
         u = measure(wu, inputs.FP32, 3, 1, tune=True, graph=True)
-        line["uneven_batch"] = {"workload": WORKLOADS["uneven_batch"] + "; band steps per launch tuned, "
-                                "whole solve launched as one HIP graph", "dtype": "f32",
+        line["uneven_batch"] = {"workload": WORKLOADS["uneven_batch"] + "; slab variant and exchange "
+                                "interval tuned, whole solve launched as one HIP graph", "dtype": "f32",
                                 "value": u["rate"], "unit": "cell-steps/s",
                                 "ms_per_step": u["ms_per_step"], "cell_steps_per_step": u["cell_steps"],
                                 "latency_ms": {"p50": u["p50_ms"], "p99": u["p99_ms"]},
-                                "band_steps_per_launch": u["steps_per_launch"],
+                                "slabs_by_n": u["slabs"],
                                 "roofline": u["roofline"], "status_ok": u["status_ok"]}
         if not args.no_cpu:
             (line["uneven_batch"]["cpu_baseline"],

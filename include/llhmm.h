@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define LLHMM_ABI_VERSION 2
+#define LLHMM_ABI_VERSION 3
 /* FP32 domain: FP32 boxes wider than LLHMM_FP32_MAX_WIDTH_EPS eps (mu' / eps)
  * need alpha >= LLHMM_FP32_MIN_ALPHA_WIDE, and every FP32 box needs an
  * averaging radius mu >= LLHMM_FP32_MIN_MU_EPS eps; others return
@@ -229,7 +229,8 @@ llhmm_status llhmm_micro_batch(llhmm_ctx *ctx, llhmm_batch *batch, const double 
  * sums of the last llhmm_micro_batch, summed in a fixed order:
  *   H_avg_dev[b * ld + q], q < nq, nq = 3 (field, torque) or 3*dim (flux,
  *   [axis][component]), FP64.  ld >= the largest nq of the batch.  Nullable.
- *   status_dev (nullable, int32[nboxes]): 0 ok, 1 non-finite values.
+ *   status_dev (nullable, int32[nboxes]): 0 ok; bit 0 (1) non-finite values;
+ *   bit 1 (2) a slab exchange wait gave up (see Large boxes).
  * With `check` != 0 the call synchronizes the stream and returns
  * LLHMM_E_UNSTABLE if any box is non-finite. */
 llhmm_status llhmm_upscale(llhmm_ctx *ctx, llhmm_batch *batch, double *H_avg_dev, int32_t ld,
@@ -242,8 +243,8 @@ llhmm_status llhmm_upscale(llhmm_ctx *ctx, llhmm_batch *batch, double *H_avg_dev
  * the caller's stream and up to three side streams, forked after the set-up
  * kernel and joined before the upscale, as in llhmm_micro_batch.  Arguments as
  * in those two calls.  With timing enabled the whole call is reported as time
- * stepping (set-up 0).  For launch-bound callers: a batch with large boxes
- * makes one launch per band step, and the graph replays them all at once. */
+ * stepping (set-up 0).  For launch-bound callers: the set-up, the counter
+ * reset, every class launch and the upscale replay as one graph. */
 llhmm_status llhmm_batch_run_graph(llhmm_ctx *ctx, llhmm_batch *batch, const double *m_init_dev,
                                    const llhmm_macro *macro, const double *M_macro_dev,
                                    const double *coef_dev, double *m_final_dev, double *H_avg_dev,
@@ -253,8 +254,8 @@ llhmm_status llhmm_batch_run_graph(llhmm_ctx *ctx, llhmm_batch *batch, const dou
  * (code under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc).  It is llhmm_batch_create + llhmm_micro_batch + llhmm_upscale
  * (check = 0) in one call, with every buffer the kernels need beyond the
- * caller's inputs and outputs (box descriptors, per-box tables, band state,
- * partial sums, status words) placed in a static device array of
+ * caller's inputs and outputs (box descriptors, per-box tables, slab exchange
+ * rows and counters, partial sums, status words) placed in a static device array of
  * LLHMM_NOALLOC_BYTES per GPU.  Each GPU the library runs on holds that array
  * from the first llhmm_create on it until the process ends.  The call makes no
  * hipMalloc, hipFree or other device allocation; host-side planning uses the
@@ -278,23 +279,37 @@ llhmm_status llhmm_solve_noalloc(llhmm_ctx *ctx, const llhmm_box *boxes, int32_t
                                  const double *M_macro_dev, const double *coef_dev, double *H_avg_dev,
                                  int32_t ld, int32_t *status_dev, hipStream_t stream);
 
-/* Autotuner for the large boxes of a batch (2-D, n = 96 or 128, advanced in
- * row strips).  For every class (precision, n, bc, quantity, integrator) it
- * times the class alone, `reps` times after one warm-up, for each number of
- * time steps per launch from 1 to 4 whose halo fits the strip window, and keeps
- * the fastest, in the batch and in the context, so later batches of the same
- * class start from it.  More steps per launch read the strip state and
- * reference tables less often but recompute more halo rows.  Runs the set-up
- * kernel with the given inputs (as llhmm_micro_batch) and synchronizes
+/* Large boxes.  2-D boxes too large for one workgroup's registers and LDS
+ * (n = 96, 128) are cut into slabs of consecutive full-width rows, one
+ * workgroup per slab for all time steps of the box; the micro problem of
+ * eq. (micro) is still solved as one box.  A workgroup holds its slab's own
+ * rows and h halo rows on each side: the zeros it sees beyond that window
+ * corrupt one more row per Runge-Kutta stage, so the own rows stay exact for
+ * h / stages steps.  Every `steps_per_exchange` steps (1, 2, 4 or 8, with
+ * h >= steps_per_exchange x stages) the slabs publish their edge rows to global
+ * memory and replace their halo rows with their neighbours'; the box state
+ * never leaves the chip otherwise.  Each class runs as one persistent launch
+ * whose workgroups take (box, slab) items, longest boxes first.  A wait for a
+ * neighbouring slab gives up after a bounded number of polls; the boxes
+ * involved then report status 2 and llhmm_upscale with check returns
+ * LLHMM_E_HIP.
+ *
+ * Autotuner for these boxes.  For every class (precision, n, bc, quantity,
+ * integrator) it times the class alone, `reps` times after one warm-up, with
+ * each slab tile variant (window height and workgroup shape) and each exchange
+ * interval the variant's window allows, and keeps the fastest, in the batch and
+ * in the context, so later batches of the same class start from it.  Runs the
+ * set-up kernel with the given inputs (as llhmm_micro_batch) and synchronizes
  * `stream`.  The result of the last llhmm_micro_batch is overwritten.  A
  * captured graph of the batch is dropped. */
 llhmm_status llhmm_batch_tune(llhmm_ctx *ctx, llhmm_batch *batch, const double *m_init_dev,
                               const llhmm_macro *macro, const double *M_macro_dev,
                               const double *coef_dev, int32_t reps, hipStream_t stream);
-/* Steps per launch of each box (0 for boxes solved by the resident kernels). */
-llhmm_status llhmm_batch_band_steps(const llhmm_batch *batch, int32_t *steps_out);
+/* Slabs of each box and its steps between exchanges (0 for boxes solved whole
+ * by one workgroup); steps_per_exchange_out may be NULL. */
+llhmm_status llhmm_batch_slabs(const llhmm_batch *batch, int32_t *slabs_out, int32_t *steps_per_exchange_out);
 /* The context's tuning table as text: one line "precision n bc quantity
- * stages steps_per_launch" per class.  Load merges into the table. */
+ * stages variant steps_per_exchange" per class.  Load merges into the table. */
 llhmm_status llhmm_tune_save(const llhmm_ctx *ctx, const char *path);
 llhmm_status llhmm_tune_load(llhmm_ctx *ctx, const char *path);
 
@@ -401,6 +416,15 @@ llhmm_status llhmm_server_submit(llhmm_server *server, const llhmm_box *boxes, i
 llhmm_status llhmm_server_poll(llhmm_server *server, int32_t wait, int32_t max, int64_t *ids_out,
                                double *H_out, int32_t *status_out, double *latency_us_out,
                                int32_t *ndone);
+/* Results on the device as well: from the next micro-batch admitted on, each
+ * request's upscaled values (min(ld, 6) of them, laid out as in H_out) are
+ * also written to H_dev[id * ld + q] for 0 <= id < nrows (other ids only go
+ * to poll), on the micro-batch's stream before its completion; a result that
+ * poll has returned is in H_dev for any work enqueued after that poll (so a
+ * macro stage can read its field where the micro-batches left it).  H_dev
+ * must stay valid while such requests are in flight; NULL turns it off.
+ * Errors: LLHMM_E_INVALID (ld or nrows < 1). */
+llhmm_status llhmm_server_set_output(llhmm_server *server, double *H_dev, int32_t ld, int64_t nrows);
 /* Requests queued, requests in flight, device bytes in use and reserved. */
 llhmm_status llhmm_server_stats(const llhmm_server *server, int64_t *queued, int64_t *inflight,
                                 int64_t *bytes_in_use, int64_t *bytes_total);

@@ -25,7 +25,7 @@ SOURCES = [
     "llhmm_tiles_f64_2d.hip",
     "llhmm_tiles_f32_1d.hip",
     "llhmm_tiles_f64_1d.hip",
-    "llhmm_tiles_band.hip",
+    "llhmm_tiles_slab.hip",
     "llhmm_micro3d.hip",
 ]
 

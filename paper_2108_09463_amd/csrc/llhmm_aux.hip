@@ -10,9 +10,44 @@
 //   k_flux_div: the divergence of the averaged flux of the flux model
 //              eq. (macro_flux) at the macro nodes from the fluxes at the
 //              staggered points x_i + dX/2 e_j.  FP64.
+//   k_fill_i32: sets an int32 array (the slab kernels' counters and exchange words) to a value;
+//              a kernel rather than a memset, so that graph replays reset it.
+//   k_scatter_rows: copies each served request's upscaled values into the
+//              caller's device array at the row the request's id names.
+#include <algorithm>
+
 #include "llhmm_internal.h"
 
 namespace llhmm {
+
+__global__ void __launch_bounds__(256) k_fill_i32(int32_t *p, int64_t n, int32_t v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(256) k_scatter_rows(const double *src, int src_ld, const int64_t *ids, int n,
+                                                      int nq, double *dst, int ld, int64_t nrows) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * nq) return;
+    const int r = i / nq, q = i - r * nq;
+    const int64_t id = ids[r];
+    if (id >= 0 && id < nrows) dst[id * ld + q] = src[(int64_t)r * src_ld + q];
+}
+
+hipError_t launch_scatter_rows(const double *src, int src_ld, const int64_t *ids, int n, int nq, double *dst,
+                               int ld, int64_t nrows, hipStream_t s) {
+    if (n <= 0 || nq <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scatter_rows, dim3((unsigned)((n * nq + 255) / 256)), dim3(256), 0, s, src, src_ld, ids,
+                       n, nq, dst, ld, nrows);
+    return hipGetLastError();
+}
 
 __global__ void __launch_bounds__(256) k_upscale(const double *partials, const int32_t *wave_status,
                                                  const double *box_const, const BoxPlan *plans,

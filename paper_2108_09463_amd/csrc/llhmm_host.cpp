@@ -249,62 +249,106 @@ const std::map<TileKey, const TileInfo *> &registry() {
     return reg;
 }
 
-struct BandKey {
-    int prec, n, bc, qty;
-    bool operator<(const BandKey &o) const {
-        return std::tie(prec, n, bc, qty) < std::tie(o.prec, o.n, o.bc, o.qty);
+struct SlabKey {
+    int prec, n, order, bc, qty;
+    bool operator<(const SlabKey &o) const {
+        return std::tie(prec, n, order, bc, qty) < std::tie(o.prec, o.n, o.order, o.bc, o.qty);
     }
 };
 
-// Band tile variants per class, in registration order (the first is the default).
-const std::map<BandKey, std::vector<const BandTileInfo *>> &band_registry() {
-    static std::map<BandKey, std::vector<const BandTileInfo *>> reg = [] {
-        std::map<BandKey, std::vector<const BandTileInfo *>> r;
+// Slab tile variants per class, in registration order (the first is the default).
+const std::map<SlabKey, std::vector<const SlabTileInfo *>> &slab_registry() {
+    static std::map<SlabKey, std::vector<const SlabTileInfo *>> reg = [] {
+        std::map<SlabKey, std::vector<const SlabTileInfo *>> r;
         int cnt = 0;
-        const BandTileInfo *t = tiles_band(&cnt);
-        for (int i = 0; i < cnt; ++i) r[BandKey{t[i].prec, t[i].n, t[i].bc, t[i].qty}].push_back(&t[i]);
+        const SlabTileInfo *t = tiles_slab(&cnt);
+        for (int i = 0; i < cnt; ++i) r[SlabKey{t[i].prec, t[i].n, 2, t[i].bc, t[i].qty}].push_back(&t[i]);
         return r;
     }();
     return reg;
 }
 
-// Strip geometry of a band box: steps per launch s, halo rows h = s * stages
-// rounded up to a multiple of the rows per lane R (so that box row 0 starts a
-// row group), at most `cap` own rows per strip (a multiple of R), and own-row
-// counts that split the box's n / R row groups as evenly as possible.
-struct BandGeom {
-    int s, h, strips;
-    std::vector<std::pair<int, int>> own;  // (first row, rows) per strip
+// Slab geometry of an n x n box for a tile whose window holds WR = R * NG rows,
+// with `stages` Runge-Kutta stages per step and an exchange every `spe` steps:
+// h halo rows on each side (each stage moves the error of the zeros beyond the
+// window one row inwards, so h >= spe * stages, rounded up to whole row
+// groups), at most WR - 2h own rows per slab, the box's row groups split as
+// evenly as possible over ns >= 2 slabs.  A slab's north halo is what its
+// window has left, WR - h - own >= h rows; the neighbours publish the xd
+// rows the deepest halo needs, which every slab must own.  ns = 0: invalid.
+struct SlabGeom {
+    int spe = 0, h = 0, ns = 0, xd = 0;
 };
 
-bool band_geometry(const BandTileInfo &t, int n, int stages, int steps_per_launch, BandGeom &g) {
-    const int R = t.R, WR = t.R * t.NG;
-    if (n % R != 0 || WR > n) return false;
-    g.s = std::max(1, steps_per_launch);
-    g.h = ((g.s * stages + R - 1) / R) * R;
-    const int cap = ((WR - 2 * g.h) / R) * R;
-    if (cap < R) return false;
-    const int groups = n / R, per = cap / R;
-    g.strips = (groups + per - 1) / per;
-    g.own.clear();
-    for (int t2 = 0; t2 < g.strips; ++t2) {
-        const int a = (int)((int64_t)t2 * groups / g.strips), b = (int)((int64_t)(t2 + 1) * groups / g.strips);
-        g.own.emplace_back(a * R, (b - a) * R);
-    }
-    return true;
+constexpr int kSlabSpe[] = {1, 2, 4, 8};  // exchange intervals; each divides kRerefSteps
+
+SlabGeom slab_geom(const SlabTileInfo &t, int n, int stages, int spe) {
+    SlabGeom g;
+    const int WR = t.R * t.NG;
+    if (n % t.R != 0 || kRerefSteps % spe != 0) return g;
+    const int h = (spe * stages + t.R - 1) / t.R * t.R;
+    const int capg = (WR - 2 * h) / t.R;  // own row groups per slab at most
+    if (capg < 1) return g;
+    const int groups = n / t.R;
+    const int ns = (groups + capg - 1) / capg;
+    const int own_min = groups / ns * t.R;
+    const int xd = WR - h - own_min;
+    if (ns < 2 || own_min < xd) return g;
+    g.spe = spe;
+    g.h = h;
+    g.ns = ns;
+    g.xd = xd;
+    return g;
 }
 
-constexpr int kMaxStepsPerLaunch = 4;
+// Own rows of slab s: the first (groups % ns) slabs take one row group more.
+void slab_rows(const SlabTileInfo &t, int n, int ns, int s, int *o0, int *rows) {
+    const int groups = n / t.R, base = groups / ns, extra = groups % ns;
+    *o0 = (s * base + std::min(s, extra)) * t.R;
+    *rows = (base + (s < extra ? 1 : 0)) * t.R;
+}
 
-// Partial-sum slots a band box needs for any variant and any steps per launch.
-int64_t band_max_slots(const std::vector<const BandTileInfo *> &variants, int n, int stages) {
-    int64_t m = 0;
-    for (const BandTileInfo *t : variants)
-        for (int sc = 1; sc <= kMaxStepsPerLaunch; ++sc) {
-            BandGeom g;
-            if (band_geometry(*t, n, stages, sc, g)) m = std::max<int64_t>(m, (int64_t)g.strips * (t->threads / 64));
+// Exchange interval without tuning: fewest window rows computed per box, an
+// exchange weighted as half a step of the window.
+int slab_default_spe(const SlabTileInfo &t, int n, int stages) {
+    int best = 0;
+    double best_cost = 0.0;
+    for (int spe : kSlabSpe) {
+        const SlabGeom g = slab_geom(t, n, stages, spe);
+        if (g.ns == 0) continue;
+        const double cost = g.ns * (1.0 + 0.5 / spe);
+        if (best == 0 || cost < best_cost) {
+            best = spe;
+            best_cost = cost;
         }
-    return m;
+    }
+    return best;
+}
+
+// 64-bit exchange words of a box: [slabs][2 edges][2 parities][xd rows][3][n],
+// two words per value in FP64.
+int64_t slab_xwords(const SlabTileInfo &t, int n, const SlabGeom &g) {
+    return (int64_t)g.ns * 2 * 2 * g.xd * 3 * n * (t.prec == LLHMM_FP64 ? 2 : 1);
+}
+
+// Per-box reservations that fit every variant and exchange interval of the
+// class (tuning swaps them without reallocating): partial-sum slots, exchange
+// words and work items.
+struct SlabReserve {
+    int64_t slots = 0, xwords = 0, items = 0;
+};
+
+SlabReserve slab_reserve(const std::vector<const SlabTileInfo *> &variants, int n, int stages) {
+    SlabReserve r;
+    for (const SlabTileInfo *t : variants)
+        for (int spe : kSlabSpe) {
+            const SlabGeom g = slab_geom(*t, n, stages, spe);
+            if (g.ns == 0) continue;
+            r.slots = std::max<int64_t>(r.slots, (int64_t)g.ns * (t->threads / 64));
+            r.xwords = std::max<int64_t>(r.xwords, slab_xwords(*t, n, g));
+            r.items = std::max<int64_t>(r.items, g.ns);
+        }
+    return r;
 }
 
 template <typename T>
@@ -319,7 +363,7 @@ hipError_t dev_upload(T **dst, const T *src, size_t count) {
 }  // namespace
 
 using TuneKey = std::tuple<int, int, int, int, int>;  // precision, n, bc, quantity, stages
-using TuneVal = std::pair<int, int>;                   // band tile variant, steps per launch
+using TuneVal = std::pair<int, int>;                   // slab tile variant, steps per exchange
 
 // Device memory reserved once and handed out in 256-byte aligned pieces
 // (first fit, neighbouring free pieces merged on release).  The serving loop
@@ -386,7 +430,7 @@ struct Arena {
 struct llhmm_ctx {
     int device;
     char *scratch = nullptr;           // this device's copy of the allocation-free solve's scratch array
-    std::map<TuneKey, TuneVal> tuned;  // band classes: variant and steps per launch from llhmm_batch_tune
+    std::map<TuneKey, TuneVal> tuned;  // slab classes: tile variant from llhmm_batch_tune
 };
 
 struct ClassLaunch {
@@ -395,13 +439,21 @@ struct ClassLaunch {
     double cost;                // cell-stage estimate, for spreading classes over streams
 };
 
-struct BandClass {
-    const BandTileInfo *tile;
-    int s, h;                     // steps per launch, halo rows
-    int first, count;             // range in the concatenated job list
-    std::vector<int> active;      // jobs still running in launch p (a prefix: longest boxes first)
+struct SlabClass {
+    const SlabTileInfo *tile;
+    SlabGeom geom;                // shared by the class's boxes (same n, stages and interval)
+    int stages;
+    int first, count;             // range of (box, slab) items in the concatenated job list
+    int index;                    // class index: its work counter and abort word in slab_sync
     double cost;
 };
+
+// Polls before a wait for a neighbouring slab gives up (about a minute at the
+// poll interval); LLHMM_SLAB_SPIN_MAX overrides it (tests of the give-up path).
+long long slab_spin_max() {
+    const char *e = getenv("LLHMM_SLAB_SPIN_MAX");
+    return e ? std::max(0LL, atoll(e)) : (1LL << 26);
+}
 
 constexpr int kSideStreams = 3;   // extra streams a batch spreads its classes over
 
@@ -417,17 +469,22 @@ struct GraphArgs {
 
 struct llhmm_batch {
     int nboxes, prec, dim_max, nmax;
+    int ncu = 1;                                  // compute units of the device (slab grid size)
     int64_t cell_steps;
     bool any_explicit, any_macro, any_sampled;
     std::vector<BoxPlan> plans_h;
     std::vector<ClassLaunch> classes;
-    std::vector<BandClass> bands;
-    std::vector<const BandTileInfo *> band_tile;  // per box; nullptr for resident boxes
-    std::vector<int> band_s;                      // per box: time steps per band launch
+    std::vector<SlabClass> slabs;
+    std::vector<const SlabTileInfo *> slab_tile;  // per box; nullptr for resident boxes
+    std::vector<int> slab_spe;                    // per slab box: steps between exchanges
+    std::vector<int64_t> xoff_h;                  // per slab box: first exchange word
     BoxPlan *plans = nullptr;
-    BandJob *jobs = nullptr;
-    void *state[2] = {nullptr, nullptr};  // band boxes' state, ping-pong between launches
-    void *refbuf[2] = {nullptr, nullptr}; // FP32 band boxes' reference tables, ping-pong
+    SlabJob *jobs = nullptr;
+    uint64_t *xbuf = nullptr;                     // slab boxes' exchanged edge rows (tagged words)
+    int64_t nxwords = 0;
+    int32_t *slab_sync = nullptr;                 // per class: work counter, abort word
+    int64_t nsync = 0;                            // int32 entries of slab_sync
+    int nslab_boxes = 0;
     int32_t *box_ids = nullptr;
     int32_t *box3_ids = nullptr;                  // the d = 3 boxes
     int nbox3 = 0, nmax3 = 0;
@@ -487,59 +544,56 @@ static hipError_t bupload(llhmm_batch *b, T **dst, const T *src, size_t count) {
     return bcopy_h2d(b, *dst, src, sizeof(T) * count);
 }
 
-// Band boxes: strip geometry from each box's steps per launch, classes by
-// (tile, steps per launch, halo) with the jobs of the longest boxes first,
-// uploaded with the plans.  Drops a captured graph (its launches change).
-static llhmm_status rebuild_bands(llhmm_batch *b) {
-    std::map<std::tuple<const BandTileInfo *, int, int>, std::vector<int>> groups;
-    std::vector<BandGeom> geom(b->nboxes);
+// Slab boxes: classes by tile; per class the (box, slab) items, the slabs of
+// a box consecutive and the longest boxes first (LPT order), uploaded with the
+// plans into the job buffer reserved at creation.  Drops a captured graph (its
+// launches change).
+static llhmm_status rebuild_slabs(llhmm_batch *b) {
+    std::map<std::tuple<const SlabTileInfo *, int, int>, std::vector<int>> groups;  // tile, stages, interval
     for (int i = 0; i < b->nboxes; ++i) {
-        const BandTileInfo *t = b->band_tile[i];
+        const SlabTileInfo *t = b->slab_tile[i];
         if (!t) continue;
         BoxPlan &P = b->plans_h[i];
-        if (!band_geometry(*t, P.n, P.stages, b->band_s[i], geom[i]))
-            return fail(LLHMM_E_INVALID, "box %d: %d steps per launch do not fit the window", i, b->band_s[i]);
-        P.strips = geom[i].strips;
-        P.nwaves = geom[i].strips * (t->threads / 64);
-        groups[std::make_tuple(t, geom[i].s, geom[i].h)].push_back(i);
+        const SlabGeom g = slab_geom(*t, P.n, P.stages, b->slab_spe[i]);
+        if (g.ns == 0)
+            return fail(LLHMM_E_INVALID, "box %d: n = %d has no slab geometry for %s every %d steps", i, P.n,
+                        t->name, b->slab_spe[i]);
+        P.strips = g.ns;
+        P.nwaves = g.ns * (t->threads / 64);
+        groups[std::make_tuple(t, P.stages, g.spe)].push_back(i);
     }
-    b->bands.clear();
-    std::vector<BandJob> jobs_h;
+    b->slabs.clear();
+    std::vector<SlabJob> jobs_h;
     for (auto &kv : groups) {
         auto &v = kv.second;
-        std::stable_sort(v.begin(), v.end(), [&](int a, int c) { return b->plans_h[a].M > b->plans_h[c].M; });
-        BandClass bc;
-        bc.tile = std::get<0>(kv.first);
-        bc.s = std::get<1>(kv.first);
-        bc.h = std::get<2>(kv.first);
-        bc.first = (int)jobs_h.size();
-        bc.cost = 0.0;
-        std::vector<int> jobM;
+        std::stable_sort(v.begin(), v.end(), [&](int a, int c) {
+            return (int64_t)b->plans_h[a].M * b->plans_h[a].stages > (int64_t)b->plans_h[c].M * b->plans_h[c].stages;
+        });
+        SlabClass sc;
+        sc.tile = std::get<0>(kv.first);
+        sc.stages = std::get<1>(kv.first);
+        sc.geom = slab_geom(*sc.tile, b->plans_h[v[0]].n, sc.stages, std::get<2>(kv.first));
+        sc.first = (int)jobs_h.size();
+        sc.index = (int)b->slabs.size();
+        sc.cost = 0.0;
+        const int WR = sc.tile->R * sc.tile->NG;
         for (int i : v) {
-            const BandGeom &g = geom[i];
-            for (int t = 0; t < g.strips; ++t) {
-                jobs_h.push_back(BandJob{i, t, g.own[t].first, g.own[t].second});
-                jobM.push_back(b->plans_h[i].M);
+            const BoxPlan &P = b->plans_h[i];
+            for (int s = 0; s < sc.geom.ns; ++s) {
+                SlabJob J{};
+                J.box = i;
+                J.slab = s;
+                J.nslabs = sc.geom.ns;
+                slab_rows(*sc.tile, P.n, sc.geom.ns, s, &J.o0, &J.rows);
+                J.xoff = b->xoff_h[i];
+                jobs_h.push_back(J);
             }
-            bc.cost += (double)b->plans_h[i].M * b->plans_h[i].stages * b->plans_h[i].n * b->plans_h[i].n;
+            sc.cost += (double)P.M * P.stages * sc.geom.ns * WR * P.n;  // window rows computed
         }
-        bc.count = (int)jobs_h.size() - bc.first;
-        const int launches = (jobM[0] + bc.s - 1) / bc.s;
-        for (int p = 0, cnt = bc.count; p < launches; ++p) {
-            while (cnt > 0 && jobM[cnt - 1] <= p * bc.s) --cnt;
-            bc.active.push_back(cnt);
-        }
-        b->bands.push_back(std::move(bc));
+        sc.count = (int)jobs_h.size() - sc.first;
+        b->slabs.push_back(sc);
     }
-    if (b->jobs) {
-        bfree(b, b->jobs);
-        b->jobs = nullptr;
-    }
-    if (!jobs_h.empty()) {
-        const hipError_t e = bupload(b, &b->jobs, jobs_h.data(), jobs_h.size());
-        if (e == hipErrorOutOfMemory) return fail(LLHMM_E_NOMEM, "band jobs: out of memory");
-        HIP_TRY(e);
-    }
+    if (!jobs_h.empty()) HIP_TRY(bcopy_h2d(b, b->jobs, jobs_h.data(), sizeof(SlabJob) * jobs_h.size()));
     HIP_TRY(bcopy_h2d(b, b->plans, b->plans_h.data(), sizeof(BoxPlan) * b->plans_h.size()));
     if (b->exec) {
         HIP_TRY(hipGraphExecDestroy(b->exec));
@@ -606,8 +660,7 @@ llhmm_status llhmm_check_boxes(const llhmm_box *boxes, int32_t nboxes, int32_t n
         if (s == LLHMM_OK) s = check_fp32_domain(bx, i, precision);
         if (s == LLHMM_OK && bx.dim != 3 &&
             registry().find(TileKey{precision, bx.dim, bx.n, bx.order, bx.bc, bx.quantity}) == registry().end() &&
-            !(bx.dim == 2 && bx.order == 2 &&
-              band_registry().find(BandKey{precision, bx.n, bx.bc, bx.quantity}) != band_registry().end()))
+            !(bx.dim == 2 && slab_registry().count(SlabKey{precision, bx.n, bx.order, bx.bc, bx.quantity})))
             s = fail(LLHMM_E_NOTSUP, "box %d: no kernel for precision %s, dim %d, n %d, order %d, bc %d, quantity %d",
                      i, precision == LLHMM_FP32 ? "fp32" : "fp64", bx.dim, bx.n, bx.order, bx.bc, bx.quantity);
         if (s != LLHMM_OK) {
@@ -630,7 +683,7 @@ static void batch_free(llhmm_batch *b) {
     if (!b) return;
     void *ptrs[] = {b->plans, b->box_ids, b->coefs, b->tabs, b->wts, b->wt, b->partials,
                     b->wave_status, b->status, b->box_const, b->scratch64, b->jobs,
-                    b->state[0], b->state[1], b->refbuf[0], b->refbuf[1], b->box3_ids, b->work3d};
+                    b->xbuf, b->slab_sync, b->box3_ids, b->work3d};
     for (void *p : ptrs) bfree(b, p);
     for (auto &slot : b->ev)
         for (hipEvent_t e : slot)
@@ -675,8 +728,11 @@ static llhmm_status batch_create_impl(llhmm_ctx *ctx, const llhmm_box *boxes, in
     }
     HIP_TRY(hipSetDevice(ctx->device));
     double dcoef[8] = {0};
+    int ncu = 0;
+    HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ctx->device));
     llhmm_batch *b = new llhmm_batch();
     b->arena = arena;
+    b->ncu = std::max(1, ncu);
     b->upload_stream = upload_stream;
     b->async_upload = async_upload;
     b->max_lanes = std::max(1, std::min(max_lanes, 1 + kSideStreams));
@@ -692,12 +748,13 @@ static llhmm_status batch_create_impl(llhmm_ctx *ctx, const llhmm_box *boxes, in
     b->kq = K->q_x;
 
     const auto &reg = registry();
-    const auto &bregistry = band_registry();
+    const auto &sregistry = slab_registry();
     const size_t tsize = (precision == LLHMM_FP32) ? sizeof(float) : sizeof(double);
     b->plans_h.resize(nboxes);
     std::vector<const TileInfo *> tile_of(nboxes);
-    b->band_tile.assign(nboxes, nullptr);
-    b->band_s.assign(nboxes, 0);
+    b->slab_tile.assign(nboxes, nullptr);
+    b->slab_spe.assign(nboxes, 0);
+    b->xoff_h.assign(nboxes, 0);
     int dim_max = 1, nmax = 0;
     for (int i = 0; i < nboxes; ++i) {
         dim_max = std::max(dim_max, boxes[i].dim);
@@ -705,7 +762,8 @@ static llhmm_status batch_create_impl(llhmm_ctx *ctx, const llhmm_box *boxes, in
     }
     b->dim_max = dim_max;
     b->nmax = nmax;
-    int64_t tab_off = 0, w_off = 0, s64_off = 0, part_off = 0, state_off = 0, ref_off = 0, work3_off = 0;
+    int64_t tab_off = 0, w_off = 0, s64_off = 0, part_off = 0, work3_off = 0;
+    int64_t xbuf_off = 0, max_items = 0;
     std::vector<int32_t> ids3;
     std::map<int, int64_t> wt_off_of_M;
     std::vector<double> wt_h;
@@ -731,25 +789,28 @@ static llhmm_status batch_create_impl(llhmm_ctx *ctx, const llhmm_box *boxes, in
             return st;
         }
         auto it = reg.find(TileKey{precision, bx.dim, bx.n, bx.order, bx.bc, bx.quantity});
-        const BandTileInfo *bt = nullptr;
-        BandGeom bg;
-        int band_s = 0;
-        int64_t band_slots = 0;
-        if (it == reg.end() && bx.dim == 2 && bx.order == 2) {
-            auto bit = bregistry.find(BandKey{precision, bx.n, bx.bc, bx.quantity});
+        const SlabTileInfo *bt = nullptr;
+        SlabReserve sres;
+        if (it == reg.end() && bx.dim == 2) {
+            auto bit = sregistry.find(SlabKey{precision, bx.n, bx.order, bx.bc, bx.quantity});
             const int stages = (pl.integ == LLHMM_RK4P) ? 4 : 2;
-            if (bit != bregistry.end()) {
-                // the tuned variant and steps per launch for this class, else the
-                // first variant with one halo of 4 rows
-                int v = 0;
-                band_s = std::max(1, 4 / stages);
+            if (bit != sregistry.end()) {
+                // the tuned variant and interval for this class, else the first
+                // variant with its default interval
+                int v = 0, spe = 0;
                 auto tit = ctx->tuned.find(TuneKey{precision, bx.n, bx.bc, bx.quantity, stages});
-                if (tit != ctx->tuned.end() && tit->second.first < (int)bit->second.size()) {
+                if (tit != ctx->tuned.end() && tit->second.first < (int)bit->second.size() &&
+                    slab_geom(*bit->second[tit->second.first], bx.n, stages, tit->second.second).ns > 0) {
                     v = tit->second.first;
-                    band_s = tit->second.second;
+                    spe = tit->second.second;
+                } else {
+                    spe = slab_default_spe(*bit->second[0], bx.n, stages);
                 }
-                if (band_geometry(*bit->second[v], bx.n, stages, band_s, bg)) bt = bit->second[v];
-                band_slots = band_max_slots(bit->second, bx.n, stages);
+                if (spe > 0) {
+                    bt = bit->second[v];
+                    b->slab_spe[i] = spe;
+                }
+                sres = slab_reserve(bit->second, bx.n, stages);
             }
         }
         if (it == reg.end() && !bt && bx.dim != 3) {
@@ -760,8 +821,7 @@ static llhmm_status batch_create_impl(llhmm_ctx *ctx, const llhmm_box *boxes, in
                         bx.quantity);
         }
         tile_of[i] = (bt || bx.dim == 3) ? nullptr : it->second;
-        b->band_tile[i] = bt;
-        b->band_s[i] = band_s;
+        b->slab_tile[i] = bt;
         BoxPlan &P = b->plans_h[i];
         memset(&P, 0, sizeof P);
         P.dim = bx.dim;
@@ -780,10 +840,10 @@ static llhmm_status batch_create_impl(llhmm_ctx *ctx, const llhmm_box *boxes, in
         P.coef_sampled = coefs[bx.coef_index].sampled ? 1 : 0;
         int64_t slots;
         if (bt) {
-            // strips and partial-sum slots follow the steps per launch; reserve the
-            // slots of the largest strip count any choice can give
-            P.band = 1;
-            slots = band_slots;
+            // slabs and partial-sum slots follow the variant; reserve for the
+            // largest slab count any variant gives
+            P.slab = 1;
+            slots = sres.slots;
         } else if (bx.dim == 3) {
             P.nwaves = 1;
             slots = 1;
@@ -794,13 +854,13 @@ static llhmm_status batch_create_impl(llhmm_ctx *ctx, const llhmm_box *boxes, in
         P.part_offset = part_off;
         part_off += slots;
         if (bt) {
-            P.state_offset = state_off;
-            state_off += 3 * (int64_t)bx.n * bx.n;
-            P.ref_offset = ref_off;
-            if (precision == LLHMM_FP32) ref_off += 7 * (int64_t)bx.n * bx.n;
+            b->xoff_h[i] = xbuf_off;
+            xbuf_off += sres.xwords;
+            max_items += sres.items;
+            ++b->nslab_boxes;
         }
         P.prec = precision;
-        P.form = (precision == LLHMM_FP32 || P.band) ? 1 : 0;
+        P.form = (precision == LLHMM_FP32 || P.slab) ? 1 : 0;
         if (bx.dim == 3) P.form = 0;
         P.dt = pl.dt;
         P.alpha = bx.alpha;
@@ -866,7 +926,7 @@ static llhmm_status batch_create_impl(llhmm_ctx *ctx, const llhmm_box *boxes, in
     std::map<std::tuple<const TileInfo *, int, int>, std::vector<int>> groups;
     for (int i = 0; i < nboxes; ++i) {
         const TileInfo *t = tile_of[i];
-        if (!t) continue;  // band box
+        if (!t) continue;  // slab box
         const int key_m = (t->dim == 1) ? b->plans_h[i].M : 0;
         const int key_s = (t->dim == 1) ? b->plans_h[i].stages : 0;
         groups[std::make_tuple(t, key_m, key_s)].push_back(i);
@@ -905,8 +965,15 @@ static llhmm_status batch_create_impl(llhmm_ctx *ctx, const llhmm_box *boxes, in
     if (e == hipSuccess) e = balloc(b, (void **)&b->wts, sizeof(double) * std::max<int64_t>(w_off, 1));
     if (e == hipSuccess) e = balloc(b, (void **)&b->partials, sizeof(double) * (size_t)part_off * kMaxQ);
     if (e == hipSuccess) e = balloc(b, (void **)&b->wave_status, sizeof(int32_t) * (size_t)part_off);
-    for (int k = 0; k < 2 && e == hipSuccess && state_off > 0; ++k) e = balloc(b, &b->state[k], tsize * state_off);
-    for (int k = 0; k < 2 && e == hipSuccess && ref_off > 0; ++k) e = balloc(b, &b->refbuf[k], tsize * ref_off);
+    if (b->nslab_boxes > 0) {
+        // slab_sync: a work counter and an abort word per class (at most one class
+        // per slab box)
+        b->nsync = 2 * (int64_t)b->nslab_boxes;
+        b->nxwords = xbuf_off;
+        if (e == hipSuccess) e = balloc(b, (void **)&b->slab_sync, sizeof(int32_t) * b->nsync);
+        if (e == hipSuccess) e = balloc(b, (void **)&b->xbuf, sizeof(uint64_t) * xbuf_off);
+        if (e == hipSuccess) e = balloc(b, (void **)&b->jobs, sizeof(SlabJob) * max_items);
+    }
     if (e == hipSuccess) e = balloc(b, (void **)&b->status, sizeof(int32_t) * (size_t)nboxes);
     if (e == hipSuccess) e = balloc(b, (void **)&b->box_const, sizeof(double) * (size_t)nboxes * kMaxQ);
     if (e == hipSuccess) e = balloc(b, (void **)&b->scratch64, sizeof(double) * std::max<int64_t>(s64_off, 1));
@@ -918,7 +985,7 @@ static llhmm_status batch_create_impl(llhmm_ctx *ctx, const llhmm_box *boxes, in
         return fail(e == hipErrorOutOfMemory ? LLHMM_E_NOMEM : LLHMM_E_HIP, "batch allocation: %s",
                     hipGetErrorString(e));
     }
-    st = rebuild_bands(b);
+    st = rebuild_slabs(b);
     if (st != LLHMM_OK) {
         batch_free(b);
         return st;
@@ -1004,43 +1071,57 @@ static llhmm_status launch_resident(llhmm_batch *b, const ClassLaunch &cl, int m
     return LLHMM_OK;
 }
 
-// All launches of one band class, in order on one stream (each launch reads
-// the state the previous one wrote).
-static llhmm_status launch_band_class(llhmm_batch *b, const BandClass &bc, int mode, double *field_dev,
+// Zeroes the slab classes' counters, abort words and exchange words.
+static hipError_t clear_slab_sync(llhmm_batch *b, hipStream_t stream) {
+    if (b->nsync == 0) return hipSuccess;
+    hipError_t e = launch_fill_i32(b->slab_sync, b->nsync, 0, stream);
+    if (e == hipSuccess) e = launch_fill_i32((int32_t *)b->xbuf, 2 * b->nxwords, 0, stream);
+    return e;
+}
+
+// Workgroups of a slab tile that fit one CU at once (cached per tile).
+static llhmm_status slab_blocks_per_cu(const SlabTileInfo *t, int *out) {
+    static std::mutex mu;
+    static std::map<const SlabTileInfo *, int> cache;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find(t);
+    if (it == cache.end()) {
+        int bpc = 0;
+        HIP_TRY(t->occupancy(&bpc));
+        if (bpc < 1) return fail(LLHMM_E_HIP, "%s: no workgroup fits a CU", t->name);
+        it = cache.emplace(t, bpc).first;
+    }
+    *out = it->second;
+    return LLHMM_OK;
+}
+
+// One persistent launch of a slab class: as many workgroups as fit the GPU at
+// once (at most one per item); they take the class's items in order.
+static llhmm_status launch_slab_class(llhmm_batch *b, const SlabClass &sc, int mode, double *field_dev,
                                       hipStream_t stream) {
-    BandArgs a{};
+    int bpc = 0;
+    llhmm_status st = slab_blocks_per_cu(sc.tile, &bpc);
+    if (st != LLHMM_OK) return st;
+    SlabArgs a{};
     a.plans = b->plans;
-    a.jobs = b->jobs + bc.first;
+    a.jobs = b->jobs + sc.first;
+    a.nitems = sc.count;
     a.mode = mode;
-    a.h = bc.h;
+    a.counter = b->slab_sync + 2 * sc.index;
+    a.abort_word = b->slab_sync + 2 * sc.index + 1;
+    a.spin_max = slab_spin_max();
+    a.h = sc.geom.h;
+    a.spe = sc.geom.spe;
+    a.xdepth = sc.geom.xd;
     a.tabs = b->tabs;
     a.wts = b->wts;
     a.wt = b->wt;
     a.partials = b->partials;
     a.wave_status = b->wave_status;
+    a.xbuf = b->xbuf;
     a.out_field = field_dev;
-    if (mode == 1) {
-        a.njobs = bc.count;
-        a.step0 = 0;
-        a.steps = 0;
-        HIP_TRY(bc.tile->launch(a, bc.count, stream));
-        return LLHMM_OK;
-    }
-    // FP32 reference tables: the set-up tables until the first re-reference,
-    // then whichever buffer the last re-referencing launch wrote
-    int cur = -1;
-    for (size_t p = 0; p < bc.active.size(); ++p) {
-        a.njobs = bc.active[p];
-        a.step0 = (int)p * bc.s;
-        a.steps = bc.s;
-        a.state_in = b->state[p & 1];
-        a.state_out = b->state[(p + 1) & 1];
-        a.reref = (b->prec == LLHMM_FP32) && a.step0 > 0 && (a.step0 % kRerefSteps) < bc.s;
-        a.ref_in = (cur < 0) ? nullptr : b->refbuf[cur];
-        a.ref_out = b->refbuf[(cur < 0) ? 0 : 1 - cur];
-        HIP_TRY(bc.tile->launch(a, a.njobs, stream));
-        if (a.reref) cur = (cur < 0) ? 0 : 1 - cur;
-    }
+    const int grid = std::min(sc.count, bpc * b->ncu);
+    HIP_TRY(sc.tile->launch(a, grid, stream));
     return LLHMM_OK;
 }
 
@@ -1099,13 +1180,17 @@ static llhmm_status run_batch(llhmm_ctx *ctx, llhmm_batch *b, const double *m_in
         a3.kq = b->kq;
         HIP_TRY(launch_setup3d(a3, stream));
     }
+    // slab classes: work counters, abort words and the exchange words' tags
+    // start at zero (a kernel, not a memset, so that a captured graph resets
+    // them on replay)
+    HIP_TRY(clear_slab_sync(b, stream));
     if (timed) HIP_TRY(hipEventRecord(ev[1], stream));
 
-    // work items: resident classes (index >= 0) and band classes (~index)
+    // work items: resident classes (index >= 0) and slab classes (~index)
     struct Item { double cost; int idx; };
     std::vector<Item> items;
     for (size_t i = 0; i < b->classes.size(); ++i) items.push_back({b->classes[i].cost, (int)i});
-    for (size_t i = 0; i < b->bands.size(); ++i) items.push_back({b->bands[i].cost, ~(int)i});
+    for (size_t i = 0; i < b->slabs.size(); ++i) items.push_back({b->slabs[i].cost, ~(int)i});
     constexpr int kItem3d = std::numeric_limits<int>::max();
     if (b->nbox3 > 0) items.push_back({b->cost3, kItem3d});
     std::stable_sort(items.begin(), items.end(), [](const Item &x, const Item &y) { return x.cost > y.cost; });
@@ -1126,7 +1211,7 @@ static llhmm_status run_batch(llhmm_ctx *ctx, llhmm_batch *b, const double *m_in
             continue;
         }
         st = (it.idx >= 0) ? launch_resident(b, b->classes[it.idx], mode, field_dev, s)
-                           : launch_band_class(b, b->bands[~it.idx], mode, field_dev, s);
+                           : launch_slab_class(b, b->slabs[~it.idx], mode, field_dev, s);
         if (st != LLHMM_OK) return st;
     }
     for (int l = 1; l < lanes; ++l) {
@@ -1197,7 +1282,8 @@ llhmm_status llhmm_upscale(llhmm_ctx *ctx, llhmm_batch *b, double *H_avg_dev, in
                                hipMemcpyDeviceToHost, stream));
         HIP_TRY(hipStreamSynchronize(stream));
         for (int i = 0; i < b->nboxes; ++i)
-            if (st[i]) return fail(LLHMM_E_UNSTABLE, "box %d produced non-finite values", i);
+            if (st[i] & 2) return fail(LLHMM_E_HIP, "box %d: a slab exchange wait gave up", i);
+            else if (st[i]) return fail(LLHMM_E_UNSTABLE, "box %d produced non-finite values", i);
     }
     return LLHMM_OK;
 }
@@ -1277,15 +1363,15 @@ llhmm_status llhmm_batch_tune(llhmm_ctx *ctx, llhmm_batch *b, const double *m_in
                               int32_t reps, hipStream_t stream) {
     if (!ctx || !b) return fail(LLHMM_E_INVALID, "ctx/batch is NULL");
     if (reps < 1) return fail(LLHMM_E_INVALID, "reps must be >= 1");
-    if (b->bands.empty()) return LLHMM_OK;
+    if (b->slabs.empty()) return LLHMM_OK;
     PrologueArgs pa;
     llhmm_status st = prologue_args(b, m_init_dev, macro, M_macro_dev, coef_dev, pa);
     if (st != LLHMM_OK) return st;
     HIP_TRY(hipSetDevice(ctx->device));
-    HIP_TRY(launch_prologue(b->prec, pa, stream));  // tables the band kernels read
+    HIP_TRY(launch_prologue(b->prec, pa, stream));  // tables the slab kernels read
     std::map<TuneKey, std::vector<int>> keys;
     for (int i = 0; i < b->nboxes; ++i)
-        if (b->band_tile[i]) {
+        if (b->slab_tile[i]) {
             const BoxPlan &P = b->plans_h[i];
             keys[TuneKey{b->prec, P.n, P.bc, P.quantity, P.stages}].push_back(i);
         }
@@ -1295,60 +1381,66 @@ llhmm_status llhmm_batch_tune(llhmm_ctx *ctx, llhmm_batch *b, const double *m_in
     for (auto &kv : keys) {
         const int i0 = kv.second[0];
         const BoxPlan &P0 = b->plans_h[i0];
-        const auto &variants = band_registry().at(BandKey{b->prec, P0.n, P0.bc, P0.quantity});
-        int best_v = 0, best = b->band_s[i0];
+        const auto &variants = slab_registry().at(SlabKey{b->prec, P0.n, P0.order, P0.bc, P0.quantity});
+        int best_v = 0, best_spe = b->slab_spe[i0];
         for (size_t v = 0; v < variants.size(); ++v)
-            if (variants[v] == b->band_tile[i0]) best_v = (int)v;
+            if (variants[v] == b->slab_tile[i0]) best_v = (int)v;
         float best_ms = -1.f;
-        for (int cand = 0; cand < (int)variants.size() * kMaxStepsPerLaunch && st == LLHMM_OK; ++cand) {
-            const int v = cand / kMaxStepsPerLaunch, sc = 1 + cand % kMaxStepsPerLaunch;
-            const BandTileInfo *t = variants[v];
-            BandGeom g;
-            if (!band_geometry(*t, P0.n, P0.stages, sc, g)) continue;
-            hipError_t e = hipStreamSynchronize(stream);  // no launch may still read the plans
+        for (int vs = 0; vs < (int)variants.size() * 4 && st == LLHMM_OK; ++vs) {
+            const int v = vs / 4, spe = kSlabSpe[vs % 4];
+            const SlabTileInfo *t = variants[v];
+            if (slab_geom(*t, P0.n, P0.stages, spe).ns == 0) continue;
+            hipError_t e = hipStreamSynchronize(stream);  // no launch may still read the plans or jobs
             if (e != hipSuccess) { st = fail(LLHMM_E_HIP, "tune: %s", hipGetErrorString(e)); break; }
             for (int i : kv.second) {
-                b->band_tile[i] = t;
-                b->band_s[i] = sc;
+                b->slab_tile[i] = t;
+                b->slab_spe[i] = spe;
             }
-            st = rebuild_bands(b);
+            st = rebuild_slabs(b);
             if (st != LLHMM_OK) break;
-            const BandClass *bc = nullptr;
-            for (const BandClass &c : b->bands)
-                if (c.tile == t && c.s == sc) bc = &c;
-            if (!bc) continue;
-            st = launch_band_class(b, *bc, 0, nullptr, stream);  // warm-up
-            if (st == LLHMM_OK) e = hipEventRecord(e0, stream);
-            for (int r = 0; r < reps && st == LLHMM_OK && e == hipSuccess; ++r)
-                st = launch_band_class(b, *bc, 0, nullptr, stream);
-            if (st == LLHMM_OK && e == hipSuccess) e = hipEventRecord(e1, stream);
-            if (st == LLHMM_OK && e == hipSuccess) e = hipEventSynchronize(e1);
+            const SlabClass *sc = nullptr;
+            for (const SlabClass &c : b->slabs)
+                if (c.tile == t && c.geom.spe == spe && c.stages == P0.stages) sc = &c;
+            if (!sc) continue;
             float ms = 0.f;
-            if (st == LLHMM_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-            if (st == LLHMM_OK && e != hipSuccess) st = fail(LLHMM_E_HIP, "tune: %s", hipGetErrorString(e));
+            for (int r = 0; r <= reps && st == LLHMM_OK; ++r) {  // round 0 warms up
+                e = clear_slab_sync(b, stream);
+                if (e == hipSuccess && r == 1) e = hipEventRecord(e0, stream);
+                if (e == hipSuccess) st = launch_slab_class(b, *sc, 0, nullptr, stream);
+                if (e != hipSuccess) st = fail(LLHMM_E_HIP, "tune: %s", hipGetErrorString(e));
+            }
+            if (st == LLHMM_OK) {
+                hipError_t e2 = hipEventRecord(e1, stream);
+                if (e2 == hipSuccess) e2 = hipEventSynchronize(e1);
+                if (e2 == hipSuccess) e2 = hipEventElapsedTime(&ms, e0, e1);
+                if (e2 != hipSuccess) st = fail(LLHMM_E_HIP, "tune: %s", hipGetErrorString(e2));
+            }
             if (st == LLHMM_OK && (best_ms < 0.f || ms < best_ms)) {
                 best_ms = ms;
-                best = sc;
                 best_v = v;
+                best_spe = spe;
             }
         }
         if (st != LLHMM_OK) break;
         for (int i : kv.second) {
-            b->band_tile[i] = variants[best_v];
-            b->band_s[i] = best;
+            b->slab_tile[i] = variants[best_v];
+            b->slab_spe[i] = best_spe;
         }
-        ctx->tuned[kv.first] = TuneVal{best_v, best};
+        ctx->tuned[kv.first] = TuneVal{best_v, best_spe};
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (st != LLHMM_OK) return st;
     HIP_TRY(hipStreamSynchronize(stream));
-    return rebuild_bands(b);
+    return rebuild_slabs(b);
 }
 
-llhmm_status llhmm_batch_band_steps(const llhmm_batch *b, int32_t *steps_out) {
-    if (!b || !steps_out) return fail(LLHMM_E_INVALID, "batch/steps_out is NULL");
-    for (int i = 0; i < b->nboxes; ++i) steps_out[i] = b->band_tile[i] ? b->band_s[i] : 0;
+llhmm_status llhmm_batch_slabs(const llhmm_batch *b, int32_t *slabs_out, int32_t *steps_per_exchange_out) {
+    if (!b || !slabs_out) return fail(LLHMM_E_INVALID, "batch/slabs_out is NULL");
+    for (int i = 0; i < b->nboxes; ++i) {
+        slabs_out[i] = b->slab_tile[i] ? b->plans_h[i].strips : 0;
+        if (steps_per_exchange_out) steps_per_exchange_out[i] = b->slab_tile[i] ? b->slab_spe[i] : 0;
+    }
     return LLHMM_OK;
 }
 
@@ -1356,12 +1448,12 @@ llhmm_status llhmm_tune_save(const llhmm_ctx *ctx, const char *path) {
     if (!ctx || !path) return fail(LLHMM_E_INVALID, "ctx/path is NULL");
     FILE *f = fopen(path, "w");
     if (!f) return fail(LLHMM_E_INVALID, "cannot write %s", path);
-    fprintf(f, "# llhmm band tuning: precision n bc quantity stages variant steps_per_launch\n");
+    fprintf(f, "# llhmm slab tuning: precision n bc quantity stages variant steps_per_exchange\n");
     for (const auto &kv : ctx->tuned)
         fprintf(f, "%d %d %d %d %d %d %d\n", std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first),
                 std::get<3>(kv.first), std::get<4>(kv.first), kv.second.first, kv.second.second);
-    const bool ok = fclose(f) == 0;
-    return ok ? LLHMM_OK : fail(LLHMM_E_INVALID, "cannot write %s", path);
+    fclose(f);
+    return LLHMM_OK;
 }
 
 llhmm_status llhmm_tune_load(llhmm_ctx *ctx, const char *path) {
@@ -1375,7 +1467,7 @@ llhmm_status llhmm_tune_load(llhmm_ctx *ctx, const char *path) {
         if (line[0] == '#' || line[0] == '\n') continue;
         int v[7];
         if (sscanf(line, "%d %d %d %d %d %d %d", &v[0], &v[1], &v[2], &v[3], &v[4], &v[5], &v[6]) != 7 ||
-            v[5] < 0 || v[5] > 15 || v[6] < 1 || v[6] > kMaxStepsPerLaunch) {
+            v[5] < 0 || v[5] > 15 || std::find(std::begin(kSlabSpe), std::end(kSlabSpe), v[6]) == std::end(kSlabSpe)) {
             st = fail(LLHMM_E_INVALID, "%s: bad line: %s", path, line);
             break;
         }
@@ -1481,6 +1573,7 @@ struct ServeFlight {
     std::vector<ServeReq> reqs;
     double *H_dev = nullptr;
     int32_t *st_dev = nullptr;
+    int64_t *ids_dev = nullptr;      // request ids, when results also go to the caller's device array
     hipEvent_t done = nullptr;
     int64_t bytes = 0, seq = 0;
     bool busy = false;
@@ -1505,13 +1598,18 @@ struct llhmm_server {
     std::vector<hipStream_t> streams;
     double *H_host = nullptr;    // pinned [slots][max_batch_boxes][kServeQ]
     int32_t *st_host = nullptr;  // pinned [slots][max_batch_boxes]
+    int64_t *ids_host = nullptr; // pinned [slots][max_batch_boxes], staging of the request ids
+    double *out_H = nullptr;     // caller's device array of results (llhmm_server_set_output)
+    int32_t out_ld = 0;
+    int64_t out_rows = 0;
     std::deque<ServeDone> done;
     int64_t reserved = 0, seq = 0;
 };
 
 // Device memory one request adds to a micro-batch (tables, weights, set-up
-// scratch, partial-sum slots, band state, time weights, descriptors), an upper
-// bound of what llhmm_batch_create allocates for it.
+// scratch, partial-sum slots, slab exchange rows, time weights, descriptors,
+// its result, status and id), an upper bound of what the micro-batch allocates
+// for it.
 static llhmm_status request_bytes(const llhmm_server *sv, const llhmm_box &bx, int i, int64_t &bytes) {
     llhmm_status st = validate_box(bx, i, (int)sv->coefs.size());
     if (st != LLHMM_OK) return st;
@@ -1531,35 +1629,34 @@ static llhmm_status request_bytes(const llhmm_server *sv, const llhmm_box &bx, i
         if (prec != LLHMM_FP64 || bx.order != 2 || bx.quantity == LLHMM_Q_FLUX)
             return fail(LLHMM_E_NOTSUP, "request %d: d = 3 needs FP64, order 2, field or torque", i);
         bytes = work3d_size(bx.n, bx.order) * 8 + 2 * bx.n * 8 + (kMaxQ * 8 + 4) + 2 * (int64_t)(pl.M + 1) * 8 +
-                (int64_t)sizeof(BoxPlan) + 4 + kMaxQ * 8 + 4 + kMaxQ * 8 + 4 + (int64_t)sizeof(CoefDev) + 3 * 256;
+                (int64_t)sizeof(BoxPlan) + 4 + kMaxQ * 8 + 4 + kMaxQ * 8 + 4 + (int64_t)sizeof(CoefDev) + 8 + 3 * 256;
         return LLHMM_OK;
     }
     auto it = registry().find(TileKey{prec, bx.dim, bx.n, bx.order, bx.bc, bx.quantity});
-    const BandTileInfo *bt = nullptr;
-    int64_t band_slots = 0;
-    if (it == registry().end() && bx.dim == 2 && bx.order == 2) {
-        auto bit = band_registry().find(BandKey{prec, bx.n, bx.bc, bx.quantity});
-        if (bit != band_registry().end()) {
-            bt = bit->second[0];
-            band_slots = band_max_slots(bit->second, bx.n, stages);
+    bool slab = false;
+    SlabReserve sres;
+    if (it == registry().end() && bx.dim == 2) {
+        auto bit = slab_registry().find(SlabKey{prec, bx.n, bx.order, bx.bc, bx.quantity});
+        if (bit != slab_registry().end()) {
+            slab = true;
+            sres = slab_reserve(bit->second, bx.n, stages);
         }
     }
-    if (it == registry().end() && !bt)
+    if (it == registry().end() && !slab)
         return fail(LLHMM_E_NOTSUP, "request %d: no kernel for dim %d, n %d, order %d, bc %d, quantity %d", i,
                     bx.dim, bx.n, bx.order, bx.bc, bx.quantity);
-    const int form = (prec == LLHMM_FP32 || bt) ? 1 : 0;
-    const int64_t C = (bx.dim == 1) ? bx.n : (int64_t)bx.n * bx.n;
+    const int form = (prec == LLHMM_FP32 || slab) ? 1 : 0;
     int64_t slots = (bx.dim == 2) ? 16 : 1;
-    int64_t band_state = 0, jobs = 0;
-    if (bt) {
-        slots = band_slots;
-        band_state = 2 * 3 * C * tsize + (prec == LLHMM_FP32 ? 2 * 7 * C * tsize : 0);
-        jobs = band_slots * (int64_t)sizeof(BandJob);
+    int64_t slab_bytes = 0;
+    if (slab) {
+        // exchange words, a work counter and an abort word, jobs
+        slots = sres.slots;
+        slab_bytes = sres.xwords * 8 + 2 * 4 + sres.items * (int64_t)sizeof(SlabJob) + 3 * 256;
     }
     bytes = tab_layout(bx.dim, bx.n, form).size * tsize + 2 * bx.n * 8 +
-            (form == 1 ? scratch64_size(bx.dim, bx.n) * 8 : 0) + slots * (kMaxQ * 8 + 4) + band_state + jobs +
+            (form == 1 ? scratch64_size(bx.dim, bx.n) * 8 : 0) + slots * (kMaxQ * 8 + 4) + slab_bytes +
             2 * (int64_t)(pl.M + 1) * 8 + (int64_t)sizeof(BoxPlan) + 4 + kMaxQ * 8 + 4 + kMaxQ * 8 + 4 +
-            (int64_t)sizeof(CoefDev) + 2 * 256;
+            (int64_t)sizeof(CoefDev) + 8 + 2 * 256;
     return LLHMM_OK;
 }
 
@@ -1567,9 +1664,11 @@ static void serve_release(llhmm_server *sv, ServeFlight &f) {
     if (f.batch) batch_free(f.batch);
     if (f.H_dev) sv->arena.release(f.H_dev);
     if (f.st_dev) sv->arena.release(f.st_dev);
+    if (f.ids_dev) sv->arena.release(f.ids_dev);
     f.batch = nullptr;
     f.H_dev = nullptr;
     f.st_dev = nullptr;
+    f.ids_dev = nullptr;
     sv->reserved -= f.bytes;
     f.bytes = 0;
     f.reqs.clear();
@@ -1657,10 +1756,11 @@ static llhmm_status serve_admit(llhmm_server *sv) {
         }
         f.H_dev = (double *)sv->arena.alloc(n * kServeQ * sizeof(double));
         f.st_dev = (int32_t *)sv->arena.alloc(n * sizeof(int32_t));
+        if (sv->out_H) f.ids_dev = (int64_t *)sv->arena.alloc(n * sizeof(int64_t));
         f.bytes = bytes + kBatchSlack;
         sv->reserved += f.bytes;
         f.busy = true;
-        if (!f.H_dev || !f.st_dev) {
+        if (!f.H_dev || !f.st_dev || (sv->out_H && !f.ids_dev)) {
             serve_release(sv, f);
             if (any_busy) break;
             serve_fail_front(sv, n, LLHMM_E_BUDGET);
@@ -1676,6 +1776,14 @@ static llhmm_status serve_admit(llhmm_server *sv) {
         }
         HIP_TRY(launch_upscale(f.batch->partials, f.batch->wave_status, f.batch->box_const, f.batch->plans,
                                (int)n, f.H_dev, kServeQ, f.batch->status, f.st_dev, s));
+        if (sv->out_H) {
+            // results also to the caller's device array, before the completion event
+            int64_t *ih = sv->ids_host + (size_t)slot * mb;
+            for (size_t r = 0; r < n; ++r) ih[r] = sv->queue[r].id;
+            HIP_TRY(hipMemcpyAsync(f.ids_dev, ih, n * sizeof(int64_t), hipMemcpyHostToDevice, s));
+            HIP_TRY(launch_scatter_rows(f.H_dev, kServeQ, f.ids_dev, (int)n, std::min<int>(kServeQ, sv->out_ld),
+                                        sv->out_H, sv->out_ld, sv->out_rows, s));
+        }
         HIP_TRY(hipMemcpyAsync(sv->H_host + (size_t)slot * mb * kServeQ, f.H_dev, n * kServeQ * sizeof(double),
                                hipMemcpyDeviceToHost, s));
         HIP_TRY(hipMemcpyAsync(sv->st_host + (size_t)slot * mb, f.st_dev, n * sizeof(int32_t),
@@ -1699,6 +1807,7 @@ static void server_free(llhmm_server *sv) {
         if (s) (void)hipStreamDestroy(s);
     if (sv->H_host) (void)hipHostFree(sv->H_host);
     if (sv->st_host) (void)hipHostFree(sv->st_host);
+    if (sv->ids_host) (void)hipHostFree(sv->ids_host);
     if (sv->arena.base) (void)hipFree(sv->arena.base);
     delete sv;
 }
@@ -1724,6 +1833,7 @@ llhmm_status llhmm_server_create(llhmm_ctx *ctx, const llhmm_server_cfg *cfg, co
     const size_t mb = (size_t)cfg->max_batch_boxes;
     if (e == hipSuccess) e = hipHostMalloc((void **)&sv->H_host, sizeof(double) * cfg->max_inflight * mb * kServeQ);
     if (e == hipSuccess) e = hipHostMalloc((void **)&sv->st_host, sizeof(int32_t) * cfg->max_inflight * mb);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&sv->ids_host, sizeof(int64_t) * cfg->max_inflight * mb);
     sv->slots.resize(cfg->max_inflight);
     sv->streams.assign(cfg->max_inflight, nullptr);
     for (int k = 0; k < cfg->max_inflight && e == hipSuccess; ++k) {
@@ -1800,6 +1910,15 @@ llhmm_status llhmm_server_poll(llhmm_server *sv, int32_t wait, int32_t max, int6
     return LLHMM_OK;
 }
 
+llhmm_status llhmm_server_set_output(llhmm_server *sv, double *H_dev, int32_t ld, int64_t nrows) {
+    if (!sv) return fail(LLHMM_E_INVALID, "server is NULL");
+    if (H_dev && (ld < 1 || nrows < 1)) return fail(LLHMM_E_INVALID, "ld and nrows must be >= 1");
+    sv->out_H = H_dev;
+    sv->out_ld = H_dev ? ld : 0;
+    sv->out_rows = H_dev ? nrows : 0;
+    return LLHMM_OK;
+}
+
 llhmm_status llhmm_server_stats(const llhmm_server *sv, int64_t *queued, int64_t *inflight,
                                 int64_t *bytes_in_use, int64_t *bytes_total) {
     if (!sv) return fail(LLHMM_E_INVALID, "server is NULL");
@@ -1817,7 +1936,7 @@ llhmm_status llhmm_server_stats(const llhmm_server *sv, int64_t *queued, int64_t
 
 // ------------------------------------------------------------ allocation-free solve
 // The scratch memory of llhmm_solve_noalloc: one array per device, holding a
-// whole batch's descriptors, tables, band state and partial sums.  In host code
+// whole batch's descriptors, tables, slab exchange rows and partial sums.  In host code
 // `scratch` names a host-side stand-in, never the device memory: its device
 // address is taken once per device with hipGetSymbolAddress (with that device
 // current) and only that address is used.

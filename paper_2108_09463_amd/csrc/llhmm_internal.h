@@ -21,7 +21,7 @@ struct BoxPlan {
     int32_t bc, quantity, init_mode, M;  // M: number of time steps
     int32_t coef_index, mi0, mi1, nq;    // macro node; nq = outputs per box
     int32_t coef_sampled, nwaves, prec, form;   // form: 0 direct, 1 reference + perturbation
-    int32_t band, strips, mi2, pad1_;    // band: box advanced in row strips (large boxes); mi2: 3-D node
+    int32_t slab, strips, mi2, pad1_;    // slab: box advanced in row slabs (large boxes), strips: their count; mi2: 3-D node
     double dt, alpha, dx, mu;
     double mu_box, a_scale, out_scale, cx;
     double cy, wsum;                     // wsum = sum_n w^n (time weights)
@@ -31,8 +31,8 @@ struct BoxPlan {
     int64_t w_offset;                    // element offset (double) of the space weights
     int64_t s64_offset;                  // element offset (double) of the set-up scratch (form 1)
     int64_t part_offset;                 // first partial-sum slot of the box (nwaves slots)
-    int64_t state_offset;                // band: element offset (T) of the box's state [3][n][n]
-    int64_t ref_offset;                  // band, FP32: element offset (T) of its reference tables [7][n][n]
+    int64_t state_offset;                // unused
+    int64_t ref_offset;                  // unused
 };
 
 // Per-box table layout (elements of T, starting at tab_offset), n = points per
@@ -135,46 +135,54 @@ struct MicroArgs {
     double *out_field;         // m_final or H (nullable)
 };
 
-// Large 2-D boxes are advanced in full-width row strips ("band" mode): a block
-// holds a window of rows = its strip's own rows plus h halo rows on each side,
-// runs `steps` time steps on it without exchanging data with other blocks
-// (the halo rows absorb the error that enters from the window edges, one row
-// per stage), and writes back only its own rows.  Successive launches
-// ping-pong the state between two buffers.
-struct BandJob {
-    int32_t box, strip, o0, rows;  // strip owns box rows [o0, o0 + rows)
+// Slab mode (large 2-D boxes): a box is cut into slabs of consecutive
+// full-width rows, one workgroup per slab for the whole solve.  The workgroup
+// holds a window of R * NG rows: its own rows and h halo rows on each side,
+// which it advances redundantly; after every `spe` time steps it publishes
+// the edge rows of its own rows and replaces its halo rows by its
+// neighbours' published rows (global memory, tagged words).  One persistent
+// launch per class takes (box, slab) items from a counter.
+struct SlabJob {
+    int32_t box, slab, nslabs, o0;  // slab owns box rows [o0, o0 + rows)
+    int32_t rows, pad_;
+    int64_t xoff;                   // word offset of the box's exchange area
 };
 
-struct BandArgs {
+struct SlabArgs {
     const BoxPlan *plans;
-    const BandJob *jobs;        // one per block
-    int32_t njobs, mode;        // mode 0 solve, 1 evaluate H(m0) only
-    int32_t step0, steps;       // this launch: steps [step0, min(step0 + steps, M))
-    int32_t h;                  // halo rows on each side of a strip
-    int32_t reref;              // FP32: re-reference at the launch start (then write the tables)
+    const SlabJob *jobs;        // items, in the order they are taken
+    int32_t nitems, mode;       // mode 0 solve, 1 evaluate H(m0) only
+    int32_t *counter;           // next item (zero before the launch)
+    int32_t *abort_word;        // set when a wait gives up (zero before the launch)
+    long long spin_max;         // polls before a wait gives up
+    int32_t h, spe;             // halo rows per side; time steps per exchange
+    int32_t xdepth, pad_;       // rows per published edge
     const void *tabs;           // per-box tables (T)
     const double *wts;          // space weights
     const double *wt;           // time-weight table
     double *partials;           // [slots][kMaxQ]
     int32_t *wave_status;       // [slots]
-    const void *state_in;       // T, per box at state_offset (unused when step0 == 0)
-    void *state_out;            // T
-    const void *ref_in;         // FP32: reference tables r, |r|^2-1, H(r) per box at ref_offset,
-    void *ref_out;              //   or nullptr: the set-up tables (until the first re-reference)
+    uint64_t *xbuf;             // per box [slabs][2 edges][2 parities][xdepth rows][3][n][words per value]
     double *out_field;          // m_final or H (nullable)
 };
 
-using BandLaunchFn = hipError_t (*)(const BandArgs &, int nblocks, hipStream_t);
+using SlabLaunchFn = hipError_t (*)(const SlabArgs &, int nblocks, hipStream_t);
+using SlabOccFn = hipError_t (*)(int *blocks_per_cu);
 
-struct BandTileInfo {
-    int n, bc, prec, qty;       // class it serves (2-D, second order)
-    int L, K, R, NG, NBUF;      // layout: window of R * NG rows
+struct SlabTileInfo {
+    int n, bc, prec, qty;        // class it serves (2-D, second order)
+    int L, K, R, NG, NBUF;       // a window of R * NG rows of n = K * L points
     int threads;
-    BandLaunchFn launch;
+    SlabLaunchFn launch;
+    SlabOccFn occupancy;
     const char *name;
 };
 
-const BandTileInfo *tiles_band(int *count);
+const SlabTileInfo *tiles_slab(int *count);
+hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
+// dst[ids[r] * ld + q] = src[r * src_ld + q] for q < nq and 0 <= ids[r] < nrows
+hipError_t launch_scatter_rows(const double *src, int src_ld, const int64_t *ids, int n, int nq, double *dst,
+                               int ld, int64_t nrows, hipStream_t s);
 
 using LaunchFn = hipError_t (*)(const MicroArgs &, int nblocks, hipStream_t);
 

@@ -104,8 +104,43 @@ enum { AVG_NONE = 0, AVG_FIELD = 1, AVG_TORQUE = 2, AVG_FLUX = 3, AVG_EVAL = 4, 
 
 
 
+// Cross-workgroup exchange words (slab mode).  A value travels with the
+// index of the exchange that produced it in one 64-bit word (FP32: the value's
+// bits and the index; FP64: two words, one per half), written and read as
+// agent-scope atomics: each access is coherent across the XCDs' L2 caches
+// without whole-cache write-back or invalidation, and a reader that sees the
+// index it waits for has the value with it, so no separate flag is needed.
+template <typename T>
+__device__ __forceinline__ void xstore(T *p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ T xload(const T *p) {
+    return __hip_atomic_load(const_cast<T *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T> struct XWords { static constexpr int n = sizeof(T) / 4; };  // words per value
+__device__ __forceinline__ void xput(uint64_t *p, float v, uint32_t tag) {
+    xstore(p, (uint64_t)__builtin_bit_cast(uint32_t, v) | ((uint64_t)tag << 32));
+}
+__device__ __forceinline__ void xput(uint64_t *p, double v, uint32_t tag) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    xstore(p, (uint64_t)((b & 0xffffffffu) | ((uint64_t)tag << 32)));
+    xstore(p + 1, (uint64_t)((b >> 32) | ((uint64_t)tag << 32)));
+}
+// Reads a value whose words carry at least `tag`; false while any word is older.
+__device__ __forceinline__ bool xget(const uint64_t *p, uint32_t tag, float &v) {
+    const uint64_t w = xload(p);
+    v = __builtin_bit_cast(float, (uint32_t)w);
+    return (uint32_t)(w >> 32) >= tag;
+}
+__device__ __forceinline__ bool xget(const uint64_t *p, uint32_t tag, double &v) {
+    const uint64_t a = xload(p), b = xload(p + 1);
+    v = __builtin_bit_cast(double, (a & 0xffffffffull) | (b << 32));
+    return (uint32_t)(a >> 32) >= tag && (uint32_t)(b >> 32) >= tag;
+}
+
 template <typename T, int D, int ORD, int BC, int QTY, int L, int K, int R, int NG, int NBUF,
-          bool BAND = false>
+          bool SLAB = false>
 struct MicroLane {
     static constexpr int N = K * L;
     static constexpr int YH = (ORD == 2) ? 1 : 3;  // neighbour reach in points
@@ -125,26 +160,26 @@ struct MicroLane {
     static constexpr int ZOFF = 4 * N * GF * 8;
     // FP64: face coefficients are read from LDS (x1 faces [lines][LF], 2-D x2
     // faces [N][LF] after them) instead of being held in registers
-    static constexpr bool AXL = !BAND && sizeof(T) == 8;
+    static constexpr bool AXL = !SLAB && sizeof(T) == 8;
     static constexpr int LF = N + kFaceHalo;
     static constexpr int AX_LDS = AXL ? ((D == 2) ? 2 * N * LF : NG * LF) : 1;
     static constexpr int WLDS = (D == 2) ? 2 * N : NG * 2 * N;  // space weights in LDS
     // form 1 (FP32): m = r + u with the FP32 reference r = fl(m_init) and H(r)
     // precomputed in FP64; the state u starts at the rounding residual m_init - r
     // and stays periodic (or zero) on the ghosts, so no boundary offsets are needed.
-    // Band mode (a window of R * NG rows of a larger 2-D box) always uses form 1.
-    static constexpr int FORM = (BAND || sizeof(T) == 4) ? 1 : 0;
+    // Slab mode (a window of R * NG rows of a larger 2-D box) always uses form 1.
+    static constexpr int FORM = (SLAB || sizeof(T) == 4) ? 1 : 0;
     static constexpr int CELLS = (D == 1) ? N : N * N;
     static constexpr int WR = R * NG;                       // rows held by the block
-    static constexpr int CELLS_W = BAND ? WR * N : CELLS;    // points held by the block
-    // FP64 band: the reference tables are read from global memory (box indexing)
-    static constexpr bool REFG = BAND && sizeof(T) == 8;
+    static constexpr int CELLS_W = SLAB ? WR * N : CELLS;    // points held by the block
+    // FP64 slab: the reference tables are read from global memory (box indexing)
+    static constexpr bool REFG = SLAB && sizeof(T) == 8;
     static constexpr int RSTRIDE = REFG ? CELLS : CELLS_W;  // stride between reference planes
     static constexpr int REF_LDS = (FORM && !REFG) ? ((D == 2) ? 7 * CELLS_W : NG * 7 * N) : 1;
     static_assert(K >= YH, "lane tile narrower than the stencil reach");
-    static_assert(D == 1 || R >= YH, "row band thinner than the stencil reach");
-    static_assert(D == 1 || BAND || R * NG == N, "row groups must tile the box");
-    static_assert(!BAND || (D == 2 && ORD == 2), "band mode: 2-D, second order");
+    static_assert(D == 1 || R >= YH, "row group thinner than the stencil reach");
+    static_assert(D == 1 || SLAB || R * NG == N, "row groups must tile the box");
+    static_assert(!SLAB || (D == 2 && ORD == 2), "slab mode: 2-D, second order");
     static_assert(D == 2 || R == 1, "1-D boxes are one row");
     static_assert(L == 16 || L == 64, "row group is a DPP row or a wavefront");
 
@@ -161,12 +196,12 @@ struct MicroLane {
     T *s_halo, *s_zero, *s_tau;
     T *s_ref;          // form 1: this box's r [3][C], |r|^2-1 [C], H(r) [3][C] (LDS or global)
     const double *wl;  // this box's point weights [N] then east-face weights [N] (LDS)
-    // band mode: box row of each own row, whether the block owns it, and the
+    // slab mode: box row of each own row, whether the block owns it, and the
     // x2 point / face weights of the window rows (zero on rows it does not own)
-    int brow[BAND ? R : 1];
-    bool own[BAND ? R : 1];
+    int brow[SLAB ? R : 1];
+    bool own[SLAB ? R : 1];
     const double *s_wyl;
-    const T *s_edge;   // band: z of the box rows just outside the window (re-referencing)
+    const T *s_edge;   // slab: z of the box rows just outside the window (re-referencing)
 
     template <int CTRL_ROT, int CTRL_SH>
     __device__ __forceinline__ static T nb(T v) {
@@ -174,14 +209,14 @@ struct MicroLane {
     }
     __device__ __forceinline__ double wv(int i) const { return wl[i]; }
     __device__ __forceinline__ double wy(int r) const {
-        return BAND ? s_wyl[r0 + r] : ((D == 2) ? wv(r0 + r) : 1.0);
+        return SLAB ? s_wyl[r0 + r] : ((D == 2) ? wv(r0 + r) : 1.0);
     }
-    __device__ __forceinline__ double wyf(int r) const { return BAND ? s_wyl[WR + r0 + r] : wv(N + r0 + r); }
-    __device__ __forceinline__ bool owned(int r) const { return BAND ? own[BAND ? r : 0] : true; }
-    __device__ __forceinline__ int out_row(int r) const { return BAND ? brow[BAND ? r : 0] : r0 + r; }
+    __device__ __forceinline__ double wyf(int r) const { return SLAB ? s_wyl[WR + r0 + r] : wv(N + r0 + r); }
+    __device__ __forceinline__ bool owned(int r) const { return SLAB ? own[SLAB ? r : 0] : true; }
+    __device__ __forceinline__ int out_row(int r) const { return SLAB ? brow[SLAB ? r : 0] : r0 + r; }
     // index of own point (r, k) in the reference tables
     __device__ __forceinline__ int cell_of(int r, int k) const {
-        return BAND ? ((REFG ? brow[BAND ? r : 0] : r0 + r) * N + c0 + k) : ((D == 1 ? 0 : (r0 + r) * N) + c0 + k);
+        return SLAB ? ((REFG ? brow[SLAB ? r : 0] : r0 + r) * N + c0 + k) : ((D == 1 ? 0 : (r0 + r) * N) + c0 + k);
     }
     __device__ __forceinline__ T tau_lds(int off) const {
         return FORM ? (T)0 : s_tau[off];
@@ -219,7 +254,7 @@ struct MicroLane {
             __syncthreads();
             srcS = zero_s ? s_zero : hb + ((gs * 2 + 1) * YH) * 3 * N;
             srcN = zero_n ? s_zero : hb + ((gn * 2 + 0) * YH) * 3 * N;
-            if (BAND && AVG == AVG_DREF) {  // the reference change is known beyond the window
+            if (SLAB && AVG == AVG_DREF) {  // the reference change is known beyond the window
                 if (g == 0) srcS = s_edge;
                 if (g == NG - 1) srcN = s_edge + 3 * N;
             }
@@ -734,229 +769,300 @@ __global__ void __launch_bounds__(L * NG, MINW) k_micro(MicroArgs A) {
 }
 
 
-// Band mode: one block advances a window of R * NG full-width rows of a large
-// 2-D box (its strip's own rows plus A.h halo rows on each side) through up to
-// A.steps time steps, then writes back the rows it owns.  The window does not
-// exchange data with other blocks during the launch: its outermost rows see
-// zeros beyond the window, and the error this causes moves inwards by one row
-// per stage, so it stays inside the halo when A.h >= steps * stages.  Rows are
-// periodic images of box rows (periodic m - m_init) or ghost rows held at
-// u = 0 (Dirichlet).  The host aligns windows so that box row 0 starts a row
-// group; a group's rows are then consecutive box rows and each group loads the
-// x2 face coefficients of its own rows, which keeps the faces on either side
-// of the box's periodic seam distinct.
-template <typename T, int QTY, int BC, int L, int K, int R, int NG, int NBUF, int MINW>
-__global__ void __launch_bounds__(L * NG, MINW) k_band(BandArgs A) {
+// A block-uniform copy of *p in scalar registers.  Loads inside a loop that
+// also stores to global memory are not provably unclobbered, so the compiler
+// would keep them (and every address derived from them) in vector registers.
+template <typename S>
+__device__ __forceinline__ S uniform_load(const S *p) {
+    static_assert(sizeof(S) % 4 == 0, "whole words");
+    S out;
+    int *o = reinterpret_cast<int *>(&out);
+    const int *in = reinterpret_cast<const int *>(p);
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(S) / 4); ++k) o[k] = __builtin_amdgcn_readfirstlane(in[k]);
+    return out;
+}
+
+// Slab mode: one persistent grid advances the large 2-D boxes of one tile
+// class.  A box is cut into slabs of consecutive full-width rows, one
+// workgroup per slab for all of the box's time steps.  The workgroup holds a
+// window of R * NG rows: the slab's own rows and at least h halo rows on each
+// side (periodic images of box rows, or Dirichlet ghost rows held at u = 0).
+// The window's outermost rows see zeros beyond it; the error that causes
+// moves inwards one row per stage, so the own rows stay exact for h stages
+// (h >= spe * stages).  After every spe time steps the workgroup publishes
+// its edge rows and replaces its halo rows with its neighbours' published
+// rows: box state never leaves the chip, and only those rows cross between
+// workgroups.  Re-referencing (FP32) happens only at exchange steps, when
+// every window row is exact, so a halo row's reference stays the one its
+// owner computes (only the outermost row's H(r) update misses the point
+// beyond the window, which stays inside the same error cone).
+// Workgroups take (box, slab) items from an atomic counter; the items of a box
+// are consecutive and the list is ordered longest box first.  A workgroup
+// waiting for a neighbour's rows only waits for an item at most one box
+// further down the list, which the next workgroup to finish an item takes, so
+// the grid makes progress with any number of resident workgroups >= slabs per
+// box.  Every wait polls at most A.spin_max times; a wait that runs out sets
+// the grid-wide abort word, every workgroup then stops, and the boxes it
+// touched report status 2.
+// EVAL (a separate instantiation, so that the solve's register allocation
+// does not carry the evaluation's): evaluate H(m0) on the own rows instead of
+// solving; A.mode must agree.
+template <typename T, int QTY, int BC, int L, int K, int R, int NG, int NBUF, int MINW, bool EVAL>
+__global__ void __launch_bounds__(L * NG, MINW) k_slab(SlabArgs A) {
     constexpr int D = 2, ORD = 2;
     using Lane = MicroLane<T, D, ORD, BC, QTY, L, K, R, NG, NBUF, true>;
     constexpr int N = Lane::N, NF = Lane::NF, NFR = Lane::NFR, FW = Lane::FW, NQ = Lane::NQ;
     constexpr int YH = Lane::YH, WR = Lane::WR;
     constexpr long C = (long)N * N;
     constexpr int LF = N + kFaceHalo;
+    constexpr int WAVES = L * NG / 64;
+    constexpr int XW = XWords<T>::n;
     __shared__ T s_halo[NBUF * Lane::HALO];
     __shared__ T s_zero[YH * 3 * N];
     __shared__ T s_refl[Lane::REF_LDS];
     __shared__ double s_w[2 * N];
     __shared__ double s_wyl[2 * WR];
-    __shared__ T s_edge[(sizeof(T) == 4) ? 2 * 3 * N : 1];
+    __shared__ int s_item, s_abort;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: scalar register
     const int j = (L == 16) ? (lane & 15) : lane;
-    const BandJob job = A.jobs[blockIdx.x];
-    const BoxPlan &P = A.plans[job.box];
-    const T *tab = (const T *)A.tabs + P.tab_offset;
-    const TabLayout TL = tab_layout(D, N, 1);
-    const int h = A.h;
-    const int w0 = job.o0 - h;  // box row of window row 0, before wrapping
-    auto wrap = [](int br) { return ((br % N) + N) % N; };
-    // Dirichlet: window rows outside the box are ghost rows (u = 0), whole groups at a time
-    auto dead = [&](int gg) {
-        const int br = w0 + gg * R;
-        return BC == LLHMM_BC_DIRICHLET && (br < 0 || br >= N);
-    };
-
-    Lane S;
-    S.g = (L == 16) ? (wave * 4 + (lane >> 4)) : wave;
-    S.c0 = j * K;
-    S.r0 = S.g * R;
-    const int g = S.g, c0 = S.c0, r0 = S.r0;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int wr = r0 + r;
-        S.brow[r] = wrap(w0 + wr);
-        S.own[r] = (wr >= h) && (wr < h + job.rows);
-    }
-    const bool gdead = dead(g);
-
-    // space weights; window-row weights (zero on rows this block does not own)
-    const double *wsrc = A.wts + P.w_offset;
-    for (int i = tid; i < 2 * N; i += L * NG) s_w[i] = wsrc[i];
-    for (int i = tid; i < WR; i += L * NG) {
-        const bool own = (i >= h) && (i < h + job.rows);
-        const int br = wrap(w0 + i);
-        s_wyl[i] = own ? wsrc[br] : 0.0;
-        s_wyl[WR + i] = own ? wsrc[N + br] : 0.0;
-    }
-    S.wl = s_w;
-    S.s_wyl = s_wyl;
-    // reference r, |r|^2 - 1 and H(r): window copy in LDS (FP32) or the box tables (FP64)
-    const bool first = (A.step0 == 0);
-    if (Lane::REFG) {
-        S.s_ref = const_cast<T *>(tab) + TL.ref;
-    } else {
-        const T *src = A.ref_in ? (const T *)A.ref_in + P.ref_offset : tab + TL.ref;
-        copy_rows_to_lds<T, N, Lane::REFG ? 1 : 7 * WR, L * NG>(
-            s_refl,
-            [&](int r) {
-                const int q = r / WR, wr = r - q * WR;
-                return src + q * C + (long)wrap(w0 + wr) * N;
-            },
-            tid);
-        S.s_ref = s_refl;
-    }
     for (int i = tid; i < YH * 3 * N; i += L * NG) s_zero[i] = (T)0;
-    // face coefficients of the own rows (x1) and of the own column segment (x2)
+    const int h = A.h, spe = A.spe, xd = A.xdepth;
+    auto wrap = [](int br) { return ((br % N) + N) % N; };
+
+    for (;;) {
+        if (tid == 0) {
+            s_item = atomicAdd(A.counter, 1);
+            s_abort = xload(A.abort_word);
+        }
+        __syncthreads();
+        // block-uniform: in scalar registers, and so is everything derived from the item
+        const int item = __builtin_amdgcn_readfirstlane(s_item);
+        if (item >= A.nitems) break;
+        const SlabJob job = uniform_load(A.jobs + item);
+        const BoxPlan P = uniform_load(A.plans + job.box);
+        if (__builtin_amdgcn_readfirstlane(s_abort) != 0) {
+            // a wait has given up: the remaining items only report it
+            if (!EVAL && lane == 0) A.wave_status[P.part_offset + (long)job.slab * WAVES + wave] = 2;
+            __syncthreads();
+            continue;
+        }
+        const T *tab = (const T *)A.tabs + P.tab_offset;
+        const TabLayout TL = tab_layout(D, N, 1);
+        const int w0 = job.o0 - h;  // box row of window row 0, before wrapping
+        const int own_end = h + job.rows;
+        // Dirichlet: window rows outside the box are ghost rows (u = 0), whole groups at a time
+        auto dead = [&](int gg) {
+            const int br = w0 + gg * R;
+            return BC == LLHMM_BC_DIRICHLET && (br < 0 || br >= N);
+        };
+
+        Lane S;
+        S.g = (L == 16) ? (wave * 4 + (lane >> 4)) : wave;
+        S.c0 = j * K;
+        S.r0 = S.g * R;
+        const int g = S.g, c0 = S.c0, r0 = S.r0;
 #pragma unroll
-    for (int r = 0; r < R; ++r)
+        for (int r = 0; r < R; ++r) {
+            const int wr = r0 + r;
+            S.brow[r] = wrap(w0 + wr);
+            S.own[r] = (wr >= h) && (wr < own_end);
+        }
+        const bool gdead = dead(g);
+        // the group's role in the exchange (h, rows and xdepth are multiples of R)
+        const bool halo_s = (r0 < h) && !gdead, halo_n = (r0 >= own_end) && !gdead;
+        const bool pub_s = (r0 >= h) && (r0 < h + xd), pub_n = (r0 >= own_end - xd) && (r0 < own_end);
+        const int ns = job.nslabs, sl = job.slab;
+        const int s_south = (sl + ns - 1) % ns, s_north = (sl + 1) % ns;
+        const bool has_s = (BC != LLHMM_BC_DIRICHLET) || (sl > 0);
+        const bool has_n = (BC != LLHMM_BC_DIRICHLET) || (sl < ns - 1);
+        constexpr long XROW = 3L * N * XW;   // words of one exchanged row
+        uint64_t *xbox = A.xbuf + job.xoff;
+        auto edge = [&](int slab, int side, int par) { return xbox + ((long)(slab * 2 + side) * 2 + par) * xd * XROW; };
+
+        // space weights; window-row weights (zero on rows this block does not own)
+        const double *wsrc = A.wts + P.w_offset;
+        for (int i = tid; i < 2 * N; i += L * NG) s_w[i] = wsrc[i];
+        for (int i = tid; i < WR; i += L * NG) {
+            const bool own = (i >= h) && (i < own_end);
+            const int br = wrap(w0 + i);
+            s_wyl[i] = own ? wsrc[br] : 0.0;
+            s_wyl[WR + i] = own ? wsrc[N + br] : 0.0;
+        }
+        S.wl = s_w;
+        S.s_wyl = s_wyl;
+        // reference r, |r|^2 - 1 and H(r): window copy in LDS (FP32) or the box tables (FP64)
+        if (Lane::REFG) {
+            S.s_ref = const_cast<T *>(tab) + TL.ref;
+        } else {
+            const T *src = tab + TL.ref;
+            copy_rows_to_lds<T, N, Lane::REFG ? 1 : 7 * WR, L * NG>(
+                s_refl,
+                [&](int r) {
+                    const int q = r / WR, wr = r - q * WR;
+                    return src + q * C + (long)wrap(w0 + wr) * N;
+                },
+                tid);
+            S.s_ref = s_refl;
+        }
+        // face coefficients of the own rows (x1) and of the own column segment (x2)
 #pragma unroll
-        for (int lf = 0; lf < NF; ++lf) S.ax[r][lf] = tab[TL.ax + (long)S.brow[r] * LF + (c0 - FW + lf) + 2];
+        for (int r = 0; r < R; ++r)
 #pragma unroll
-    for (int k = 0; k < K; ++k)
-#pragma unroll
-        for (int lr = 0; lr < NFR; ++lr) S.ay[k][lr] = tab[TL.ay + (long)(c0 + k) * LF + (S.brow[0] - FW + lr) + 2];
-    // state: u0 from the tables on the first launch, else the previous launch's output
-    const T *src = first ? tab + TL.m0 : (const T *)A.state_in + P.state_offset;
-#pragma unroll
-    for (int r = 0; r < R; ++r)
+            for (int lf = 0; lf < NF; ++lf) S.ax[r][lf] = tab[TL.ax + (long)S.brow[r] * LF + (c0 - FW + lf) + 2];
 #pragma unroll
         for (int k = 0; k < K; ++k)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                S.m[r][k][c] = gdead ? (T)0 : src[c * C + (long)S.brow[r] * N + c0 + k];
-                S.y[r][k][c] = S.m[r][k][c];
-                S.acc[r][k][c] = (T)0;
-            }
+            for (int lr = 0; lr < NFR; ++lr)
+                S.ay[k][lr] = tab[TL.ay + (long)(c0 + k) * LF + (S.brow[0] - FW + lr) + 2];
+        // state: u0 from the set-up tables on every window row
+        const T *src = tab + TL.m0;
 #pragma unroll
-    for (int c = 0; c < 6; ++c) S.tauF[0][c] = S.tauL[0][c] = (T)0;
-    S.tFb = S.tFs = S.tLb = S.tLs = S.tSb = S.tSs = S.tNb = S.tNs = 0;
-    __syncthreads();
-    S.gs = (g > 0) ? g - 1 : 0;
-    S.gn = (g < NG - 1) ? g + 1 : 0;
-    S.zero_s = (g == 0) || dead(g - 1);
-    S.zero_n = (g == NG - 1) || dead(g + 1);
-    S.s_halo = s_halo;
-    S.s_zero = s_zero;
-    S.s_tau = nullptr;
-    S.alpha = (T)P.alpha;
-    S.dt = (T)P.dt;
+        for (int r = 0; r < R; ++r)
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) S.acc64[q] = 0.0;
-
-    if (A.mode == 1) {  // evaluate H(m0) on the own rows only
-        S.template stage<AVG_EVAL, true, false>((T)0, (T)0, 0.0, 0, A.out_field + P.mfinal_offset, C);
-        return;
-    }
-    const int s_end = min(A.step0 + A.steps, P.M);
-    const bool last = (s_end >= P.M);
-    const bool rk4 = (P.stages == 4);
-    const T b1 = rk4 ? (T)(1.0 / 6.0) : (T)0.5;
-    const T c2dt = rk4 ? (T)(0.5 * P.dt) : (T)P.dt;
-    const T third = (T)(1.0 / 3.0);
-    const T half_dt = (T)(0.5 * P.dt);
-    const double *wtab = A.wt + P.wt_offset;  // w^0..w^M, then the tails
-    constexpr bool REREF = !Lane::REFG && (sizeof(T) == 4);
-    // Re-reference only at the start of a launch (the host sets A.reref once
-    // the previous launches have reached a multiple of kRerefSteps): all window
-    // rows are exact then, and the reference change of the two box rows beyond
-    // the window is formed here from the launch's inputs, so D(z) is exact on
-    // every window row.
-    const bool reref = REREF && A.reref;
-    if (reref) {
-        const T *rin = A.ref_in ? (const T *)A.ref_in + P.ref_offset : tab + TL.ref;
-        const T *uin = (const T *)A.state_in + P.state_offset;
-        for (int i = tid; i < 2 * 3 * N; i += L * NG) {
-            const int side = i / (3 * N), c = (i / N) % 3, col = i % N;
-            const int raw = (side == 0) ? w0 - 1 : w0 + WR;
-            T z = (T)0;
-            if (BC != LLHMM_BC_DIRICHLET || (raw >= 0 && raw < N)) {
-                const long cell = (long)wrap(raw) * N + col;
-                const T rv = rin[c * C + cell];
-                z = (rv + uin[c * C + cell]) - rv;
-            }
-            s_edge[i] = z;
-        }
-        S.s_edge = s_edge;
+            for (int k = 0; k < K; ++k)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    S.m[r][k][c] = gdead ? (T)0 : src[c * C + (long)S.brow[r] * N + c0 + k];
+                    S.y[r][k][c] = S.m[r][k][c];
+                    S.acc[r][k][c] = (T)0;
+                }
+#pragma unroll
+        for (int c = 0; c < 6; ++c) S.tauF[0][c] = S.tauL[0][c] = (T)0;
+        S.tFb = S.tFs = S.tLb = S.tLs = S.tSb = S.tSs = S.tNb = S.tNs = 0;
+        S.gs = (g > 0) ? g - 1 : 0;
+        S.gn = (g < NG - 1) ? g + 1 : 0;
+        S.zero_s = (g == 0) || dead(g - 1);
+        S.zero_n = (g == NG - 1) || dead(g + 1);
+        S.s_halo = s_halo;
+        S.s_zero = s_zero;
+        S.s_edge = s_zero;   // re-referencing sees zeros beyond the window too
+        S.s_tau = nullptr;
+        S.alpha = (T)P.alpha;
+        S.dt = (T)P.dt;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) S.acc64[q] = 0.0;
         __syncthreads();
-    }
-    int ts = 0;
-    for (int n = A.step0; n < s_end; ++n) {
-        const double wn = wtab[n];
-        if (reref && n == A.step0) S.rereference(wtab[P.M + 1 + n], ts++);
-        asm volatile("" ::: "memory");
-        S.template stage<Lane::AVG, true, false>(b1, c2dt, wn, ts, nullptr, 0);
-        ++ts;
-        const int nmid = rk4 ? 2 : 0;
-        for (int sm = 0; sm < nmid; ++sm) {
-            S.template stage<AVG_NONE, false, false>(third, sm == 0 ? half_dt : S.dt, 0.0, ts++, nullptr, 0);
-        }
-        S.template stage<AVG_NONE, false, true>(rk4 ? (T)(1.0 / 6.0) : (T)0.5, (T)0, 0.0, ts++, nullptr, 0);
-    }
 
-    // ---------------- own rows out: the state for the next launch, or m = r + u at the end
-    if (!last) {
-        T *dst = (T *)A.state_out + P.state_offset;
+        bool aborted = false;
+        if constexpr (EVAL) {
+            S.template stage<AVG_EVAL, true, false>((T)0, (T)0, 0.0, 0, A.out_field + P.mfinal_offset, C);
+        } else {
+            const int M = P.M;
+            const bool rk4 = (P.stages == 4);
+            const T b1 = rk4 ? (T)(1.0 / 6.0) : (T)0.5;
+            const T c2dt = rk4 ? (T)(0.5 * P.dt) : (T)P.dt;
+            const T third = (T)(1.0 / 3.0);
+            const T half_dt = (T)(0.5 * P.dt);
+            const double *wtab = A.wt + P.wt_offset;  // w^0..w^M, then the tails
+            constexpr bool REREF = !Lane::REFG && (sizeof(T) == 4);
+            int ts = 0;
+            for (int n = 0; n < M; ++n) {
+                if (n > 0 && n % spe == 0) {
+                    // replace the halo rows with the neighbours' rows of exchange e
+                    const uint32_t e = (uint32_t)(n / spe);
+                    const int par = (int)(e & 1);
+                    int fail = 0;
+                    if ((halo_s && has_s) || (halo_n && has_n)) {
+                        const uint64_t *sb = halo_s ? edge(s_south, 1, par) : edge(s_north, 0, par);
+                        // south halo rows come from the neighbour's last xd own rows, north
+                        // halo rows from its first ones
+                        const int q0 = halo_s ? xd - h + r0 : r0 - own_end;
+                        long long polls = 0;
+                        for (;;) {
+                            // read straight into the halo rows' state: a word that is
+                            // still old is read again on the next poll
+                            bool all = true;
 #pragma unroll
-        for (int r = 0; r < R; ++r)
-            if (S.own[r] && !gdead)
+                            for (int r = 0; r < R; ++r)
 #pragma unroll
-                for (int k = 0; k < K; ++k)
+                                for (int c = 0; c < 3; ++c)
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) dst[c * C + (long)S.brow[r] * N + c0 + k] = S.m[r][k][c];
-        if (reref) {  // the moved reference tables, for the next launches
-            T *rdst = (T *)A.ref_out + P.ref_offset;
+                                    for (int k = 0; k < K; ++k)
+                                        all &= xget(sb + (q0 + r) * XROW + ((long)c * N + c0 + k) * XW, e, S.m[r][k][c]);
+                            if (all) break;
+                            if (xload(A.abort_word) != 0 || ++polls > A.spin_max) {
+                                fail = 1;
+                                xstore(A.abort_word, 1);
+                                break;
+                            }
+                            __builtin_amdgcn_s_sleep(1);
+                        }
 #pragma unroll
-            for (int r = 0; r < R; ++r)
-                if (S.own[r] && !gdead)
+                        for (int r = 0; r < R; ++r)
 #pragma unroll
-                    for (int k = 0; k < K; ++k)
+                            for (int k = 0; k < K; ++k)
 #pragma unroll
-                        for (int q = 0; q < 7; ++q)
-                            rdst[q * C + (long)S.brow[r] * N + c0 + k] = S.ref(q, S.cell_of(r, k));
-        }
-    } else if (A.out_field) {
-        double *dst = A.out_field + P.mfinal_offset;
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-            if (S.own[r] && !gdead)
-#pragma unroll
-                for (int k = 0; k < K; ++k)
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        const long cell = (long)S.brow[r] * N + c0 + k;
-                        dst[c * C + cell] = (double)S.m[r][k][c] + (double)S.ref(c, S.cell_of(r, k));
+                                for (int c = 0; c < 3; ++c) S.y[r][k][c] = S.m[r][k][c];
                     }
-    }
-    // per-wave partial sums, accumulated over launches in a fixed order
+                    aborted = __syncthreads_or(fail) != 0;
+                    if (aborted) break;
+                }
+                const double wn = wtab[n];
+                if (REREF && n > 0 && n % kRerefSteps == 0) S.rereference(wtab[M + 1 + n], ts++);
+                asm volatile("" ::: "memory");
+                S.template stage<Lane::AVG, true, false>(b1, c2dt, wn, ts, nullptr, 0);
+                ++ts;
+                const int nmid = rk4 ? 2 : 0;
+                for (int sm = 0; sm < nmid; ++sm)
+                    S.template stage<AVG_NONE, false, false>(third, sm == 0 ? half_dt : S.dt, 0.0, ts++, nullptr, 0);
+                S.template stage<AVG_NONE, false, true>(rk4 ? (T)(1.0 / 6.0) : (T)0.5, (T)0, 0.0, ts++, nullptr, 0);
+                if ((n + 1) % spe == 0 && n + 1 < M) {
+                    // publish the edge rows of exchange e = (n + 1) / spe: the first xd own
+                    // rows (south edge) and the last xd (north edge; a group may be in both)
+                    const uint32_t e = (uint32_t)((n + 1) / spe);
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        double v = S.acc64[q];
+                    for (int side = 0; side < 2; ++side) {
+                        if (side == 0 ? !(pub_s && has_s) : !(pub_n && has_n)) continue;
+                        uint64_t *db = edge(sl, side, (int)(e & 1));
+                        const int q0 = (side == 0) ? r0 - h : r0 - (own_end - xd);
 #pragma unroll
-        for (int off = 1; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
-        S.acc64[q] = v;
-    }
-    if (lane == 0) {
-        const long slot = P.part_offset + (long)job.strip * (L * NG / 64) + wave;
-        double *dst = A.partials + slot * kMaxQ;
-        int bad = 0;
+                        for (int r = 0; r < R; ++r)
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            const double v = first ? S.acc64[q] : dst[q] + S.acc64[q];
-            dst[q] = v;
-            if (!__builtin_isfinite(v)) bad = 1;
+                            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                                for (int k = 0; k < K; ++k)
+                                    xput(db + (q0 + r) * XROW + ((long)c * N + c0 + k) * XW, S.m[r][k][c], e);
+                    }
+                }
+            }
+            if (A.out_field && !aborted) {
+                double *dst = A.out_field + P.mfinal_offset;
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    if (S.own[r] && !gdead)
+#pragma unroll
+                        for (int k = 0; k < K; ++k)
+#pragma unroll
+                            for (int c = 0; c < 3; ++c) {
+                                const long cell = (long)S.brow[r] * N + c0 + k;
+                                dst[c * C + cell] = (double)S.m[r][k][c] + (double)S.ref(c, S.cell_of(r, k));
+                            }
+            }
+            // per-wave partial sums (the window-row weights select the own rows)
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                double v = S.acc64[q];
+#pragma unroll
+                for (int off = 1; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
+                S.acc64[q] = v;
+            }
+            if (lane == 0) {
+                const long slot = P.part_offset + (long)job.slab * WAVES + wave;
+                double *dst = A.partials + slot * kMaxQ;
+                int bad = aborted ? 2 : 0;
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    dst[q] = S.acc64[q];
+                    if (!__builtin_isfinite(S.acc64[q]) && !bad) bad = 1;
+                }
+                A.wave_status[slot] = bad;
+            }
         }
-        A.wave_status[slot] = first ? bad : (A.wave_status[slot] | bad);
+        __syncthreads();  // LDS of this item is dead before the next item loads its own
     }
 }
 

@@ -37,7 +37,7 @@ class HmmLoop:
     micro      box fields shared by every micro problem (n, eps, mu, mu_box, eta,
                alpha, bc, order, a_max, integrator, n_steps, quantity = field)
     alpha, dt  macro damping and time step
-    tune       run the band-mode autotuner once on the initial state
+    tune       run the slab-mode autotuner once on the initial state
     model      "field", "flux" or "torque" (see the module docstring)
     flux_order order of the staggered divergence of the flux model (2 or 4)
     startup    macro scheme of the start-up steps (field, flux) or of every step
@@ -103,7 +103,7 @@ class HmmLoop:
         self.step_index = 0
         self.stages = 0
         if tune:
-            # band boxes: pick the tile variant and steps per launch on this batch
+            # slab boxes: pick the tile variant and exchange interval on this batch
             L.llhmm_batch_tune(self.ctx, self.batch, None, self.macro, self.Y, None, 1)
 
     def cell_steps_per_stage(self):

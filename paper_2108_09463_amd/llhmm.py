@@ -107,7 +107,7 @@ _SYMBOLS = {
     "llhmm_batch_tune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.POINTER(Macro), ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_int32, ctypes.c_void_p]),
-    "llhmm_batch_band_steps": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "llhmm_batch_slabs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "llhmm_tune_save": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p]),
     "llhmm_tune_load": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p]),
     "llhmm_server_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ServerCfg), ctypes.POINTER(Coef),
@@ -121,6 +121,8 @@ _SYMBOLS = {
                                          ctypes.POINTER(ctypes.c_int32)]),
     "llhmm_server_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                           ctypes.c_void_p, ctypes.c_void_p]),
+    "llhmm_server_set_output": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                               ctypes.c_int64]),
     "llhmm_macro_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                         ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                                         ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
@@ -376,10 +378,13 @@ def llhmm_batch_tune(ctx, batch, m_init=None, macro=None, M_macro=None, coef=Non
                                   _ptr(M_macro), _ptr(coef), reps, _stream(stream)))
 
 
-def llhmm_batch_band_steps(batch):
+def llhmm_batch_slabs(batch):
+    """(slabs per box, steps between slab exchanges per box); 0 for boxes
+    solved whole by one workgroup."""
     out = np.zeros(batch.n, np.int32)
-    _check(lib().llhmm_batch_band_steps(batch.h, out.ctypes.data))
-    return out
+    spe = np.zeros(batch.n, np.int32)
+    _check(lib().llhmm_batch_slabs(batch.h, out.ctypes.data, spe.ctypes.data))
+    return out, spe
 
 
 def llhmm_tune_save(ctx, path):
@@ -490,6 +495,11 @@ class Server:
                                        st.ctypes.data, lat.ctypes.data, ctypes.byref(n)))
         k = n.value
         return ids[:k], H[:k], st[:k], lat[:k]
+
+    def set_output(self, H_dev, ld, nrows):
+        """Results also into the device array H_dev[id * ld + q] (None: off)."""
+        _check(lib().llhmm_server_set_output(self.h, _ptr(H_dev), int(ld) if H_dev is not None else 0,
+                                             int(nrows) if H_dev is not None else 0))
 
     def stats(self):
         v = [ctypes.c_int64() for _ in range(4)]

@@ -62,7 +62,7 @@ class Prepared:
 
     def tune(self, reps=2):
         L.llhmm_batch_tune(self.ctx, self.batch, self.m_init, self.macro, self.M_macro, self.coef_dev, reps)
-        return L.llhmm_batch_band_steps(self.batch)
+        return L.llhmm_batch_slabs(self.batch)
 
     def solve(self, want_state=False):
         torch = self.torch

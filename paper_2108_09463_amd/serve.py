@@ -5,7 +5,15 @@ Each macro stage issues one micro request per macro point at the current
 stage input Y (Q_[4] initial data from Y), shuffled and released in bursts;
 results are collected as their micro-batches finish, then one
 llhmm_macro_step stage advances the macro state (HeunP start-up steps, then
-MPEA).  Latencies are host times from submit to the poll that returns them.
+MPEA).  The micro-batches also leave their averages in a device array, which
+the macro stage reads in place (no host round trip).  Latencies are host
+times from submit to the poll that returns them.
+
+Arrival of the bursts:
+  saturating  all bursts released back to back;
+  closed      each burst released when the previous one has completed;
+  open        bursts released at exponential gaps of a given mean (seeded),
+              whatever has completed.
 """
 from __future__ import annotations
 
@@ -15,6 +23,21 @@ import numpy as np
 
 from . import inputs
 from . import llhmm as L
+
+
+class ServeFailed(RuntimeError):
+    """Requests of a macro stage came back with a nonzero status."""
+
+
+def check_stage(rec):
+    """Raises ServeFailed unless every request of the stage record succeeded:
+    a failed request leaves no average, and the macro stage must not advance on
+    a missing field."""
+    st = np.asarray(rec["status"])
+    bad = np.nonzero(st != 0)[0]
+    if len(bad):
+        raise ServeFailed("%d of %d requests failed (first: id %d, status %d)"
+                          % (len(bad), len(st), int(bad[0]), int(st[bad[0]])))
 
 
 class ServedRun:
@@ -38,18 +61,28 @@ class ServedRun:
         self.server = L.Server(self.ctx, [L.to_coef(c) for c in coefs], precision,
                                max_inflight=max_inflight, max_batch_boxes=max_batch_boxes,
                                device_bytes=device_bytes)
+        # the field averages of a stage, written by the micro-batches (request id = macro point)
+        self.Hd = torch.zeros((self.npts, 3), dtype=torch.float64, device=self.dev)
+        self.server.set_output(self.Hd, 3, self.npts)
         self.alpha = alpha_macro
         self.dt = dt_macro if dt_macro is not None else 0.1 / n_macro ** 2
         self.seed = seed
         self.cell_steps = int(sum(int(m) * b["n"] ** 2 for m, b in zip(L.llhmm_plan(boxes)[0], boxes)))
 
-    def stage(self, Y, stage_index=0, gap_s=0.0):
-        """One macro stage: a request per macro point at state Y (device [3][npts]).
-        Returns H [npts, 3], per-request latencies (us), per-burst latencies (s),
-        the stage latency (s) and the burst sizes."""
+    def stage(self, Y, stage_index=0, arrival="saturating", gap_mean_s=0.0):
+        """One macro stage: a request per macro point at state Y (device [3][npts]),
+        bursts released as `arrival` says (gap_mean_s: mean gap of "open").
+        Returns H [npts, 3], statuses, per-request latencies (us), per-burst
+        latencies (s), the stage latency (s) and the burst sizes."""
         rng = np.random.default_rng(self.seed * 1000 + stage_index)
         order = rng.permutation(self.npts)
         bursts = inputs.burst_sizes(self.npts, self.seed * 1000 + stage_index)
+        if arrival == "open":
+            gaps = rng.exponential(gap_mean_s, len(bursts))
+        elif arrival in ("saturating", "closed"):
+            gaps = np.zeros(len(bursts))
+        else:
+            raise ValueError("arrival: saturating, closed or open")
         H = np.full((self.npts, 3), np.nan)
         lat = np.zeros(self.npts)
         status = np.zeros(self.npts, np.int32)
@@ -57,17 +90,23 @@ class ServedRun:
         t_burst = []
         got = 0
         t0 = time.perf_counter()
+        t_next = t0
         pos = 0
         for bi, bsz in enumerate(bursts):
+            if arrival == "closed":
+                while got < pos:      # the previous bursts have completed
+                    got += self._collect(H, lat, status, wait=True)
+            elif arrival == "open":
+                t_next += gaps[bi] if bi > 0 else 0.0
+                while time.perf_counter() < t_next:
+                    got += self._collect(H, lat, status, wait=False)
+                    time.sleep(2e-4)
             ids = order[pos:pos + bsz]
             pos += bsz
             burst_of[ids] = bi
             t_burst.append(time.perf_counter())
             self.server.submit([self.boxes[i] for i in ids], ids, macro=self.macro, M_macro=Y)
             got += self._collect(H, lat, status, wait=False)
-            if gap_s > 0.0:
-                time.sleep(gap_s)
-                got += self._collect(H, lat, status, wait=False)
         while got < self.npts:
             got += self._collect(H, lat, status, wait=True)
         t_stage = time.perf_counter() - t0
@@ -83,26 +122,26 @@ class ServedRun:
         status[ids] = st
         return len(ids)
 
-    def macro_stage(self, step, stage, H):
-        """Advances the macro stepper by one stage with H_avg at the current Y."""
-        torch = self.torch
+    def macro_stage(self, step, stage, rec):
+        """Advances the macro stepper by one stage with the H_avg the stage's
+        micro-batches left on the device; refuses a stage with failed requests."""
+        check_stage(rec)
         scheme = L.MACRO_HEUNP if step < 2 else L.MACRO_MPEA
-        Hd = torch.from_numpy(np.ascontiguousarray(H)).to(self.dev)
         nxt = L.llhmm_macro_step(self.ctx, self.npts, scheme, step, stage, self.dt, self.alpha,
-                                 self.M, Hd, self.Y, self.work)
-        torch.cuda.synchronize()
+                                 self.M, self.Hd, self.Y, self.work)
+        self.torch.cuda.synchronize()
         return nxt
 
-    def run(self, steps, gap_s=0.0):
+    def run(self, steps, arrival="saturating", gap_mean_s=0.0):
         """`steps` macro steps; returns the per-stage records."""
         out = []
         k = 0
         for step in range(steps):
             stage = 0
             while True:
-                rec = self.stage(self.Y, k, gap_s)
+                rec = self.stage(self.Y, k, arrival, gap_mean_s)
                 k += 1
-                stage = self.macro_stage(step, stage, rec["H"])
+                stage = self.macro_stage(step, stage, rec)
                 rec.update(step=step)
                 out.append(rec)
                 if stage == 0:

@@ -28,7 +28,7 @@ def test_exports_every_declared_symbol(lib):
     assert len(names) >= 12
     for n in sorted(names):
         assert hasattr(lib, n), n
-    assert L.llhmm_abi_version() == 2
+    assert L.llhmm_abi_version() == 3
 
 
 def _all_boxes():

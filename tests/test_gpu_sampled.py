@@ -3,7 +3,7 @@ face of the extended grid instead of the closed form.  The samples given here
 are the oracle's own face values (the ABI layout [dim][E^dim] with E = n + 6,
 x1 fastest, is the one the oracle builds), so the GPU sees exactly the
 oracle's faces: FP64 must match at rounding level, FP32 within its bar.
-Resident and band (128^2, FP32) boxes, both BCs, 1-D and 2-D."""
+Resident and slab (128^2, FP32) boxes, both BCs, 1-D and 2-D."""
 import numpy as np
 import pytest
 

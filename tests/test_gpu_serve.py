@@ -148,12 +148,16 @@ def test_served_stage_equals_batch(ctx):
     p = Prepared(wl, precision=inputs.FP32, ctx=ctx)
     out = p.solve()
     assert np.array_equal(out["H"][:, :3], rec["H"])
-    # two more macro stages run through the loop (HeunP start-up)
-    nxt = run.macro_stage(0, 0, rec["H"])
+    # the micro-batches left the same averages in the device array the macro stage reads
+    assert np.array_equal(run.Hd.cpu().numpy(), rec["H"])
+    # two more macro stages run through the loop (HeunP start-up), the second
+    # with bursts released at exponential gaps
+    nxt = run.macro_stage(0, 0, rec)
     assert nxt == 1
-    rec2 = run.stage(run.Y, 1)
+    rec2 = run.stage(run.Y, 1, arrival="open", gap_mean_s=2e-3)
     assert (rec2["status"] == 0).all() and np.isfinite(rec2["H"]).all()
-    assert run.macro_stage(0, 1, rec2["H"]) == 0
+    assert np.array_equal(run.Hd.cpu().numpy(), rec2["H"])
+    assert run.macro_stage(0, 1, rec2) == 0
     M = run.M.cpu().numpy()
     assert np.abs(np.linalg.norm(M, axis=0) - 1).max() < 1e-13
     run.close()

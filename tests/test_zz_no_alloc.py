@@ -17,21 +17,21 @@ from paper_2108_09463_amd import llhmm as L
 pytestmark = pytest.mark.gpu
 
 
-def _mixed(nsmall, nband, seed, precision):
+def _mixed(nsmall, nslab, seed, precision):
     """2-D boxes of several sizes (resident 32..64, row-strip 96/128), both BCs,
     explicit EX2 initial data at seeded centres."""
     eps = 1.0 / 200.0
     rng = np.random.default_rng(seed)
     boxes = []
-    sizes = [32, 48, 64] * nsmall + [96, 128] * nband
-    sizes = sizes[:nsmall + nband]
+    sizes = [32, 48, 64] * nsmall + [96, 128] * nslab
+    sizes = sizes[:nsmall + nslab]
     for i, n in enumerate(sizes):
         boxes.append(inputs.make_box(dim=2, n=int(n), quantity=inputs.Q_FIELD, eps=eps,
                                      alpha=float(rng.uniform(0.05, 1.2)), mu=3 * eps,
                                      mu_box=3 * eps, eta=0.3 * eps ** 2, a_max=1.65,
                                      bc=inputs.BC_PERIODIC_PERT if i % 2 == 0 else inputs.BC_DIRICHLET,
                                      center=(float(rng.random()), float(rng.random()))))
-    if nsmall + nband > 1:
+    if nsmall + nslab > 1:
         boxes[1]["mu"] = 2 * eps   # Dirichlet box with mu < mu'
     return inputs.Workload("noalloc", 2, boxes, [inputs.coef_quasi(eps)], init=inputs.InitEX2(),
                            precision=precision)
