@@ -70,7 +70,7 @@ typedef enum {
     LLHMM_E_INVALID = -1,   /* argument violates the paper's assumptions or the contract */
     LLHMM_E_NOMEM = -2,     /* device or host allocation failed */
     LLHMM_E_BUDGET = -3,    /* a box class does not fit the on-chip budget of any kernel */
-    LLHMM_E_UNSTABLE = -4,  /* a box produced non-finite values (see status words) */
+    LLHMM_E_UNSTABLE = -4,  /* a box produced non-finite values or an unresolved final state (status words) */
     LLHMM_E_HIP = -5,       /* a HIP runtime call failed */
     LLHMM_E_NOTSUP = -6     /* valid request, no kernel built for it */
 } llhmm_status;
@@ -230,9 +230,14 @@ llhmm_status llhmm_micro_batch(llhmm_ctx *ctx, llhmm_batch *batch, const double 
  *   H_avg_dev[b * ld + q], q < nq, nq = 3 (field, torque) or 3*dim (flux,
  *   [axis][component]), FP64.  ld >= the largest nq of the batch.  Nullable.
  *   status_dev (nullable, int32[nboxes]): 0 ok; bit 0 (1) non-finite values;
- *   bit 1 (2) a slab exchange wait gave up (see Large boxes).
- * With `check` != 0 the call synchronizes the stream and returns
- * LLHMM_E_UNSTABLE if any box is non-finite. */
+ *   bit 1 (2) a slab exchange wait gave up (see Large boxes); bit 2 (4) the
+ *   final state is not resolved: two neighbouring grid points differ by more
+ *   than 0.5 (an unstable run leaves grid-scale noise, which the projection
+ *   keeps on the unit sphere; x1 neighbours, and x2 neighbours held by one
+ *   lane); bit 3 (8) the final state left the unit sphere, ||m|^2 - 1| above
+ *   1e-4 (FP32) or 1e-10 (FP64).  Bits 2 and 3 test the final state only.
+ * With `check` != 0 the call synchronizes the stream and returns LLHMM_E_HIP
+ * for bit 1 and LLHMM_E_UNSTABLE for bits 0, 2 and 3. */
 llhmm_status llhmm_upscale(llhmm_ctx *ctx, llhmm_batch *batch, double *H_avg_dev, int32_t ld,
                            int32_t *status_dev, int32_t check, hipStream_t stream);
 
@@ -286,9 +291,9 @@ llhmm_status llhmm_solve_noalloc(llhmm_ctx *ctx, const llhmm_box *boxes, int32_t
  * rows and h halo rows on each side: the zeros it sees beyond that window
  * corrupt one more row per Runge-Kutta stage, so the own rows stay exact for
  * h / stages steps.  Every `steps_per_exchange` steps (1, 2, 4 or 8, with
- * h >= steps_per_exchange x stages) the slabs publish their edge rows to global
- * memory and replace their halo rows with their neighbours'; the box state
- * never leaves the chip otherwise.  Each class runs as one persistent launch
+ * h >= steps_per_exchange x stages) the slabs publish their h edge rows on
+ * each side to global memory and replace their halo rows with their
+ * neighbours'; the box state never leaves the chip otherwise.  Each class runs as one persistent launch
  * whose workgroups take (box, slab) items, longest boxes first.  A wait for a
  * neighbouring slab gives up after a bounded number of polls; the boxes
  * involved then report status 2 and llhmm_upscale with check returns

@@ -273,9 +273,9 @@ const std::map<SlabKey, std::vector<const SlabTileInfo *>> &slab_registry() {
 // h halo rows on each side (each stage moves the error of the zeros beyond the
 // window one row inwards, so h >= spe * stages, rounded up to whole row
 // groups), at most WR - 2h own rows per slab, the box's row groups split as
-// evenly as possible over ns >= 2 slabs.  A slab's north halo is what its
-// window has left, WR - h - own >= h rows; the neighbours publish the xd
-// rows the deepest halo needs, which every slab must own.  ns = 0: invalid.
+// evenly as possible over ns >= 2 slabs.  Every slab keeps h halo rows on each
+// side (window rows beyond them stay unused) and publishes xd = h rows at each
+// edge, which it must own.  ns = 0: invalid.
 struct SlabGeom {
     int spe = 0, h = 0, ns = 0, xd = 0;
 };
@@ -292,7 +292,7 @@ SlabGeom slab_geom(const SlabTileInfo &t, int n, int stages, int spe) {
     const int groups = n / t.R;
     const int ns = (groups + capg - 1) / capg;
     const int own_min = groups / ns * t.R;
-    const int xd = WR - h - own_min;
+    const int xd = h;
     if (ns < 2 || own_min < xd) return g;
     g.spe = spe;
     g.h = h;
@@ -444,9 +444,13 @@ struct SlabClass {
     SlabGeom geom;                // shared by the class's boxes (same n, stages and interval)
     int stages;
     int first, count;             // range of (box, slab) items in the concatenated job list
-    int index;                    // class index: its work counter and abort word in slab_sync
+    int nq;                       // work queues, one per XCD
+    int qoff[kMaxXcc + 1];        // queue q: items [first + qoff[q], first + qoff[q + 1])
+    int index;                    // class index: its counters and abort word in slab_sync
     double cost;
 };
+
+constexpr int kSlabSyncInts = 16;  // per class in slab_sync: kMaxXcc queue counters, abort word, padding
 
 // Polls before a wait for a neighbouring slab gives up (about a minute at the
 // poll interval); LLHMM_SLAB_SPIN_MAX overrides it (tests of the give-up path).
@@ -470,6 +474,7 @@ struct GraphArgs {
 struct llhmm_batch {
     int nboxes, prec, dim_max, nmax;
     int ncu = 1;                                  // compute units of the device (slab grid size)
+    int nxcc = 1;                                 // XCDs of the device (slab work queues)
     int64_t cell_steps;
     bool any_explicit, any_macro, any_sampled;
     std::vector<BoxPlan> plans_h;
@@ -576,21 +581,34 @@ static llhmm_status rebuild_slabs(llhmm_batch *b) {
         sc.first = (int)jobs_h.size();
         sc.index = (int)b->slabs.size();
         sc.cost = 0.0;
+        sc.nq = b->nxcc;
         const int WR = sc.tile->R * sc.tile->NG;
+        // boxes onto the XCD queues, longest first onto the least loaded
+        std::vector<std::vector<int>> q(sc.nq);
+        std::vector<double> qload(sc.nq, 0.0);
         for (int i : v) {
-            const BoxPlan &P = b->plans_h[i];
-            for (int s = 0; s < sc.geom.ns; ++s) {
-                SlabJob J{};
-                J.box = i;
-                J.slab = s;
-                J.nslabs = sc.geom.ns;
-                slab_rows(*sc.tile, P.n, sc.geom.ns, s, &J.o0, &J.rows);
-                J.xoff = b->xoff_h[i];
-                jobs_h.push_back(J);
+            const int k = (int)(std::min_element(qload.begin(), qload.end()) - qload.begin());
+            qload[k] += (double)b->plans_h[i].M * b->plans_h[i].stages;
+            q[k].push_back(i);
+        }
+        for (int k = 0; k < sc.nq; ++k) {
+            sc.qoff[k] = (int)jobs_h.size() - sc.first;
+            for (int i : q[k]) {
+                const BoxPlan &P = b->plans_h[i];
+                for (int s = 0; s < sc.geom.ns; ++s) {
+                    SlabJob J{};
+                    J.box = i;
+                    J.slab = s;
+                    J.nslabs = sc.geom.ns;
+                    slab_rows(*sc.tile, P.n, sc.geom.ns, s, &J.o0, &J.rows);
+                    J.xoff = b->xoff_h[i];
+                    jobs_h.push_back(J);
+                }
+                sc.cost += (double)P.M * P.stages * sc.geom.ns * WR * P.n;  // window rows computed
             }
-            sc.cost += (double)P.M * P.stages * sc.geom.ns * WR * P.n;  // window rows computed
         }
         sc.count = (int)jobs_h.size() - sc.first;
+        for (int k = sc.nq; k <= kMaxXcc; ++k) sc.qoff[k] = sc.count;
         b->slabs.push_back(sc);
     }
     if (!jobs_h.empty()) HIP_TRY(bcopy_h2d(b, b->jobs, jobs_h.data(), sizeof(SlabJob) * jobs_h.size()));
@@ -728,10 +746,12 @@ static llhmm_status batch_create_impl(llhmm_ctx *ctx, const llhmm_box *boxes, in
     }
     HIP_TRY(hipSetDevice(ctx->device));
     double dcoef[8] = {0};
-    int ncu = 0;
+    int ncu = 0, nxcc = 1;
     HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ctx->device));
+    if (hipDeviceGetAttribute(&nxcc, hipDeviceAttributeNumberOfXccs, ctx->device) != hipSuccess) nxcc = 1;
     llhmm_batch *b = new llhmm_batch();
     b->arena = arena;
+    b->nxcc = std::min(std::max(1, nxcc), kMaxXcc);
     b->ncu = std::max(1, ncu);
     b->upload_stream = upload_stream;
     b->async_upload = async_upload;
@@ -966,9 +986,9 @@ static llhmm_status batch_create_impl(llhmm_ctx *ctx, const llhmm_box *boxes, in
     if (e == hipSuccess) e = balloc(b, (void **)&b->partials, sizeof(double) * (size_t)part_off * kMaxQ);
     if (e == hipSuccess) e = balloc(b, (void **)&b->wave_status, sizeof(int32_t) * (size_t)part_off);
     if (b->nslab_boxes > 0) {
-        // slab_sync: a work counter and an abort word per class (at most one class
-        // per slab box)
-        b->nsync = 2 * (int64_t)b->nslab_boxes;
+        // slab_sync: per class (at most one class per slab box) its queue counters
+        // and abort word
+        b->nsync = kSlabSyncInts * (int64_t)b->nslab_boxes;
         b->nxwords = xbuf_off;
         if (e == hipSuccess) e = balloc(b, (void **)&b->slab_sync, sizeof(int32_t) * b->nsync);
         if (e == hipSuccess) e = balloc(b, (void **)&b->xbuf, sizeof(uint64_t) * xbuf_off);
@@ -1105,10 +1125,11 @@ static llhmm_status launch_slab_class(llhmm_batch *b, const SlabClass &sc, int m
     SlabArgs a{};
     a.plans = b->plans;
     a.jobs = b->jobs + sc.first;
-    a.nitems = sc.count;
+    a.nqueues = sc.nq;
+    for (int k = 0; k <= kMaxXcc; ++k) a.qoff[k] = sc.qoff[k];
     a.mode = mode;
-    a.counter = b->slab_sync + 2 * sc.index;
-    a.abort_word = b->slab_sync + 2 * sc.index + 1;
+    a.counter = b->slab_sync + kSlabSyncInts * sc.index;
+    a.abort_word = b->slab_sync + kSlabSyncInts * sc.index + kMaxXcc;
     a.spin_max = slab_spin_max();
     a.h = sc.geom.h;
     a.spe = sc.geom.spe;
@@ -1120,7 +1141,9 @@ static llhmm_status launch_slab_class(llhmm_batch *b, const SlabClass &sc, int m
     a.wave_status = b->wave_status;
     a.xbuf = b->xbuf;
     a.out_field = field_dev;
-    const int grid = std::min(sc.count, bpc * b->ncu);
+    // every XCD gets its share of the resident workgroups (dispatch is round robin
+    // over the XCDs); workgroups whose queue is empty end at once
+    const int grid = bpc * b->ncu;
     HIP_TRY(sc.tile->launch(a, grid, stream));
     return LLHMM_OK;
 }
@@ -1283,7 +1306,10 @@ llhmm_status llhmm_upscale(llhmm_ctx *ctx, llhmm_batch *b, double *H_avg_dev, in
         HIP_TRY(hipStreamSynchronize(stream));
         for (int i = 0; i < b->nboxes; ++i)
             if (st[i] & 2) return fail(LLHMM_E_HIP, "box %d: a slab exchange wait gave up", i);
-            else if (st[i]) return fail(LLHMM_E_UNSTABLE, "box %d produced non-finite values", i);
+            else if (st[i] & 1) return fail(LLHMM_E_UNSTABLE, "box %d produced non-finite values", i);
+            else if (st[i] & 4) return fail(LLHMM_E_UNSTABLE, "box %d: final state not resolved (neighbouring "
+                                            "points differ by more than %g)", i, kRoughMax);
+            else if (st[i] & 8) return fail(LLHMM_E_UNSTABLE, "box %d: final state left the unit sphere", i);
     }
     return LLHMM_OK;
 }

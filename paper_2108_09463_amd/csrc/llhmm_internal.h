@@ -9,7 +9,11 @@ namespace llhmm {
 
 constexpr int kGhost = LLHMM_GHOST;
 constexpr int kMaxWaves = 16;  // waves per block of the resident kernels
-constexpr int kMaxQ = 9;       // outputs per box (flux in 3-D: 3 axes x 3 components)
+// Largest distance between neighbouring points of a final state that counts as
+// resolved (status bit 4 above it)
+constexpr double kRoughMax = 0.5;
+constexpr int kMaxQ = 9;
+constexpr int kMaxXcc = 8;     // accelerator complexes (XCDs) per device, each with its own L2       // outputs per box (flux in 3-D: 3 axes x 3 components)
 constexpr int kFaceHalo = 3;   // faces -2 .. n stored per line: n + 3 entries
 // FP32 reference + perturbation form: every kRerefSteps time steps the state
 // is re-expressed around a new reference r' = fl(r + u) (MicroLane::rereference).
@@ -141,7 +145,8 @@ struct MicroArgs {
 // which it advances redundantly; after every `spe` time steps it publishes
 // the edge rows of its own rows and replaces its halo rows by its
 // neighbours' published rows (global memory, tagged words).  One persistent
-// launch per class takes (box, slab) items from a counter.
+// launch per class; its workgroups take (box, slab) items from the queue of
+// the XCD they run on.
 struct SlabJob {
     int32_t box, slab, nslabs, o0;  // slab owns box rows [o0, o0 + rows)
     int32_t rows, pad_;
@@ -151,8 +156,9 @@ struct SlabJob {
 struct SlabArgs {
     const BoxPlan *plans;
     const SlabJob *jobs;        // items, in the order they are taken
-    int32_t nitems, mode;       // mode 0 solve, 1 evaluate H(m0) only
-    int32_t *counter;           // next item (zero before the launch)
+    int32_t nqueues, mode;      // work queues (one per XCD); mode 0 solve, 1 evaluate H(m0) only
+    int32_t qoff[kMaxXcc + 1];  // queue q holds items [qoff[q], qoff[q + 1]) of jobs
+    int32_t *counter;           // next item of each queue [nqueues] (zero before the launch)
     int32_t *abort_word;        // set when a wait gives up (zero before the launch)
     long long spin_max;         // polls before a wait gives up
     int32_t h, spe;             // halo rows per side; time steps per exchange

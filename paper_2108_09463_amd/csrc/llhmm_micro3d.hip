@@ -287,6 +287,24 @@ __global__ void __launch_bounds__(kThreads3d) k_setup3d(Micro3dArgs A) {
 // faces between points i and i+1, i = j-2..j+1 (faces pre-scaled by
 // 1/(24 dx)^2), combined as 27 (F_{j+1/2} - F_{j-1/2}) - (F_{j+3/2} - F_{j-3/2}).
 // f_east: the flux on the east face j+1/2.
+// Status bits 4 and 8 of a box from its final state m [3][n^3] (points t =
+// (i2 n + i1) n + i0), block-wide: 4 when two x1-neighbouring points differ by
+// more than kRoughMax (an unresolved, grid-scale state), 8 when ||m|^2 - 1|
+// exceeds 1e-10.  Every thread of the block must call it.
+__device__ int final_state_bits(const double *m, long C, int n, int tid, int nth) {
+    int bits = 0;
+    for (long t = tid; t < C; t += nth) {
+        const double a0 = m[t], a1 = m[C + t], a2 = m[2 * C + t];
+        const double e = __builtin_fma(a0, a0, __builtin_fma(a1, a1, __builtin_fma(a2, a2, -1.0)));
+        if (!(__builtin_fabs(e) <= 1e-10)) bits |= 8;
+        if (t % n != n - 1) {
+            const double d0 = m[t + 1] - a0, d1 = m[C + t + 1] - a1, d2 = m[2 * C + t + 1] - a2;
+            if (!(__builtin_fma(d0, d0, __builtin_fma(d1, d1, d2 * d2)) <= kRoughMax * kRoughMax)) bits |= 4;
+        }
+    }
+    return (__syncthreads_or(bits & 4) ? 4 : 0) | (__syncthreads_or(bits & 8) ? 8 : 0);
+}
+
 __device__ __forceinline__ double axis_o4(const double *yc, const double *Aax, long e, long st,
                                           double &f_east) {
     double F[4];
@@ -476,13 +494,14 @@ __global__ void __launch_bounds__(kThreads3d) k_micro3d_o4(Micro3dArgs A) {
             for (int c = 0; c < 9; ++c) s_red[tid][c] = s_red[tid][c] + s_red[tid + half][c];
         __syncthreads();
     }
+    const int hbits = final_state_bits(B.m, C, n, tid, kThreads3d);
     if (tid == 0) {
         double *dst = A.partials + P.part_offset * kMaxQ;
-        int bad = 0;
+        int bad = hbits;
         for (int q = 0; q < kMaxQ; ++q) {
             const double v = (q < 9) ? s_red[0][q] : 0.0;
             dst[q] = v;
-            if (!__builtin_isfinite(v)) bad = 1;
+            if (!__builtin_isfinite(v)) bad |= 1;
         }
         A.wave_status[P.part_offset] = bad;
     }
@@ -750,13 +769,14 @@ __global__ void __launch_bounds__(NT, 1) k_micro3d(Micro3dArgs A) {
             for (int c = 0; c < NQ; ++c) s_red[tid][c] = s_red[tid][c] + s_red[tid + half][c];
         __syncthreads();
     }
+    const int hbits = final_state_bits(B.m, C, n, tid, NT);
     if (tid == 0) {
         double *dst = A.partials + P.part_offset * kMaxQ;
-        int bad = 0;
+        int bad = hbits;
         for (int q = 0; q < kMaxQ; ++q) {
             const double v = (q < NQ) ? s_red[0][q] : 0.0;
             dst[q] = v;
-            if (!__builtin_isfinite(v)) bad = 1;
+            if (!__builtin_isfinite(v)) bad |= 1;
         }
         A.wave_status[P.part_offset] = bad;
     }

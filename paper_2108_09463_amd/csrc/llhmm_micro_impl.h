@@ -119,13 +119,23 @@ __device__ __forceinline__ T xload(const T *p) {
     return __hip_atomic_load(const_cast<T *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 template <typename T> struct XWords { static constexpr int n = sizeof(T) / 4; };  // words per value
+// Exchange words go between workgroups on one XCD: a plain store leaves them in
+// that XCD's L2, where the agent-scope loads of its other CUs find them,
+// without the write-through to memory an agent-scope store makes.
+__device__ __forceinline__ void xstore_xcd(uint64_t *p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
 __device__ __forceinline__ void xput(uint64_t *p, float v, uint32_t tag) {
-    xstore(p, (uint64_t)__builtin_bit_cast(uint32_t, v) | ((uint64_t)tag << 32));
+    xstore_xcd(p, (uint64_t)__builtin_bit_cast(uint32_t, v) | ((uint64_t)tag << 32));
 }
 __device__ __forceinline__ void xput(uint64_t *p, double v, uint32_t tag) {
     const uint64_t b = __builtin_bit_cast(uint64_t, v);
-    xstore(p, (uint64_t)((b & 0xffffffffu) | ((uint64_t)tag << 32)));
-    xstore(p + 1, (uint64_t)((b >> 32) | ((uint64_t)tag << 32)));
+    xstore_xcd(p, (uint64_t)((b & 0xffffffffu) | ((uint64_t)tag << 32)));
+    xstore_xcd(p + 1, (uint64_t)((b >> 32) | ((uint64_t)tag << 32)));
+}
+// The accelerator complex (XCD) this wave runs on.
+__device__ __forceinline__ int xcc_id() {
+    return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20);  // HW_REG_XCC_ID, bits 3:0
 }
 // Reads a value whose words carry at least `tag`; false while any word is older.
 __device__ __forceinline__ bool xget(const uint64_t *p, uint32_t tag, float &v) {
@@ -153,7 +163,10 @@ struct MicroLane {
     static constexpr int NFRD = (D == 2) ? NFR : 1;
     static constexpr int NQ = (QTY == LLHMM_Q_FLUX) ? 3 * D : 3;
     static constexpr int AVG = (QTY == LLHMM_Q_FIELD) ? 1 : ((QTY == LLHMM_Q_TORQUE) ? 2 : 3);
-    static constexpr int HALO = (D == 2) ? NG * 2 * YH * 3 * N : 1;
+    // LDS halo per row group: its first and last YH rows (one copy when R == YH,
+    // where they are the same rows)
+    static constexpr int HSIDES = (R == YH) ? 1 : 2;
+    static constexpr int HALO = (D == 2) ? NG * HSIDES * YH * 3 * N : 1;
     // 2-D boundary offsets in LDS: [2N lines/columns][2 sides][GF faces][hi 4, lo 4],
     // then a zero block read by lanes without boundary faces
     static constexpr int TAU_LDS = (D == 2) ? 4 * N * GF * 8 + 24 : 1;
@@ -248,12 +261,12 @@ struct MicroLane {
                 for (int c = 0; c < 3; ++c)
 #pragma unroll
                     for (int k = 0; k < K; ++k) {
-                        hb[(((g * 2 + 0) * YH + q) * 3 + c) * N + c0 + k] = y[q][k][c];
-                        hb[(((g * 2 + 1) * YH + q) * 3 + c) * N + c0 + k] = y[R - YH + q][k][c];
+                        hb[(((g * HSIDES + 0) * YH + q) * 3 + c) * N + c0 + k] = y[q][k][c];
+                        if (HSIDES == 2) hb[(((g * HSIDES + 1) * YH + q) * 3 + c) * N + c0 + k] = y[R - YH + q][k][c];
                     }
             __syncthreads();
-            srcS = zero_s ? s_zero : hb + ((gs * 2 + 1) * YH) * 3 * N;
-            srcN = zero_n ? s_zero : hb + ((gn * 2 + 0) * YH) * 3 * N;
+            srcS = zero_s ? s_zero : hb + ((gs * HSIDES + HSIDES - 1) * YH) * 3 * N;
+            srcN = zero_n ? s_zero : hb + ((gn * HSIDES + 0) * YH) * 3 * N;
             if (SLAB && AVG == AVG_DREF) {  // the reference change is known beyond the window
                 if (g == 0) srcS = s_edge;
                 if (g == NG - 1) srcN = s_edge + 3 * N;
@@ -512,6 +525,69 @@ struct MicroLane {
         }
     }
 
+    // Status bits of the final state of this lane's own points (every lane of
+    // the group calls it; `live`: the lane holds box points):
+    //   4  two neighbouring points differ by more than kRoughMax (an
+    //      unresolved, grid-scale state: what an unstable run leaves, since
+    //      the projection keeps it on the unit sphere);
+    //   8  ||m|^2 - 1| exceeds the precision's drift tolerance.
+    // Neighbours along x1 (the next lane's first column through DPP; the pair
+    // across the box edge is skipped) and along x2 within the lane's rows.
+    __device__ __forceinline__ int health(bool live) const {
+        T mf[R][K][3];
+        int bits = 0;
+        // an opaque zero: keeps the table addresses below from being computed
+        // ahead of the time loop, where they would only add register pressure
+        int opaque;
+        asm volatile("v_mov_b32 %0, 0" : "=v"(opaque));
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const int cell = cell_of(r, k) + opaque;
+                T e;
+                if (FORM == 1) {
+                    const T r0v = ref(0, cell), r1v = ref(1, cell), r2v = ref(2, cell);
+                    const T u0 = m[r][k][0], u1 = m[r][k][1], u2 = m[r][k][2];
+                    e = fma_t((T)2, fma_t(r0v, u0, fma_t(r1v, u1, r2v * u2)),
+                              fma_t(u0, u0, fma_t(u1, u1, fma_t(u2, u2, ref(3, cell)))));
+                    mf[r][k][0] = r0v + u0;
+                    mf[r][k][1] = r1v + u1;
+                    mf[r][k][2] = r2v + u2;
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) mf[r][k][c] = m[r][k][c];
+                    e = fma_t(mf[r][k][0], mf[r][k][0], fma_t(mf[r][k][1], mf[r][k][1],
+                                                             fma_t(mf[r][k][2], mf[r][k][2], (T)-1)));
+                }
+                const T tol = (sizeof(T) == 4) ? (T)1e-4 : (T)1e-10;
+                if (live && owned(r) && !(__builtin_fabs(e) <= tol)) bits |= 8;
+            }
+        const bool edge_lane = (L == 16) ? ((threadIdx.x & 15) == 15) : ((threadIdx.x & 63) == 63);
+        auto far = [](T a0, T a1, T a2, T b0, T b1, T b2) {
+            const T d0 = a0 - b0, d1 = a1 - b1, d2 = a2 - b2;
+            return !(fma_t(d0, d0, fma_t(d1, d1, d2 * d2)) <= (T)(kRoughMax * kRoughMax));
+        };
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            T east[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) east[c] = dpp_mov<DppCtl<L>::ROT_FR>(mf[r][0][c]);
+            if (!(live && owned(r))) continue;
+#pragma unroll
+            for (int k = 0; k + 1 < K; ++k)
+                if (far(mf[r][k][0], mf[r][k][1], mf[r][k][2], mf[r][k + 1][0], mf[r][k + 1][1], mf[r][k + 1][2]))
+                    bits |= 4;
+            if (!edge_lane && far(mf[r][K - 1][0], mf[r][K - 1][1], mf[r][K - 1][2], east[0], east[1], east[2]))
+                bits |= 4;
+            if (D == 2 && r + 1 < R && owned(r + 1 < R ? r + 1 : r) &&
+                far(mf[r][0][0], mf[r][0][1], mf[r][0][2], mf[(r + 1 < R) ? r + 1 : r][0][0],
+                    mf[(r + 1 < R) ? r + 1 : r][0][1], mf[(r + 1 < R) ? r + 1 : r][0][2]))
+                bits |= 4;
+        }
+        return bits;
+    }
+
     // FP32 form 1 only.  Over many small steps the FP32 perturbation u keeps
     // only the top bits of each step's increment once |u| has grown, and the
     // stencil's 1/dx^2 turns the lost bits into field error.  Re-referencing
@@ -754,15 +830,19 @@ __global__ void __launch_bounds__(L * NG, MINW) k_micro(MicroArgs A) {
         for (int off = 1; off < RED; off <<= 1) v += __shfl_xor(v, off, 64);
         S.acc64[q] = v;
     }
+    // final-state checks over the row group (1-D: one box) or the wavefront (2-D)
+    const int hb = S.health(active);
+    const uint64_t gmask = (D == 1 && L == 16) ? (0xFFFFull << ((lane >> 4) * 16)) : ~0ull;
+    const int hbits = ((__ballot((hb & 4) != 0) & gmask) ? 4 : 0) | ((__ballot((hb & 8) != 0) & gmask) ? 8 : 0);
     const bool writer = (D == 1) ? (j == 0) : (lane == 0);
     if (writer && active) {
         const int wslot = (D == 1) ? 0 : wave;
         double *dst = A.partials + (P.part_offset + wslot) * kMaxQ;
-        int bad = 0;
+        int bad = hbits;
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
             dst[q] = S.acc64[q];
-            if (!__builtin_isfinite(S.acc64[q])) bad = 1;
+            if (!__builtin_isfinite(S.acc64[q])) bad |= 1;
         }
         A.wave_status[P.part_offset + wslot] = bad;
     }
@@ -797,12 +877,13 @@ __device__ __forceinline__ S uniform_load(const S *p) {
 // every window row is exact, so a halo row's reference stays the one its
 // owner computes (only the outermost row's H(r) update misses the point
 // beyond the window, which stays inside the same error cone).
-// Workgroups take (box, slab) items from an atomic counter; the items of a box
-// are consecutive and the list is ordered longest box first.  A workgroup
-// waiting for a neighbour's rows only waits for an item at most one box
-// further down the list, which the next workgroup to finish an item takes, so
-// the grid makes progress with any number of resident workgroups >= slabs per
-// box.  Every wait polls at most A.spin_max times; a wait that runs out sets
+// Each XCD has its own queue of (box, slab) items, taken through an atomic
+// counter by the workgroups running on it, so all slabs of a box share one L2
+// and exchange through it.  In a queue the items of a box are consecutive and
+// the boxes longest first.  A workgroup waiting for a neighbour's rows only
+// waits for an item of its own box, which is taken before any later item, so
+// a queue makes progress with any number of resident workgroups on its XCD
+// >= slabs per box.  Every wait polls at most A.spin_max times; a wait that runs out sets
 // the grid-wide abort word, every workgroup then stops, and the boxes it
 // touched report status 2.
 // EVAL (a separate instantiation, so that the solve's register allocation
@@ -831,17 +912,18 @@ __global__ void __launch_bounds__(L * NG, MINW) k_slab(SlabArgs A) {
     const int j = (L == 16) ? (lane & 15) : lane;
     for (int i = tid; i < YH * 3 * N; i += L * NG) s_zero[i] = (T)0;
     const int h = A.h, spe = A.spe, xd = A.xdepth;
+    const int queue = __builtin_amdgcn_readfirstlane(xcc_id() % A.nqueues);
     auto wrap = [](int br) { return ((br % N) + N) % N; };
 
     for (;;) {
         if (tid == 0) {
-            s_item = atomicAdd(A.counter, 1);
+            s_item = atomicAdd(A.counter + queue, 1);
             s_abort = xload(A.abort_word);
         }
         __syncthreads();
         // block-uniform: in scalar registers, and so is everything derived from the item
-        const int item = __builtin_amdgcn_readfirstlane(s_item);
-        if (item >= A.nitems) break;
+        const int item = A.qoff[queue] + __builtin_amdgcn_readfirstlane(s_item);
+        if (item >= A.qoff[queue + 1]) break;
         const SlabJob job = uniform_load(A.jobs + item);
         const BoxPlan P = uniform_load(A.plans + job.box);
         if (__builtin_amdgcn_readfirstlane(s_abort) != 0) {
@@ -854,10 +936,12 @@ __global__ void __launch_bounds__(L * NG, MINW) k_slab(SlabArgs A) {
         const TabLayout TL = tab_layout(D, N, 1);
         const int w0 = job.o0 - h;  // box row of window row 0, before wrapping
         const int own_end = h + job.rows;
-        // Dirichlet: window rows outside the box are ghost rows (u = 0), whole groups at a time
+        // Dead row groups, held at u = 0 and never exchanged: Dirichlet ghost rows
+        // outside the box, and the window rows beyond the north halo (a slab with
+        // fewer own rows than the window allows keeps an h-row halo on each side)
         auto dead = [&](int gg) {
             const int br = w0 + gg * R;
-            return BC == LLHMM_BC_DIRICHLET && (br < 0 || br >= N);
+            return (BC == LLHMM_BC_DIRICHLET && (br < 0 || br >= N)) || gg * R >= own_end + h;
         };
 
         Lane S;
@@ -972,6 +1056,16 @@ __global__ void __launch_bounds__(L * NG, MINW) k_slab(SlabArgs A) {
                         // halo rows from its first ones
                         const int q0 = halo_s ? xd - h + r0 : r0 - own_end;
                         long long polls = 0;
+                        // first wait on one word per lane (the last its publisher writes),
+                        // then read the rest
+                        {
+                            T v;
+                            const uint64_t *sw = sb + (q0 + R - 1) * XROW + ((long)2 * N + c0 + K - 1) * XW;
+                            while (!xget(sw, e, v)) {
+                                if (xload(A.abort_word) != 0 || ++polls > A.spin_max) break;
+                                __builtin_amdgcn_s_sleep(1);
+                            }
+                        }
                         for (;;) {
                             // read straight into the halo rows' state: a word that is
                             // still old is read again on the next poll
@@ -1050,16 +1144,18 @@ __global__ void __launch_bounds__(L * NG, MINW) k_slab(SlabArgs A) {
                 for (int off = 1; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
                 S.acc64[q] = v;
             }
+            const int hb = aborted ? 0 : S.health(!gdead);
+            const int hbits = (__ballot((hb & 4) != 0) ? 4 : 0) | (__ballot((hb & 8) != 0) ? 8 : 0);
             if (lane == 0) {
                 const long slot = P.part_offset + (long)job.slab * WAVES + wave;
                 double *dst = A.partials + slot * kMaxQ;
-                int bad = aborted ? 2 : 0;
+                bool finite = true;
 #pragma unroll
                 for (int q = 0; q < NQ; ++q) {
                     dst[q] = S.acc64[q];
-                    if (!__builtin_isfinite(S.acc64[q]) && !bad) bad = 1;
+                    finite = finite && __builtin_isfinite(S.acc64[q]);
                 }
-                A.wave_status[slot] = bad;
+                A.wave_status[slot] = aborted ? 2 : (hbits | (finite ? 0 : 1));
             }
         }
         __syncthreads();  // LDS of this item is dead before the next item loads its own

@@ -63,6 +63,24 @@ def test_three_d_roofline_bytes_fourth_order():
     assert r["frac"] == pytest.approx(want / 4.0e-3 / 8.0e12, rel=1e-12)
 
 
+def test_three_d_roofline_is_valu_primary():
+    """The d = 3 record's roofline is the VALU one (algorithmic flops over the
+    FP64 peak); the streamed-byte figure rides along as secondary."""
+    eps = 0.01
+    boxes = [inputs.make_box(dim=3, n=8, order=2, bc=0, quantity=inputs.Q_FIELD, integrator=2,
+                             n_steps=6, eps=eps, alpha=0.3, mu=3 * eps, mu_box=3 * eps,
+                             eta=0.3 * eps ** 2, a_max=1.5, center=(0.1, 0.2, 0.3), macro_index=(0, 0, 0))]
+    flops = bench.algorithmic_flops(boxes)
+    M, _, _ = L.llhmm_plan(boxes)
+    assert flops == 281 * int(M[0]) * 8 ** 3          # F = 4 * 33 + 149 for d = 3, order 2, RK4P
+    valu = dict(bound="alu", achieved=flops / 1e-3 / 1e12, peak=bench.PEAK_FP64 / 1e12, unit="TFLOP/s",
+                frac=flops / 1e-3 / bench.PEAK_FP64, traffic=None)
+    roof = bench.three_d_roofline(dict(roofline=valu, kernel_ms=1.0), boxes)
+    assert roof["bound"] == "alu" and roof["unit"] == "TFLOP/s"
+    assert roof["frac"] == pytest.approx(flops / 1e-3 / 78.6e12, rel=1e-12)
+    assert roof["streamed_hbm"]["bound"] == "hbm" and roof["kernel"] == "k_micro3d"
+
+
 def test_traffic_reported_only_for_the_measured_sources(tmp_path, monkeypatch):
     src = tmp_path / "kernel.hip"
     src.write_text("// kernel v1\n")

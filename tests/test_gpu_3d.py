@@ -33,17 +33,29 @@ def ctx():
     return L.llhmm_create(0)
 
 
+def stable_steps(b, n_steps):
+    """Forces n_steps on box b, shortening eta where needed so that dt stays
+    within the stability rule (a forced dt above it leaves an unresolved final
+    state, which the library flags with status bit 4)."""
+    if n_steps > 0:
+        m = int(L.llhmm_plan([dict(b, n_steps=0)])[0][0])
+        if m > n_steps:
+            b["eta"] *= 0.999 * n_steps / m
+        b["n_steps"] = n_steps
+    return b
+
+
 def boxes3(ns, bc, q, integ, seed, n_steps=0, eta=0.3, order=2):
     eps = 1.0 / 100.0
     rng = np.random.default_rng(seed)
     out = []
     for n in ns:
-        out.append(inputs.make_box(dim=3, n=n, order=order, bc=bc, quantity=q, integrator=integ,
-                                   n_steps=n_steps, eps=eps, alpha=float(rng.uniform(0.05, 1.2)),
-                                   mu=(2.5 if bc else 3.0) * eps, mu_box=3 * eps,
-                                   eta=eta * eps ** 2, a_max=1.5,
-                                   center=tuple(float(v) for v in rng.random(3)),
-                                   macro_index=(0, 0, 0)))
+        out.append(stable_steps(inputs.make_box(dim=3, n=n, order=order, bc=bc, quantity=q, integrator=integ,
+                                                eps=eps, alpha=float(rng.uniform(0.05, 1.2)),
+                                                mu=(2.5 if bc else 3.0) * eps, mu_box=3 * eps,
+                                                eta=eta * eps ** 2, a_max=1.5,
+                                                center=tuple(float(v) for v in rng.random(3)),
+                                                macro_index=(0, 0, 0)), n_steps))
     return out
 
 
@@ -232,11 +244,11 @@ def test_3d_macro_interpolated_init(ctx):
     boxes = []
     for k, off in (((2, 5, 7), (0.0, 0.0, 0.0)), ((6, 1, 3), (0.5, 0.0, 0.0)),
                    ((0, 7, 4), (0.0, 0.5, 0.5))):
-        boxes.append(inputs.make_box(dim=3, n=16, order=2, bc=1, quantity=0, integrator=2,
-                                     n_steps=10, init_mode=1, eps=eps, alpha=0.5, mu=2.5 * eps,
-                                     mu_box=3 * eps, eta=0.3 * eps ** 2, a_max=1.5,
-                                     center=tuple((k[a] + off[a]) * dX for a in range(3)),
-                                     macro_index=k))
+        boxes.append(stable_steps(inputs.make_box(dim=3, n=16, order=2, bc=1, quantity=0, integrator=2,
+                                                  init_mode=1, eps=eps, alpha=0.5, mu=2.5 * eps,
+                                                  mu_box=3 * eps, eta=0.3 * eps ** 2, a_max=1.5,
+                                                  center=tuple((k[a] + off[a]) * dX for a in range(3)),
+                                                  macro_index=k), 10))
     wl = workload(boxes)
     wl.macro = dict(n=nm, dX=dX, x0=(0.0, 0.0, 0.0), M=M)
     p = Prepared(wl, precision=inputs.FP64, ctx=ctx)
