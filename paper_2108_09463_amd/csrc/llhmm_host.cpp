@@ -134,6 +134,11 @@ llhmm_status check_fp32_domain(const llhmm_box &b, int i, int precision) {
                     "box %d: FP32 cannot hold the 1e-5 bar with an averaging radius mu = %.4g eps < %g eps; "
                     "solve it in FP64",
                     i, b.mu / b.eps, (double)LLHMM_FP32_MIN_MU_EPS);
+    if (b.order == 4 && b.eps * b.n < LLHMM_FP32_MIN_PPE_O4 * 2.0 * b.mu_box * (1.0 - 1e-12))
+        return fail(LLHMM_E_NOTSUP,
+                    "box %d: the fourth-order stencil in FP32 needs at least %g grid points per eps (here %.4g); "
+                    "solve it in FP64",
+                    i, (double)LLHMM_FP32_MIN_PPE_O4, b.eps * b.n / (2.0 * b.mu_box));
     return LLHMM_OK;
 }
 
@@ -262,7 +267,7 @@ const std::map<SlabKey, std::vector<const SlabTileInfo *>> &slab_registry() {
         std::map<SlabKey, std::vector<const SlabTileInfo *>> r;
         int cnt = 0;
         const SlabTileInfo *t = tiles_slab(&cnt);
-        for (int i = 0; i < cnt; ++i) r[SlabKey{t[i].prec, t[i].n, 2, t[i].bc, t[i].qty}].push_back(&t[i]);
+        for (int i = 0; i < cnt; ++i) r[SlabKey{t[i].prec, t[i].n, t[i].order, t[i].bc, t[i].qty}].push_back(&t[i]);
         return r;
     }();
     return reg;
@@ -271,8 +276,8 @@ const std::map<SlabKey, std::vector<const SlabTileInfo *>> &slab_registry() {
 // Slab geometry of an n x n box for a tile whose window holds WR = R * NG rows,
 // with `stages` Runge-Kutta stages per step and an exchange every `spe` steps:
 // h halo rows on each side (each stage moves the error of the zeros beyond the
-// window one row inwards, so h >= spe * stages, rounded up to whole row
-// groups), at most WR - 2h own rows per slab, the box's row groups split as
+// window inwards by the stencil's reach, one row at second order and three at
+// fourth, so h >= reach * spe * stages, rounded up to whole row groups), at most WR - 2h own rows per slab, the box's row groups split as
 // evenly as possible over ns >= 2 slabs.  Every slab keeps h halo rows on each
 // side (window rows beyond them stay unused) and publishes xd = h rows at each
 // edge, which it must own.  ns = 0: invalid.
@@ -286,7 +291,8 @@ SlabGeom slab_geom(const SlabTileInfo &t, int n, int stages, int spe) {
     SlabGeom g;
     const int WR = t.R * t.NG;
     if (n % t.R != 0 || kRerefSteps % spe != 0) return g;
-    const int h = (spe * stages + t.R - 1) / t.R * t.R;
+    const int reach = (t.order == 2) ? 1 : 3;
+    const int h = (reach * spe * stages + t.R - 1) / t.R * t.R;
     const int capg = (WR - 2 * h) / t.R;  // own row groups per slab at most
     if (capg < 1) return g;
     const int groups = n / t.R;
@@ -880,7 +886,7 @@ static llhmm_status batch_create_impl(llhmm_ctx *ctx, const llhmm_box *boxes, in
             ++b->nslab_boxes;
         }
         P.prec = precision;
-        P.form = (precision == LLHMM_FP32 || P.slab) ? 1 : 0;
+        P.form = (precision == LLHMM_FP32 || P.slab || (tile_of[i] && (tile_of[i]->opt & kOptForm1))) ? 1 : 0;
         if (bx.dim == 3) P.form = 0;
         P.dt = pl.dt;
         P.alpha = bx.alpha;
@@ -1671,7 +1677,7 @@ static llhmm_status request_bytes(const llhmm_server *sv, const llhmm_box &bx, i
     if (it == registry().end() && !slab)
         return fail(LLHMM_E_NOTSUP, "request %d: no kernel for dim %d, n %d, order %d, bc %d, quantity %d", i,
                     bx.dim, bx.n, bx.order, bx.bc, bx.quantity);
-    const int form = (prec == LLHMM_FP32 || slab) ? 1 : 0;
+    const int form = (prec == LLHMM_FP32 || slab || (!slab && (it->second->opt & kOptForm1))) ? 1 : 0;
     int64_t slots = (bx.dim == 2) ? 16 : 1;
     int64_t slab_bytes = 0;
     if (slab) {

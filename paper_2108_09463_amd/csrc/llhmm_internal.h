@@ -13,6 +13,10 @@ constexpr int kMaxWaves = 16;  // waves per block of the resident kernels
 // resolved (status bit 4 above it)
 constexpr double kRoughMax = 0.5;
 constexpr int kMaxQ = 9;
+// Layout options of the resident kernels (bits of MicroLane's OPT):
+constexpr int kOptForm1 = 1;  // reference + perturbation form in FP64 too (no boundary offsets)
+constexpr int kOptRefG = 2;   // form-1 reference tables read from global memory instead of LDS
+constexpr int kOptHReg = 4;   // H(r) of the own points in registers; LDS keeps r and |r|^2 - 1
 constexpr int kMaxXcc = 8;     // accelerator complexes (XCDs) per device, each with its own L2       // outputs per box (flux in 3-D: 3 axes x 3 components)
 constexpr int kFaceHalo = 3;   // faces -2 .. n stored per line: n + 3 entries
 // FP32 reference + perturbation form: every kRerefSteps time steps the state
@@ -176,7 +180,7 @@ using SlabLaunchFn = hipError_t (*)(const SlabArgs &, int nblocks, hipStream_t);
 using SlabOccFn = hipError_t (*)(int *blocks_per_cu);
 
 struct SlabTileInfo {
-    int n, bc, prec, qty;        // class it serves (2-D, second order)
+    int n, order, bc, prec, qty;  // class it serves (2-D)
     int L, K, R, NG, NBUF;       // a window of R * NG rows of n = K * L points
     int threads;
     SlabLaunchFn launch;
@@ -198,6 +202,7 @@ struct TileInfo {
     int threads, boxes_per_block;
     LaunchFn launch;
     const char *name;
+    int opt;                          // layout options (kOpt* bits of the kernel)
 };
 
 const TileInfo *tiles_f32_2d(int *count);

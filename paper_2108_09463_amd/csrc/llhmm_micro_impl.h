@@ -150,7 +150,7 @@ __device__ __forceinline__ bool xget(const uint64_t *p, uint32_t tag, double &v)
 }
 
 template <typename T, int D, int ORD, int BC, int QTY, int L, int K, int R, int NG, int NBUF,
-          bool SLAB = false>
+          bool SLAB = false, int OPT = 0>
 struct MicroLane {
     static constexpr int N = K * L;
     static constexpr int YH = (ORD == 2) ? 1 : 3;  // neighbour reach in points
@@ -163,10 +163,11 @@ struct MicroLane {
     static constexpr int NFRD = (D == 2) ? NFR : 1;
     static constexpr int NQ = (QTY == LLHMM_Q_FLUX) ? 3 * D : 3;
     static constexpr int AVG = (QTY == LLHMM_Q_FIELD) ? 1 : ((QTY == LLHMM_Q_TORQUE) ? 2 : 3);
-    // LDS halo per row group: its first and last YH rows (one copy when R == YH,
-    // where they are the same rows)
-    static constexpr int HSIDES = (R == YH) ? 1 : 2;
-    static constexpr int HALO = (D == 2) ? NG * HSIDES * YH * 3 * N : 1;
+    // LDS halo per row group: its first and last YH rows, or all R rows once
+    // when those overlap (R <= 2 YH); the last YH rows of a group's block are
+    // its top rows either way
+    static constexpr int HROWS = (2 * YH >= R) ? R : 2 * YH;
+    static constexpr int HALO = (D == 2) ? NG * HROWS * 3 * N : 1;
     // 2-D boundary offsets in LDS: [2N lines/columns][2 sides][GF faces][hi 4, lo 4],
     // then a zero block read by lanes without boundary faces
     static constexpr int TAU_LDS = (D == 2) ? 4 * N * GF * 8 + 24 : 1;
@@ -181,22 +182,30 @@ struct MicroLane {
     // precomputed in FP64; the state u starts at the rounding residual m_init - r
     // and stays periodic (or zero) on the ghosts, so no boundary offsets are needed.
     // Slab mode (a window of R * NG rows of a larger 2-D box) always uses form 1.
-    static constexpr int FORM = (SLAB || sizeof(T) == 4) ? 1 : 0;
+    static constexpr int FORM = (SLAB || sizeof(T) == 4 || (OPT & kOptForm1)) ? 1 : 0;
     static constexpr int CELLS = (D == 1) ? N : N * N;
     static constexpr int WR = R * NG;                       // rows held by the block
     static constexpr int CELLS_W = SLAB ? WR * N : CELLS;    // points held by the block
     // FP64 slab: the reference tables are read from global memory (box indexing)
-    static constexpr bool REFG = SLAB && sizeof(T) == 8;
+    static constexpr bool REFG = (SLAB && sizeof(T) == 8) || (OPT & kOptRefG);
+    // FP32 fourth-order slabs keep H(r) in registers too (the window's seven
+    // planes and the wider halo would not fit the LDS)
+    static constexpr bool HREG = ((OPT & kOptHReg) || (SLAB && ORD == 4)) && FORM && !REFG;
     static constexpr int RSTRIDE = REFG ? CELLS : CELLS_W;  // stride between reference planes
-    static constexpr int REF_LDS = (FORM && !REFG) ? ((D == 2) ? 7 * CELLS_W : NG * 7 * N) : 1;
-    static_assert(K >= YH, "lane tile narrower than the stencil reach");
+    static constexpr int REF_PLANES = HREG ? 4 : 7;          // planes held in LDS
+    static constexpr int REF_LDS = (FORM && !REFG) ? ((D == 2) ? REF_PLANES * CELLS_W : NG * 7 * N) : 1;
+    // x1 neighbours more than K points away come from lanes further off (several
+    // DPP moves); the boundary offsets of form 0 assume one lane holds them all
+    static_assert(K >= YH || FORM == 1, "lane tile narrower than the stencil reach");
+    static_assert(!HREG || D == 2, "H(r) in registers: 2-D");
     static_assert(D == 1 || R >= YH, "row group thinner than the stencil reach");
     static_assert(D == 1 || SLAB || R * NG == N, "row groups must tile the box");
-    static_assert(!SLAB || (D == 2 && ORD == 2), "slab mode: 2-D, second order");
+    static_assert(!SLAB || D == 2, "slab mode: 2-D");
     static_assert(D == 2 || R == 1, "1-D boxes are one row");
     static_assert(L == 16 || L == 64, "row group is a DPP row or a wavefront");
 
     T m[R][K][3], y[R][K][3], acc[R][K][3];
+    T hr[HREG ? R : 1][HREG ? K : 1][3];  // H(r) of the own points (kOptHReg)
     T ax[AXL ? 1 : R][AXL ? 1 : NF];
     T ay[AXL ? 1 : KD][AXL ? 1 : NFRD];
     const T *s_axl;  // AXL: this group's face coefficients in LDS
@@ -235,12 +244,18 @@ struct MicroLane {
         return FORM ? (T)0 : s_tau[off];
     }
     __device__ __forceinline__ T ref(int q, int cell) const { return s_ref[q * RSTRIDE + cell]; }
+    // component c of H(r) at own point (r, k)
+    __device__ __forceinline__ T href(int r, int k, int c, int cell) const {
+        return HREG ? hr[HREG ? r : 0][HREG ? k : 0][c] : ref(4 + c, cell);
+    }
     // face coefficient of x1 face lf of own row r / x2 face lr of own column k
     __device__ __forceinline__ T axv(int r, int lf) const {
         return AXL ? s_axl[(r0 + r) * LF + c0 - FW + lf + 2] : ax[AXL ? 0 : r][AXL ? 0 : lf];
     }
     __device__ __forceinline__ T ayv(int k, int lr) const {
-        return AXL ? s_axl[N * LF + (c0 + k) * LF + r0 - FW + lr + 2] : ay[AXL ? 0 : k][AXL ? 0 : lr];
+        // x2 faces in LDS face-row major ([LF][N]): the lanes of a row group read
+        // consecutive words, free of bank conflicts
+        return AXL ? s_axl[N * LF + (r0 - FW + lr + 2) * N + c0 + k] : ay[AXL ? 0 : k][AXL ? 0 : lr];
     }
 
     // One Runge-Kutta stage on stage input y: H(y), f(y), accumulator and
@@ -261,15 +276,25 @@ struct MicroLane {
                 for (int c = 0; c < 3; ++c)
 #pragma unroll
                     for (int k = 0; k < K; ++k) {
-                        hb[(((g * HSIDES + 0) * YH + q) * 3 + c) * N + c0 + k] = y[q][k][c];
-                        if (HSIDES == 2) hb[(((g * HSIDES + 1) * YH + q) * 3 + c) * N + c0 + k] = y[R - YH + q][k][c];
+                        if (HROWS == 2 * YH) {
+                            hb[((g * HROWS + q) * 3 + c) * N + c0 + k] = y[q][k][c];
+                            hb[((g * HROWS + YH + q) * 3 + c) * N + c0 + k] = y[R - YH + q][k][c];
+                        }
                     }
+            if (HROWS == R && HROWS != 2 * YH) {
+#pragma unroll
+                for (int q = 0; q < R; ++q)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c)
+#pragma unroll
+                        for (int k = 0; k < K; ++k) hb[((g * HROWS + q) * 3 + c) * N + c0 + k] = y[q][k][c];
+            }
             __syncthreads();
-            srcS = zero_s ? s_zero : hb + ((gs * HSIDES + HSIDES - 1) * YH) * 3 * N;
-            srcN = zero_n ? s_zero : hb + ((gn * HSIDES + 0) * YH) * 3 * N;
+            srcS = zero_s ? s_zero : hb + (gs * HROWS + HROWS - YH) * 3 * N;
+            srcN = zero_n ? s_zero : hb + (gn * HROWS + 0) * 3 * N;
             if (SLAB && AVG == AVG_DREF) {  // the reference change is known beyond the window
                 if (g == 0) srcS = s_edge;
-                if (g == NG - 1) srcN = s_edge + 3 * N;
+                if (g == NG - 1) srcN = s_edge + YH * 3 * N;
             }
         }
         auto yat = [&](int q, int k, int c) -> T {  // local row q in [-YH, R+YH); halo rows from LDS
@@ -327,8 +352,17 @@ struct MicroLane {
                 for (int i = 0; i < YH; ++i)
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
-                        yw[i][c] = nb<DppCtl<L>::ROT_FL, DppCtl<L>::SH_FL>(y[r][K - YH + i][c]);
-                        ye[i][c] = nb<DppCtl<L>::ROT_FR, DppCtl<L>::SH_FR>(y[r][i][c]);
+                        // column c0 - YH + i: `hw` lanes to the west; c0 + K + i: `he` lanes east
+                        constexpr int KK = K;
+                        const int hw = (YH - i + KK - 1) / KK, he = i / KK + 1;
+                        T vw = y[r][(K - YH + i + hw * K) % K][c], ve = y[r][i % K][c];
+#pragma unroll
+                        for (int hop = 0; hop < (YH + KK - 1) / KK; ++hop) {
+                            if (hop < hw) vw = nb<DppCtl<L>::ROT_FL, DppCtl<L>::SH_FL>(vw);
+                            if (hop < he) ve = nb<DppCtl<L>::ROT_FR, DppCtl<L>::SH_FR>(ve);
+                        }
+                        yw[i][c] = vw;
+                        ye[i][c] = ve;
                     }
             }
             // row values at local column p in [-YH, K+YH)
@@ -434,7 +468,7 @@ struct MicroLane {
 #pragma unroll
                         for (int c = 0; c < 3; ++c)
                             eval_out[c * eval_cells + (long)out_row(r) * N + c0 + k] =
-                                (double)H[c] + (FORM ? (double)ref(4 + c, cell) : 0.0);
+                                (double)H[c] + (FORM ? (double)href(r, k, c, cell) : 0.0);
                     }
                     continue;
                 }
@@ -447,9 +481,9 @@ struct MicroLane {
                     m0 += ref(0, cell);
                     m1 += ref(1, cell);
                     m2 += ref(2, cell);
-                    h0 += ref(4, cell);
-                    h1 += ref(5, cell);
-                    h2 += ref(6, cell);
+                    h0 += href(r, k, 0, cell);
+                    h1 += href(r, k, 1, cell);
+                    h2 += href(r, k, 2, cell);
                 }
                 const T cx = m1 * h2 - m2 * h1;
                 const T cy = m2 * h0 - m0 * h2;
@@ -626,16 +660,18 @@ struct MicroLane {
                 const int cell = cell_of(r, k);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    s_ref[(4 + c) * RSTRIDE + cell] = s_ref[(4 + c) * RSTRIDE + cell] + acc[r][k][c];
+                    if (HREG) hr[HREG ? r : 0][HREG ? k : 0][c] = hr[HREG ? r : 0][HREG ? k : 0][c] + acc[r][k][c];
+                    else s_ref[(4 + c) * RSTRIDE + cell] = s_ref[(4 + c) * RSTRIDE + cell] + acc[r][k][c];
                     y[r][k][c] = m[r][k][c];
                 }
             }
     }
 };
 
-template <typename T, int D, int ORD, int BC, int QTY, int L, int K, int R, int NG, int NBUF, int MINW>
+template <typename T, int D, int ORD, int BC, int QTY, int L, int K, int R, int NG, int NBUF, int MINW,
+          int OPT = 0>
 __global__ void __launch_bounds__(L * NG, MINW) k_micro(MicroArgs A) {
-    using Lane = MicroLane<T, D, ORD, BC, QTY, L, K, R, NG, NBUF>;
+    using Lane = MicroLane<T, D, ORD, BC, QTY, L, K, R, NG, NBUF, false, OPT>;
     constexpr int N = Lane::N, NF = Lane::NF, NFR = Lane::NFR, FW = Lane::FW, GF = Lane::GF;
     constexpr int YH = Lane::YH, NQ = Lane::NQ;
     __shared__ T s_halo[NBUF * Lane::HALO];
@@ -677,7 +713,12 @@ __global__ void __launch_bounds__(L * NG, MINW) k_micro(MicroArgs A) {
     if (Lane::AXL) {
         // x1 faces then (2-D) x2 faces; ay follows ax in the table
         if (D == 2) {
-            for (int i = tid; i < 2 * N * LF; i += L * NG) s_ax[i] = tab[TL.ax + i];
+            // x1 faces as stored ([lines][LF]); x2 faces transposed to [LF][N]
+            for (int i = tid; i < N * LF; i += L * NG) s_ax[i] = tab[TL.ax + i];
+            for (int i = tid; i < N * LF; i += L * NG) {
+                const int f = i / N, col = i - f * N;
+                s_ax[N * LF + i] = tab[TL.ay + (long)col * LF + f];
+            }
             S.s_axl = s_ax;
         } else {
             for (int i = j; i < LF; i += L) s_ax[g * LF + i] = tab[TL.ax + i];
@@ -719,12 +760,25 @@ __global__ void __launch_bounds__(L * NG, MINW) k_micro(MicroArgs A) {
     }
     S.s_ref = nullptr;
     if (FORM == 1) {
-        // reference, |r|^2 - 1 and H(r) of this box into LDS (7 values per point)
-        if (D == 2) {
+        // reference, |r|^2 - 1 and H(r) of this box into LDS (7 values per point);
+        // kOptHReg: H(r) of the own points into registers; kOptRefG: read in place
+        if (D == 2 && Lane::REFG) {
+            S.s_ref = const_cast<T *>(tab) + TL.ref;
+        } else if (D == 2) {
             const T *src = tab + TL.ref;
-            copy_rows_to_lds<T, N, (D == 2) ? 7 * N : 1, L * NG>(
+            copy_rows_to_lds<T, N, (D == 2) ? Lane::REF_PLANES * N : 1, L * NG>(
                 s_refl, [&](int r) { return src + (long)r * N; }, tid);
             S.s_ref = s_refl;
+            if (Lane::HREG) {
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+#pragma unroll
+                    for (int k = 0; k < K; ++k)
+#pragma unroll
+                        for (int c = 0; c < 3; ++c)
+                            S.hr[Lane::HREG ? r : 0][Lane::HREG ? k : 0][c] =
+                                src[(4 + c) * CELLS + (long)(r0 + r) * N + c0 + k];
+            }
         } else {
             for (int i = j; i < 7 * N; i += L) s_refl[g * 7 * N + i] = tab[TL.ref + i];
             S.s_ref = s_refl + g * 7 * N;
@@ -889,9 +943,9 @@ __device__ __forceinline__ S uniform_load(const S *p) {
 // EVAL (a separate instantiation, so that the solve's register allocation
 // does not carry the evaluation's): evaluate H(m0) on the own rows instead of
 // solving; A.mode must agree.
-template <typename T, int QTY, int BC, int L, int K, int R, int NG, int NBUF, int MINW, bool EVAL>
+template <typename T, int ORD, int QTY, int BC, int L, int K, int R, int NG, int NBUF, int MINW, bool EVAL>
 __global__ void __launch_bounds__(L * NG, MINW) k_slab(SlabArgs A) {
-    constexpr int D = 2, ORD = 2;
+    constexpr int D = 2;
     using Lane = MicroLane<T, D, ORD, BC, QTY, L, K, R, NG, NBUF, true>;
     constexpr int N = Lane::N, NF = Lane::NF, NFR = Lane::NFR, FW = Lane::FW, NQ = Lane::NQ;
     constexpr int YH = Lane::YH, WR = Lane::WR;
@@ -900,7 +954,7 @@ __global__ void __launch_bounds__(L * NG, MINW) k_slab(SlabArgs A) {
     constexpr int WAVES = L * NG / 64;
     constexpr int XW = XWords<T>::n;
     __shared__ T s_halo[NBUF * Lane::HALO];
-    __shared__ T s_zero[YH * 3 * N];
+    __shared__ T s_zero[2 * YH * 3 * N];   // zero rows: beyond Dirichlet edges, and both window edges
     __shared__ T s_refl[Lane::REF_LDS];
     __shared__ double s_w[2 * N];
     __shared__ double s_wyl[2 * WR];
@@ -910,7 +964,7 @@ __global__ void __launch_bounds__(L * NG, MINW) k_slab(SlabArgs A) {
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: scalar register
     const int j = (L == 16) ? (lane & 15) : lane;
-    for (int i = tid; i < YH * 3 * N; i += L * NG) s_zero[i] = (T)0;
+    for (int i = tid; i < 2 * YH * 3 * N; i += L * NG) s_zero[i] = (T)0;
     const int h = A.h, spe = A.spe, xd = A.xdepth;
     const int queue = __builtin_amdgcn_readfirstlane(xcc_id() % A.nqueues);
     auto wrap = [](int br) { return ((br % N) + N) % N; };
@@ -983,7 +1037,7 @@ __global__ void __launch_bounds__(L * NG, MINW) k_slab(SlabArgs A) {
             S.s_ref = const_cast<T *>(tab) + TL.ref;
         } else {
             const T *src = tab + TL.ref;
-            copy_rows_to_lds<T, N, Lane::REFG ? 1 : 7 * WR, L * NG>(
+            copy_rows_to_lds<T, N, Lane::REFG ? 1 : Lane::REF_PLANES * WR, L * NG>(
                 s_refl,
                 [&](int r) {
                     const int q = r / WR, wr = r - q * WR;
@@ -991,6 +1045,16 @@ __global__ void __launch_bounds__(L * NG, MINW) k_slab(SlabArgs A) {
                 },
                 tid);
             S.s_ref = s_refl;
+            if (Lane::HREG) {
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+#pragma unroll
+                    for (int k = 0; k < K; ++k)
+#pragma unroll
+                        for (int c = 0; c < 3; ++c)
+                            S.hr[Lane::HREG ? r : 0][Lane::HREG ? k : 0][c] =
+                                src[(4 + c) * C + (long)S.brow[r] * N + c0 + k];
+            }
         }
         // face coefficients of the own rows (x1) and of the own column segment (x2)
 #pragma unroll

@@ -27,6 +27,14 @@ static const TileInfo kTiles[] = {
     LLHMM_TILE(float, 1, 2, 2, 0, 2, 64, 1, 8, 8, 2, 2),
     LLHMM_TILE(float, 1, 2, 2, 1, 1, 64, 1, 8, 8, 2, 2),
     LLHMM_TILE(float, 1, 2, 2, 1, 2, 64, 1, 8, 8, 2, 2),
+    // fourth order at n = 32 (two points per lane: x1 neighbours up to two lanes
+    // away) and n = 64 (one point per lane, three lanes away)
+#define LLHMM_O4_F32(BC, QTY)                                      \
+    LLHMM_TILE(float, 1, 2, 4, BC, QTY, 16, 2, 4, 8, 1, 1),       \
+        LLHMM_TILE(float, 1, 2, 4, BC, QTY, 64, 1, 8, 8, 1, 1)
+    LLHMM_O4_F32(0, 0), LLHMM_O4_F32(0, 1), LLHMM_O4_F32(0, 2),
+    LLHMM_O4_F32(1, 0), LLHMM_O4_F32(1, 1), LLHMM_O4_F32(1, 2),
+#undef LLHMM_O4_F32
 };
 const TileInfo *tiles_f32_2d(int *count) {
     *count = (int)(sizeof(kTiles) / sizeof(kTiles[0]));

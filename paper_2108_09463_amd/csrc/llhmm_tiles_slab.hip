@@ -1,5 +1,5 @@
-// Slab-mode tile classes: 2-D second-order boxes too large for one
-// workgroup's registers and LDS (n = 96, 128), cut into row slabs that
+// Slab-mode tile classes: 2-D boxes too large for one workgroup's registers
+// and LDS (n = 96, 128), cut into row slabs that
 // co-resident workgroups advance together, each in a window of R * NG rows
 // with halo rows (k_slab).  Per class the first variant is the default;
 // llhmm_batch_tune times the others.
@@ -7,30 +7,36 @@
 
 namespace llhmm {
 
-template <typename T, int QTY, int BC, int L, int K, int R, int NG, int NBUF, int MINW>
+template <typename T, int ORD, int QTY, int BC, int L, int K, int R, int NG, int NBUF, int MINW>
 hipError_t launch_slab(const SlabArgs &a, int nblocks, hipStream_t s) {
     if (a.mode == 1)
-        hipLaunchKernelGGL((k_slab<T, QTY, BC, L, K, R, NG, NBUF, MINW, true>), dim3(nblocks), dim3(L * NG), 0, s, a);
+        hipLaunchKernelGGL((k_slab<T, ORD, QTY, BC, L, K, R, NG, NBUF, MINW, true>), dim3(nblocks), dim3(L * NG), 0, s,
+                           a);
     else
-        hipLaunchKernelGGL((k_slab<T, QTY, BC, L, K, R, NG, NBUF, MINW, false>), dim3(nblocks), dim3(L * NG), 0, s, a);
+        hipLaunchKernelGGL((k_slab<T, ORD, QTY, BC, L, K, R, NG, NBUF, MINW, false>), dim3(nblocks), dim3(L * NG), 0,
+                           s, a);
     return hipGetLastError();
 }
 
-template <typename T, int QTY, int BC, int L, int K, int R, int NG, int NBUF, int MINW>
+template <typename T, int ORD, int QTY, int BC, int L, int K, int R, int NG, int NBUF, int MINW>
 hipError_t occupancy_slab(int *blocks_per_cu) {
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        blocks_per_cu, (const void *)k_slab<T, QTY, BC, L, K, R, NG, NBUF, MINW, false>, L * NG, 0);
+        blocks_per_cu, (const void *)k_slab<T, ORD, QTY, BC, L, K, R, NG, NBUF, MINW, false>, L * NG, 0);
 }
 
-#define LLHMM_SLAB(T, PREC, BC, QTY, L, K, R, NG, NBUF, MINW)                                              \
-    SlabTileInfo{(K) * (L), BC, PREC, QTY, L, K, R, NG, NBUF, (L) * (NG),                                  \
-                 &launch_slab<T, QTY, BC, L, K, R, NG, NBUF, MINW>,                                        \
-                 &occupancy_slab<T, QTY, BC, L, K, R, NG, NBUF, MINW>,                                     \
-                 "slab " #T " bc" #BC " q" #QTY " L" #L " K" #K " R" #R " NG" #NG " B" #NBUF " W" #MINW}
+#define LLHMM_SLAB(T, PREC, ORD, BC, QTY, L, K, R, NG, NBUF, MINW)                                         \
+    SlabTileInfo{(K) * (L), ORD, BC, PREC, QTY, L, K, R, NG, NBUF, (L) * (NG),                             \
+                 &launch_slab<T, ORD, QTY, BC, L, K, R, NG, NBUF, MINW>,                                   \
+                 &occupancy_slab<T, ORD, QTY, BC, L, K, R, NG, NBUF, MINW>,                                \
+                 "slab " #T " o" #ORD " bc" #BC " q" #QTY " L" #L " K" #K " R" #R " NG" #NG " B" #NBUF " W" #MINW}
 
 #define LLHMM_SLAB_QTY(T, PREC, BC, L, K, R, NG, NBUF, MINW)                                               \
-    LLHMM_SLAB(T, PREC, BC, 0, L, K, R, NG, NBUF, MINW), LLHMM_SLAB(T, PREC, BC, 1, L, K, R, NG, NBUF, MINW), \
-        LLHMM_SLAB(T, PREC, BC, 2, L, K, R, NG, NBUF, MINW)
+    LLHMM_SLAB(T, PREC, 2, BC, 0, L, K, R, NG, NBUF, MINW), LLHMM_SLAB(T, PREC, 2, BC, 1, L, K, R, NG, NBUF, MINW), \
+        LLHMM_SLAB(T, PREC, 2, BC, 2, L, K, R, NG, NBUF, MINW)
+// fourth order: a halo of three rows per stage and step
+#define LLHMM_SLAB_QTY4(T, PREC, BC, L, K, R, NG, NBUF, MINW)                                              \
+    LLHMM_SLAB(T, PREC, 4, BC, 0, L, K, R, NG, NBUF, MINW), LLHMM_SLAB(T, PREC, 4, BC, 1, L, K, R, NG, NBUF, MINW), \
+        LLHMM_SLAB(T, PREC, 4, BC, 2, L, K, R, NG, NBUF, MINW)
 
 static const SlabTileInfo kSlab[] = {
     // FP32: windows of 32 rows (LDS holds the window's reference tables)
@@ -46,6 +52,18 @@ static const SlabTileInfo kSlab[] = {
     LLHMM_SLAB_QTY(double, 0, 1, 64, 2, 2, 8, 2, 1),
     LLHMM_SLAB_QTY(double, 0, 0, 16, 6, 1, 16, 1, 1),
     LLHMM_SLAB_QTY(double, 0, 1, 16, 6, 1, 16, 1, 1),
+    // fourth order (H(r) in registers for FP32): a halo of 3 rows per stage (12
+    // for an RK4P step), which every slab must own at least once over: 40-row
+    // windows for n = 128 (8 slabs of 16 rows), 36-row windows of three-row
+    // groups for n = 96 (8 slabs of 12 rows)
+    LLHMM_SLAB_QTY4(float, 1, 0, 64, 2, 4, 10, 1, 1),
+    LLHMM_SLAB_QTY4(float, 1, 1, 64, 2, 4, 10, 1, 1),
+    LLHMM_SLAB_QTY4(float, 1, 0, 16, 6, 3, 12, 1, 1),
+    LLHMM_SLAB_QTY4(float, 1, 1, 16, 6, 3, 12, 1, 1),
+    LLHMM_SLAB_QTY4(double, 0, 0, 64, 2, 4, 10, 1, 1),
+    LLHMM_SLAB_QTY4(double, 0, 1, 64, 2, 4, 10, 1, 1),
+    LLHMM_SLAB_QTY4(double, 0, 0, 16, 6, 3, 12, 1, 1),
+    LLHMM_SLAB_QTY4(double, 0, 1, 16, 6, 3, 12, 1, 1),
 };
 
 const SlabTileInfo *tiles_slab(int *count) {

@@ -318,8 +318,13 @@ def two_d_batch(n_macro=32, seed=2, precision=FP64, order=2, n=64, integrator=IN
                                   a_max=1.5, center=(i / n_macro, j / n_macro),
                                   macro_index=(i, j)))
     macro = dict(n=n_macro, dX=1.0 / n_macro, x0=(0.0, 0.0), M=M, seed=used_seed)
-    return Workload("two_d_batch", 2, boxes, [coef_product(eps)], macro=macro,
-                    precision=precision)
+    return Workload("two_d_batch" if order == 2 else "two_d_batch_o4", 2, boxes, [coef_product(eps)],
+                    macro=macro, precision=precision)
+
+
+def two_d_batch_o4(n_macro=32, seed=2, precision=FP64):
+    """two_d_batch with the fourth-order conservative stencil."""
+    return two_d_batch(n_macro, seed, precision, order=4)
 
 
 def three_d_batch(nboxes=512, seed=6, n=32, precision=FP64, order=2):

@@ -225,6 +225,7 @@ def llhmm_plan(boxes):
 FP32_MAX_WIDTH_EPS = 8.0      # LLHMM_FP32_MAX_WIDTH_EPS
 FP32_MIN_ALPHA_WIDE = 0.5      # LLHMM_FP32_MIN_ALPHA_WIDE
 FP32_MIN_MU_EPS = 2.0          # LLHMM_FP32_MIN_MU_EPS
+FP32_MIN_PPE_O4 = 8.0          # LLHMM_FP32_MIN_PPE_O4
 
 
 def llhmm_check_boxes(boxes, precision, ncoefs=1 << 30):

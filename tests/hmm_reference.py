@@ -2,7 +2,8 @@
 
 * ``homogenized(ppe)``: the discrete homogenized matrix A^H of the micro
   stencil (cell problem on P = ppe points per period, oracle.cell) and the
-  spectral reference M0(T) of eq. (hom) for EX2 on a 48 x 48 grid.  The micro
+  spectral reference M0(T) of eq. (hom) for EX2 (or EX3: same initial data,
+  coefficient (1.1 + 0.5 sin)(1.1 + 0.5 sin)) on a 48 x 48 grid.  The micro
   problems discretize a^eps with dx = eps / P at a fixed phase, so the HMM loop
   converges to eq. (hom) with this discrete A^H; the continuous A^H differs
   from it by the micro discretization error, which the paper assumes small.
@@ -25,19 +26,29 @@ ALPHA = 0.01       # macro damping of the Section 4.5 experiment
 DT_FACTOR = 0.08   # macro dt = DT_FACTOR dX^2 (MPEA is stable below ~0.1 here)
 
 
-def steps_for(n_macro, T):
-    s = int(np.ceil(T / (DT_FACTOR / n_macro ** 2)))
+def steps_for(n_macro, T, factor=DT_FACTOR):
+    s = int(np.ceil(T / (factor / n_macro ** 2)))
     return s, T / s
 
 
-@functools.lru_cache(maxsize=None)
-def discrete_AH(ppe):
-    return cell.homogenized_2d(inputs.coef_ex2(1.0), ppe)
+COEF = {"EX2": inputs.coef_ex2, "EX3": inputs.coef_ex3}
+MU_OVER_EPS = {"EX2": 3.9, "EX3": 4.2}   # the averaging radius of the paper's setups
+A_MAX = {"EX2": 1.6, "EX3": 2.56}
 
 
 @functools.lru_cache(maxsize=None)
-def M0(ppe, T, A_key=None):
-    A = discrete_AH(ppe) if A_key is None else np.array(A_key).reshape(2, 2)
+def discrete_AH(ppe, example="EX2"):
+    return cell.homogenized_2d(COEF[example](1.0), ppe)
+
+
+def micro_setup(setup, example="EX2"):
+    """The box fields of an HMM setup for one example."""
+    return dict(inputs.hmm_micro(setup, mu_over_eps=MU_OVER_EPS[example]), a_max=A_MAX[example])
+
+
+@functools.lru_cache(maxsize=None)
+def M0(ppe, T, A_key=None, example="EX2"):
+    A = discrete_AH(ppe, example) if A_key is None else np.array(A_key).reshape(2, 2)
     Mi = inputs.ex2_macro(NF)
     return hg.solve_hom(Mi, A, ALPHA, T, hg.stable_steps(A, NF, ALPHA, T, 2))
 
@@ -57,9 +68,9 @@ def l2_err(M, ref):
     return float(np.sqrt(np.mean(np.sum((M - r) ** 2, axis=0))))
 
 
-def ideal_loop(n_macro, ppe, T):
-    A = discrete_AH(ppe)
-    steps, dt = steps_for(n_macro, T)
+def ideal_loop(n_macro, ppe, T, example="EX2", factor=DT_FACTOR):
+    A = discrete_AH(ppe, example)
+    steps, dt = steps_for(n_macro, T, factor)
     M = hg.run_loop(inputs.ex2_macro(n_macro),
                     lambda Y: hg.q4_node_field(Y.reshape(3, n_macro, n_macro), A,
                                                1.0 / n_macro).reshape(3, -1),

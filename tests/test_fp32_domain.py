@@ -101,6 +101,25 @@ def test_host_check_refuses_exactly_the_rule():
     assert nref == 94
 
 
+def test_fourth_order_needs_eight_points_per_eps():
+    """Fourth order in FP32: n = 32 on a 3 eps box (5.3 points per eps) is
+    refused, n = 48 and 64 (8 and 10.7) are admitted, and FP64 takes them all;
+    second order is not affected.  (GPU sweep of 16 boxes per size and BC:
+    periodic n = 32 reached 7e-6 and a parity box 1.2e-5; n >= 48 stayed below
+    1.4e-6.)"""
+    eps = 1.0 / 200.0
+    for n, ok in ((32, False), (48, True), (64, True)):
+        for order in (2, 4):
+            b = inputs.make_box(dim=2, n=n, order=order, bc=0, quantity=0, eps=eps, alpha=0.1, mu=3 * eps,
+                                mu_box=3 * eps, eta=eps ** 2, a_max=1.65, center=(0.3, 0.4))
+            st, bad, msg = L.llhmm_check_boxes([b], inputs.FP32)
+            want = L.OK if (ok or order == 2) else L.E_NOTSUP
+            assert st == want, (n, order, msg)
+            assert L.llhmm_check_boxes([b], inputs.FP64)[0] == L.OK
+            if not ok and order == 4:
+                assert "points per eps" in msg
+
+
 def test_workloads_lie_in_fp32_domain():
     """The FP32 workloads (batched 1-D, uneven 2-D, served, HMM loops) are admitted."""
     wls = [inputs.one_d_batch(nboxes=64).boxes, inputs.uneven_batch(nboxes=512).boxes,

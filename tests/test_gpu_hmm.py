@@ -33,9 +33,9 @@ def ctx():
     return L.llhmm_create(0)
 
 
-def gpu_loop(ctx, n_macro, setup, steps, dt, precision=inputs.FP32, model="field"):
-    tmpl = inputs.hmm_micro(setup)
-    loop = HmmLoop(n_macro, inputs.ex2_macro(n_macro), inputs.coef_ex2(tmpl["eps"]), tmpl,
+def gpu_loop(ctx, n_macro, setup, steps, dt, precision=inputs.FP32, model="field", example="EX2"):
+    tmpl = inputs.hmm_micro(setup) if example == "EX2" else R.micro_setup(setup, example)
+    loop = HmmLoop(n_macro, inputs.ex2_macro(n_macro), R.COEF[example](tmpl["eps"]), tmpl,
                    R.ALPHA, dt, precision=precision, ctx=ctx, model=model)
     try:
         print(f"hmm loop model={model} n_macro={n_macro} setup={setup} steps={steps} "
@@ -81,6 +81,47 @@ def test_loop_converges_to_homogenized_solution(ctx):
     assert errs["s5", 24] < 3.0 * ideal[24]
     assert errs["s1", 12] / errs["s1", 24] < 2.0
     assert max(errs.values()) < naive
+
+
+@pytest.mark.parametrize("precision", [inputs.FP64, inputs.FP32])
+def test_ex3_loop_matches_oracle_loop(ctx, precision):
+    """EX3 (same macro initial data as EX2, coefficient
+    (1.1 + 0.5 sin 2pi x1/eps)(1.1 + 0.5 sin 2pi x2/eps), mu = 4.2 eps as in the
+    paper's EX3 setups, so the box of setup s2, mu' = 5.33 eps): six macro
+    steps against the oracle-driven loop, with the field-model bar."""
+    n, steps = 12, 6
+    _, dt = R.steps_for(n, 0.1)
+    Mg, stages = gpu_loop(ctx, n, "s2", steps, dt, precision, example="EX3")
+    tmpl = R.micro_setup("s2", "EX3")
+    Mo = R.oracle_loop(n, "s2", steps, dt, tmpl=tmpl, coef=inputs.coef_ex3(tmpl["eps"]))
+    from oracle import homogenized as hg
+    Hmax = 2.0 * np.abs(hg.q4_node_field(inputs.ex2_macro(n), R.discrete_AH(6, "EX3"), 1.0 / n)).max()
+    tol_H = 1e-5 if precision == inputs.FP32 else 3e-11
+    bound = stages * dt * (1 + R.ALPHA) * (44.0 / 12.0) * tol_H * Hmax
+    err = np.abs(Mg - Mo).max()
+    print("EX3 loop parity", precision, err, bound)
+    assert stages == 8
+    assert err <= bound, (err, bound)
+    assert np.abs(Mg - inputs.ex2_macro(n)).max() > 1e3 * bound
+
+
+def test_ex3_loop_converges_to_homogenized_solution(ctx):
+    """EX3 with the low-averaging-error setup: the loop follows its E_avg = 0
+    loop against M0 of eq. (hom) with the EX3 discrete A^H and converges like
+    dX^4.  EX3's larger A^H (1.08 against EX2's 0.62) takes a proportionally
+    smaller macro step, 0.04 dX^2 (at 0.08 dX^2 the n = 24 loop grew
+    unstable while its E_avg = 0 loop did not)."""
+    T = 0.01
+    ref = R.M0(5, T, example="EX3")
+    errs = {}
+    for n in (12, 24):
+        steps, dt = R.steps_for(n, T, 0.04)
+        M, _ = gpu_loop(ctx, n, "s5", steps, dt, example="EX3")
+        errs[n] = R.l2_err(M, ref)
+    ideal = {n: R.l2_err(R.ideal_loop(n, 5, T, example="EX3", factor=0.04), ref) for n in (12, 24)}
+    print("EX3 errors", errs, "ideal", ideal)
+    assert errs[12] / errs[24] > 8.0
+    assert errs[24] < 3.0 * ideal[24]
 
 
 @pytest.mark.parametrize("precision", [inputs.FP64, inputs.FP32])

@@ -171,6 +171,11 @@ CASES_2D += [(inputs.FP64, 48, 2, bc, 0) for bc in (0, 1)] + [(inputs.FP64, 64, 
 CASES_2D += [(inputs.FP32, 32, 2, bc, q) for bc in (0, 1) for q in (0, 1, 2)]
 CASES_2D += [(inputs.FP32, 48, o, bc, 0) for o in (2, 4) for bc in (0, 1)]
 CASES_2D += [(inputs.FP32, 64, 2, bc, 0) for bc in (0, 1)]
+# fourth order at n = 32 and 64 (lanes narrower than the stencil's reach; FP64 in
+# the reference + perturbation form)
+CASES_2D += [(inputs.FP64, n, 4, bc, q) for n in (32, 64) for bc in (0, 1) for q in (0, 1, 2)]
+CASES_2D += [(inputs.FP64, 48, 4, bc, 0) for bc in (0, 1)]
+CASES_2D += [(inputs.FP32, 64, 4, bc, q) for bc in (0, 1) for q in (0, 1, 2)]   # n = 32: refused in FP32
 
 
 @pytest.mark.parametrize("prec,n,order,bc,qty", CASES_2D)
@@ -185,7 +190,9 @@ def test_parity_2d_macro_init(ctx, prec):
 
 
 @pytest.mark.parametrize("prec,n,order,bc", [(inputs.FP64, 32, 2, 0), (inputs.FP64, 48, 2, 1),
-                                             (inputs.FP64, 64, 2, 0), (inputs.FP32, 48, 4, 0)])
+                                             (inputs.FP64, 64, 2, 0), (inputs.FP32, 48, 4, 0),
+                                             (inputs.FP64, 32, 4, 1), (inputs.FP64, 64, 4, 0),
+                                             (inputs.FP32, 64, 4, 1), (inputs.FP32, 64, 4, 0)])
 def test_eval_field_elementwise(ctx, prec, n, order, bc):
     """One stencil application H(m_init) per point against the oracle."""
     from paper_2108_09463_amd.runner import Prepared, box_state
@@ -201,9 +208,12 @@ def test_eval_field_elementwise(ctx, prec, n, order, bc):
         assert np.abs(Hg - Ho).max() <= tol * scale, (i, np.abs(Hg - Ho).max() / scale)
 
 
-def test_final_state_matches_oracle(ctx):
+@pytest.mark.parametrize("order,bc", [(2, 0), (4, 1), (4, 0)])
+def test_final_state_matches_oracle(ctx, order, bc):
+    """FP64 final state point by point (fourth order: m = r + u of the
+    reference + perturbation form)."""
     from paper_2108_09463_amd.runner import Prepared, box_state
-    wl = small_2d(32, 2, 0, 0)
+    wl = small_2d(32, order, bc, 0)
     p = Prepared(wl, precision=inputs.FP64, ctx=ctx)
     out = p.solve(want_state=True)
     ora = run_oracle(wl, want_state=True)

@@ -69,6 +69,19 @@ def test_slab_parity_heun(ctx, prec):
     check(ctx, slab_batch([128, 96, 128], 0, 0, integrator=inputs.HEUNP, seed=22), prec)
 
 
+@pytest.mark.parametrize("prec,bc,integ", [(inputs.FP64, 0, inputs.INTEG_AUTO), (inputs.FP64, 1, inputs.HEUNP),
+                                            (inputs.FP32, 0, inputs.HEUNP), (inputs.FP32, 1, inputs.INTEG_AUTO)])
+def test_slab_parity_order4(ctx, prec, bc, integ):
+    """Fourth-order stencil on n = 128 and 96 boxes: three halo rows per stage,
+    so 12 per RK4P step (8 slabs of 16 and 12 rows) and 6 per HeunP step."""
+    wl = slab_batch([128, 96], bc, 0, integrator=integ, seed=29, eta_scale=0.05, order=4)
+    p, out = run_gpu(ctx, wl, prec)
+    slabs, spe = L.llhmm_batch_slabs(p.batch)
+    print("order 4 slabs", slabs, "intervals", spe, flush=True)
+    assert (slabs >= 2).all()
+    assert_parity(wl, prec, out["H"], run_oracle(wl), label="slab order 4")
+
+
 def test_slab_torque(ctx):
     check(ctx, slab_batch([128, 96], 0, 2, seed=23), inputs.FP32)
 
