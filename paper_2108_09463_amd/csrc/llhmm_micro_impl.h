@@ -61,7 +61,18 @@ __device__ __forceinline__ double dpp_mov(double v) {
 __device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float rsqrt_t(float x) { return __builtin_amdgcn_rsqf(x); }
-__device__ __forceinline__ double rsqrt_t(double x) { return 1.0 / __builtin_sqrt(x); }
+// FP64 1/sqrt(x): the hardware estimate refined by two Newton steps
+// y <- y + y (1 - x y^2) / 2, each squaring the relative error, so the result is
+// within about an ulp (the projection's argument is |m|^2 ~ 1, a normal number)
+__device__ __forceinline__ double rsqrt_t(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const double r = __builtin_fma(-x * y, y, 1.0);
+        y = __builtin_fma(0.5 * y, r, y);
+    }
+    return y;
+}
 // 1/x: the hardware reciprocal in FP32 (the projection divides a perturbation-size
 // quantity by 1 + sqrt(1 + e) ~ 2, where its 1-ulp error is far below the state's
 // rounding); exact division in FP64.
@@ -197,6 +208,9 @@ struct MicroLane {
     // x1 neighbours more than K points away come from lanes further off (several
     // DPP moves); the boundary offsets of form 0 assume one lane holds them all
     static_assert(K >= YH || FORM == 1, "lane tile narrower than the stencil reach");
+    // periodic second-order 2-D form 0: x1 fluxes formed once per face (as in form 1)
+    // with the seam offsets added by FMA, x2 seam offsets only in the edge row groups
+    static constexpr bool SEAM0 = (ORD == 2) && (FORM == 0) && (BC == LLHMM_BC_PERIODIC_PERT) && (D == 2);
     static_assert(!HREG || D == 2, "H(r) in registers: 2-D");
     static_assert(D == 1 || R >= YH, "row group thinner than the stencil reach");
     static_assert(D == 1 || SLAB || R * NG == N, "row groups must tile the box");
@@ -308,8 +322,9 @@ struct MicroLane {
             if (ORD == 2) gr = yat(q + 1, k, c) - yat(q, k, c);
             else gr = (T)27 * (yat(q + 1, k, c) - yat(q, k, c)) - (yat(q + 2, k, c) - yat(q - 1, k, c));
             if (FORM == 1 || (lr >= GF && lr < NFR - GF)) return ayv(k, lr) * gr;
-            // boundary face: flux + tau as a double word (hi by FMA, then lo)
             const int off = (lr < GF) ? tSb + k * tSs + lr * 8 : tNb + k * tNs + (lr - (NFR - GF)) * 8;
+            if constexpr (SEAM0) return fma_t(ayv(k, lr), gr, tau_lds(off + c));
+            // boundary face: flux + tau as a double word (hi by FMA, then lo)
             return fma_t(ayv(k, lr), gr, tau_lds(off + c)) + tau_lds(off + 4 + c);
         };
         // sliding window of x2 face fluxes: faces lr = r .. r+FW+FE-1 before row r
@@ -333,8 +348,14 @@ struct MicroLane {
             // neighbour), and the west flux of column 0 as the left neighbour's last
             // east gradient times this lane's own west-face coefficient, so the two
             // sides of the box's periodic seam keep their own coefficients.
-            constexpr bool X1FAST = (ORD == 2) && (FORM == 1) && (BC == LLHMM_BC_PERIODIC_PERT);
+            // Periodic second order, form 0: the same, with the box seam's flux offset
+            // (lanes at the row's ends; zero elsewhere) taken into the seam faces'
+            // FMA.  Its rounding residual is left out: the seam gradient itself is
+            // rounded at that level.
+            constexpr bool X1FAST = (ORD == 2) && (FORM == 1 || SEAM0) && (BC == LLHMM_BC_PERIODIC_PERT);
             T ge[X1FAST ? K : 1][3], Fwest[3];
+            auto tau_w = [&](int c) -> T { return SEAM0 ? tau_lds(tFb + r * tFs + c) : (T)0; };
+            auto tau_e = [&](int c) -> T { return SEAM0 ? tau_lds(tLb + r * tLs + c) : (T)0; };
             if constexpr (X1FAST) {
 #pragma unroll
                 for (int k = 0; k < K; ++k)
@@ -343,7 +364,10 @@ struct MicroLane {
                         ge[k][c] = (k + 1 < K) ? y[r][(k + 1 < K) ? k + 1 : 0][c] - y[r][k][c]
                                                : dpp_mov<DppCtl<L>::ROT_FR>(y[r][0][c]) - y[r][K - 1][c];
 #pragma unroll
-                for (int c = 0; c < 3; ++c) Fwest[c] = axv(r, 0) * dpp_mov<DppCtl<L>::ROT_FL>(ge[K - 1][c]);
+                for (int c = 0; c < 3; ++c) {
+                    const T gw = dpp_mov<DppCtl<L>::ROT_FL>(ge[K - 1][c]);
+                    Fwest[c] = SEAM0 ? fma_t(axv(r, 0), gw, tau_w(c)) : axv(r, 0) * gw;
+                }
             }
             // x1 halo values from the neighbouring lanes (taken before any update of this row)
             T yw[YH][3], ye[YH][3];
@@ -403,10 +427,14 @@ struct MicroLane {
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
                         if (k + 1 < K || AVG == AVG_FLUX || (AVG == AVG_DREF && QTY == LLHMM_Q_FLUX)) {
-                            const T fe = axv(r, k + 1) * ge[k][c];
+                            const T fe = (SEAM0 && k + 1 == K) ? fma_t(axv(r, K), ge[k][c], tau_e(c))
+                                                               : axv(r, k + 1) * ge[k][c];
                             H[c] = fe - Fwest[c];
                             Fx_east[c] = fe;
                             Fwest[c] = fe;
+                        } else if (SEAM0) {
+                            H[c] = fma_t(axv(r, K), ge[K - 1][c], tau_e(c)) - Fwest[c];
+                            Fx_east[c] = (T)0;
                         } else {
                             H[c] = fma_t(axv(r, K), ge[K - 1][c], -Fwest[c]);
                             Fx_east[c] = (T)0;
