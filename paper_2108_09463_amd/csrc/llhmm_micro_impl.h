@@ -211,6 +211,9 @@ struct MicroLane {
     // periodic second-order 2-D form 0: x1 fluxes formed once per face (as in form 1)
     // with the seam offsets added by FMA, x2 seam offsets only in the edge row groups
     static constexpr bool SEAM0 = (ORD == 2) && (FORM == 0) && (BC == LLHMM_BC_PERIODIC_PERT) && (D == 2);
+    // second-order 2-D stages update the group's interior rows before waiting
+    // for the other groups' halo rows
+    static constexpr bool SPLIT = (ORD == 2) && (D == 2) && (R >= 3);
     static_assert(!HREG || D == 2, "H(r) in registers: 2-D");
     static_assert(D == 1 || R >= YH, "row group thinner than the stencil reach");
     static_assert(D == 1 || SLAB || R * NG == N, "row groups must tile the box");
@@ -303,6 +306,11 @@ struct MicroLane {
 #pragma unroll
                         for (int k = 0; k < K; ++k) hb[((g * HROWS + q) * 3 + c) * N + c0 + k] = y[q][k][c];
             }
+        }
+        // the other groups' halo rows, readable after the barrier
+        auto halo_ready = [&]() {
+            if (D != 2) return;
+            const T *hb = s_halo + (NBUF == 2 ? (tstage & 1) * HALO : 0);
             __syncthreads();
             srcS = zero_s ? s_zero : hb + (gs * HROWS + HROWS - YH) * 3 * N;
             srcN = zero_n ? s_zero : hb + (gn * HROWS + 0) * 3 * N;
@@ -310,7 +318,8 @@ struct MicroLane {
                 if (g == 0) srcS = s_edge;
                 if (g == NG - 1) srcN = s_edge + YH * 3 * N;
             }
-        }
+        };
+        if (!SPLIT) halo_ready();
         auto yat = [&](int q, int k, int c) -> T {  // local row q in [-YH, R+YH); halo rows from LDS
             if (q < 0) return *(const T *)(srcS + ((q + YH) * 3 + c) * N + c0 + k);
             if (q >= R) return *(const T *)(srcN + ((q - R) * 3 + c) * N + c0 + k);
@@ -327,22 +336,46 @@ struct MicroLane {
             // boundary face: flux + tau as a double word (hi by FMA, then lo)
             return fma_t(ayv(k, lr), gr, tau_lds(off + c)) + tau_lds(off + 4 + c);
         };
-        // sliding window of x2 face fluxes: faces lr = r .. r+FW+FE-1 before row r
+        // sliding window of x2 face fluxes: faces lr = r .. r+FW+FE-1 before row r.
+        // SPLIT: rows 1 .. R-2 first (their faces are the group's own), then the
+        // barrier, then rows 0 and R-1 with the halo faces; face 1 (row 0's north
+        // face) and face R-1 (row R-1's south face) are kept from the first pass.
         T F2[(D == 2) ? FW + FE : 1][KD][3];
+        T Fk1[SPLIT ? KD : 1][3], FkL[SPLIT ? KD : 1][3];
         if (D == 2) {
 #pragma unroll
             for (int w = 0; w < FW + FE; ++w)
 #pragma unroll
                 for (int k = 0; k < K; ++k)
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) F2[w][k][c] = face2(w, k, c);
+                    for (int c = 0; c < 3; ++c) {
+                        F2[w][k][c] = face2(SPLIT ? w + 1 : w, k, c);
+                        if (SPLIT) Fk1[SPLIT ? k : 0][c] = F2[w][k][c];
+                    }
         }
         double sq[NQ];
 #pragma unroll
         for (int q = 0; q < NQ; ++q) sq[q] = 0.0;
 
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
+        for (int it = 0; it < R; ++it) {
+            const int r = SPLIT ? ((it < R - 2) ? it + 1 : ((it == R - 2) ? 0 : R - 1)) : it;
+            if (SPLIT && it == R - 2) {
+                halo_ready();
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        FkL[SPLIT ? k : 0][c] = F2[0][k][c];
+                        F2[0][k][c] = face2(0, k, c);
+                    }
+            }
+            if (SPLIT && it == R - 1) {
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) F2[0][k][c] = FkL[SPLIT ? k : 0][c];
+            }
             // Periodic second order, form 1: every x1 face flux is formed once.  The
             // east gradients of the own columns (the last one reaches the right
             // neighbour), and the west flux of column 0 as the left neighbour's last
@@ -455,7 +488,7 @@ struct MicroLane {
                 if (D == 2) {
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
-                        const T fnew = face2(r + FW + FE, k, c);
+                        const T fnew = (SPLIT && r == 0) ? Fk1[SPLIT ? k : 0][c] : face2(r + FW + FE, k, c);
                         T h2;
                         if (ORD == 2) h2 = fnew - F2[0][k][c];
                         else h2 = (T)27 * (F2[(ORD == 2) ? 0 : 2][k][c] - F2[(ORD == 2) ? 0 : 1][k][c]) - (fnew - F2[0][k][c]);

@@ -12,7 +12,7 @@ static const TileInfo kTiles[] = {
     LLHMM_TILE(float, 1, 2, 2, 0, 2, 16, 2, 4, 8, 2, 2),
     LLHMM_TILE(float, 1, 2, 2, 0, 2, 16, 3, 3, 16, 2, 2),
     LLHMM_TILE(float, 1, 2, 4, 0, 2, 16, 3, 3, 16, 1, 1),
-    LLHMM_TILE(float, 1, 2, 2, 0, 0, 64, 1, 8, 8, 2, 2),
+    LLHMM_TILE_OPT(float, 1, 2, 2, 0, 0, 64, 1, 4, 16, 2, 1, kOptHReg),
     LLHMM_TILE(float, 1, 2, 2, 1, 0, 16, 2, 4, 8, 2, 2),
     LLHMM_TILE(float, 1, 2, 2, 1, 0, 16, 3, 3, 16, 2, 2),
     LLHMM_TILE(float, 1, 2, 4, 1, 0, 16, 3, 3, 16, 1, 1),
@@ -22,11 +22,11 @@ static const TileInfo kTiles[] = {
     LLHMM_TILE(float, 1, 2, 2, 1, 2, 16, 2, 4, 8, 2, 2),
     LLHMM_TILE(float, 1, 2, 2, 1, 2, 16, 3, 3, 16, 2, 2),
     LLHMM_TILE(float, 1, 2, 4, 1, 2, 16, 3, 3, 16, 1, 1),
-    LLHMM_TILE(float, 1, 2, 2, 1, 0, 64, 1, 8, 8, 2, 2),
-    LLHMM_TILE(float, 1, 2, 2, 0, 1, 64, 1, 8, 8, 2, 2),
-    LLHMM_TILE(float, 1, 2, 2, 0, 2, 64, 1, 8, 8, 2, 2),
-    LLHMM_TILE(float, 1, 2, 2, 1, 1, 64, 1, 8, 8, 2, 2),
-    LLHMM_TILE(float, 1, 2, 2, 1, 2, 64, 1, 8, 8, 2, 2),
+    LLHMM_TILE_OPT(float, 1, 2, 2, 1, 0, 64, 1, 4, 16, 2, 1, kOptHReg),
+    LLHMM_TILE_OPT(float, 1, 2, 2, 0, 1, 64, 1, 4, 16, 2, 1, kOptHReg),
+    LLHMM_TILE_OPT(float, 1, 2, 2, 0, 2, 64, 1, 4, 16, 2, 1, kOptHReg),
+    LLHMM_TILE_OPT(float, 1, 2, 2, 1, 1, 64, 1, 4, 16, 2, 1, kOptHReg),
+    LLHMM_TILE_OPT(float, 1, 2, 2, 1, 2, 64, 1, 4, 16, 2, 1, kOptHReg),
     // fourth order at n = 32 (two points per lane: x1 neighbours up to two lanes
     // away) and n = 64 (one point per lane, three lanes away)
 #define LLHMM_O4_F32(BC, QTY)                                      \
