@@ -298,7 +298,12 @@ llhmm_status llhmm_solve_noalloc(llhmm_ctx *ctx, const llhmm_box *boxes, int32_t
  * h / stages steps.  Every `steps_per_exchange` steps (1, 2, 4 or 8, with
  * h >= steps_per_exchange x stages) the slabs publish their h edge rows on
  * each side to global memory and replace their halo rows with their
- * neighbours'; the box state never leaves the chip otherwise.  Each class runs as one persistent launch
+ * neighbours'.  With steps_per_exchange 0 (second order) the exchange comes
+ * at every Runge-Kutta stage instead: the window is the slab's own rows
+ * (h = 0), the slab publishes its first and last row after every stage,
+ * and its edge rows read the neighbours' published rows in place of halo
+ * rows, so no row is computed twice.  The box state never leaves the chip
+ * otherwise.  Each class runs as one persistent launch
  * whose workgroups take (box, slab) items, longest boxes first.  A wait for a
  * neighbouring slab gives up after a bounded number of polls; the boxes
  * involved then report status 2 and llhmm_upscale with check returns
@@ -315,8 +320,9 @@ llhmm_status llhmm_solve_noalloc(llhmm_ctx *ctx, const llhmm_box *boxes, int32_t
 llhmm_status llhmm_batch_tune(llhmm_ctx *ctx, llhmm_batch *batch, const double *m_init_dev,
                               const llhmm_macro *macro, const double *M_macro_dev,
                               const double *coef_dev, int32_t reps, hipStream_t stream);
-/* Slabs of each box and its steps between exchanges (0 for boxes solved whole
- * by one workgroup); steps_per_exchange_out may be NULL. */
+/* Slabs of each box (0 for boxes solved whole by one workgroup) and its steps
+ * between exchanges (0: at every stage, or a box solved whole);
+ * steps_per_exchange_out may be NULL. */
 llhmm_status llhmm_batch_slabs(const llhmm_batch *batch, int32_t *slabs_out, int32_t *steps_per_exchange_out);
 /* The context's tuning table as text: one line "precision n bc quantity
  * stages variant steps_per_exchange" per class.  Load merges into the table. */

@@ -285,13 +285,28 @@ struct SlabGeom {
     int spe = 0, h = 0, ns = 0, xd = 0;
 };
 
-constexpr int kSlabSpe[] = {1, 2, 4, 8};  // exchange intervals; each divides kRerefSteps
+// exchange intervals in steps, each dividing kRerefSteps; 0: at every stage
+constexpr int kSlabSpe[] = {0, 1, 2, 4, 8};
+constexpr int kNumSpe = (int)(sizeof(kSlabSpe) / sizeof(kSlabSpe[0]));
 
 SlabGeom slab_geom(const SlabTileInfo &t, int n, int stages, int spe) {
     SlabGeom g;
     const int WR = t.R * t.NG;
-    if (n % t.R != 0 || kRerefSteps % spe != 0) return g;
+    if (n % t.R != 0 || spe < 0 || (spe > 0 && kRerefSteps % spe != 0)) return g;
     const int reach = (t.order == 2) ? 1 : 3;
+    if (spe == 0) {
+        // every stage (second order): no halo rows in the window; the slab's
+        // first and last rows go to the neighbours after each stage
+        if (t.order != 2) return g;
+        const int groups = n / t.R;
+        const int ns = (groups + t.NG - 1) / t.NG;
+        if (ns < 2 || groups / ns * t.R < reach) return g;
+        g.spe = 0;
+        g.h = 0;
+        g.ns = ns;
+        g.xd = reach;
+        return g;
+    }
     const int h = (reach * spe * stages + t.R - 1) / t.R * t.R;
     const int capg = (WR - 2 * h) / t.R;  // own row groups per slab at most
     if (capg < 1) return g;
@@ -315,15 +330,17 @@ void slab_rows(const SlabTileInfo &t, int n, int ns, int s, int *o0, int *rows) 
 }
 
 // Exchange interval without tuning: fewest window rows computed per box, an
-// exchange weighted as half a step of the window.
+// exchange weighted as half a step of the window (a fifth of a step when it
+// comes at every stage, where it overlaps the interior rows; without interior
+// rows, R < 3, the per-stage exchange is left to the tuner).  -1: none fits.
 int slab_default_spe(const SlabTileInfo &t, int n, int stages) {
-    int best = 0;
+    int best = -1;
     double best_cost = 0.0;
     for (int spe : kSlabSpe) {
         const SlabGeom g = slab_geom(t, n, stages, spe);
-        if (g.ns == 0) continue;
-        const double cost = g.ns * (1.0 + 0.5 / spe);
-        if (best == 0 || cost < best_cost) {
+        if (g.ns == 0 || (spe == 0 && t.R < 3)) continue;
+        const double cost = g.ns * (1.0 + (spe == 0 ? 0.2 : 0.5 / spe));
+        if (best < 0 || cost < best_cost) {
             best = spe;
             best_cost = cost;
         }
@@ -832,7 +849,7 @@ static llhmm_status batch_create_impl(llhmm_ctx *ctx, const llhmm_box *boxes, in
                 } else {
                     spe = slab_default_spe(*bit->second[0], bx.n, stages);
                 }
-                if (spe > 0) {
+                if (spe >= 0) {
                     bt = bit->second[v];
                     b->slab_spe[i] = spe;
                 }
@@ -1418,8 +1435,8 @@ llhmm_status llhmm_batch_tune(llhmm_ctx *ctx, llhmm_batch *b, const double *m_in
         for (size_t v = 0; v < variants.size(); ++v)
             if (variants[v] == b->slab_tile[i0]) best_v = (int)v;
         float best_ms = -1.f;
-        for (int vs = 0; vs < (int)variants.size() * 4 && st == LLHMM_OK; ++vs) {
-            const int v = vs / 4, spe = kSlabSpe[vs % 4];
+        for (int vs = 0; vs < (int)variants.size() * kNumSpe && st == LLHMM_OK; ++vs) {
+            const int v = vs / kNumSpe, spe = kSlabSpe[vs % kNumSpe];
             const SlabTileInfo *t = variants[v];
             if (slab_geom(*t, P0.n, P0.stages, spe).ns == 0) continue;
             hipError_t e = hipStreamSynchronize(stream);  // no launch may still read the plans or jobs

@@ -241,6 +241,20 @@ struct MicroLane {
     bool own[SLAB ? R : 1];
     const double *s_wyl;
     const T *s_edge;   // slab: z of the box rows just outside the window (re-referencing)
+    // slab, exchange at every stage (the window is the slab's own rows): the
+    // neighbouring slabs' edge rows of each stage input come through tagged
+    // words into LDS rows; the edge groups publish their first / last YH rows
+    // of every stage result
+    bool xs_on;                     // per-stage exchange
+    bool xs_get[2], xs_put[2];      // [south, north]: read the neighbour's rows / publish own edge rows
+    bool xs_pub;                    // publish this stage's result
+    int xs_fail;                    // a wait gave up
+    const uint64_t *xs_src[2];      // neighbours' edge words (parity 0; parity 1 at + xs_par)
+    uint64_t *xs_dst[2];            // own edge words
+    long xs_par;
+    T *s_xrow;                      // LDS [2 sides][YH rows][3][N]
+    int32_t *xs_abort;
+    long long xs_spin;
 
     template <int CTRL_ROT, int CTRL_SH>
     __device__ __forceinline__ static T nb(T v) {
@@ -273,6 +287,67 @@ struct MicroLane {
         // x2 faces in LDS face-row major ([LF][N]): the lanes of a row group read
         // consecutive words, free of bank conflicts
         return AXL ? s_axl[N * LF + (r0 - FW + lr + 2) * N + c0 + k] : ay[AXL ? 0 : k][AXL ? 0 : lr];
+    }
+
+    // Per-stage exchange: reads the neighbours' edge rows that carry `tag` into
+    // the LDS rows (a wait gives up after xs_spin polls or when another
+    // workgroup has given up; the stage then goes on with whatever it read).
+    __device__ __forceinline__ void xs_receive(uint32_t tag) {
+        constexpr int XW = XWords<T>::n;
+        const long par = (long)(tag & 1) * xs_par;
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            if (!xs_get[side]) continue;
+            const uint64_t *sb = xs_src[side] + par;
+            T *dst = s_xrow + side * YH * 3 * N;
+            long long polls = 0;
+            {
+                // first wait on the word this lane's publisher writes last
+                T v;
+                const uint64_t *sw = sb + ((long)((YH - 1) * 3 + 2) * N + c0 + K - 1) * XW;
+                while (!xget(sw, tag, v)) {
+                    if (xload(xs_abort) != 0 || ++polls > xs_spin) break;
+                    __builtin_amdgcn_s_sleep(1);
+                }
+            }
+            for (;;) {
+                bool all = true;
+#pragma unroll
+                for (int q = 0; q < YH; ++q)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c)
+#pragma unroll
+                        for (int k = 0; k < K; ++k) {
+                            T v;
+                            all &= xget(sb + ((long)(q * 3 + c) * N + c0 + k) * XW, tag, v);
+                            dst[(q * 3 + c) * N + c0 + k] = v;
+                        }
+                if (all) break;
+                if (xload(xs_abort) != 0 || ++polls > xs_spin) {
+                    xs_fail = 1;
+                    xstore(xs_abort, 1);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+    }
+    // Publishes the edge rows of the current y (the next stage's input) with `tag`.
+    __device__ __forceinline__ void xs_publish(uint32_t tag) {
+        constexpr int XW = XWords<T>::n;
+        const long par = (long)(tag & 1) * xs_par;
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            if (!xs_put[side]) continue;
+            uint64_t *db = xs_dst[side] + par;
+#pragma unroll
+            for (int q = 0; q < YH; ++q)
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+#pragma unroll
+                    for (int k = 0; k < K; ++k)
+                        xput(db + ((long)(q * 3 + c) * N + c0 + k) * XW, y[side == 0 ? q : R - YH + q][k][c], tag);
+        }
     }
 
     // One Runge-Kutta stage on stage input y: H(y), f(y), accumulator and
@@ -311,10 +386,16 @@ struct MicroLane {
         auto halo_ready = [&]() {
             if (D != 2) return;
             const T *hb = s_halo + (NBUF == 2 ? (tstage & 1) * HALO : 0);
+            // stage 0 reads the neighbours' rows of the initial state, loaded
+            // from the tables with the window
+            if (SLAB && xs_on && tstage > 0) xs_receive((uint32_t)tstage);
             __syncthreads();
             srcS = zero_s ? s_zero : hb + (gs * HROWS + HROWS - YH) * 3 * N;
             srcN = zero_n ? s_zero : hb + (gn * HROWS + 0) * 3 * N;
-            if (SLAB && AVG == AVG_DREF) {  // the reference change is known beyond the window
+            if (SLAB && xs_on) {
+                if (xs_get[0]) srcS = s_xrow;
+                if (xs_get[1]) srcN = s_xrow + YH * 3 * N;
+            } else if (SLAB && AVG == AVG_DREF) {  // the reference change is known beyond the window
                 if (g == 0) srcS = s_edge;
                 if (g == NG - 1) srcN = s_edge + YH * 3 * N;
             }
@@ -618,6 +699,7 @@ struct MicroLane {
 #pragma unroll
             for (int q = 0; q < NQ; ++q) acc64[q] = fma(wn, sq[q], acc64[q]);
         }
+        if (SLAB && xs_on && xs_pub && AVG != AVG_DREF && AVG != AVG_EVAL) xs_publish((uint32_t)tstage + 1);
     }
 
     // Status bits of the final state of this lane's own points (every lane of
@@ -713,6 +795,8 @@ struct MicroLane {
                 }
                 s_ref[3 * RSTRIDE + cell] = (T)(n2 - 1.0);
             }
+        // per-stage slab exchange: the neighbours take this z for their edge rows
+        if (SLAB && xs_on) xs_publish((uint32_t)tstage);
         stage<AVG_DREF, true, false>((T)0, (T)0, w_tail, tstage, nullptr, 0);
 #pragma unroll
         for (int r = 0; r < R; ++r)
@@ -726,6 +810,7 @@ struct MicroLane {
                     y[r][k][c] = m[r][k][c];
                 }
             }
+        if (SLAB && xs_on) xs_publish((uint32_t)tstage + 1);
     }
 };
 
@@ -1004,10 +1089,10 @@ __device__ __forceinline__ S uniform_load(const S *p) {
 // EVAL (a separate instantiation, so that the solve's register allocation
 // does not carry the evaluation's): evaluate H(m0) on the own rows instead of
 // solving; A.mode must agree.
-template <typename T, int ORD, int QTY, int BC, int L, int K, int R, int NG, int NBUF, int MINW, bool EVAL>
+template <typename T, int ORD, int QTY, int BC, int L, int K, int R, int NG, int NBUF, int MINW, bool EVAL, int OPT = 0>
 __global__ void __launch_bounds__(L * NG, MINW) k_slab(SlabArgs A) {
     constexpr int D = 2;
-    using Lane = MicroLane<T, D, ORD, BC, QTY, L, K, R, NG, NBUF, true>;
+    using Lane = MicroLane<T, D, ORD, BC, QTY, L, K, R, NG, NBUF, true, OPT>;
     constexpr int N = Lane::N, NF = Lane::NF, NFR = Lane::NFR, FW = Lane::FW, NQ = Lane::NQ;
     constexpr int YH = Lane::YH, WR = Lane::WR;
     constexpr long C = (long)N * N;
@@ -1019,6 +1104,8 @@ __global__ void __launch_bounds__(L * NG, MINW) k_slab(SlabArgs A) {
     __shared__ T s_refl[Lane::REF_LDS];
     __shared__ double s_w[2 * N];
     __shared__ double s_wyl[2 * WR];
+    // per-stage exchange (second order): the neighbours' edge rows
+    __shared__ T s_xrow[(ORD == 2) ? 2 * YH * 3 * N : 1];
     __shared__ int s_item, s_abort;
 
     const int tid = threadIdx.x;
@@ -1027,6 +1114,9 @@ __global__ void __launch_bounds__(L * NG, MINW) k_slab(SlabArgs A) {
     const int j = (L == 16) ? (lane & 15) : lane;
     for (int i = tid; i < 2 * YH * 3 * N; i += L * NG) s_zero[i] = (T)0;
     const int h = A.h, spe = A.spe, xd = A.xdepth;
+    // spe == 0: exchange at every stage; the window holds only the slab's own
+    // rows (h == 0) and the edge groups read their neighbours' rows from LDS
+    const bool xs = (ORD == 2) && (spe == 0);
     const int queue = __builtin_amdgcn_readfirstlane(xcc_id() % A.nqueues);
     auto wrap = [](int br) { return ((br % N) + N) % N; };
 
@@ -1149,6 +1239,30 @@ __global__ void __launch_bounds__(L * NG, MINW) k_slab(SlabArgs A) {
         S.s_halo = s_halo;
         S.s_zero = s_zero;
         S.s_edge = s_zero;   // re-referencing sees zeros beyond the window too
+        {
+            const int g_last = (own_end + R - 1) / R - 1;  // last own group (h == 0 with xs)
+            S.xs_on = xs;
+            S.xs_get[0] = S.xs_put[0] = xs && (g == 0) && has_s;
+            S.xs_get[1] = S.xs_put[1] = xs && (g == g_last) && has_n;
+            S.xs_pub = true;
+            S.xs_fail = 0;
+            S.xs_src[0] = edge(s_south, 1, 0);
+            S.xs_src[1] = edge(s_north, 0, 0);
+            S.xs_dst[0] = edge(sl, 0, 0);
+            S.xs_dst[1] = edge(sl, 1, 0);
+            S.xs_par = (long)xd * XROW;
+            S.s_xrow = s_xrow;
+            S.xs_abort = A.abort_word;
+            S.xs_spin = A.spin_max;
+            // stage 0 reads the neighbours' initial rows straight from the tables
+            for (int i = tid; i < (xs ? 2 * YH * 3 * N : 0); i += L * NG) {
+                const int side = i / (YH * 3 * N), rem = i - side * (YH * 3 * N);
+                const int q = rem / (3 * N), c = (rem / N) % 3, col = rem % N;
+                const int br = (side == 0) ? job.o0 - YH + q : job.o0 + job.rows + q;
+                s_xrow[i] = (br >= 0 && br < N) || BC != LLHMM_BC_DIRICHLET ? src[c * C + (long)wrap(br) * N + col]
+                                                                             : (T)0;
+            }
+        }
         S.s_tau = nullptr;
         S.alpha = (T)P.alpha;
         S.dt = (T)P.dt;
@@ -1170,7 +1284,7 @@ __global__ void __launch_bounds__(L * NG, MINW) k_slab(SlabArgs A) {
             constexpr bool REREF = !Lane::REFG && (sizeof(T) == 4);
             int ts = 0;
             for (int n = 0; n < M; ++n) {
-                if (n > 0 && n % spe == 0) {
+                if (!xs && n > 0 && n % spe == 0) {
                     // replace the halo rows with the neighbours' rows of exchange e
                     const uint32_t e = (uint32_t)(n / spe);
                     const int par = (int)(e & 1);
@@ -1228,7 +1342,16 @@ __global__ void __launch_bounds__(L * NG, MINW) k_slab(SlabArgs A) {
                 const int nmid = rk4 ? 2 : 0;
                 for (int sm = 0; sm < nmid; ++sm)
                     S.template stage<AVG_NONE, false, false>(third, sm == 0 ? half_dt : S.dt, 0.0, ts++, nullptr, 0);
+                // per-stage exchange: the last stage's result goes out unless the next
+                // step starts by re-referencing (which publishes its own rows)
+                S.xs_pub = !(REREF && (n + 1) % kRerefSteps == 0);
                 S.template stage<AVG_NONE, false, true>(rk4 ? (T)(1.0 / 6.0) : (T)0.5, (T)0, 0.0, ts++, nullptr, 0);
+                S.xs_pub = true;
+                if (xs) {
+                    aborted = __syncthreads_or(S.xs_fail) != 0;
+                    if (aborted) break;
+                    continue;
+                }
                 if ((n + 1) % spe == 0 && n + 1 < M) {
                     // publish the edge rows of exchange e = (n + 1) / spe: the first xd own
                     // rows (south edge) and the last xd (north edge; a group may be in both)

@@ -7,28 +7,36 @@
 
 namespace llhmm {
 
-template <typename T, int ORD, int QTY, int BC, int L, int K, int R, int NG, int NBUF, int MINW>
+template <typename T, int ORD, int QTY, int BC, int L, int K, int R, int NG, int NBUF, int MINW, int OPT>
 hipError_t launch_slab(const SlabArgs &a, int nblocks, hipStream_t s) {
     if (a.mode == 1)
-        hipLaunchKernelGGL((k_slab<T, ORD, QTY, BC, L, K, R, NG, NBUF, MINW, true>), dim3(nblocks), dim3(L * NG), 0, s,
-                           a);
+        hipLaunchKernelGGL((k_slab<T, ORD, QTY, BC, L, K, R, NG, NBUF, MINW, true, OPT>), dim3(nblocks), dim3(L * NG),
+                           0, s, a);
     else
-        hipLaunchKernelGGL((k_slab<T, ORD, QTY, BC, L, K, R, NG, NBUF, MINW, false>), dim3(nblocks), dim3(L * NG), 0,
-                           s, a);
+        hipLaunchKernelGGL((k_slab<T, ORD, QTY, BC, L, K, R, NG, NBUF, MINW, false, OPT>), dim3(nblocks),
+                           dim3(L * NG), 0, s, a);
     return hipGetLastError();
 }
 
-template <typename T, int ORD, int QTY, int BC, int L, int K, int R, int NG, int NBUF, int MINW>
+template <typename T, int ORD, int QTY, int BC, int L, int K, int R, int NG, int NBUF, int MINW, int OPT>
 hipError_t occupancy_slab(int *blocks_per_cu) {
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        blocks_per_cu, (const void *)k_slab<T, ORD, QTY, BC, L, K, R, NG, NBUF, MINW, false>, L * NG, 0);
+        blocks_per_cu, (const void *)k_slab<T, ORD, QTY, BC, L, K, R, NG, NBUF, MINW, false, OPT>, L * NG, 0);
 }
 
-#define LLHMM_SLAB(T, PREC, ORD, BC, QTY, L, K, R, NG, NBUF, MINW)                                         \
+#define LLHMM_SLAB_OPT(T, PREC, ORD, BC, QTY, L, K, R, NG, NBUF, MINW, OPT)                                \
     SlabTileInfo{(K) * (L), ORD, BC, PREC, QTY, L, K, R, NG, NBUF, (L) * (NG),                             \
-                 &launch_slab<T, ORD, QTY, BC, L, K, R, NG, NBUF, MINW>,                                   \
-                 &occupancy_slab<T, ORD, QTY, BC, L, K, R, NG, NBUF, MINW>,                                \
-                 "slab " #T " o" #ORD " bc" #BC " q" #QTY " L" #L " K" #K " R" #R " NG" #NG " B" #NBUF " W" #MINW}
+                 &launch_slab<T, ORD, QTY, BC, L, K, R, NG, NBUF, MINW, OPT>,                              \
+                 &occupancy_slab<T, ORD, QTY, BC, L, K, R, NG, NBUF, MINW, OPT>,                           \
+                 "slab " #T " o" #ORD " bc" #BC " q" #QTY " L" #L " K" #K " R" #R " NG" #NG " B" #NBUF " W" #MINW \
+                 " opt" #OPT}
+#define LLHMM_SLAB(T, PREC, ORD, BC, QTY, L, K, R, NG, NBUF, MINW) \
+    LLHMM_SLAB_OPT(T, PREC, ORD, BC, QTY, L, K, R, NG, NBUF, MINW, 0)
+// second order, H(r) in registers
+#define LLHMM_SLAB_QTY_HR(T, PREC, BC, L, K, R, NG, NBUF, MINW)                                            \
+    LLHMM_SLAB_OPT(T, PREC, 2, BC, 0, L, K, R, NG, NBUF, MINW, kOptHReg),                                  \
+        LLHMM_SLAB_OPT(T, PREC, 2, BC, 1, L, K, R, NG, NBUF, MINW, kOptHReg),                              \
+        LLHMM_SLAB_OPT(T, PREC, 2, BC, 2, L, K, R, NG, NBUF, MINW, kOptHReg)
 
 #define LLHMM_SLAB_QTY(T, PREC, BC, L, K, R, NG, NBUF, MINW)                                               \
     LLHMM_SLAB(T, PREC, 2, BC, 0, L, K, R, NG, NBUF, MINW), LLHMM_SLAB(T, PREC, 2, BC, 1, L, K, R, NG, NBUF, MINW), \
