@@ -214,6 +214,10 @@ struct MicroLane {
     // second-order 2-D stages update the group's interior rows before waiting
     // for the other groups' halo rows
     static constexpr bool SPLIT = (ORD == 2) && (D == 2) && (R >= 3);
+    // SEAM0 with one column per lane: a lane has at most one seam face, and its
+    // x1 part is a_e g_e + (T - a_w g_w) by two FMAs, T the lane's seam offset
+    // (held negated for the west seam in the unused low-word slots)
+    static constexpr bool SEAMK1 = SEAM0 && (K == 1);
     static_assert(!HREG || D == 2, "H(r) in registers: 2-D");
     static_assert(D == 1 || R >= YH, "row group thinner than the stencil reach");
     static_assert(D == 1 || SLAB || R * NG == N, "row groups must tile the box");
@@ -228,6 +232,7 @@ struct MicroLane {
     const T *s_axl;  // AXL: this group's face coefficients in LDS
     T tauF[(D == 1) ? GF : 1][6], tauL[(D == 1) ? GF : 1][6];  // hi[3], lo[3]
     int tFb, tFs, tLb, tLs, tSb, tSs, tNb, tNs;  // LDS offsets: base + index * stride
+    int tTb, tTs;  // SEAMT: the lane's seam offset (-tau west at lane 0, +tau east at lane L-1)
     double acc64[NQ];
     int g, c0, r0, gs, gn;
     bool zero_s, zero_n;
@@ -467,6 +472,7 @@ struct MicroLane {
             // FMA.  Its rounding residual is left out: the seam gradient itself is
             // rounded at that level.
             constexpr bool X1FAST = (ORD == 2) && (FORM == 1 || SEAM0) && (BC == LLHMM_BC_PERIODIC_PERT);
+            constexpr bool SEAMT = SEAMK1 && AVG != AVG_FLUX;
             T ge[X1FAST ? K : 1][3], Fwest[3];
             auto tau_w = [&](int c) -> T { return SEAM0 ? tau_lds(tFb + r * tFs + c) : (T)0; };
             auto tau_e = [&](int c) -> T { return SEAM0 ? tau_lds(tLb + r * tLs + c) : (T)0; };
@@ -480,7 +486,8 @@ struct MicroLane {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     const T gw = dpp_mov<DppCtl<L>::ROT_FL>(ge[K - 1][c]);
-                    Fwest[c] = SEAM0 ? fma_t(axv(r, 0), gw, tau_w(c)) : axv(r, 0) * gw;
+                    if (SEAMT) Fwest[c] = fma_t(-axv(r, 0), gw, tau_lds(tTb + r * tTs + c));  // T - F_w
+                    else Fwest[c] = SEAM0 ? fma_t(axv(r, 0), gw, tau_w(c)) : axv(r, 0) * gw;
                 }
             }
             // x1 halo values from the neighbouring lanes (taken before any update of this row)
@@ -546,6 +553,9 @@ struct MicroLane {
                             H[c] = fe - Fwest[c];
                             Fx_east[c] = fe;
                             Fwest[c] = fe;
+                        } else if (SEAMT) {
+                            H[c] = fma_t(axv(r, K), ge[K - 1][c], Fwest[c]);
+                            Fx_east[c] = (T)0;
                         } else if (SEAM0) {
                             H[c] = fma_t(axv(r, K), ge[K - 1][c], tau_e(c)) - Fwest[c];
                             Fx_east[c] = (T)0;
@@ -934,7 +944,7 @@ __global__ void __launch_bounds__(L * NG, MINW) k_micro(MicroArgs A) {
         for (int q = 0; q < ((D == 1) ? GF : 1); ++q)
 #pragma unroll
             for (int c = 0; c < 6; ++c) S.tauF[q][c] = S.tauL[q][c] = (T)0;
-        S.tFb = S.tFs = S.tLb = S.tLs = S.tSb = S.tSs = S.tNb = S.tNs = 0;
+        S.tFb = S.tFs = S.tLb = S.tLs = S.tSb = S.tSs = S.tNb = S.tNs = S.tTb = S.tTs = 0;
     } else {
         // boundary offsets: 1-D in registers (lanes 0 and L-1), 2-D in LDS
         if (D == 1) {
@@ -951,7 +961,12 @@ __global__ void __launch_bounds__(L * NG, MINW) k_micro(MicroArgs A) {
         } else {
             // tables hold [2N][2 sides][3][8]; LDS keeps the GF faces that are used
             constexpr int TS = GF * 8;
-            for (int i = tid; i < 4 * N * TS; i += L * NG) s_tau[i] = tab[TL.tau1 + (i / TS) * 24 + i % TS];
+            for (int i = tid; i < 4 * N * TS; i += L * NG) {
+                const int pr = i / TS, e = i % TS;  // (line, side) pair, entry
+                // SEAMK1: the west x1 offsets' low-word slots hold -hi
+                const bool neg = Lane::SEAMK1 && pr < 2 * N && (pr & 1) == 0 && e >= 4 && e < 7;
+                s_tau[i] = neg ? -tab[TL.tau1 + pr * 24 + e - 4] : tab[TL.tau1 + pr * 24 + e];
+            }
             for (int i = tid; i < 24; i += L * NG) s_tau[Lane::ZOFF + i] = (T)0;
             for (int i = tid; i < YH * 3 * N; i += L * NG) s_zero[i] = (T)0;
             S.tFb = (j == 0) ? (r0 * 2 + 0) * TS : Lane::ZOFF;
@@ -962,6 +977,8 @@ __global__ void __launch_bounds__(L * NG, MINW) k_micro(MicroArgs A) {
             S.tSs = (g == 0) ? 2 * TS : 0;
             S.tNb = (g == NG - 1) ? 2 * N * TS + (c0 * 2 + 1) * TS : Lane::ZOFF;
             S.tNs = (g == NG - 1) ? 2 * TS : 0;
+            S.tTb = (j == 0) ? (r0 * 2 + 0) * TS + 4 : ((j == L - 1) ? (r0 * 2 + 1) * TS : Lane::ZOFF);
+            S.tTs = (j == 0 || j == L - 1) ? 2 * TS : 0;
         }
     }
     __syncthreads();
@@ -1231,7 +1248,7 @@ __global__ void __launch_bounds__(L * NG, MINW) k_slab(SlabArgs A) {
                 }
 #pragma unroll
         for (int c = 0; c < 6; ++c) S.tauF[0][c] = S.tauL[0][c] = (T)0;
-        S.tFb = S.tFs = S.tLb = S.tLs = S.tSb = S.tSs = S.tNb = S.tNs = 0;
+        S.tFb = S.tFs = S.tLb = S.tLs = S.tSb = S.tSs = S.tNb = S.tNs = S.tTb = S.tTs = 0;
         S.gs = (g > 0) ? g - 1 : 0;
         S.gn = (g < NG - 1) ? g + 1 : 0;
         S.zero_s = (g == 0) || dead(g - 1);
