@@ -50,11 +50,12 @@ static const SlabTileInfo kSlab[] = {
     // FP32: windows of 32 rows (LDS holds the window's reference tables)
     LLHMM_SLAB_QTY(float, 1, 0, 64, 2, 4, 8, 1, 1),
     LLHMM_SLAB_QTY(float, 1, 1, 64, 2, 4, 8, 1, 1),
-    LLHMM_SLAB_QTY(float, 1, 0, 16, 6, 2, 16, 1, 1),
-    LLHMM_SLAB_QTY(float, 1, 1, 16, 6, 2, 16, 1, 1),
-    // FP32 n = 96, second variant: one row per lane, 8 waves (two per SIMD)
+    // FP32 n = 96: one row per lane, 8 waves (two per SIMD) first; two rows per
+    // lane in 4 waves second
     LLHMM_SLAB_QTY(float, 1, 0, 16, 6, 1, 32, 1, 1),
     LLHMM_SLAB_QTY(float, 1, 1, 16, 6, 1, 32, 1, 1),
+    LLHMM_SLAB_QTY(float, 1, 0, 16, 6, 2, 16, 1, 1),
+    LLHMM_SLAB_QTY(float, 1, 1, 16, 6, 2, 16, 1, 1),
     // FP64: windows of 16 rows (reference tables read from global memory)
     LLHMM_SLAB_QTY(double, 0, 0, 64, 2, 2, 8, 2, 1),
     LLHMM_SLAB_QTY(double, 0, 1, 64, 2, 2, 8, 2, 1),
