@@ -58,12 +58,16 @@ extern "C" {
  * roundings of the scheme (state, stencil, right-hand side, stored tables)
  * move the upscaled average by about 1e-5 relative or more: on weakly damped
  * wide boxes the average cancels many digits, and below mu = 2 eps too few
- * points enter it for the rounding noise to average out.  Fourth-order FP32
+ * points enter it for the rounding noise to average out.  The width bound
+ * keeps a margin: the FP32 result of such a box moves by up to half its error
+ * between tile variants of the same arithmetic (their roundings differ), and
+ * weakly damped boxes of 6.4 and 8 eps reached 8.8e-6 and 1.13e-5, against at
+ * most 6.1e-6 from 6 eps down.  Fourth-order FP32
  * boxes also need at least LLHMM_FP32_MIN_PPE_O4 grid points per eps
  * (eps / dx, dx = 2 mu' / n): on coarser grids the wider stencil's roundings
  * reached 1.2e-5 (n = 32, mu' = 3 eps, 5.3 points per eps), against at most
  * 1.4e-6 from 8 points per eps on. */
-#define LLHMM_FP32_MAX_WIDTH_EPS 8.0
+#define LLHMM_FP32_MAX_WIDTH_EPS 6.0
 #define LLHMM_FP32_MIN_ALPHA_WIDE 0.5
 #define LLHMM_FP32_MIN_MU_EPS 2.0
 #define LLHMM_FP32_MIN_PPE_O4 8.0

@@ -222,7 +222,7 @@ def llhmm_plan(boxes):
     return M, dt, integ
 
 
-FP32_MAX_WIDTH_EPS = 8.0      # LLHMM_FP32_MAX_WIDTH_EPS
+FP32_MAX_WIDTH_EPS = 6.0      # LLHMM_FP32_MAX_WIDTH_EPS
 FP32_MIN_ALPHA_WIDE = 0.5      # LLHMM_FP32_MIN_ALPHA_WIDE
 FP32_MIN_MU_EPS = 2.0          # LLHMM_FP32_MIN_MU_EPS
 FP32_MIN_PPE_O4 = 8.0          # LLHMM_FP32_MIN_PPE_O4

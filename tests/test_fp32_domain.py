@@ -12,9 +12,11 @@ rounding it misses the oracle by several 1e-5 on a wide weakly damped box
 misses by a similar amount), and each rounded component alone moves the
 average by more than 5e-6, so no single change of the FP32 arithmetic brings
 the box within 1e-5.  With an averaging radius of one eps the emulated error
-is close to the bar.  At the domain's edges (mu' = 8 eps with alpha = 0.01,
+is close to the bar.  At the domain's edges (mu' = 6 eps with alpha = 0.01,
 and mu' = 16 eps with alpha = 0.5) the FP32 emulation stays within half the
-bar.
+bar; the width bound sits below the 8 eps where the GPU measured 1.13e-5 with
+one tile variant (alpha = 0.1, eta = eps^2), so that the rounding differences
+between variants stay inside the bar.
 """
 import numpy as np
 import pytest
@@ -61,7 +63,7 @@ def test_fp32_misses_bar_on_wide_weakly_damped_box(wide_weak):
         assert e1 > 5e-6, comp
 
 
-@pytest.mark.parametrize("n,ppe,alpha", [(64, 4, 0.01), (128, 4, 0.5)])
+@pytest.mark.parametrize("n,ppe,alpha", [(48, 4, 0.01), (128, 4, 0.5)])
 def test_fp32_within_bar_at_domain_edges(n, ppe, alpha):
     box, coef, ref = _box(n, ppe, alpha)
     assert box["mu_box"] / box["eps"] == pytest.approx(n / (2 * ppe))
@@ -98,7 +100,7 @@ def test_host_check_refuses_exactly_the_rule():
         assert (st == L.E_NOTSUP) == want, (lab, st, msg)
         assert st in (L.OK, L.E_NOTSUP)
         assert L.llhmm_check_boxes([box], inputs.FP64)[0] == L.OK
-    assert nref == 94
+    assert nref == 100
 
 
 def test_fourth_order_needs_eight_points_per_eps():
