@@ -56,6 +56,12 @@ static const SlabTileInfo kSlab[] = {
     LLHMM_SLAB_QTY(float, 1, 1, 16, 6, 1, 32, 1, 1),
     LLHMM_SLAB_QTY(float, 1, 0, 16, 6, 2, 16, 1, 1),
     LLHMM_SLAB_QTY(float, 1, 1, 16, 6, 2, 16, 1, 1),
+    // FP32 with H(r) in registers: the LDS left over takes a double-buffered
+    // halo (one barrier per stage)
+    LLHMM_SLAB_QTY_HR(float, 1, 0, 64, 2, 4, 8, 2, 1),
+    LLHMM_SLAB_QTY_HR(float, 1, 1, 64, 2, 4, 8, 2, 1),
+    LLHMM_SLAB_QTY_HR(float, 1, 0, 16, 6, 1, 32, 2, 1),
+    LLHMM_SLAB_QTY_HR(float, 1, 1, 16, 6, 1, 32, 2, 1),
     // FP64: windows of 16 rows (reference tables read from global memory)
     LLHMM_SLAB_QTY(double, 0, 0, 64, 2, 2, 8, 2, 1),
     LLHMM_SLAB_QTY(double, 0, 1, 64, 2, 2, 8, 2, 1),
