@@ -47,21 +47,22 @@ hipError_t occupancy_slab(int *blocks_per_cu) {
         LLHMM_SLAB(T, PREC, 4, BC, 2, L, K, R, NG, NBUF, MINW)
 
 static const SlabTileInfo kSlab[] = {
-    // FP32: windows of 32 rows (LDS holds the window's reference tables)
-    LLHMM_SLAB_QTY(float, 1, 0, 64, 2, 4, 8, 1, 1),
-    LLHMM_SLAB_QTY(float, 1, 1, 64, 2, 4, 8, 1, 1),
-    // FP32 n = 96: one row per lane, 8 waves (two per SIMD) first; two rows per
-    // lane in 4 waves second
-    LLHMM_SLAB_QTY(float, 1, 0, 16, 6, 1, 32, 1, 1),
-    LLHMM_SLAB_QTY(float, 1, 1, 16, 6, 1, 32, 1, 1),
-    LLHMM_SLAB_QTY(float, 1, 0, 16, 6, 2, 16, 1, 1),
-    LLHMM_SLAB_QTY(float, 1, 1, 16, 6, 2, 16, 1, 1),
-    // FP32 with H(r) in registers: the LDS left over takes a double-buffered
-    // halo (one barrier per stage)
+    // FP32: windows of 32 rows.  First (the defaults, the tuner's choice on the
+    // uneven batch): H(r) in registers, so the LDS left over by r and |r|^2 - 1
+    // takes a double-buffered halo (one barrier per stage)
     LLHMM_SLAB_QTY_HR(float, 1, 0, 64, 2, 4, 8, 2, 1),
     LLHMM_SLAB_QTY_HR(float, 1, 1, 64, 2, 4, 8, 2, 1),
     LLHMM_SLAB_QTY_HR(float, 1, 0, 16, 6, 1, 32, 2, 1),
     LLHMM_SLAB_QTY_HR(float, 1, 1, 16, 6, 1, 32, 2, 1),
+    // then the window's reference tables all in LDS, single-buffered halo
+    LLHMM_SLAB_QTY(float, 1, 0, 64, 2, 4, 8, 1, 1),
+    LLHMM_SLAB_QTY(float, 1, 1, 64, 2, 4, 8, 1, 1),
+    // FP32 n = 96 with the tables in LDS: one row per lane (8 waves), then two
+    // rows per lane (4 waves)
+    LLHMM_SLAB_QTY(float, 1, 0, 16, 6, 1, 32, 1, 1),
+    LLHMM_SLAB_QTY(float, 1, 1, 16, 6, 1, 32, 1, 1),
+    LLHMM_SLAB_QTY(float, 1, 0, 16, 6, 2, 16, 1, 1),
+    LLHMM_SLAB_QTY(float, 1, 1, 16, 6, 2, 16, 1, 1),
     // FP64: windows of 16 rows (reference tables read from global memory)
     LLHMM_SLAB_QTY(double, 0, 0, 64, 2, 2, 8, 2, 1),
     LLHMM_SLAB_QTY(double, 0, 1, 64, 2, 2, 8, 2, 1),
