@@ -111,7 +111,11 @@ typedef struct {
     double phase[LLHMM_MAX_TERMS][3];
 } llhmm_coef;
 
-/* One micro problem (eq. (micro)).  d = 3 boxes (the problem allows d <= 3,
+/* One micro problem (eq. (micro)).  2-D boxes are built for n = 16, 32, 48,
+ * 64, 80, 96, 112 and 128 at second order (resident kernels up to 64, row slabs
+ * above) and for n = 32 to 128 except 80 and 112 at fourth order; 1-D boxes for
+ * n = 64, 128 and 256; d = 3 boxes for even n <= 64 (FP64).  Other sizes return
+ * LLHMM_E_NOTSUP.  d = 3 boxes (the problem allows d <= 3,
  * Section 2.1) are supported in FP64 with a closed-form or sampled
  * coefficient, the second- or fourth-order stencil, and the field, torque and
  * flux quantities (flux: nine outputs, [axis][component]); d = 3 in FP32
@@ -294,7 +298,7 @@ llhmm_status llhmm_solve_noalloc(llhmm_ctx *ctx, const llhmm_box *boxes, int32_t
                                  int32_t ld, int32_t *status_dev, hipStream_t stream);
 
 /* Large boxes.  2-D boxes too large for one workgroup's registers and LDS
- * (n = 96, 128) are cut into slabs of consecutive full-width rows, one
+ * (n = 80, 96, 112, 128) are cut into slabs of consecutive full-width rows, one
  * workgroup per slab for all time steps of the box; the micro problem of
  * eq. (micro) is still solved as one box.  A workgroup holds its slab's own
  * rows and h halo rows on each side: the zeros it sees beyond that window

@@ -27,6 +27,11 @@ static const TileInfo kTiles[] = {
     LLHMM_TILE_OPT(float, 1, 2, 2, 0, 2, 64, 1, 4, 16, 2, 1, kOptHReg),
     LLHMM_TILE_OPT(float, 1, 2, 2, 1, 1, 64, 1, 4, 16, 2, 1, kOptHReg),
     LLHMM_TILE_OPT(float, 1, 2, 2, 1, 2, 64, 1, 4, 16, 2, 1, kOptHReg),
+    // n = 16: 4 row groups of 4 rows, one point per lane (one wavefront per box)
+#define LLHMM_N16_F32(BC, QTY) LLHMM_TILE(float, 1, 2, 2, BC, QTY, 16, 1, 4, 4, 2, 16)
+    LLHMM_N16_F32(0, 0), LLHMM_N16_F32(0, 1), LLHMM_N16_F32(0, 2),
+    LLHMM_N16_F32(1, 0), LLHMM_N16_F32(1, 1), LLHMM_N16_F32(1, 2),
+#undef LLHMM_N16_F32
     // fourth order at n = 32 (two points per lane: x1 neighbours up to two lanes
     // away) and n = 64 (one point per lane, three lanes away)
 #define LLHMM_O4_F32(BC, QTY)                                      \

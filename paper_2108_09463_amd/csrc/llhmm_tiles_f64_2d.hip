@@ -21,6 +21,11 @@ static const TileInfo kTiles[] = {
     LLHMM_TILE(double, 0, 2, 2, 0, 2, 64, 1, 8, 8, 2, 2),
     LLHMM_TILE(double, 0, 2, 2, 1, 1, 64, 1, 8, 8, 2, 2),
     LLHMM_TILE(double, 0, 2, 2, 1, 2, 64, 1, 8, 8, 2, 2),
+    // n = 16: 4 row groups of 4 rows, one point per lane (one wavefront per box)
+#define LLHMM_N16_F64(BC, QTY) LLHMM_TILE(double, 0, 2, 2, BC, QTY, 16, 1, 4, 4, 2, 16)
+    LLHMM_N16_F64(0, 0), LLHMM_N16_F64(0, 1), LLHMM_N16_F64(0, 2),
+    LLHMM_N16_F64(1, 0), LLHMM_N16_F64(1, 1), LLHMM_N16_F64(1, 2),
+#undef LLHMM_N16_F64
     // fourth order in the reference + perturbation form (no boundary offsets, so
     // lanes narrower than the stencil's reach are allowed): n = 32 with the
     // reference tables in LDS, n = 64 with them read from global memory

@@ -1,5 +1,5 @@
 // Slab-mode tile classes: 2-D boxes too large for one workgroup's registers
-// and LDS (n = 96, 128), cut into row slabs that
+// and LDS (n = 80, 96, 112, 128), cut into row slabs that
 // co-resident workgroups advance together, each in a window of R * NG rows
 // with halo rows (k_slab).  Per class the first variant is the default;
 // llhmm_batch_tune times the others.
@@ -63,11 +63,21 @@ static const SlabTileInfo kSlab[] = {
     LLHMM_SLAB_QTY(float, 1, 1, 16, 6, 1, 32, 1, 1),
     LLHMM_SLAB_QTY(float, 1, 0, 16, 6, 2, 16, 1, 1),
     LLHMM_SLAB_QTY(float, 1, 1, 16, 6, 2, 16, 1, 1),
+    // FP32 n = 80 (5 points per lane, 32-row windows, H(r) in registers) and
+    // n = 112 (7 points per lane, 16-row windows, one wave per SIMD)
+    LLHMM_SLAB_QTY_HR(float, 1, 0, 16, 5, 1, 32, 2, 1),
+    LLHMM_SLAB_QTY_HR(float, 1, 1, 16, 5, 1, 32, 2, 1),
+    LLHMM_SLAB_QTY(float, 1, 0, 16, 7, 1, 16, 2, 1),
+    LLHMM_SLAB_QTY(float, 1, 1, 16, 7, 1, 16, 2, 1),
     // FP64: windows of 16 rows (reference tables read from global memory)
     LLHMM_SLAB_QTY(double, 0, 0, 64, 2, 2, 8, 2, 1),
     LLHMM_SLAB_QTY(double, 0, 1, 64, 2, 2, 8, 2, 1),
     LLHMM_SLAB_QTY(double, 0, 0, 16, 6, 1, 16, 1, 1),
     LLHMM_SLAB_QTY(double, 0, 1, 16, 6, 1, 16, 1, 1),
+    LLHMM_SLAB_QTY(double, 0, 0, 16, 5, 1, 16, 1, 1),
+    LLHMM_SLAB_QTY(double, 0, 1, 16, 5, 1, 16, 1, 1),
+    LLHMM_SLAB_QTY(double, 0, 0, 16, 7, 1, 16, 1, 1),
+    LLHMM_SLAB_QTY(double, 0, 1, 16, 7, 1, 16, 1, 1),
     // fourth order (H(r) in registers for FP32): a halo of 3 rows per stage (12
     // for an RK4P step), which every slab must own at least once over: 40-row
     // windows for n = 128 (8 slabs of 16 rows), 36-row windows of three-row
