@@ -83,9 +83,9 @@ COUNTER_FILES = {"fp32": "profiles/k_micro_f32_two_d_batch_counters.txt",
 
 
 def measured_counters(name):
-    """VALU issue utilisation and LDS bank-conflict rate of the time-stepping
-    kernel from the committed PMC summary, or None when absent or taken on
-    other kernel sources."""
+    """VALU issue rate (wave64 instructions per CU per clock) and LDS
+    bank-conflict rate of the time-stepping kernel from the committed PMC
+    summary, or None when absent or taken on other kernel sources."""
     path = os.path.join(ROOT, COUNTER_FILES[name])
     if not os.path.exists(path):
         return None
@@ -97,7 +97,7 @@ def measured_counters(name):
     if kv.get("kernel_sources_sha256_16") != kernel_source_hash(KERNEL_SOURCES):
         return None
     try:
-        return {"valu_issue_utilisation": float(kv["valu_issue_utilisation"]),
+        return {"valu_issue_rate": float(kv["valu_issue_rate"]),
                 "valu_busy": float(kv["valu_busy"]),
                 "lds_bank_conflict_rate": float(kv["lds_bank_conflict_rate"]),
                 "hardware_over_algorithmic_flops": float(kv["hardware_over_algorithmic"]),
