@@ -209,7 +209,8 @@ struct MicroLane {
     // DPP moves); the boundary offsets of form 0 assume one lane holds them all
     static_assert(K >= YH || FORM == 1, "lane tile narrower than the stencil reach");
     // periodic second-order 2-D form 0: x1 fluxes formed once per face (as in form 1)
-    // with the seam offsets added by FMA, x2 seam offsets only in the edge row groups
+    // with the seam offsets added by FMA; seam faces on both axes take the
+    // offset's high word only
     static constexpr bool SEAM0 = (ORD == 2) && (FORM == 0) && (BC == LLHMM_BC_PERIODIC_PERT) && (D == 2);
     // second-order 2-D stages update the group's interior rows before waiting
     // for the other groups' halo rows
