@@ -39,14 +39,19 @@ __device__ double coef_closed(const CoefDev &c, double x0, double x1) {
 }
 
 // Sine factors of a closed-form coefficient, tabulated once per box: for term
-// t, S[(t * 4 + k) * kTabLen + idx] with k = 0: x1 factor at x1 faces f
+// t, S[(t * K + k) * len + idx] (K = 4 row kinds in 2-D, 2 in 1-D; len = n + 3)
+// with k = 0: x1 factor at x1 faces f
 // (idx f + 2), 1: x1 factor at points, 2: x2 factor at x2 faces, 3: x2 factor
 // at points.  Each entry is the same expression coef_closed evaluates, so a
 // coefficient built from the table is bit-identical to the direct one.
 constexpr int kCoefTabTerms = 4;
-constexpr int kTabLen = 256 + 3;
+// 2-D boxes have n <= 128 and four row kinds, 1-D boxes n <= 256 and two: one
+// size fits both, small enough for four set-up blocks per CU
+constexpr int kCoefTabSize = kCoefTabTerms * 4 * (128 + 3);
+static_assert(kCoefTabTerms * 2 * (256 + 3) <= kCoefTabSize, "1-D sine tables");
 struct CoefTables {
     const double *S;  // nullptr: evaluate directly
+    int kinds, len;   // row kinds per term, entries per row
 };
 
 // a^eps on the face between point (i0, i1) and (i0, i1) + e_axis (unscaled).
@@ -64,10 +69,10 @@ __device__ double face_coef(const PrologueArgs &A, const BoxPlan &P, const CoefT
         double a = c.c0;
         for (int t = 0; t < c.n_terms; ++t) {
             double p = c.amp[t];
-            const double *St = CT.S + t * 4 * kTabLen;
-            if (c.freq[t][0] != 0.0) p = p * (axis == 0 ? St[i0 + 2] : St[kTabLen + i0]);
+            const double *St = CT.S + t * CT.kinds * CT.len;
+            if (c.freq[t][0] != 0.0) p = p * (axis == 0 ? St[i0 + 2] : St[CT.len + i0]);
             if (c.dim == 2 && c.freq[t][1] != 0.0)
-                p = p * (axis == 1 ? St[2 * kTabLen + i1 + 2] : St[3 * kTabLen + i1]);
+                p = p * (axis == 1 ? St[2 * CT.len + i1 + 2] : St[3 * CT.len + i1]);
             a = a + p;
         }
         return a;
@@ -274,7 +279,7 @@ __device__ double ref_flux(const BoxPlan &P, const T *tab, const TabLayout &L, c
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_prologue(PrologueArgs A) {
+__global__ void __launch_bounds__(256, 4) k_prologue(PrologueArgs A) {
     const int box = blockIdx.x;
     const BoxPlan P = A.plans[box];
     if (P.dim == 3) return;  // d = 3 boxes have their own set-up kernel (k_setup3d)
@@ -291,17 +296,17 @@ __global__ void __launch_bounds__(256) k_prologue(PrologueArgs A) {
     __shared__ double s_Mloc[75];
     __shared__ double s_Lb[kLagMax * 5];
     __shared__ double s_Lb1[kLagMax2 * 5];
-    __shared__ double s_sin[kCoefTabTerms * 4 * kTabLen];
+    __shared__ double s_sin[kCoefTabSize];
     InitTables IT{s_Mloc, s_Lb, s_Lb1};
-    CoefTables CT{nullptr};
+    CoefTables CT{nullptr, (D == 2) ? 4 : 2, N + 3};
     {
         const CoefDev &c = A.coefs[P.coef_index];
-        if (!P.coef_sampled && c.n_terms <= kCoefTabTerms) {
+        if (!P.coef_sampled && c.n_terms <= kCoefTabTerms && c.n_terms * CT.kinds * CT.len <= kCoefTabSize) {
             // sine factors at every face and point position, once per box
             const double two_pi = 6.283185307179586;
-            const int len = N + 3;
-            for (int t2 = tid; t2 < c.n_terms * 4 * len; t2 += nth) {
-                const int t = t2 / (4 * len), k = (t2 / len) % 4, idx = t2 % len;
+            const int len = CT.len, kinds = CT.kinds;
+            for (int t2 = tid; t2 < c.n_terms * kinds * len; t2 += nth) {
+                const int t = t2 / (kinds * len), k = (t2 / len) % kinds, idx = t2 % len;
                 const int ax = k / 2;
                 const bool face = (k % 2) == 0;
                 if (face ? idx > N + 2 : idx >= N) continue;
@@ -309,7 +314,7 @@ __global__ void __launch_bounds__(256) k_prologue(PrologueArgs A) {
                 if (ax == 1 && (c.dim != 2 || D != 2)) continue;
                 double x = (ax == 0 ? P.cx : P.cy) + grid_xi(P, gi);
                 if (face) x = x + 0.5 * P.dx;
-                s_sin[(t * 4 + k) * kTabLen + idx] = sin(two_pi * c.freq[t][ax] * x + c.phase[t][ax]);
+                s_sin[(t * kinds + k) * len + idx] = sin(two_pi * c.freq[t][ax] * x + c.phase[t][ax]);
             }
             CT.S = s_sin;
         }
