@@ -392,10 +392,13 @@ struct MicroLane {
         auto halo_ready = [&]() {
             if (D != 2) return;
             const T *hb = s_halo + (NBUF == 2 ? (tstage & 1) * HALO : 0);
-            // stage 0 reads the neighbours' rows of the initial state, loaded
-            // from the tables with the window
-            if (SLAB && xs_on && tstage > 0) xs_receive((uint32_t)tstage);
             __syncthreads();
+            // The edge groups wait for the neighbour slabs' rows after the
+            // barrier, so the other groups go on meanwhile.  Each lane reads back
+            // only the LDS words it wrote itself: no second barrier.  Stage 0
+            // reads the neighbours' rows of the initial state, loaded from the
+            // tables with the window.
+            if (SLAB && xs_on && tstage > 0) xs_receive((uint32_t)tstage);
             srcS = zero_s ? s_zero : hb + (gs * HROWS + HROWS - YH) * 3 * N;
             srcN = zero_n ? s_zero : hb + (gn * HROWS + 0) * 3 * N;
             if (SLAB && xs_on) {
