@@ -660,7 +660,8 @@ llhmm_status llhmm_create(llhmm_ctx **ctx, int32_t device) {
     char *scratch_dev = nullptr;
     const llhmm_status st = scratch_address(device, &scratch_dev);
     if (st != LLHMM_OK) return st;
-    *ctx = new llhmm_ctx{device};
+    *ctx = new llhmm_ctx();
+    (*ctx)->device = device;
     (*ctx)->scratch = scratch_dev;
     return LLHMM_OK;
 }

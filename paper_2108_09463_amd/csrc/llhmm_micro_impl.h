@@ -832,7 +832,7 @@ template <typename T, int D, int ORD, int BC, int QTY, int L, int K, int R, int 
           int OPT = 0>
 __global__ void __launch_bounds__(L * NG, MINW) k_micro(MicroArgs A) {
     using Lane = MicroLane<T, D, ORD, BC, QTY, L, K, R, NG, NBUF, false, OPT>;
-    constexpr int N = Lane::N, NF = Lane::NF, NFR = Lane::NFR, FW = Lane::FW, GF = Lane::GF;
+    constexpr int N = Lane::N, NF = Lane::NF, FW = Lane::FW, GF = Lane::GF;
     constexpr int YH = Lane::YH, NQ = Lane::NQ;
     __shared__ T s_halo[NBUF * Lane::HALO];
     __shared__ T s_zero[(D == 2) ? YH * 3 * N : 1];
