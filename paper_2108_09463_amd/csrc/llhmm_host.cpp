@@ -330,16 +330,22 @@ void slab_rows(const SlabTileInfo &t, int n, int ns, int s, int *o0, int *rows) 
 }
 
 // Exchange interval without tuning: fewest window rows computed per box, an
-// exchange weighted as half a step of the window (a fifth of a step when it
-// comes at every stage, where it overlaps the interior rows; without interior
-// rows, R < 3, the per-stage exchange is left to the tuner).  -1: none fits.
+// exchange weighted as half a step of the window.  An exchange at every stage
+// weighs a fifth of a step when interior rows (R >= 3) overlap its wait.
+// Without them the wait is exposed: it weighs a step in FP64 and 1.2 steps in
+// FP32, whose stages are cheaper.  Measured, the 32-row FP32 windows then keep
+// one exchange per step (a quarter of their rows are halo), while the 16-row
+// windows, half halo at one exchange per step, run up to twice as fast with
+// the exchange at every stage (all FP64 classes; FP32 n = 112 with RK4P, not
+// with HeunP, whose halo is half as deep).  -1: none fits.
 int slab_default_spe(const SlabTileInfo &t, int n, int stages) {
     int best = -1;
     double best_cost = 0.0;
     for (int spe : kSlabSpe) {
         const SlabGeom g = slab_geom(t, n, stages, spe);
-        if (g.ns == 0 || (spe == 0 && t.R < 3)) continue;
-        const double cost = g.ns * (1.0 + (spe == 0 ? 0.2 : 0.5 / spe));
+        if (g.ns == 0) continue;
+        const double wait = (t.R >= 3) ? 0.2 : (t.prec == LLHMM_FP64 ? 1.0 : 1.2);
+        const double cost = g.ns * (1.0 + (spe == 0 ? wait : 0.5 / spe));
         if (best < 0 || cost < best_cost) {
             best = spe;
             best_cost = cost;
