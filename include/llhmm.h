@@ -315,7 +315,11 @@ llhmm_status llhmm_solve_noalloc(llhmm_ctx *ctx, const llhmm_box *boxes, int32_t
  * whose workgroups take (box, slab) items, longest boxes first.  A wait for a
  * neighbouring slab gives up after a bounded number of polls; the boxes
  * involved then report status 2 and llhmm_upscale with check returns
- * LLHMM_E_HIP.
+ * LLHMM_E_HIP.  Untuned, a class takes its first tile variant and the interval
+ * with the fewest window rows per box, an exchange counted as half a step;
+ * an exchange at every stage counts a fifth of a step when the variant has
+ * interior rows to hide its wait (3 or more rows per lane), else one step
+ * (FP64) or 1.2 steps (FP32).
  *
  * Autotuner for these boxes.  For every class (precision, n, bc, quantity,
  * integrator) it times the class alone, `reps` times after one warm-up, with
