@@ -12,16 +12,18 @@ constexpr int kMaxWaves = 16;  // waves per block of the resident kernels
 // Largest distance between neighbouring points of a final state that counts as
 // resolved (status bit 4 above it)
 constexpr double kRoughMax = 0.5;
-constexpr int kMaxQ = 9;
+constexpr int kMaxQ = 9;       // outputs per box (flux in 3-D: 3 axes x 3 components)
 // Layout options of the resident kernels (bits of MicroLane's OPT):
 constexpr int kOptForm1 = 1;  // reference + perturbation form in FP64 too (no boundary offsets)
 constexpr int kOptRefG = 2;   // form-1 reference tables read from global memory instead of LDS
 constexpr int kOptHReg = 4;   // H(r) of the own points in registers; LDS keeps r and |r|^2 - 1
-constexpr int kMaxXcc = 8;     // accelerator complexes (XCDs) per device, each with its own L2       // outputs per box (flux in 3-D: 3 axes x 3 components)
+constexpr int kMaxXcc = 8;     // accelerator complexes (XCDs) per device, each with its own L2
 constexpr int kFaceHalo = 3;   // faces -2 .. n stored per line: n + 3 entries
 // FP32 reference + perturbation form: every kRerefSteps time steps the state
 // is re-expressed around a new reference r' = fl(r + u) (MicroLane::rereference).
 constexpr int kRerefSteps = 8;
+// Slab kernels: steps between the workgroup-wide checks for a wait that gave up
+constexpr int kAbortCheckSteps = 8;
 
 // Per-box plan as the kernels read it.
 struct BoxPlan {

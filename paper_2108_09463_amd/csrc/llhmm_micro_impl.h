@@ -1105,8 +1105,9 @@ __device__ __forceinline__ S uniform_load(const S *p) {
 // waits for an item of its own box, which is taken before any later item, so
 // a queue makes progress with any number of resident workgroups on its XCD
 // >= slabs per box.  Every wait polls at most A.spin_max times; a wait that runs out sets
-// the grid-wide abort word, every workgroup then stops, and the boxes it
-// touched report status 2.
+// the grid-wide abort word, every later wait ends at once on it, every
+// workgroup stops at its next check (every kAbortCheckSteps steps and after
+// the last step), and the boxes it touched report status 2.
 // EVAL (a separate instantiation, so that the solve's register allocation
 // does not carry the evaluation's): evaluate H(m0) on the own rows instead of
 // solving; A.mode must agree.
@@ -1352,8 +1353,7 @@ __global__ void __launch_bounds__(L * NG, MINW) k_slab(SlabArgs A) {
 #pragma unroll
                                 for (int c = 0; c < 3; ++c) S.y[r][k][c] = S.m[r][k][c];
                     }
-                    aborted = __syncthreads_or(fail) != 0;
-                    if (aborted) break;
+                    S.xs_fail |= fail;
                 }
                 const double wn = wtab[n];
                 if (REREF && n > 0 && n % kRerefSteps == 0) S.rereference(wtab[M + 1 + n], ts++);
@@ -1368,11 +1368,14 @@ __global__ void __launch_bounds__(L * NG, MINW) k_slab(SlabArgs A) {
                 S.xs_pub = !(REREF && (n + 1) % kRerefSteps == 0);
                 S.template stage<AVG_NONE, false, true>(rk4 ? (T)(1.0 / 6.0) : (T)0.5, (T)0, 0.0, ts++, nullptr, 0);
                 S.xs_pub = true;
-                if (xs) {
+                // a wait that gave up is seen by the whole workgroup every few
+                // steps and after the last one (the other waits end at once on
+                // the abort word meanwhile)
+                if ((n + 1) % kAbortCheckSteps == 0 || n + 1 == M) {
                     aborted = __syncthreads_or(S.xs_fail) != 0;
                     if (aborted) break;
-                    continue;
                 }
+                if (xs) continue;
                 if ((n + 1) % spe == 0 && n + 1 < M) {
                     // publish the edge rows of exchange e = (n + 1) / spe: the first xd own
                     // rows (south edge) and the last xd (north edge; a group may be in both)
